@@ -1,0 +1,163 @@
+"""Pins of the oracle's shifted CG (Sec. 2.2, eq. 5 and the Hermitian-seed argument).
+
+* Converged solutions equal the spectral solution W diag(1/(z - lambda)) W^H v from a
+  dense eigen-decomposition (4^4 lattice).
+* At a fixed iteration k every shifted iterate is the Galerkin (FOM) solution on the
+  Krylov space K_k(A, v), computed here from an independently built Lanczos basis;
+  it does not depend on the seed shift.
+* One shift equal to the seed reduces to textbook CG (scipy's cg, positive definite seed).
+* The implicit residual sqrt(rho)/|pi_j| equals the true shifted residual (collinearity).
+* Conjugate nodes have conjugate scalars, hence identical convergence iterations.
+* Failure paths: zero source, maxiter, breakdown on B v = 0, a shift on an eigenvalue.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as sla
+
+import synth
+from oracle import quadrature as quad
+from oracle import solvers, wilson
+
+CFG1 = synth.CONFIGS["wilson4_fp64"]
+
+
+@pytest.fixture(scope="module")
+def cfg1_spec():
+    U = CFG1.gauge()
+    A = wilson.hermitian_wilson(U, CFG1.dims, CFG1.kappa)
+    lam, W = np.linalg.eigh(A.toarray())
+    return A, lam, W
+
+
+def spectral_solve(lam, W, z, v):
+    c = W.conj().T @ v
+    return np.array([W @ (c / (zj - lam)) for zj in z])
+
+
+def test_converged_matches_spectral_solution(cfg1_spec):
+    A, lam, W = cfg1_spec
+    v = CFG1.sources().reshape(-1)
+    z, _ = quad.line_nodes(CFG1.N, CFG1.gamma, CFG1.rho, CFG1.beta)
+    r = solvers.shifted_cg(lambda x: A @ x, v, z, CFG1.gamma, 1e-12)
+    assert r.status == "ok"
+    Y = spectral_solve(lam, W, z, v)
+    assert np.linalg.norm(r.Y - Y) / np.linalg.norm(Y) < 1e-10
+    assert solvers.true_residuals(lambda x: A @ x, v, z, r.Y).max() < 2e-12
+
+
+def lanczos_basis(A, v, k):
+    """Orthonormal basis of K_k(A, v) by Lanczos with full reorthogonalisation."""
+    Q = np.zeros((v.size, k), dtype=complex)
+    Q[:, 0] = v / np.linalg.norm(v)
+    for i in range(1, k):
+        w = A @ Q[:, i - 1]
+        for _ in range(2):
+            w -= Q[:, :i] @ (Q[:, :i].conj().T @ w)
+        Q[:, i] = w / np.linalg.norm(w)
+    return Q
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.07, -0.3])
+def test_iterates_are_galerkin_solutions(cfg1_spec, sigma):
+    A, _, _ = cfg1_spec
+    v = CFG1.sources().reshape(-1)
+    z, _ = quad.line_nodes(CFG1.N, CFG1.gamma, CFG1.rho, CFG1.beta)
+    k = 12
+    snap = {}
+
+    def rec(it, st):
+        if it == k - 1:
+            snap["X"] = st["X"].copy()
+
+    solvers.shifted_cg(lambda x: A @ x, v, z, sigma, 1e-30, maxiter=k, record=rec)
+    Q = lanczos_basis(A, v, k)
+    AQ = A @ Q
+    for j, zj in enumerate(z):
+        Hk = Q.conj().T @ (zj * Q - AQ)
+        x = Q @ np.linalg.solve(Hk, Q.conj().T @ v)
+        assert np.linalg.norm(snap["X"][j] - x) / np.linalg.norm(x) < 1e-9
+
+
+def test_single_shift_at_seed_is_textbook_cg(cfg1_spec):
+    A, _, _ = cfg1_spec
+    v = CFG1.sources().reshape(-1)
+    sigma = 2.5   # > ||A|| <= 1 + 8 kappa: the seed matrix is positive definite
+    k = 15
+    snap = {}
+
+    def rec(it, st):
+        if it == k - 1:
+            snap["x"] = st["X"][0].copy()
+
+    solvers.shifted_cg(lambda x: A @ x, v, np.array([sigma + 0j]), sigma, 1e-30, maxiter=k, record=rec)
+    B = sla.LinearOperator(A.shape, matvec=lambda x: sigma * x - A @ x, dtype=complex)
+    xs = []
+    sla.cg(B, v, rtol=1e-30, atol=0.0, maxiter=k, callback=lambda xk: xs.append(xk.copy()))
+    assert np.linalg.norm(snap["x"] - xs[k - 1]) / np.linalg.norm(xs[k - 1]) < 1e-12
+
+
+def test_implicit_equals_true_residual(cfg1_spec):
+    A, _, _ = cfg1_spec
+    v = CFG1.sources().reshape(-1)
+    z, _ = quad.line_nodes(CFG1.N, CFG1.gamma, CFG1.rho, CFG1.beta)
+    snap = {}
+
+    def rec(it, st):
+        if it == 29:
+            snap.update(X=st["X"].copy(), pi=st["pi"].copy(), rho=st["rho"])
+
+    solvers.shifted_cg(lambda x: A @ x, v, z, CFG1.gamma, 1e-30, maxiter=30, record=rec)
+    implicit = np.sqrt(snap["rho"]) / np.abs(snap["pi"])
+    true = np.array([np.linalg.norm(v - (zj * x - A @ x)) for zj, x in zip(z, snap["X"])])
+    assert np.abs(implicit - true).max() / true.max() < 1e-9
+
+
+def test_conjugate_nodes_share_convergence(cfg1_spec):
+    A, _, _ = cfg1_spec
+    v = CFG1.sources().reshape(-1)
+    z, _ = quad.line_nodes(CFG1.N, CFG1.gamma, CFG1.rho, CFG1.beta)
+    r = solvers.shifted_cg(lambda x: A @ x, v, z, CFG1.gamma, 1e-12)
+    assert np.array_equal(r.conv_iter[0::2], r.conv_iter[1::2])
+    # nodes closer to the real-axis ends need more iterations (Sec. 3, Fig. 1 trend)
+    assert r.conv_iter[0] >= r.conv_iter[CFG1.N // 2]
+
+
+def test_zero_source_rejected(cfg1_spec):
+    A, _, _ = cfg1_spec
+    with pytest.raises(ValueError):
+        solvers.shifted_cg(lambda x: A @ x, np.zeros(CFG1.n, complex), np.array([0.1j]), 0.0)
+
+
+def test_maxiter_reports_not_converged(cfg1_spec):
+    A, _, _ = cfg1_spec
+    v = CFG1.sources().reshape(-1)
+    r = solvers.shifted_cg(lambda x: A @ x, v, np.array([0.05j]), 0.0, 1e-12, maxiter=1)
+    assert r.status == "notconv" and r.iters == 1 and r.conv_iter[0] == -1
+
+
+def free_field_mode(dims):
+    """Zero-momentum spinor with spin 0, colour 0: A v = (1 - 8 kappa) v for unit links.
+    At kappa = 1/8 every term is a dyadic rational, so A v = 0 holds exactly."""
+    V = int(np.prod(dims))
+    v = np.zeros((V, 4, 3), dtype=complex)
+    v[:, 0, 0] = 1.0
+    return v.reshape(-1)
+
+
+def test_breakdown_when_seed_annihilates_source():
+    dims, kappa = (4, 4, 4, 4), 0.125
+    A = wilson.hermitian_wilson(synth.unit_gauge(dims), dims, kappa)
+    v = free_field_mode(dims)
+    assert np.all(A @ v == 0)
+    r = solvers.shifted_cg(lambda x: A @ x, v, np.array([0.01j]), 0.0, 1e-12)
+    assert r.status == "breakdown" and r.iters == 0
+
+
+def test_shift_on_an_eigenvalue_never_converges():
+    dims, kappa = (4, 4, 4, 4), 0.12
+    A = wilson.hermitian_wilson(synth.unit_gauge(dims), dims, kappa)
+    v = synth.sources(256, 1, 7).reshape(-1)
+    z = np.array([0.04 + 0j, 0.04 + 0.05j, -0.1 + 0.05j])
+    r = solvers.shifted_cg(lambda x: A @ x, v, z, 0.0, 1e-12, maxiter=300)
+    assert r.status == "notconv"
+    assert r.conv_iter[0] == -1 and r.conv_iter[1] > 0 and r.conv_iter[2] > 0
