@@ -1,0 +1,214 @@
+/*
+ * sscg.h - Sakurai-Sugiura eigensolver for the Hermitian Wilson fermion matrix,
+ * with one shifted-CG run solving every quadrature shift (gfx950 / MI355X).
+ *
+ * Paper: H. Ohno, Y. Kuramashi, T. Sakurai, H. Tadano, "A quadrature-based
+ * eigensolver with a Krylov subspace method for shifted linear systems for
+ * Hermitian eigenproblems in lattice QCD" (arXiv:1004.0292).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  Lattice   dims = {Lx, Ly, Lz, Lt}, V = Lx Ly Lz Lt sites, periodic in all four
+ *            directions; site s = x + Lx (y + Ly (z + Lz t)).
+ *  Spinors   complex128 (interleaved re, im doubles), canonical layout
+ *            [nsrc][V][4 spin][3 colour]; a vector has n = 12 V complex entries,
+ *            entry 12 s + 3 spin + colour.
+ *  Gauge     complex128 [4 mu][V][3][3], row-major colour matrices; mu = 0..3 is
+ *            x, y, z, t and U_mu(x) multiplies psi(x + mu) in the forward hop.
+ *  Matrix    A = gamma5 (I - kappa D) (Sec. 4), Hermitian, with the Wilson hopping
+ *            matrix (r = 1)
+ *              (D psi)(x) = sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                                   + (1 + gamma_mu) U_mu(x-mu)^H psi(x-mu)]
+ *            and Dirac matrices in the chiral basis, gamma5 = diag(1, 1, -1, -1).
+ *  Memory    "device" pointers are HIP device allocations on the context's device
+ *            (e.g. torch tensors); "host" pointers are ordinary host memory. The
+ *            caller owns every buffer it passes; the context owns the packed gauge
+ *            field and all workspaces (allocated on first use of a given shape,
+ *            reused, freed by sscg_destroy). Nothing is allocated inside the
+ *            iteration loop.
+ *  Streams   all device work runs on the stream given to sscg_create (NULL = the
+ *            default stream). Calls marked "stream-ordered" return before the work
+ *            is done; the others synchronise that stream before returning.
+ *  Errors    every int-returning call returns SSCG_OK or a negative status; no
+ *            exception or abort crosses the ABI. On error the outputs are
+ *            undefined and sscg_last_error() holds a message. One context must not
+ *            be used from two host threads at once.
+ */
+#ifndef SSCG_H
+#define SSCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sscg_ctx sscg_ctx;
+
+enum {
+  SSCG_OK = 0,
+  SSCG_EINVAL = -1,      /* bad argument (size, pointer, parameter range)        */
+  SSCG_ENOMEM = -2,      /* device or pinned host allocation failed              */
+  SSCG_EDEVICE = -3,     /* a HIP call failed                                    */
+  SSCG_ENOTCONV = -4,    /* maxiter reached before every shift converged         */
+  SSCG_EBREAKDOWN = -5,  /* <p, (sigma I - A) p> = 0 or a non-finite CG scalar   */
+  SSCG_ESTATE = -6       /* call out of order (e.g. no gauge field set)          */
+};
+
+enum { SSCG_FP64 = 0,    /* every vector, product and scalar in FP64                 */
+       SSCG_MIXED = 1 }; /* FP64 until the largest active shifted residual falls
+                            below switch_tol, then FP32 dslash and vector updates
+                            with FP64 reliable updates of the seed residual; scalar
+                            recurrences and dot products stay FP64                 */
+
+enum { SSCG_PATH_LINES = 0, SSCG_PATH_CIRCLE = 1 };
+enum { SSCG_RR = 0, SSCG_HANKEL = 1 };
+
+/* Create a context for one lattice on HIP device `device`, using `hip_stream`
+ * (a hipStream_t, or NULL for the default stream). dims: host int32[4].
+ * kappa: hopping parameter (Sec. 4); r: Wilson parameter, must be 1.
+ * Returns SSCG_EINVAL for non-positive dims or r != 1. */
+int sscg_create(sscg_ctx **out, const int32_t dims[4], double kappa, double r,
+                int32_t device, void *hip_stream);
+void sscg_destroy(sscg_ctx *ctx);
+const char *sscg_last_error(const sscg_ctx *ctx);
+/* Library-wide message for failures before a context exists (sscg_create). */
+const char *sscg_global_error(void);
+
+/* Set the gauge links: U host complex128 [4][V][3][3] (copied). link_reals = 18
+ * stores full 3x3 links; 12 stores the first two rows and rebuilds the third as
+ * the conjugated cross product of the first two on load (valid for SU(3) only;
+ * applies to the FP32 arithmetic of SSCG_MIXED; FP64 always keeps 18). */
+int sscg_set_gauge(sscg_ctx *ctx, const double *U, int32_t link_reals);
+
+/* y = A x for nsrc spinors (Sec. 4; the matrix whose eigenpairs are sought, Sec. 2.1).
+ * x, y: device complex128 canonical [nsrc][V][4][3]; must not overlap.
+ * prec SSCG_FP64 computes in FP64; SSCG_MIXED rounds x and the links to FP32,
+ * applies A in FP32 and widens the result. Stream-ordered. */
+int sscg_apply_A(sscg_ctx *ctx, const void *x, void *y, int32_t nsrc, int32_t prec);
+
+typedef struct {
+  double tol;            /* per-shift stop: ||r_j|| <= tol ||v|| (Sec. 4 criterion)   */
+  int32_t maxiter;       /* seed iterations at most                                    */
+  int32_t prec;          /* SSCG_FP64 | SSCG_MIXED                                     */
+  int32_t ru_interval;   /* MIXED: reliable update every this many FP32 iterations    */
+  int32_t poll_every;    /* host checks the device "all converged" word this often    */
+  double switch_tol;     /* MIXED: FP64 -> FP32 switch when max active ||r_j||/||v||
+                            is below this                                              */
+  int32_t use_graph;     /* 1: replay the iterations between polls as a HIP graph     */
+} sscg_solve_opts;
+
+/* Default options: tol 1e-12, maxiter 100000, FP64, ru 50, poll 50, switch 1e-6, graph 1. */
+void sscg_default_opts(sscg_solve_opts *o);
+
+/* Shifted CG (Sec. 2.2, eqs. 4-5): solves (z_j I - A) y_{l,j} = v_l for every
+ * shift j < nshift and source l < nsrc from the single Hermitian seed system
+ * (sigma_seed I - A) x = v_l with a real seed shift (one product with A per
+ * iteration and source serves all shifts). Converged shifts are frozen.
+ *   v          device complex128 [nsrc][n] canonical
+ *   z          host complex128 [nshift] (interleaved re, im)
+ *   y          device complex128 [nsrc][nshift][n] canonical (output; also used as
+ *              the solver's accumulator storage during the call)
+ *   conv_iter  host int32 [nsrc][nshift] (output, may be NULL): iteration after
+ *              which the shift met the tolerance, -1 if it never did
+ *   true_res   host double [nsrc][nshift] (output, may be NULL):
+ *              ||v_l - (z_j I - A) y_{l,j}|| / ||v_l|| recomputed in FP64
+ *   iters      host int32 [nsrc] (output, may be NULL): seed iterations per source
+ * Returns SSCG_ENOTCONV if some shift did not converge within maxiter (outputs are
+ * still written), SSCG_EBREAKDOWN on a CG breakdown, SSCG_EINVAL for a zero or
+ * non-finite source. Blocking. */
+int sscg_shifted_cg_solve(sscg_ctx *ctx, const void *v, int32_t nsrc,
+                          const double *z, int32_t nshift, double sigma_seed,
+                          const sscg_solve_opts *opts, void *y, int32_t *conv_iter,
+                          double *true_res, int32_t *iters);
+
+/* Moment sums eq. (2): s_{l,k} = sum_j c[k][j] y_{l,j} for k < nmom, with
+ * c[k][j] = w_j zeta_j^k supplied by the caller (host complex128 [nmom][nshift]).
+ * y device complex128 [nsrc][nshift][n]; s device complex128 [nsrc][nmom][n].
+ * Any layout of the n entries works as long as y and s agree. Stream-ordered. */
+int sscg_ss_moments(sscg_ctx *ctx, const void *y, int32_t nsrc, int32_t nshift,
+                    const double *c, int32_t nmom, void *s);
+
+typedef struct {
+  double gamma, rho, beta;  /* interval centre and half-width, line offset (Sec. 3) */
+  int32_t N;                /* quadrature points                                    */
+  int32_t M;                /* moments per source                                   */
+  int32_t Nprime;           /* acceptance rectangle: the Nprime nodes nearest gamma
+                               (Sec. 3); 0 = N                                       */
+  int32_t path;             /* SSCG_PATH_LINES | SSCG_PATH_CIRCLE                   */
+  int32_t method;           /* SSCG_RR (Rayleigh-Ritz) | SSCG_HANKEL (Sec. 2.1)      */
+  double rank_tol;          /* numerical rank: keep singular values > rank_tol*max  */
+  double spur_tol;          /* report pairs with ||A x - lambda x|| <= spur_tol      */
+  sscg_solve_opts solve;
+} sscg_ss_params;
+
+typedef struct {
+  int32_t rank;             /* dimension of the extraction subspace                 */
+  int32_t n_candidates;     /* Ritz / Hankel values before acceptance               */
+  int32_t iters;            /* max seed iterations over sources                     */
+  int32_t solve_status;     /* status of the shifted-CG stage                       */
+  double t_solve, t_moments, t_extract;  /* seconds                                 */
+} sscg_ss_info;
+
+void sscg_default_ss_params(sscg_ss_params *p);
+
+/* Eigenpairs of A in [gamma - rho, gamma + rho] (Sec. 2-3): line (or circle)
+ * quadrature, shifted CG for all nodes, moments eq. (2), Rayleigh-Ritz or block
+ * Hankel extraction (Sec. 2.1, block form with nsrc sources), then the acceptance
+ * rectangle of Sec. 3 and the residual filter res <= spur_tol.
+ *   v       device complex128 [nsrc][n] canonical sources
+ *   lambda  host double [max_eigs] (output, ascending)
+ *   X       device complex128 [max_eigs][n] canonical unit eigenvectors, or NULL
+ *   res     host double [max_eigs]: ||A x - lambda x||_2 (output)
+ *   n_found host int32 (output): pairs accepted; if more than max_eigs qualify,
+ *           the max_eigs nearest gamma are returned and n_found is the full count
+ *   info    host (output, may be NULL)
+ * Blocking. */
+int sscg_ss_eigs(sscg_ctx *ctx, const sscg_ss_params *p, const void *v, int32_t nsrc,
+                 int32_t max_eigs, double *lambda, void *X, double *res,
+                 int32_t *n_found, sscg_ss_info *info);
+
+/* Quadrature on the two horizontal lines z = gamma + rho (x +- i beta), -1 <= x <= 1
+ * (Sec. 3): N/2 equally spaced points per line with both ends included, even j on
+ * the upper line; weights solve sum_j w_j zeta_j^(k-1) = delta_k0, k < N.
+ * Outputs host complex128 [N] each (z, zeta = (z - gamma)/rho, w). N even, >= 4. */
+int sscg_quad_lines(int32_t N, double gamma, double rho, double beta,
+                    double *z, double *zeta, double *w);
+/* Circle of centre gamma, radius rho (Sec. 2.1): z_j = gamma + rho e^{2 pi i (j+1/2)/N},
+ * dimensionless weights w_j = zeta_j / N. */
+int sscg_quad_circle(int32_t N, double gamma, double rho, double *z, double *zeta, double *w);
+
+/* Several independent problems (own lattice, gauge, sources, shifts, seed) solved
+ * together: every stage of every iteration is one grouped kernel launch covering
+ * all problems, and the iterations between polls replay as one HIP graph.
+ * Arrays of length nprob; entry i has the meaning of the same argument of
+ * sscg_shifted_cg_solve for context ctxs[i] (all contexts on one device and
+ * stream; opts shared, prec applies to all). Each problem's result equals its
+ * own sscg_shifted_cg_solve run with the same options. Blocking. */
+int sscg_batch_solve(sscg_ctx *const *ctxs, int32_t nprob, const void *const *v,
+                     const int32_t *nsrc, const double *const *z, const int32_t *nshift,
+                     const double *sigma_seed, const sscg_solve_opts *opts,
+                     void *const *y, int32_t *const *conv_iter, double *const *true_res,
+                     int32_t *const *iters);
+
+/* Eigen-decomposition of a small Hermitian matrix (host, FP64, cyclic Jacobi), the
+ * dense step of the Rayleigh-Ritz and Hankel extraction (Sec. 2.1).
+ *   A      host complex128 n x n, column-major (element (i, j) at 2 (i + n j)); read only
+ *   evals  host double [n] (output, ascending)
+ *   evecs  host complex128 n x n column-major (output, column k = unit eigenvector k),
+ *          or NULL
+ * Only the Hermitian part of A is used. Needs no device. */
+int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs);
+
+/* Per-stage timing of the last solve on this context, from HIP events on the
+ * context's stream, in milliseconds summed over the solve; counts in calls.
+ * stage: 0 dslash, 1 seed alpha scalars, 2 seed residual update, 3 shift scalars,
+ * 4 fused shift update, 5 reliable update, 6 whole iteration loop.
+ * Timing is recorded only when enabled with sscg_set_profiling(ctx, 1). */
+int sscg_set_profiling(sscg_ctx *ctx, int32_t on);
+int sscg_stage_times(const sscg_ctx *ctx, double ms[8], int64_t calls[8]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSCG_H */

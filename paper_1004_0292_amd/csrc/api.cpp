@@ -1,0 +1,1167 @@
+// Host runtime and C-ABI of the sscg library (declared in include/sscg.h).
+//
+// A context owns one lattice: its packed gauge field (FP64 18-real and, for the
+// mixed mode, FP32 18- or 12-real), and the solver workspaces, grown on demand
+// and reused. The shifted CG (Sec. 2.2) runs as a loop of grouped launches
+// (dslash, seed scalars, seed residual, shift scalars, fused shift update) whose
+// scalar state lives in device memory; the host only polls the per-source "done"
+// words every poll_every iterations, and the iterations in between replay as one
+// HIP graph. Several contexts can be solved together (sscg_batch_solve): each
+// stage is then one launch whose blocks are split over the problems.
+#include "sscg.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sscg_internal.h"
+
+using namespace sscg;
+using cd = std::complex<double>;
+
+static std::string g_global_err;
+static constexpr int kEptHost = 2;  // entries per thread of the streaming kernels (vec.hip)
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+enum Stage { ST_DSLASH = 0, ST_ALPHA, ST_RUPD, ST_SCAL, ST_SHIFT, ST_RU, ST_LOOP, ST_N = 8 };
+
+struct sscg_ctx {
+  int device = 0;
+  hipStream_t user = nullptr;   // stream given by the caller
+  hipStream_t work = nullptr;   // private stream (graph capture needs a non-null stream)
+  hipEvent_t ev_sync = nullptr;
+  int dims[4] = {0, 0, 0, 0};
+  int V = 0;
+  int64_t n = 0;
+  double kappa = 0.0;
+  DevBuf g64, g32;
+  int link_reals = 18;
+  bool have_gauge = false;
+  std::string err;
+  // tunables (autotuned or set by the caller through the environment)
+  int nr = 2, wbatch = 8, xcd = 1;
+  // solver workspaces
+  DevBuf v64, r64, p64, q64, W, r32, p32, q32, rbase, xpart64, xpart32, tmp, pq_part, rr_part, seed,
+      shift, zdev, small, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, apply_in, apply_out;
+  SeedState *seed_host = nullptr;
+  int seed_host_cap = 0;
+  // profiling
+  bool profiling = false;
+  double stage_ms[ST_N] = {};
+  int64_t stage_calls[ST_N] = {};
+  std::vector<hipEvent_t> events;
+};
+
+static int fail(sscg_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  else g_global_err = msg;
+  return code;
+}
+#define HIPCHK(ctx, call)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) return fail(ctx, SSCG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define CHK(call)             \
+  do {                        \
+    int s_ = (call);          \
+    if (s_ != SSCG_OK) return s_; \
+  } while (0)
+
+static int ensure(sscg_ctx *c, DevBuf &b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return SSCG_OK;
+  if (b.p) {
+    hipStreamSynchronize(c->work);
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, SSCG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return SSCG_OK;
+}
+static void release(DevBuf &b) {
+  if (b.p) hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+static int env_int(const char *name, int dflt) {
+  const char *s = getenv(name);
+  return s ? atoi(s) : dflt;
+}
+
+extern "C" {
+
+const char *sscg_global_error(void) { return g_global_err.c_str(); }
+const char *sscg_last_error(const sscg_ctx *c) { return c ? c->err.c_str() : g_global_err.c_str(); }
+
+int sscg_create(sscg_ctx **out, const int32_t dims[4], double kappa, double r, int32_t device,
+                void *hip_stream) {
+  if (!out || !dims) return fail(nullptr, SSCG_EINVAL, "null argument");
+  *out = nullptr;
+  for (int i = 0; i < 4; ++i)
+    if (dims[i] <= 0) return fail(nullptr, SSCG_EINVAL, "lattice extents must be positive");
+  if (r != 1.0) return fail(nullptr, SSCG_EINVAL, "only the Wilson parameter r = 1 is implemented");
+  const int64_t V = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+  if (V > (int64_t)1 << 30) return fail(nullptr, SSCG_EINVAL, "lattice too large");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    return fail(nullptr, SSCG_EDEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= ndev) return fail(nullptr, SSCG_EINVAL, "bad device index");
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, SSCG_EDEVICE, "hipSetDevice failed");
+  auto *c = new sscg_ctx();
+  c->device = device;
+  c->user = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return fail(nullptr, SSCG_EDEVICE, "stream creation failed");
+  }
+  for (int i = 0; i < 4; ++i) c->dims[i] = dims[i];
+  c->V = (int)V;
+  c->n = 12 * V;
+  c->kappa = kappa;
+  c->nr = env_int("SSCG_NR", 2);
+  c->wbatch = env_int("SSCG_WBATCH", 8);
+  c->xcd = env_int("SSCG_XCD", 1);
+  if (c->nr != 1 && c->nr != 2 && c->nr != 4) c->nr = 2;
+  if (c->wbatch < 1) c->wbatch = 8;
+  *out = c;
+  return SSCG_OK;
+}
+
+void sscg_destroy(sscg_ctx *c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->work);
+  DevBuf *bufs[] = {&c->g64, &c->g32, &c->v64, &c->r64, &c->p64, &c->q64, &c->W, &c->r32, &c->p32,
+                    &c->q32, &c->rbase, &c->xpart64, &c->xpart32, &c->tmp, &c->pq_part, &c->rr_part,
+                    &c->seed, &c->shift, &c->zdev, &c->small, &c->Ybuf, &c->Sbuf, &c->Qbuf, &c->AQbuf,
+                    &c->Xbuf, &c->AXbuf, &c->apply_in, &c->apply_out};
+  for (DevBuf *b : bufs) release(*b);
+  if (c->seed_host) hipHostFree(c->seed_host);
+  for (hipEvent_t e : c->events) hipEventDestroy(e);
+  hipEventDestroy(c->ev_sync);
+  hipStreamDestroy(c->work);
+  delete c;
+}
+
+void sscg_default_opts(sscg_solve_opts *o) {
+  if (!o) return;
+  o->tol = 1e-12;
+  o->maxiter = 100000;
+  o->prec = SSCG_FP64;
+  o->ru_interval = 50;
+  o->poll_every = 50;
+  o->switch_tol = 1e-6;
+  o->use_graph = 1;
+}
+
+int sscg_set_gauge(sscg_ctx *c, const double *U, int32_t link_reals) {
+  if (!c || !U) return fail(c, SSCG_EINVAL, "null argument");
+  if (link_reals != 18 && link_reals != 12) return fail(c, SSCG_EINVAL, "link_reals must be 18 or 12");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int V = c->V;
+  // host conversion canonical [4][V][3][3] -> planar [4][9][V] (FP64) and [4][LR/2][V] (FP32)
+  std::vector<double> h64((size_t)4 * 9 * V * 2);
+  std::vector<float> h32((size_t)4 * (link_reals / 2) * V * 2);
+  for (int mu = 0; mu < 4; ++mu)
+    for (int s = 0; s < V; ++s)
+      for (int e = 0; e < 9; ++e) {
+        const double re = U[2 * (((size_t)mu * V + s) * 9 + e)];
+        const double im = U[2 * (((size_t)mu * V + s) * 9 + e) + 1];
+        const size_t o = ((size_t)mu * 9 + e) * V + s;
+        h64[2 * o] = re;
+        h64[2 * o + 1] = im;
+        if (e < link_reals / 2) {
+          const size_t o32 = ((size_t)mu * (link_reals / 2) + e) * V + s;
+          h32[2 * o32] = (float)re;
+          h32[2 * o32 + 1] = (float)im;
+        }
+      }
+  CHK(ensure(c, c->g64, h64.size() * sizeof(double)));
+  CHK(ensure(c, c->g32, h32.size() * sizeof(float)));
+  HIPCHK(c, hipStreamSynchronize(c->work));
+  HIPCHK(c, hipMemcpy(c->g64.p, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->g32.p, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice));
+  c->link_reals = link_reals;
+  c->have_gauge = true;
+  return SSCG_OK;
+}
+
+int sscg_set_profiling(sscg_ctx *c, int32_t on) {
+  if (!c) return SSCG_EINVAL;
+  c->profiling = on != 0;
+  return SSCG_OK;
+}
+int sscg_stage_times(const sscg_ctx *c, double ms[8], int64_t calls[8]) {
+  if (!c || !ms || !calls) return SSCG_EINVAL;
+  for (int i = 0; i < ST_N; ++i) {
+    ms[i] = c->stage_ms[i];
+    calls[i] = c->stage_calls[i];
+  }
+  return SSCG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// internal helpers
+
+static int nblk_site(const sscg_ctx *c) { return (c->V + kBlock - 1) / kBlock; }
+static int nblk_vec(const sscg_ctx *c) { return (int)((c->n + kBlock * kEptHost - 1) / (kBlock * kEptHost)); }
+
+// FP64 dslash of nsrc planar vectors: out = A in (mode 0) or sigma in - A in (mode 1)
+static void dslash_plain(sscg_ctx *c, const void *in, void *out, int nsrc, int prec, int mode, double sigma,
+                         double *partial, const SeedState *seed, hipStream_t st) {
+  DslashBatch b{};
+  DslashJob &j = b.job[0];
+  j.in = in;
+  j.out = out;
+  j.gauge = prec == 0 ? c->g64.p : c->g32.p;
+  j.partial = partial;
+  j.seed = seed;
+  j.kappa = c->kappa;
+  j.sigma = sigma;
+  for (int i = 0; i < 4; ++i) j.dims[i] = c->dims[i];
+  j.V = c->V;
+  j.nsrc = nsrc;
+  j.nblk_site = nblk_site(c);
+  j.block_begin = 0;
+  j.nblocks = j.nblk_site * ((nsrc + c->nr - 1) / c->nr);
+  j.mode = mode;
+  b.njobs = 1;
+  b.total_blocks = j.nblocks;
+  launch_dslash(b, prec, c->nr, prec == 0 ? 18 : c->link_reals, c->xcd, st);
+}
+
+static int host_sum_partials(sscg_ctx *c, const double *dev_partial, int nvec, int nblk, std::vector<double> &out,
+                             hipStream_t st) {
+  std::vector<double> h((size_t)nvec * nblk);
+  HIPCHK(c, hipMemcpyAsync(h.data(), dev_partial, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  out.assign(nvec, 0.0);
+  for (int v = 0; v < nvec; ++v)
+    for (int b = 0; b < nblk; ++b) out[v] += h[(size_t)v * nblk + b];
+  return SSCG_OK;
+}
+
+// Order the private stream after the caller's stream.
+static int join_user(sscg_ctx *c) {
+  HIPCHK(c, hipEventRecord(c->ev_sync, c->user));
+  HIPCHK(c, hipStreamWaitEvent(c->work, c->ev_sync, 0));
+  return SSCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// shifted CG over one or several problems
+
+struct Prob {
+  sscg_ctx *c = nullptr;
+  const void *v = nullptr;  // canonical device
+  int L = 0, N = 0;
+  double sigma = 0.0;
+  std::vector<double> z;    // 2N
+  void *y = nullptr;        // device [L][N][n]: planar FP64 during the solve
+  bool keep_planar = false; // leave y planar (internal callers)
+  int32_t *conv_iter = nullptr;
+  double *true_res = nullptr;
+  int32_t *iters = nullptr;
+  int status = SSCG_OK;
+};
+
+struct IterPlan {
+  DslashBatch d64, d32, dru;
+  ScalarBatch alpha, scal;
+  VecBatch r64, r32, u64, u32, fold_seed, rel;
+};
+
+static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts &o) {
+  memset(&pl, 0, sizeof(pl));
+  int bd = 0, bdru = 0, bs = 0, bv = 0, bu = 0;
+  const int np = (int)P.size();
+  for (int i = 0; i < np; ++i) {
+    sscg_ctx *c = P[i].c;
+    const int L = P[i].L, N = P[i].N;
+    const int nbs = nblk_site(c), nbv = nblk_vec(c);
+    const int groups = (L + c->nr - 1) / c->nr;
+    SeedState *seed = (SeedState *)c->seed.p;
+    ShiftState *shift = (ShiftState *)c->shift.p;
+    auto mk_d = [&](DslashJob &j, const void *in, void *out, const void *g, double *part, int begin) {
+      j.in = in; j.out = out; j.gauge = g; j.partial = part; j.seed = seed;
+      j.kappa = c->kappa; j.sigma = P[i].sigma;
+      for (int k = 0; k < 4; ++k) j.dims[k] = c->dims[k];
+      j.V = c->V; j.nsrc = L; j.nblk_site = nbs; j.block_begin = begin; j.nblocks = nbs * groups; j.mode = 1;
+    };
+    mk_d(pl.d64.job[i], c->p64.p, c->q64.p, c->g64.p, (double *)c->pq_part.p, bd);
+    mk_d(pl.d32.job[i], c->p32.p, c->q32.p, c->g32.p, (double *)c->pq_part.p, bd);
+    mk_d(pl.dru.job[i], c->xpart64.p, c->q64.p, c->g64.p, nullptr, bdru);
+    bd += nbs * groups;
+    bdru += nbs * groups;
+    auto mk_s = [&](ScalarJob &j, const double *part, int nblk) {
+      j.seed = seed; j.shift = shift; j.partial = part; j.nblk = nblk; j.nsrc = L; j.nshift = N;
+      j.maxiter = o.maxiter; j.block_begin = bs; j.tol = o.tol;
+    };
+    mk_s(pl.alpha.job[i], (double *)c->pq_part.p, nbs);
+    mk_s(pl.scal.job[i], (double *)c->rr_part.p, nbv);
+    bs += L;
+    auto mk_v = [&](VecJob &j, void *a, void *b, void *cc, void *d, int begin, int nblocks) {
+      j.a = a; j.b = b; j.c = cc; j.d = d; j.e = nullptr; j.partial = (double *)c->rr_part.p;
+      j.seed = seed; j.shift = shift; j.n = c->n; j.nsrc = L; j.nshift = N; j.nblk_vec = nbv;
+      j.block_begin = begin; j.nblocks = nblocks; j.wbatch = c->wbatch;
+    };
+    mk_v(pl.r64.job[i], c->r64.p, c->q64.p, nullptr, nullptr, bv, L * nbv);
+    mk_v(pl.r32.job[i], c->r32.p, c->q32.p, c->xpart32.p, c->p32.p, bv, L * nbv);
+    mk_v(pl.fold_seed.job[i], c->xpart64.p, c->xpart32.p, nullptr, nullptr, bv, L * nbv);
+    mk_v(pl.rel.job[i], c->rbase.p, c->q64.p, c->r64.p, c->r32.p, bv, L * nbv);
+    bv += L * nbv;
+    const int nbatch = (N + c->wbatch - 1) / c->wbatch;
+    mk_v(pl.u64.job[i], P[i].y, c->W.p, c->r64.p, c->p64.p, bu, L * nbatch * nbv);
+    mk_v(pl.u32.job[i], P[i].y, c->W.p, c->r32.p, c->p32.p, bu, L * nbatch * nbv);
+    bu += L * nbatch * nbv;
+  }
+  pl.d64.njobs = pl.d32.njobs = pl.dru.njobs = np;
+  pl.d64.total_blocks = pl.d32.total_blocks = bd;
+  pl.dru.total_blocks = bdru;
+  pl.alpha.njobs = pl.scal.njobs = np;
+  pl.alpha.total_blocks = pl.scal.total_blocks = bs;
+  for (VecBatch *vb : {&pl.r64, &pl.r32, &pl.fold_seed, &pl.rel}) {
+    vb->njobs = np;
+    vb->total_blocks = bv;
+  }
+  pl.u64.njobs = pl.u32.njobs = np;
+  pl.u64.total_blocks = pl.u32.total_blocks = bu;
+}
+
+struct Recorder {
+  sscg_ctx *c;
+  hipStream_t st;
+  bool on;
+  std::vector<int> stages;
+  void mark(int stage) {
+    if (!on) return;
+    const size_t k = stages.size();
+    if (k >= c->events.size()) {
+      hipEvent_t e;
+      hipEventCreate(&e);
+      c->events.push_back(e);
+    }
+    hipEventRecord(c->events[k], st);
+    stages.push_back(stage);
+  }
+  void flush() {
+    if (!on || stages.empty()) return;
+    mark(-1);
+    hipEventSynchronize(c->events[stages.size() - 1]);
+    for (size_t k = 0; k + 1 < stages.size(); ++k) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, c->events[k], c->events[k + 1]);
+      c->stage_ms[stages[k]] += ms;
+      c->stage_calls[stages[k]] += 1;
+    }
+    stages.clear();
+  }
+};
+
+static void launch_iteration(const IterPlan &pl, int prec, bool ru, int lr, int nr, int xcd, hipStream_t st,
+                             Recorder &rec) {
+  rec.mark(ST_DSLASH);
+  launch_dslash(prec == 0 ? pl.d64 : pl.d32, prec, nr, prec == 0 ? 18 : lr, xcd, st);
+  rec.mark(ST_ALPHA);
+  launch_seed_alpha(pl.alpha, st);
+  rec.mark(ST_RUPD);
+  launch_seed_r_update(prec == 0 ? pl.r64 : pl.r32, prec, st);
+  if (prec == 1 && ru) {
+    rec.mark(ST_RU);
+    launch_fold_seed(pl.fold_seed, st);
+    launch_dslash(pl.dru, 0, nr, 18, xcd, st);
+    launch_reliable_residual(pl.rel, st);
+  }
+  rec.mark(ST_SCAL);
+  launch_shift_scalars(pl.scal, st);
+  rec.mark(ST_SHIFT);
+  launch_shift_update(prec == 0 ? pl.u64 : pl.u32, prec, prec == 1 && ru, st);
+}
+
+static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
+  sscg_ctx *c = p.c;
+  const size_t n = c->n, L = p.L, N = p.N;
+  const size_t vec64 = n * sizeof(double2), vec32 = n * sizeof(float2);
+  CHK(ensure(c, c->v64, L * vec64));
+  CHK(ensure(c, c->r64, L * vec64));
+  CHK(ensure(c, c->p64, L * vec64));
+  CHK(ensure(c, c->q64, L * vec64));
+  CHK(ensure(c, c->W, L * N * vec64));
+  CHK(ensure(c, c->tmp, vec64));
+  CHK(ensure(c, c->pq_part, L * nblk_site(c) * sizeof(double)));
+  CHK(ensure(c, c->rr_part, std::max<size_t>(L * nblk_vec(c), L * 64) * sizeof(double)));
+  CHK(ensure(c, c->seed, L * sizeof(SeedState)));
+  CHK(ensure(c, c->shift, L * N * sizeof(ShiftState)));
+  CHK(ensure(c, c->zdev, N * 2 * sizeof(double)));
+  if (o.prec == SSCG_MIXED) {
+    CHK(ensure(c, c->r32, L * vec32));
+    CHK(ensure(c, c->p32, L * vec32));
+    CHK(ensure(c, c->q32, L * vec32));
+    CHK(ensure(c, c->rbase, L * vec64));
+    CHK(ensure(c, c->xpart64, L * vec64));
+    CHK(ensure(c, c->xpart32, L * vec32));
+  }
+  if (c->seed_host_cap < (int)L) {
+    if (c->seed_host) hipHostFree(c->seed_host);
+    c->seed_host = nullptr;
+    if (hipHostMalloc((void **)&c->seed_host, L * sizeof(SeedState), hipHostMallocDefault) != hipSuccess)
+      return fail(c, SSCG_ENOMEM, "pinned host allocation failed");
+    c->seed_host_cap = (int)L;
+  }
+  hipStream_t st = c->work;
+  // v -> planar FP64; r = p = v; p_j = v; x_j = 0
+  launch_pack(p.v, c->v64.p, 0, (int)L, c->V, st);
+  HIPCHK(c, hipMemcpyAsync(c->r64.p, c->v64.p, L * vec64, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->p64.p, c->v64.p, L * vec64, hipMemcpyDeviceToDevice, st));
+  for (size_t l = 0; l < L; ++l)
+    for (size_t j = 0; j < N; ++j)
+      HIPCHK(c, hipMemcpyAsync((char *)c->W.p + (l * N + j) * vec64, (char *)c->v64.p + l * vec64, vec64,
+                               hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemsetAsync(p.y, 0, L * N * vec64, st));
+  // ||v||
+  const int nb = 64;
+  launch_norm2_partial(c->v64.p, c->n, (int)L, (double *)c->rr_part.p, nb, st);
+  std::vector<double> vn2;
+  CHK(host_sum_partials(c, (double *)c->rr_part.p, (int)L, nb, vn2, st));
+  std::vector<SeedState> seeds(L);
+  for (size_t l = 0; l < L; ++l) {
+    if (!(vn2[l] > 0.0) || !std::isfinite(vn2[l]))
+      return fail(c, SSCG_EINVAL, "source " + std::to_string(l) + " is zero or not finite");
+    SeedState &s = seeds[l];
+    memset(&s, 0, sizeof(s));
+    s.rho = vn2[l];
+    s.alpha_prev = 1.0;
+    s.beta_prev = 0.0;
+    s.vnorm = std::sqrt(vn2[l]);
+    s.maxres = 1.0;
+    s.nactive = (int)N;
+  }
+  std::vector<ShiftState> sh(L * N);
+  for (size_t l = 0; l < L; ++l)
+    for (size_t j = 0; j < N; ++j) {
+      ShiftState &h = sh[l * N + j];
+      memset(&h, 0, sizeof(h));
+      h.s = make_double2(p.z[2 * j] - p.sigma, p.z[2 * j + 1]);
+      h.pi_prev = h.pi_cur = make_double2(1.0, 0.0);
+      h.active = 1;
+      h.conv_iter = -1;
+    }
+  HIPCHK(c, hipMemcpyAsync(c->seed.p, seeds.data(), L * sizeof(SeedState), hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->shift.p, sh.data(), L * N * sizeof(ShiftState), hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->zdev.p, p.z.data(), N * 2 * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  return SSCG_OK;
+}
+
+// FP64 -> FP32 switch of one problem: seed vectors, reliable-update base, and the
+// shift directions p_j (rewritten in place through one temporary vector).
+static int switch_to_fp32(Prob &p, hipStream_t st) {
+  sscg_ctx *c = p.c;
+  const size_t n = c->n, L = p.L, N = p.N, vec64 = n * sizeof(double2);
+  launch_cast(c->r64.p, 0, c->r32.p, 1, (int64_t)(L * n), st);
+  launch_cast(c->p64.p, 0, c->p32.p, 1, (int64_t)(L * n), st);
+  HIPCHK(c, hipMemcpyAsync(c->rbase.p, c->r64.p, L * vec64, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemsetAsync(c->xpart64.p, 0, L * vec64, st));
+  HIPCHK(c, hipMemsetAsync(c->xpart32.p, 0, L * n * sizeof(float2), st));
+  for (size_t k = 0; k < L * N; ++k) {
+    char *slot = (char *)c->W.p + k * vec64;
+    HIPCHK(c, hipMemcpyAsync(c->tmp.p, slot, vec64, hipMemcpyDeviceToDevice, st));
+    launch_to_fp32(c->tmp.p, slot, slot + n * sizeof(float2), (int64_t)n, st);
+  }
+  return SSCG_OK;
+}
+
+static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
+  sscg_solve_opts o = o_in;
+  if (o.poll_every < 1) o.poll_every = 1;
+  if (o.ru_interval < 1) o.ru_interval = 50;
+  sscg_ctx *c0 = P[0].c;
+  hipStream_t st = c0->work;
+  for (Prob &p : P) {
+    if (!p.c->have_gauge) return fail(p.c, SSCG_ESTATE, "no gauge field set");
+    if (p.c->device != c0->device) return fail(c0, SSCG_EINVAL, "all problems must share one device");
+    HIPCHK(p.c, hipSetDevice(p.c->device));
+    CHK(join_user(p.c));
+    CHK(prepare_problem(p, o));
+  }
+  if (P.size() > (size_t)kMaxJobs) return fail(c0, SSCG_EINVAL, "too many problems in one batch");
+  // all problems' work goes to the first context's private stream
+  for (Prob &p : P) {
+    if (p.c != c0) {
+      HIPCHK(p.c, hipEventRecord(p.c->ev_sync, p.c->work));
+      HIPCHK(c0, hipStreamWaitEvent(st, p.c->ev_sync, 0));
+    }
+  }
+  IterPlan pl;
+  build_plan(P, pl, o);
+  const int nr = c0->nr, xcd = c0->xcd;
+  int lr = 18;
+  for (Prob &p : P) lr = std::min(lr, p.c->link_reals);
+  for (Prob &p : P)
+    if (p.c->link_reals != lr) return fail(c0, SSCG_EINVAL, "all problems of a batch must use one link format");
+  for (int i = 0; i < ST_N; ++i) {
+    c0->stage_ms[i] = 0.0;
+    c0->stage_calls[i] = 0;
+  }
+  Recorder rec{c0, st, c0->profiling, {}};
+  const bool use_graph = o.use_graph && !c0->profiling;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int glen[2] = {0, 0};
+  auto capture = [&](int prec, int len, hipGraphExec_t &exec) -> int {
+    hipGraph_t g = nullptr;
+    Recorder off{c0, st, false, {}};
+    HIPCHK(c0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < len; ++k)
+      launch_iteration(pl, prec, prec == 1 && k == len - 1, lr, nr, xcd, st, off);
+    HIPCHK(c0, hipStreamEndCapture(st, &g));
+    HIPCHK(c0, hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+    HIPCHK(c0, hipGraphDestroy(g));
+    return SSCG_OK;
+  };
+  auto t0 = std::chrono::steady_clock::now();
+  int prec = 0;
+  int k = 0;
+  int rc = SSCG_OK;
+  while (k < o.maxiter) {
+    const int chunk = std::min(prec == 0 ? o.poll_every : o.ru_interval, o.maxiter - k);
+    const bool full = chunk == (prec == 0 ? o.poll_every : o.ru_interval);
+    if (use_graph && full) {
+      if (!gexec[prec] || glen[prec] != chunk) {
+        if (gexec[prec]) hipGraphExecDestroy(gexec[prec]);
+        gexec[prec] = nullptr;
+        rc = capture(prec, chunk, gexec[prec]);
+        if (rc != SSCG_OK) break;
+        glen[prec] = chunk;
+      }
+      hipError_t e = hipGraphLaunch(gexec[prec], st);
+      if (e != hipSuccess) {
+        rc = fail(c0, SSCG_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        break;
+      }
+    } else {
+      for (int kk = 0; kk < chunk; ++kk)
+        launch_iteration(pl, prec, prec == 1 && (kk == chunk - 1) && full, lr, nr, xcd, st, rec);
+    }
+    k += chunk;
+    // poll
+    bool all_done = true, can_switch = true;
+    for (Prob &p : P) {
+      hipError_t e = hipMemcpyAsync(p.c->seed_host, p.c->seed.p, p.L * sizeof(SeedState),
+                                    hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) {
+        rc = fail(c0, SSCG_EDEVICE, "poll copy failed");
+        break;
+      }
+    }
+    if (rc != SSCG_OK) break;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      rc = fail(c0, SSCG_EDEVICE, std::string("solve loop: ") + hipGetErrorString(e));
+      break;
+    }
+    rec.flush();
+    for (Prob &p : P)
+      for (int l = 0; l < p.L; ++l) {
+        const SeedState &s = p.c->seed_host[l];
+        if (!s.done) {
+          all_done = false;
+          if (!(s.maxres < o.switch_tol)) can_switch = false;
+        }
+      }
+    if (all_done) break;
+    if (o.prec == SSCG_MIXED && prec == 0 && can_switch) {
+      for (Prob &p : P) {
+        rc = switch_to_fp32(p, st);
+        if (rc != SSCG_OK) break;
+      }
+      if (rc != SSCG_OK) break;
+      prec = 1;
+    }
+  }
+  for (auto &g : gexec)
+    if (g) hipGraphExecDestroy(g);
+  if (rc != SSCG_OK) return rc;
+  if (prec == 1) {
+    // fold every shift's FP32 partial into its FP64 solution
+    for (Prob &p : P) launch_fold_shifts(p.y, p.c->W.p, p.c->n, p.L * p.N, st);
+  }
+  HIPCHK(c0, hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  c0->stage_ms[ST_LOOP] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  c0->stage_calls[ST_LOOP] = k;
+  // results
+  int worst = SSCG_OK;
+  for (Prob &p : P) {
+    sscg_ctx *c = p.c;
+    const int L = p.L, N = p.N;
+    std::vector<SeedState> seeds(L);
+    std::vector<ShiftState> sh((size_t)L * N);
+    HIPCHK(c, hipMemcpy(seeds.data(), c->seed.p, L * sizeof(SeedState), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(sh.data(), c->shift.p, (size_t)L * N * sizeof(ShiftState), hipMemcpyDeviceToHost));
+    int st_p = SSCG_OK;
+    for (int l = 0; l < L; ++l) {
+      if (p.iters) p.iters[l] = seeds[l].iters;
+      int s = seeds[l].done ? seeds[l].status : SSCG_ENOTCONV;
+      if (s == SSCG_EBREAKDOWN) st_p = SSCG_EBREAKDOWN;
+      else if (s == SSCG_ENOTCONV && st_p == SSCG_OK) st_p = SSCG_ENOTCONV;
+      for (int j = 0; j < N; ++j)
+        if (p.conv_iter) p.conv_iter[(size_t)l * N + j] = sh[(size_t)l * N + j].conv_iter;
+    }
+    p.status = st_p;
+    if (st_p == SSCG_EBREAKDOWN) worst = SSCG_EBREAKDOWN;
+    else if (st_p == SSCG_ENOTCONV && worst == SSCG_OK) worst = SSCG_ENOTCONV;
+    // FP64 true residuals ||v - (z_j - A) y_j|| / ||v||
+    if (p.true_res) {
+      const size_t n = c->n, vec64 = n * sizeof(double2);
+      const int nb = 64;
+      for (int l = 0; l < L; ++l) {
+        for (int j0 = 0; j0 < N; j0 += L) {
+          const int cnt = std::min(L, N - j0);
+          const char *yj = (const char *)p.y + ((size_t)l * N + j0) * vec64;
+          dslash_plain(c, yj, c->q64.p, cnt, 0, 0, 0.0, nullptr, nullptr, st);
+          launch_true_residual((const char *)c->v64.p + l * vec64, yj, c->q64.p, (const double *)c->zdev.p + 2 * j0,
+                               (int64_t)n, cnt, (double *)c->rr_part.p, nb, st);
+          std::vector<double> r2;
+          CHK(host_sum_partials(c, (double *)c->rr_part.p, cnt, nb, r2, st));
+          for (int t = 0; t < cnt; ++t) p.true_res[(size_t)l * N + j0 + t] = std::sqrt(r2[t]) / seeds[l].vnorm;
+        }
+      }
+    }
+    if (!p.keep_planar) {
+      const size_t n = c->n, vec64 = n * sizeof(double2);
+      for (size_t kk = 0; kk < (size_t)L * N; ++kk) {
+        char *slot = (char *)p.y + kk * vec64;
+        HIPCHK(c, hipMemcpyAsync(c->tmp.p, slot, vec64, hipMemcpyDeviceToDevice, st));
+        launch_unpack(c->tmp.p, 0, slot, 1, c->V, st);
+      }
+    }
+  }
+  HIPCHK(c0, hipStreamSynchronize(st));
+  return worst;
+}
+
+// ---------------------------------------------------------------------------
+// quadrature (host, FP64)
+
+static void quad_lines_host(int N, double gamma, double rho, double beta, std::vector<cd> &z, std::vector<cd> &zeta,
+                            std::vector<cd> &w) {
+  const int h = N / 2;
+  z.resize(N);
+  zeta.resize(N);
+  w.resize(N);
+  for (int i = 0; i < h; ++i) {
+    const double x = -1.0 + 2.0 * i / (h - 1);
+    zeta[2 * i] = cd(x, beta);
+    zeta[2 * i + 1] = cd(x, -beta);
+  }
+  // w_j = zeta_j prod_{i != j} zeta_i / (zeta_i - zeta_j): the unique solution of
+  // sum_j w_j zeta_j^(k-1) = delta_k0, k < N (Lagrange / divided-difference form).
+  for (int j = 0; j < N; ++j) {
+    cd prod = zeta[j];
+    for (int i = 0; i < N; ++i)
+      if (i != j) prod *= zeta[i] / (zeta[i] - zeta[j]);
+    w[j] = prod;
+    z[j] = gamma + rho * zeta[j];
+  }
+}
+static void quad_circle_host(int N, double gamma, double rho, std::vector<cd> &z, std::vector<cd> &zeta,
+                             std::vector<cd> &w) {
+  z.resize(N);
+  zeta.resize(N);
+  w.resize(N);
+  for (int j = 0; j < N; ++j) {
+    const double th = 2.0 * M_PI * (j + 0.5) / N;
+    zeta[j] = cd(std::cos(th), std::sin(th));
+    z[j] = gamma + rho * zeta[j];
+    w[j] = zeta[j] / (double)N;
+  }
+}
+
+extern "C" {
+
+int sscg_quad_lines(int32_t N, double gamma, double rho, double beta, double *z, double *zeta, double *w) {
+  if (N < 4 || N % 2 || !(rho > 0) || !(beta > 0)) return fail(nullptr, SSCG_EINVAL, "need even N >= 4, rho > 0, beta > 0");
+  std::vector<cd> Z, ZE, W;
+  quad_lines_host(N, gamma, rho, beta, Z, ZE, W);
+  for (int j = 0; j < N; ++j) {
+    if (z) { z[2 * j] = Z[j].real(); z[2 * j + 1] = Z[j].imag(); }
+    if (zeta) { zeta[2 * j] = ZE[j].real(); zeta[2 * j + 1] = ZE[j].imag(); }
+    if (w) { w[2 * j] = W[j].real(); w[2 * j + 1] = W[j].imag(); }
+  }
+  return SSCG_OK;
+}
+
+int sscg_quad_circle(int32_t N, double gamma, double rho, double *z, double *zeta, double *w) {
+  if (N < 2 || !(rho > 0)) return fail(nullptr, SSCG_EINVAL, "need N >= 2, rho > 0");
+  std::vector<cd> Z, ZE, W;
+  quad_circle_host(N, gamma, rho, Z, ZE, W);
+  for (int j = 0; j < N; ++j) {
+    if (z) { z[2 * j] = Z[j].real(); z[2 * j + 1] = Z[j].imag(); }
+    if (zeta) { zeta[2 * j] = ZE[j].real(); zeta[2 * j + 1] = ZE[j].imag(); }
+    if (w) { w[2 * j] = W[j].real(); w[2 * j + 1] = W[j].imag(); }
+  }
+  return SSCG_OK;
+}
+
+int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs) {
+  if (n <= 0 || !A || !evals) return fail(nullptr, SSCG_EINVAL, "bad argument");
+  herm_eig(n, A, evals, evecs);
+  return SSCG_OK;
+}
+
+int sscg_apply_A(sscg_ctx *c, const void *x, void *y, int32_t nsrc, int32_t prec) {
+  if (!c || !x || !y || nsrc <= 0) return fail(c, SSCG_EINVAL, "bad argument");
+  if (prec != SSCG_FP64 && prec != SSCG_MIXED) return fail(c, SSCG_EINVAL, "bad precision");
+  if (!c->have_gauge) return fail(c, SSCG_ESTATE, "no gauge field set");
+  HIPCHK(c, hipSetDevice(c->device));
+  const size_t es = prec == SSCG_FP64 ? sizeof(double2) : sizeof(float2);
+  CHK(ensure(c, c->apply_in, (size_t)nsrc * c->n * es));
+  CHK(ensure(c, c->apply_out, (size_t)nsrc * c->n * es));
+  hipStream_t st = c->user;
+  launch_pack(x, c->apply_in.p, prec, nsrc, c->V, st);
+  dslash_plain(c, c->apply_in.p, c->apply_out.p, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
+  launch_unpack(c->apply_out.p, prec, y, nsrc, c->V, st);
+  HIPCHK(c, hipGetLastError());
+  return SSCG_OK;
+}
+
+static int check_solve_args(sscg_ctx *c, const void *v, int nsrc, const double *z, int nshift,
+                            const sscg_solve_opts *o, const void *y) {
+  if (!c) return fail(nullptr, SSCG_EINVAL, "null context");
+  if (!v || !z || !y || !o) return fail(c, SSCG_EINVAL, "null argument");
+  if (nsrc <= 0 || nshift <= 0) return fail(c, SSCG_EINVAL, "nsrc and nshift must be positive");
+  if (nshift > 4096) return fail(c, SSCG_EINVAL, "at most 4096 shifts");
+  if (!(o->tol > 0) || o->maxiter <= 0) return fail(c, SSCG_EINVAL, "tol must be > 0 and maxiter > 0");
+  if (o->prec != SSCG_FP64 && o->prec != SSCG_MIXED) return fail(c, SSCG_EINVAL, "bad precision");
+  for (int j = 0; j < 2 * nshift; ++j)
+    if (!std::isfinite(z[j])) return fail(c, SSCG_EINVAL, "non-finite shift");
+  return SSCG_OK;
+}
+
+int sscg_shifted_cg_solve(sscg_ctx *c, const void *v, int32_t nsrc, const double *z, int32_t nshift,
+                          double sigma_seed, const sscg_solve_opts *opts, void *y, int32_t *conv_iter,
+                          double *true_res, int32_t *iters) {
+  CHK(check_solve_args(c, v, nsrc, z, nshift, opts, y));
+  if (!std::isfinite(sigma_seed)) return fail(c, SSCG_EINVAL, "non-finite seed shift");
+  std::vector<Prob> P(1);
+  P[0].c = c;
+  P[0].v = v;
+  P[0].L = nsrc;
+  P[0].N = nshift;
+  P[0].sigma = sigma_seed;
+  P[0].z.assign(z, z + 2 * nshift);
+  P[0].y = y;
+  P[0].conv_iter = conv_iter;
+  P[0].true_res = true_res;
+  P[0].iters = iters;
+  int rc = run_solve(P, *opts);
+  if (rc == SSCG_ENOTCONV) c->err = "maxiter reached before every shift converged";
+  if (rc == SSCG_EBREAKDOWN) c->err = "CG breakdown: <p, (sigma I - A) p> vanished or a scalar is not finite";
+  return rc;
+}
+
+int sscg_batch_solve(sscg_ctx *const *ctxs, int32_t nprob, const void *const *v, const int32_t *nsrc,
+                     const double *const *z, const int32_t *nshift, const double *sigma_seed,
+                     const sscg_solve_opts *opts, void *const *y, int32_t *const *conv_iter,
+                     double *const *true_res, int32_t *const *iters) {
+  if (!ctxs || nprob <= 0 || nprob > kMaxJobs || !v || !nsrc || !z || !nshift || !sigma_seed || !opts || !y)
+    return fail(ctxs ? ctxs[0] : nullptr, SSCG_EINVAL, "bad batch arguments (1..8 problems)");
+  std::vector<Prob> P(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    CHK(check_solve_args(ctxs[i], v[i], nsrc[i], z[i], nshift[i], opts, y[i]));
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == ctxs[i]) return fail(ctxs[i], SSCG_EINVAL, "a context appears twice in a batch");
+    P[i].c = ctxs[i];
+    P[i].v = v[i];
+    P[i].L = nsrc[i];
+    P[i].N = nshift[i];
+    P[i].sigma = sigma_seed[i];
+    P[i].z.assign(z[i], z[i] + 2 * nshift[i]);
+    P[i].y = y[i];
+    P[i].conv_iter = conv_iter ? conv_iter[i] : nullptr;
+    P[i].true_res = true_res ? true_res[i] : nullptr;
+    P[i].iters = iters ? iters[i] : nullptr;
+  }
+  return run_solve(P, *opts);
+}
+
+int sscg_ss_moments(sscg_ctx *c, const void *y, int32_t nsrc, int32_t nshift, const double *cf, int32_t nmom,
+                    void *s) {
+  if (!c || !y || !cf || !s || nsrc <= 0 || nshift <= 0 || nmom <= 0) return fail(c, SSCG_EINVAL, "bad argument");
+  if (nshift > 512) return fail(c, SSCG_EINVAL, "at most 512 shifts per moment sum");
+  HIPCHK(c, hipSetDevice(c->device));
+  CHK(ensure(c, c->small, (size_t)nmom * nshift * 2 * sizeof(double)));
+  hipStream_t st = c->user;
+  HIPCHK(c, hipMemcpyAsync(c->small.p, cf, (size_t)nmom * nshift * 2 * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_moments(y, nsrc, nshift, (const double *)c->small.p, nmom, s, c->n, st);
+  // the coefficient buffer must outlive the kernel: order later host writes after it
+  HIPCHK(c, hipStreamSynchronize(st));
+  return SSCG_OK;
+}
+
+void sscg_default_ss_params(sscg_ss_params *p) {
+  if (!p) return;
+  p->gamma = 0.0;
+  p->rho = 0.1;
+  p->beta = 0.25;
+  p->N = 32;
+  p->M = 16;
+  p->Nprime = 0;
+  p->path = SSCG_PATH_LINES;
+  p->method = SSCG_RR;
+  p->rank_tol = 1e-7;
+  p->spur_tol = 1e-6;
+  sscg_default_opts(&p->solve);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// extraction (Sec. 2.1): Rayleigh-Ritz or block Hankel, then acceptance (Sec. 3)
+
+// C (na x nb, row-major on host, complex) = A^H B over n rows; A, B device column sets
+static int gram(sscg_ctx *c, const void *A, int na, const void *B, int nb, std::vector<cd> &out, hipStream_t st) {
+  const int nchunk = 64;
+  const size_t nout = (size_t)na * nb;
+  CHK(ensure(c, c->small, nchunk * nout * 2 * sizeof(double) + nout * 2 * sizeof(double)));
+  double *part = (double *)c->small.p;
+  double *red = part + nchunk * nout * 2;
+  launch_gemm_cn(A, c->n, na, B, c->n, nb, c->n, part, nchunk, st);
+  launch_reduce_partials(part, nchunk, (int)(2 * nout), red, st);
+  std::vector<double> h(2 * nout);
+  HIPCHK(c, hipMemcpyAsync(h.data(), red, 2 * nout * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  out.resize(nout);
+  for (size_t k = 0; k < nout; ++k) out[k] = cd(h[2 * k], h[2 * k + 1]);
+  return SSCG_OK;
+}
+
+// C = A T with T (na x nb) row-major host complex
+static int basis_change(sscg_ctx *c, const void *A, int na, const std::vector<cd> &T, int nb, void *C,
+                        hipStream_t st) {
+  CHK(ensure(c, c->tmp, std::max<size_t>(c->tmp.bytes, (size_t)na * nb * sizeof(double2))));
+  std::vector<double> h(2 * (size_t)na * nb);
+  for (size_t k = 0; k < (size_t)na * nb; ++k) {
+    h[2 * k] = T[k].real();
+    h[2 * k + 1] = T[k].imag();
+  }
+  HIPCHK(c, hipMemcpyAsync(c->tmp.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_gemm_nn(A, c->n, na, (const double *)c->tmp.p, nb, C, c->n, c->n, st);
+  HIPCHK(c, hipStreamSynchronize(st));
+  return SSCG_OK;
+}
+
+// Hermitian eigen-decomposition of a row-major n x n complex matrix (uses the
+// column-major routine on the transpose; for a Hermitian matrix the transpose is
+// the conjugate, whose eigenvectors are the conjugates).
+static void eig_rowmajor(int n, const std::vector<cd> &A, std::vector<double> &ev, std::vector<cd> &W) {
+  std::vector<double> a(2 * (size_t)n * n), vv(2 * (size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {  // column-major element (i, j) = A[i][j]
+      a[2 * (i + (size_t)n * j)] = A[(size_t)i * n + j].real();
+      a[2 * (i + (size_t)n * j) + 1] = A[(size_t)i * n + j].imag();
+    }
+  ev.resize(n);
+  herm_eig(n, a.data(), ev.data(), vv.data());
+  W.resize((size_t)n * n);  // row-major: W[i][k] = component i of eigenvector k
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < n; ++i) W[(size_t)i * n + k] = cd(vv[2 * (i + (size_t)n * k)], vv[2 * (i + (size_t)n * k) + 1]);
+}
+
+static int apply_A_planar(sscg_ctx *c, const void *X, void *AX, int ncol, hipStream_t st) {
+  const size_t vec = c->n * sizeof(double2);
+  for (int k = 0; k < ncol; k += 8) {
+    const int cnt = std::min(8, ncol - k);
+    dslash_plain(c, (const char *)X + k * vec, (char *)AX + k * vec, cnt, 0, 0, 0.0, nullptr, nullptr, st);
+  }
+  return SSCG_OK;
+}
+
+// residual norms ||AX_c - lam_c X_c|| and ||X_c||
+static int col_residuals(sscg_ctx *c, const void *AX, const void *X, int ncol, const std::vector<double> &lam,
+                         std::vector<double> &res, std::vector<double> &xn, hipStream_t st) {
+  const int nchunk = 64;
+  CHK(ensure(c, c->small, (size_t)(2 * ncol * nchunk + ncol) * sizeof(double)));
+  double *part = (double *)c->small.p;
+  double *ldev = part + 2 * ncol * nchunk;
+  HIPCHK(c, hipMemcpyAsync(ldev, lam.data(), ncol * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_resid_cols(AX, X, c->n, ncol, ldev, c->n, part, nchunk, st);
+  std::vector<double> h((size_t)2 * ncol * nchunk);
+  HIPCHK(c, hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  res.assign(ncol, 0.0);
+  xn.assign(ncol, 0.0);
+  for (int k = 0; k < ncol; ++k)
+    for (int b = 0; b < nchunk; ++b) {
+      res[k] += h[(size_t)k * nchunk + b];
+      xn[k] += h[(size_t)(ncol + k) * nchunk + b];
+    }
+  for (int k = 0; k < ncol; ++k) {
+    xn[k] = std::sqrt(xn[k]);
+    res[k] = std::sqrt(res[k]) / (xn[k] > 0 ? xn[k] : 1.0);
+  }
+  return SSCG_OK;
+}
+
+extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v, int32_t nsrc, int32_t max_eigs,
+                            double *lambda, void *X, double *res, int32_t *n_found, sscg_ss_info *info) {
+  if (!c || !p || !v || nsrc <= 0 || max_eigs < 0 || (max_eigs > 0 && (!lambda || !res)) || !n_found)
+    return fail(c, SSCG_EINVAL, "bad argument");
+  if (p->M <= 0 || p->N < 4 || (p->path == SSCG_PATH_LINES && p->N % 2) || !(p->rho > 0) ||
+      (p->path == SSCG_PATH_LINES && !(p->beta > 0)))
+    return fail(c, SSCG_EINVAL, "bad contour parameters");
+  if (p->method == SSCG_HANKEL && 2 * p->M > p->N)
+    return fail(c, SSCG_EINVAL, "Hankel needs 2M <= N moments from N nodes");
+  if (!(p->rank_tol > 0 && p->rank_tol < 1)) return fail(c, SSCG_EINVAL, "rank_tol must lie in (0, 1)");
+  if (p->N > 512 || (int64_t)p->M * nsrc > 256)
+    return fail(c, SSCG_EINVAL, "at most 512 nodes and M * nsrc <= 256 moment columns");
+  const int Np = p->Nprime ? p->Nprime : p->N;
+  if (p->path == SSCG_PATH_LINES && (Np < 4 || Np % 2 || Np > p->N)) return fail(c, SSCG_EINVAL, "bad Nprime");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int N = p->N, M = p->M, L = nsrc;
+  const size_t n = c->n, vec = n * sizeof(double2);
+  std::vector<cd> z, zeta, w;
+  if (p->path == SSCG_PATH_LINES) quad_lines_host(N, p->gamma, p->rho, p->beta, z, zeta, w);
+  else quad_circle_host(N, p->gamma, p->rho, z, zeta, w);
+  // shifted CG into the internal (planar) solution buffer
+  CHK(ensure(c, c->Ybuf, (size_t)L * N * vec));
+  std::vector<double> zd(2 * N);
+  for (int j = 0; j < N; ++j) {
+    zd[2 * j] = z[j].real();
+    zd[2 * j + 1] = z[j].imag();
+  }
+  std::vector<Prob> P(1);
+  P[0].c = c;
+  P[0].v = v;
+  P[0].L = L;
+  P[0].N = N;
+  P[0].sigma = p->gamma;
+  P[0].z = zd;
+  P[0].y = c->Ybuf.p;
+  P[0].keep_planar = true;
+  std::vector<int32_t> iters(L);
+  P[0].iters = iters.data();
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = run_solve(P, p->solve);
+  if (rc != SSCG_OK && rc != SSCG_ENOTCONV) return rc;
+  hipStream_t st = c->work;
+  auto t1 = std::chrono::steady_clock::now();
+  // moments: S planar, column k L + l = s_{k,l} (eq. 2)
+  const int K = (p->method == SSCG_HANKEL) ? 2 * M : M;
+  const int ncol = M * L;
+  CHK(ensure(c, c->Sbuf, (size_t)ncol * vec));
+  {
+    std::vector<double> cf(2 * (size_t)M * N);
+    for (int k = 0; k < M; ++k)
+      for (int j = 0; j < N; ++j) {
+        const cd cc = w[j] * std::pow(zeta[j], k);
+        cf[2 * ((size_t)k * N + j)] = cc.real();
+        cf[2 * ((size_t)k * N + j) + 1] = cc.imag();
+      }
+    CHK(ensure(c, c->small, cf.size() * sizeof(double)));
+    HIPCHK(c, hipMemcpyAsync(c->small.p, cf.data(), cf.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_moments_strided(c->Ybuf.p, L, N, (const double *)c->small.p, M, c->Sbuf.p, (int64_t)n, 1, L, st);
+    HIPCHK(c, hipStreamSynchronize(st));
+  }
+  auto t2 = std::chrono::steady_clock::now();
+  // candidate pairs: coefficients Tc (ncol x r, row-major) with x = S_hat Tc, values lam
+  std::vector<double> lam;
+  std::vector<cd> Tc;
+  int r = 0;
+  // X and AX buffers live in the shift workspace (free after the solve) when it is large enough
+  void *Xd = nullptr, *AXd = nullptr;
+  if (c->W.bytes >= 2 * (size_t)ncol * vec) {
+    Xd = c->W.p;
+    AXd = (char *)c->W.p + (size_t)ncol * vec;
+  } else {
+    CHK(ensure(c, c->Xbuf, (size_t)ncol * vec));
+    CHK(ensure(c, c->AXbuf, (size_t)ncol * vec));
+    Xd = c->Xbuf.p;
+    AXd = c->AXbuf.p;
+  }
+  if (p->method == SSCG_RR) {
+    // Q from S_hat with unit-norm columns: two Gram passes (the second restores
+    // orthogonality lost in the first), keeping directions whose singular value
+    // exceeds rank_tol times the largest.
+    std::vector<cd> G;
+    CHK(gram(c, c->Sbuf.p, ncol, c->Sbuf.p, ncol, G, st));
+    std::vector<double> dsc(ncol);
+    for (int a = 0; a < ncol; ++a) dsc[a] = G[(size_t)a * ncol + a].real() > 0 ? 1.0 / std::sqrt(G[(size_t)a * ncol + a].real()) : 0.0;
+    std::vector<cd> Gs((size_t)ncol * ncol);
+    for (int a = 0; a < ncol; ++a)
+      for (int b = 0; b < ncol; ++b) Gs[(size_t)a * ncol + b] = dsc[a] * G[(size_t)a * ncol + b] * dsc[b];
+    std::vector<double> ev;
+    std::vector<cd> W;
+    eig_rowmajor(ncol, Gs, ev, W);
+    const double emax = ev.back();
+    std::vector<int> keep;
+    for (int k = ncol - 1; k >= 0; --k)
+      if (ev[k] > p->rank_tol * p->rank_tol * emax) keep.push_back(k);
+    r = (int)keep.size();
+    if (r == 0) return fail(c, SSCG_EBREAKDOWN, "moment matrix has rank 0");
+    std::vector<cd> T1((size_t)ncol * r);
+    for (int a = 0; a < ncol; ++a)
+      for (int q = 0; q < r; ++q) T1[(size_t)a * r + q] = dsc[a] * W[(size_t)a * ncol + keep[q]] / std::sqrt(ev[keep[q]]);
+    CHK(ensure(c, c->Qbuf, (size_t)r * vec));
+    CHK(ensure(c, c->AQbuf, (size_t)r * vec));
+    CHK(basis_change(c, c->Sbuf.p, ncol, T1, r, c->AQbuf.p, st));  // Q1 (in AQbuf for now)
+    std::vector<cd> G2;
+    CHK(gram(c, c->AQbuf.p, r, c->AQbuf.p, r, G2, st));
+    std::vector<double> ev2;
+    std::vector<cd> W2;
+    eig_rowmajor(r, G2, ev2, W2);
+    std::vector<cd> T2((size_t)r * r);
+    for (int a = 0; a < r; ++a)
+      for (int q = 0; q < r; ++q) T2[(size_t)a * r + q] = W2[(size_t)a * r + q] / std::sqrt(std::max(ev2[q], 1e-300));
+    CHK(basis_change(c, c->AQbuf.p, r, T2, r, c->Qbuf.p, st));    // Q
+    CHK(apply_A_planar(c, c->Qbuf.p, c->AQbuf.p, r, st));           // A Q
+    std::vector<cd> At;
+    CHK(gram(c, c->Qbuf.p, r, c->AQbuf.p, r, At, st));
+    std::vector<cd> Wr;
+    eig_rowmajor(r, At, lam, Wr);
+    CHK(basis_change(c, c->Qbuf.p, r, Wr, r, Xd, st));
+    CHK(basis_change(c, c->AQbuf.p, r, Wr, r, AXd, st));
+  } else {
+    // block Hankel: M_k = V^H s_k = sum_j w_j zeta_j^k (V^H y_{.,j}) for k < 2M
+    CHK(ensure(c, c->v64, (size_t)L * vec));
+    launch_pack(v, c->v64.p, 0, L, c->V, st);
+    std::vector<cd> Gv;  // [a][l N + j] = <v_a, y_{l,j}>
+    CHK(gram(c, c->v64.p, L, c->Ybuf.p, L * N, Gv, st));
+    std::vector<cd> mu((size_t)K * L * L, cd(0, 0));
+    for (int k = 0; k < K; ++k)
+      for (int j = 0; j < N; ++j) {
+        const cd cc = w[j] * std::pow(zeta[j], k);
+        for (int a = 0; a < L; ++a)
+          for (int l = 0; l < L; ++l) mu[((size_t)k * L + a) * L + l] += cc * Gv[(size_t)a * L * N + (size_t)l * N + j];
+      }
+    const int m = M * L;
+    std::vector<cd> H((size_t)m * m), Hs((size_t)m * m);
+    for (int bi = 0; bi < M; ++bi)
+      for (int bj = 0; bj < M; ++bj)
+        for (int a = 0; a < L; ++a)
+          for (int l = 0; l < L; ++l) {
+            H[(size_t)(bi * L + a) * m + bj * L + l] = mu[((size_t)(bi + bj) * L + a) * L + l];
+            Hs[(size_t)(bi * L + a) * m + bj * L + l] = mu[((size_t)(bi + bj + 1) * L + a) * L + l];
+          }
+    // H is Hermitian positive semidefinite for a real filter (f_0 > 0 on the real
+    // axis for both paths); reduce on its dominant eigenvectors.
+    std::vector<double> ev;
+    std::vector<cd> W;
+    eig_rowmajor(m, H, ev, W);
+    const double emax = ev.back();
+    std::vector<int> keep;
+    for (int k = m - 1; k >= 0; --k)
+      if (ev[k] > p->rank_tol * emax) keep.push_back(k);
+    r = (int)keep.size();
+    if (r == 0) return fail(c, SSCG_EBREAKDOWN, "Hankel matrix has rank 0");
+    std::vector<cd> Wr((size_t)m * r);
+    for (int a = 0; a < m; ++a)
+      for (int q = 0; q < r; ++q) Wr[(size_t)a * r + q] = W[(size_t)a * m + keep[q]] / std::sqrt(ev[keep[q]]);
+    std::vector<cd> red((size_t)r * r, cd(0, 0));
+    for (int q1 = 0; q1 < r; ++q1)
+      for (int q2 = 0; q2 < r; ++q2) {
+        cd s = 0;
+        for (int a = 0; a < m; ++a) {
+          cd t = 0;
+          for (int b = 0; b < m; ++b) t += Hs[(size_t)a * m + b] * Wr[(size_t)b * r + q2];
+          s += std::conj(Wr[(size_t)a * r + q1]) * t;
+        }
+        red[(size_t)q1 * r + q2] = s;
+      }
+    std::vector<double> eta;
+    std::vector<cd> T;
+    eig_rowmajor(r, red, eta, T);
+    lam.resize(r);
+    for (int q = 0; q < r; ++q) lam[q] = p->gamma + p->rho * eta[q];
+    Tc.assign((size_t)m * r, cd(0, 0));
+    for (int a = 0; a < m; ++a)
+      for (int q = 0; q < r; ++q) {
+        cd s = 0;
+        for (int b = 0; b < r; ++b) s += Wr[(size_t)a * r + b] * T[(size_t)b * r + q];
+        Tc[(size_t)a * r + q] = s;
+      }
+    CHK(basis_change(c, c->Sbuf.p, m, Tc, r, Xd, st));
+    CHK(apply_A_planar(c, Xd, AXd, r, st));
+  }
+  std::vector<double> rs, xn;
+  CHK(col_residuals(c, AXd, Xd, r, lam, rs, xn, st));
+  // acceptance (Sec. 3)
+  double lo, hi, imax;
+  if (p->path == SSCG_PATH_LINES) {
+    std::vector<double> xr;
+    for (int j = 0; j < N; j += 2) xr.push_back(zeta[j].real());
+    std::vector<int> ord(xr.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(xr[a]) < std::fabs(xr[b]); });
+    double mn = 1e300, mx = -1e300;
+    for (int i = 0; i < Np / 2; ++i) {
+      mn = std::min(mn, xr[ord[i]]);
+      mx = std::max(mx, xr[ord[i]]);
+    }
+    lo = p->gamma + p->rho * mn;
+    hi = p->gamma + p->rho * mx;
+    imax = p->beta * p->rho;
+  } else {
+    lo = p->gamma - p->rho;
+    hi = p->gamma + p->rho;
+    imax = p->rho;
+  }
+  (void)imax;  // Ritz and Hermitian-Hankel values are real
+  std::vector<int> acc;
+  for (int q = 0; q < r; ++q)
+    if (lam[q] >= lo && lam[q] <= hi && rs[q] <= p->spur_tol) acc.push_back(q);
+  *n_found = (int)acc.size();
+  // keep the max_eigs nearest gamma, report ascending
+  std::vector<int> sel = acc;
+  std::stable_sort(sel.begin(), sel.end(), [&](int a, int b) { return std::fabs(lam[a] - p->gamma) < std::fabs(lam[b] - p->gamma); });
+  if ((int)sel.size() > max_eigs) sel.resize(max_eigs);
+  std::sort(sel.begin(), sel.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+  for (size_t i = 0; i < sel.size(); ++i) {
+    lambda[i] = lam[sel[i]];
+    res[i] = rs[sel[i]];
+    if (X) {
+      // unit-normalised column, canonical layout
+      std::vector<double> one(1, xn[sel[i]] > 0 ? 1.0 / xn[sel[i]] : 1.0);
+      HIPCHK(c, hipMemcpyAsync(c->tmp.p, (const char *)Xd + (size_t)sel[i] * vec, vec, hipMemcpyDeviceToDevice, st));
+      CHK(ensure(c, c->small, sizeof(double)));
+      HIPCHK(c, hipMemcpyAsync(c->small.p, one.data(), sizeof(double), hipMemcpyHostToDevice, st));
+      launch_colscale(c->tmp.p, (int64_t)n, 1, (const double *)c->small.p, (int64_t)n, st);
+      launch_unpack(c->tmp.p, 0, (char *)X + i * vec, 1, c->V, st);
+      HIPCHK(c, hipStreamSynchronize(st));
+    }
+  }
+  auto t3 = std::chrono::steady_clock::now();
+  if (info) {
+    info->rank = r;
+    info->n_candidates = r;
+    info->iters = *std::max_element(iters.begin(), iters.end());
+    info->solve_status = rc;
+    info->t_solve = std::chrono::duration<double>(t1 - t0).count();
+    info->t_moments = std::chrono::duration<double>(t2 - t1).count();
+    info->t_extract = std::chrono::duration<double>(t3 - t2).count();
+  }
+  HIPCHK(c, hipStreamSynchronize(st));
+  return rc == SSCG_ENOTCONV ? SSCG_ENOTCONV : SSCG_OK;
+}

@@ -1,0 +1,570 @@
+// Streaming and scalar kernels of the shifted CG method (Sec. 2.2) and the moment
+// sums (eq. 2).
+//
+// Per iteration k of the seed system B x = v, B = sigma I - A, for every source:
+//   dslash        q = B p, partial Re<p, q>                      (dslash.hip)
+//   seed_alpha    alpha_k = rho_k / <p, q>                       (one block per source)
+//   seed_r_update r <- r - alpha_k q, partial <r, r>
+//   shift_scalars rho_{k+1}, beta_k and, per shift j with s_j = z_j - sigma,
+//                 pi_{j,k+1} = (1 + c + alpha_k s_j) pi_{j,k} - c pi_{j,k-1},
+//                 c = alpha_k beta_{k-1} / alpha_{k-1},
+//                 alpha_{j,k} = alpha_k pi_{j,k}/pi_{j,k+1},
+//                 beta_{j,k} = (pi_{j,k}/pi_{j,k+1})^2 beta_k,
+//                 and the freeze test sqrt(rho_{k+1}) / |pi_{j,k+1}| <= tol ||v||
+//   shift_update  x_j += alpha_{j,k} p_j, p_j <- r/pi_{j,k+1} + beta_{j,k} p_j for
+//                 every shift updated this iteration, and p <- r + beta_k p; the
+//                 seed residual r is read once per batch of shifts.
+// Every reduction writes one partial per block and the consumer sums them in a
+// fixed order, so results do not depend on scheduling.
+#include "sscg_internal.h"
+
+namespace sscg {
+
+static constexpr int kEpt = 2;  // complex entries per thread in streaming kernels
+
+template <int NW>
+__device__ __forceinline__ double block_sum_all(double v, double *sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) t += sh[i];
+  __syncthreads();
+  return t;  // valid in every thread
+}
+template <int NW>
+__device__ __forceinline__ double block_max_all(double v, double *sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) t = fmax(t, sh[i]);
+  __syncthreads();
+  return t;
+}
+
+template <typename J>
+__device__ __forceinline__ int job_of(const J *jobs, int njobs, int b) {
+  int j = 0;
+  for (int k = 1; k < njobs; ++k) if (b >= jobs[k].block_begin) j = k;
+  return j;
+}
+
+// Smith's complex division a / b (no overflow for large |b|).
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  if (fabs(b.x) >= fabs(b.y)) {
+    const double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  } else {
+    const double r = b.x / b.y, d = b.x * r + b.y;
+    return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void seed_alpha_kernel(ScalarBatch B) {
+  __shared__ double red[kBlock / 64];
+  const int b = blockIdx.x;
+  const ScalarJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int l = b - J.block_begin;
+  SeedState &S = J.seed[l];
+  const int done = S.done;
+  __syncthreads();
+  if (threadIdx.x == 0) S.pending = 0;
+  if (done) return;
+  double v = 0.0;
+  const double *p = J.partial + (size_t)l * J.nblk;
+  for (int i = threadIdx.x; i < J.nblk; i += kBlock) v += p[i];
+  const double pq = block_sum_all<kBlock / 64>(v, red);
+  if (threadIdx.x == 0) {
+    if (pq == 0.0 || !isfinite(pq)) {
+      S.status = -5;  // SSCG_EBREAKDOWN
+      S.done = 1;
+    } else {
+      S.alpha = S.rho / pq;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void shift_scalars_kernel(ScalarBatch B) {
+  __shared__ double red[kBlock / 64];
+  const int b = blockIdx.x;
+  const ScalarJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int l = b - J.block_begin;
+  SeedState &S = J.seed[l];
+  if (S.done) return;
+  double v = 0.0;
+  const double *p = J.partial + (size_t)l * J.nblk;
+  for (int i = threadIdx.x; i < J.nblk; i += kBlock) v += p[i];
+  const double rho_new = block_sum_all<kBlock / 64>(v, red);
+  const double alpha = S.alpha, alpha_prev = S.alpha_prev, beta_prev = S.beta_prev;
+  const double beta = rho_new / S.rho;
+  const double c = alpha * beta_prev / alpha_prev;
+  const double sq = sqrt(rho_new);
+  const double thr = J.tol * S.vnorm;
+  const int it = S.iters;
+  double nact = 0.0, maxres = 0.0;
+  for (int j = threadIdx.x; j < J.nshift; j += kBlock) {
+    ShiftState &H = J.shift[(size_t)l * J.nshift + j];
+    if (H.active) {
+      const double2 pc = H.pi_cur, pp = H.pi_prev, s = H.s;
+      // (1 + c + alpha s) pi_cur - c pi_prev
+      const double2 f = make_double2(1.0 + c + alpha * s.x, alpha * s.y);
+      double2 pn = cmul(f, pc);
+      pn.x -= c * pp.x;
+      pn.y -= c * pp.y;
+      const double2 ratio = cdiv(pc, pn);
+      H.a = make_double2(alpha * ratio.x, alpha * ratio.y);
+      const double2 r2 = cmul(ratio, ratio);
+      H.b = make_double2(beta * r2.x, beta * r2.y);
+      H.ipi = cdiv(make_double2(1.0, 0.0), pn);
+      H.pi_prev = pc;
+      H.pi_cur = pn;
+      H.upd = 1;
+      const double res = sq / hypot(pn.x, pn.y);
+      if (res <= thr) {
+        H.active = 0;
+        H.conv_iter = it + 1;
+      } else {
+        nact += 1.0;
+        maxres = fmax(maxres, res / S.vnorm);
+      }
+    } else {
+      H.upd = 0;
+    }
+  }
+  const double na = block_sum_all<kBlock / 64>(nact, red);
+  const double mr = block_max_all<kBlock / 64>(maxres, red);
+  if (threadIdx.x == 0) {
+    S.alpha_prev = alpha;
+    S.beta_prev = beta;
+    S.rho = rho_new;
+    S.iters = it + 1;
+    S.nactive = (int)na;
+    S.maxres = mr;
+    S.pending = 1;
+    if (!isfinite(rho_new) || !isfinite(beta)) {
+      S.status = -5;
+      S.done = 1;
+      S.pending = 0;
+    } else if (na == 0.0) {
+      S.done = 1;
+      S.status = 0;
+    } else if (it + 1 >= J.maxiter) {
+      S.done = 1;
+      S.status = -4;  // SSCG_ENOTCONV
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// r <- r - alpha q (and x_part += alpha p in the FP32 phase); partial <r, r>.
+// job: a = r, b = q, c = x_part (or null), d = p.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
+  using C = V2<T>;
+  __shared__ double red[kBlock / 64];
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int lb = b - J.block_begin;
+  const int l = lb / J.nblk_vec, vb = lb - l * J.nblk_vec;
+  if (J.seed[l].done) return;
+  const T alpha = (T)J.seed[l].alpha;
+  C *r = reinterpret_cast<C *>(J.a) + (size_t)l * J.n;
+  const C *q = reinterpret_cast<const C *>(J.b) + (size_t)l * J.n;
+  C *xp = J.c ? reinterpret_cast<C *>(J.c) + (size_t)l * J.n : nullptr;
+  const C *p = J.d ? reinterpret_cast<const C *>(J.d) + (size_t)l * J.n : nullptr;
+  double acc = 0.0;
+  const int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < kEpt; ++e) {
+    const int64_t i = base + (int64_t)e * kBlock;
+    if (i < J.n) {
+      C rv = r[i];
+      const C qv = q[i];
+      rv.x -= alpha * qv.x;
+      rv.y -= alpha * qv.y;
+      r[i] = rv;
+      acc += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
+      if (xp) {
+        C xv = xp[i];
+        const C pv = p[i];
+        xv.x += alpha * pv.x;
+        xv.y += alpha * pv.y;
+        xp[i] = xv;
+      }
+    }
+  }
+  const double tot = block_sum_all<kBlock / 64>(acc, red);
+  if (threadIdx.x == 0) J.partial[(size_t)l * J.nblk_vec + vb] = tot;
+}
+
+// Fused multi-shift update. job: a = x (FP64 solution storage [nsrc][nshift][n]),
+// b = shift workspace [nsrc][nshift] slots of n double2: FP64 phase p_j;
+// FP32 phase p_j (first n float2) and the FP32 partial x_j (next n float2);
+// c = seed r, d = seed p (both T). FOLD (FP32 phase only) also adds the partial
+// and this iteration's step into the FP64 solution and clears the partial.
+template <typename T, bool FOLD>
+__global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
+  using C = V2<T>;
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int lb = b - J.block_begin;
+  const int nbatch = (J.nshift + J.wbatch - 1) / J.wbatch;
+  const int per_src = nbatch * J.nblk_vec;
+  const int l = lb / per_src;
+  const int rem = lb - l * per_src;
+  const int bt = rem / J.nblk_vec, vb = rem - bt * J.nblk_vec;
+  const SeedState &S = J.seed[l];
+  if (!S.pending) return;
+  const int64_t n = J.n;
+  const C *r = reinterpret_cast<const C *>(J.c) + (size_t)l * n;
+  const int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x;
+  C rv[kEpt];
+#pragma unroll
+  for (int e = 0; e < kEpt; ++e) {
+    const int64_t i = base + (int64_t)e * kBlock;
+    rv[e] = i < n ? r[i] : cmk<C>(0, 0);
+  }
+  const int j0 = bt * J.wbatch, j1 = min(j0 + J.wbatch, J.nshift);
+  for (int j = j0; j < j1; ++j) {
+    const ShiftState &H = J.shift[(size_t)l * J.nshift + j];
+    if (!H.upd) continue;
+    const size_t slot = (size_t)l * J.nshift + j;
+    if constexpr (sizeof(T) == 8) {
+      const double2 a = H.a, bb = H.b, ip = H.ipi;
+      double2 *x = reinterpret_cast<double2 *>(J.a) + slot * n;
+      double2 *p = reinterpret_cast<double2 *>(J.b) + slot * n;
+#pragma unroll
+      for (int e = 0; e < kEpt; ++e) {
+        const int64_t i = base + (int64_t)e * kBlock;
+        if (i < n) {
+          double2 xv = x[i];
+          const double2 pv = p[i];
+          cfma(xv, a, pv);
+          double2 pn = cmul(ip, rv[e]);
+          cfma(pn, bb, pv);
+          x[i] = xv;
+          p[i] = pn;
+        }
+      }
+    } else {
+      const float2 a = make_float2((float)H.a.x, (float)H.a.y);
+      const float2 bb = make_float2((float)H.b.x, (float)H.b.y);
+      const float2 ip = make_float2((float)H.ipi.x, (float)H.ipi.y);
+      float2 *p = reinterpret_cast<float2 *>(reinterpret_cast<double2 *>(J.b) + slot * n);
+      float2 *xp = p + n;
+#pragma unroll
+      for (int e = 0; e < kEpt; ++e) {
+        const int64_t i = base + (int64_t)e * kBlock;
+        if (i < n) {
+          const float2 pv = p[i];
+          float2 xv = xp[i];
+          float2 pn = cmul(ip, rv[e]);
+          cfma(pn, bb, pv);
+          p[i] = pn;
+          if constexpr (FOLD) {
+            double2 *x = reinterpret_cast<double2 *>(J.a) + slot * n;
+            double2 xm = x[i];
+            const double2 pd = make_double2(pv.x, pv.y);
+            xm.x += (double)xv.x;
+            xm.y += (double)xv.y;
+            cfma(xm, H.a, pd);
+            x[i] = xm;
+            xp[i] = make_float2(0.f, 0.f);
+          } else {
+            cfma(xv, a, pv);
+            xp[i] = xv;
+          }
+        }
+      }
+    }
+  }
+  if (bt == 0) {
+    const T beta = (T)S.beta_prev;
+    C *p = reinterpret_cast<C *>(J.d) + (size_t)l * n;
+#pragma unroll
+    for (int e = 0; e < kEpt; ++e) {
+      const int64_t i = base + (int64_t)e * kBlock;
+      if (i < n) {
+        C pv = p[i];
+        pv.x = rv[e].x + beta * pv.x;
+        pv.y = rv[e].y + beta * pv.y;
+        p[i] = pv;
+      }
+    }
+  }
+}
+
+// Reliable update: r64 = r_base - B x_part (q = B x_part already computed in FP64),
+// r32 = (float) r64, partial <r64, r64>. job: a = r_base, b = q64, c = r64, d = r32.
+__global__ __launch_bounds__(kBlock) void reliable_residual_kernel(VecBatch B) {
+  __shared__ double red[kBlock / 64];
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int lb = b - J.block_begin;
+  const int l = lb / J.nblk_vec, vb = lb - l * J.nblk_vec;
+  if (J.seed[l].done) return;
+  const size_t off = (size_t)l * J.n;
+  const double2 *rb = reinterpret_cast<const double2 *>(J.a) + off;
+  const double2 *q = reinterpret_cast<const double2 *>(J.b) + off;
+  double2 *r64 = reinterpret_cast<double2 *>(J.c) + off;
+  float2 *r32 = reinterpret_cast<float2 *>(J.d) + off;
+  double acc = 0.0;
+  const int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < kEpt; ++e) {
+    const int64_t i = base + (int64_t)e * kBlock;
+    if (i < J.n) {
+      const double2 rv = rb[i] - q[i];
+      r64[i] = rv;
+      r32[i] = make_float2((float)rv.x, (float)rv.y);
+      acc += rv.x * rv.x + rv.y * rv.y;
+    }
+  }
+  const double tot = block_sum_all<kBlock / 64>(acc, red);
+  if (threadIdx.x == 0) J.partial[(size_t)l * J.nblk_vec + vb] = tot;
+}
+
+// x_part64 += x_part32, x_part32 = 0. job: a = x_part64, b = x_part32.
+__global__ __launch_bounds__(kBlock) void fold_seed_kernel(VecBatch B) {
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int lb = b - J.block_begin;
+  const int l = lb / J.nblk_vec, vb = lb - l * J.nblk_vec;
+  if (J.seed[l].done) return;
+  const size_t off = (size_t)l * J.n;
+  double2 *x64 = reinterpret_cast<double2 *>(J.a) + off;
+  float2 *x32 = reinterpret_cast<float2 *>(J.b) + off;
+  const int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < kEpt; ++e) {
+    const int64_t i = base + (int64_t)e * kBlock;
+    if (i < J.n) {
+      const float2 xv = x32[i];
+      double2 xm = x64[i];
+      xm.x += (double)xv.x;
+      xm.y += (double)xv.y;
+      x64[i] = xm;
+      x32[i] = make_float2(0.f, 0.f);
+    }
+  }
+}
+
+// End of an FP32 phase: x_j += x_part_j, x_part_j = 0 for every (source, shift)
+// slot; the FP32 partial is the upper half of the slot's workspace.
+__global__ void fold_shifts_kernel(double2 *y, double2 *W, int64_t n) {
+  const size_t slot = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float2 *x32 = reinterpret_cast<float2 *>(W + slot * n) + n;
+  double2 *ys = y + slot * n;
+  const float2 xv = x32[i];
+  double2 v = ys[i];
+  v.x += (double)xv.x;
+  v.y += (double)xv.y;
+  ys[i] = v;
+  x32[i] = make_float2(0.f, 0.f);
+}
+
+// ---------------------------------------------------------------------------
+// Plain conversions and reductions over flat complex arrays.
+__global__ void to_fp32_kernel(const double2 *src, float2 *dst, float2 *zero, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double2 v = src[i];
+    dst[i] = make_float2((float)v.x, (float)v.y);
+    if (zero) zero[i] = make_float2(0.f, 0.f);
+  }
+}
+
+template <typename S, typename D>
+__global__ void cast_kernel(const S *src, D *dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const S v = src[i];
+    D d;
+    d.x = v.x;
+    d.y = v.y;
+    dst[i] = d;
+  }
+}
+
+// canonical complex128 [nsrc][V][12] -> planar T [nsrc][12][V]; thread per (src, c, s)
+template <typename T>
+__global__ void pack_kernel(const double2 *canon, V2<T> *planar, int nsrc, int V) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)nsrc * 12 * V;
+  if (i >= tot) return;
+  const int64_t l = i / (12 * (int64_t)V);
+  const int64_t rem = i - l * 12 * V;
+  const int c = (int)(rem / V);
+  const int s = (int)(rem - (int64_t)c * V);
+  const double2 v = canon[(l * V + s) * 12 + c];
+  V2<T> o;
+  o.x = (T)v.x;
+  o.y = (T)v.y;
+  planar[i] = o;
+}
+template <typename T>
+__global__ void unpack_kernel(const V2<T> *planar, double2 *canon, int nsrc, int V) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)nsrc * 12 * V;
+  if (i >= tot) return;
+  const int64_t l = i / (12 * (int64_t)V);
+  const int64_t rem = i - l * 12 * V;
+  const int s = (int)(rem / 12);
+  const int c = (int)(rem - (int64_t)s * 12);
+  const V2<T> v = planar[(l * 12 + c) * V + s];
+  canon[i] = make_double2((double)v.x, (double)v.y);
+}
+
+// partial[v][blk] = sum over the block's entries of |x_v|^2 (nvec vectors of n)
+__global__ __launch_bounds__(kBlock) void norm2_kernel(const double2 *x, int64_t n, double *partial, int nblk) {
+  __shared__ double red[kBlock / 64];
+  const int vec = blockIdx.y;
+  const double2 *xv = x + (size_t)vec * n;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)nblk * kBlock) {
+    const double2 v = xv[i];
+    acc += v.x * v.x + v.y * v.y;
+  }
+  const double tot = block_sum_all<kBlock / 64>(acc, red);
+  if (threadIdx.x == 0) partial[(size_t)vec * nblk + blockIdx.x] = tot;
+}
+
+// partial of || v - z_j y_j + (A y_j) ||^2 for nvec shifts of one source
+__global__ __launch_bounds__(kBlock) void true_residual_kernel(const double2 *v, const double2 *y,
+                                                               const double2 *Ay, const double *z,
+                                                               int64_t n, double *partial, int nblk) {
+  __shared__ double red[kBlock / 64];
+  const int j = blockIdx.y;
+  const double2 zj = make_double2(z[2 * j], z[2 * j + 1]);
+  const double2 *yj = y + (size_t)j * n;
+  const double2 *ayj = Ay + (size_t)j * n;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)nblk * kBlock) {
+    const double2 zy = cmul(zj, yj[i]);
+    const double2 rv = v[i] - zy + ayj[i];
+    acc += rv.x * rv.x + rv.y * rv.y;
+  }
+  const double tot = block_sum_all<kBlock / 64>(acc, red);
+  if (threadIdx.x == 0) partial[(size_t)j * nblk + blockIdx.x] = tot;
+}
+
+// s_{l,k} = sum_j c[k][j] y_{l,j}; grid (entry blocks, source, moment chunk)
+constexpr int kMomChunk = 8;
+__global__ __launch_bounds__(kBlock) void moments_kernel(const double2 *y, int nshift, const double2 *c,
+                                                         int nmom, double2 *s, int64_t n,
+                                                         int64_t s_stride_l, int64_t s_stride_k) {
+  extern __shared__ double2 csh[];  // [kMomChunk][nshift]
+  const int l = blockIdx.y;
+  const int k0 = blockIdx.z * kMomChunk;
+  const int nk = min(kMomChunk, nmom - k0);
+  for (int t = threadIdx.x; t < nk * nshift; t += kBlock) {
+    const int kk = t / nshift, j = t - kk * nshift;
+    csh[t] = c[(size_t)(k0 + kk) * nshift + j];
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double2 acc[kMomChunk];
+#pragma unroll
+  for (int kk = 0; kk < kMomChunk; ++kk) acc[kk] = make_double2(0, 0);
+  const double2 *yl = y + (size_t)l * nshift * n;
+  for (int j = 0; j < nshift; ++j) {
+    const double2 yv = yl[(size_t)j * n + i];
+#pragma unroll
+    for (int kk = 0; kk < kMomChunk; ++kk)
+      if (kk < nk) cfma(acc[kk], csh[kk * nshift + j], yv);
+  }
+#pragma unroll
+  for (int kk = 0; kk < kMomChunk; ++kk)
+    if (kk < nk) s[((size_t)l * s_stride_l + (size_t)(k0 + kk) * s_stride_k) * n + i] = acc[kk];
+}
+
+// ---------------------------------------------------------------------------
+void launch_seed_alpha(const ScalarBatch &b, hipStream_t st) {
+  hipLaunchKernelGGL(seed_alpha_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+}
+void launch_shift_scalars(const ScalarBatch &b, hipStream_t st) {
+  hipLaunchKernelGGL(shift_scalars_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+}
+void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st) {
+  if (prec == 0) hipLaunchKernelGGL(seed_r_update_kernel<double>, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+  else hipLaunchKernelGGL(seed_r_update_kernel<float>, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+}
+void launch_shift_update(const VecBatch &b, int prec, int fold, hipStream_t st) {
+  if (prec == 0) hipLaunchKernelGGL((shift_update_kernel<double, false>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+  else if (fold) hipLaunchKernelGGL((shift_update_kernel<float, true>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+  else hipLaunchKernelGGL((shift_update_kernel<float, false>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+}
+void launch_reliable_residual(const VecBatch &b, hipStream_t st) {
+  hipLaunchKernelGGL(reliable_residual_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+}
+void launch_fold_seed(const VecBatch &b, hipStream_t st) {
+  hipLaunchKernelGGL(fold_seed_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+}
+static inline unsigned nblocks1d(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+void launch_to_fp32(const void *src64, void *dst32, void *zero32, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(to_fp32_kernel, dim3(nblocks1d(n)), dim3(kBlock), 0, st,
+                     (const double2 *)src64, (float2 *)dst32, (float2 *)zero32, n);
+}
+void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st) {
+  if (n <= 0 || nslots <= 0) return;
+  hipLaunchKernelGGL(fold_shifts_kernel, dim3(nblocks1d(n), nslots), dim3(kBlock), 0, st, (double2 *)y,
+                     (double2 *)W, n);
+}
+void launch_cast(const void *src, int sp, void *dst, int dp, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  if (sp == 0 && dp == 1)
+    hipLaunchKernelGGL((cast_kernel<double2, float2>), dim3(nblocks1d(n)), dim3(kBlock), 0, st, (const double2 *)src, (float2 *)dst, n);
+  else if (sp == 1 && dp == 0)
+    hipLaunchKernelGGL((cast_kernel<float2, double2>), dim3(nblocks1d(n)), dim3(kBlock), 0, st, (const float2 *)src, (double2 *)dst, n);
+  else if (sp == 0)
+    hipLaunchKernelGGL((cast_kernel<double2, double2>), dim3(nblocks1d(n)), dim3(kBlock), 0, st, (const double2 *)src, (double2 *)dst, n);
+  else
+    hipLaunchKernelGGL((cast_kernel<float2, float2>), dim3(nblocks1d(n)), dim3(kBlock), 0, st, (const float2 *)src, (float2 *)dst, n);
+}
+void launch_pack(const void *canon, void *planar, int prec, int nsrc, int V, hipStream_t st) {
+  const int64_t tot = (int64_t)nsrc * 12 * V;
+  if (tot <= 0) return;
+  if (prec == 0) hipLaunchKernelGGL(pack_kernel<double>, dim3(nblocks1d(tot)), dim3(kBlock), 0, st, (const double2 *)canon, (double2 *)planar, nsrc, V);
+  else hipLaunchKernelGGL(pack_kernel<float>, dim3(nblocks1d(tot)), dim3(kBlock), 0, st, (const double2 *)canon, (float2 *)planar, nsrc, V);
+}
+void launch_unpack(const void *planar, int prec, void *canon, int nsrc, int V, hipStream_t st) {
+  const int64_t tot = (int64_t)nsrc * 12 * V;
+  if (tot <= 0) return;
+  if (prec == 0) hipLaunchKernelGGL(unpack_kernel<double>, dim3(nblocks1d(tot)), dim3(kBlock), 0, st, (const double2 *)planar, (double2 *)canon, nsrc, V);
+  else hipLaunchKernelGGL(unpack_kernel<float>, dim3(nblocks1d(tot)), dim3(kBlock), 0, st, (const float2 *)planar, (double2 *)canon, nsrc, V);
+}
+void launch_norm2_partial(const void *x, int64_t n, int nvec, double *partial, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(norm2_kernel, dim3(nblk, nvec), dim3(kBlock), 0, st, (const double2 *)x, n, partial, nblk);
+}
+void launch_true_residual(const void *v, const void *y, const void *Ay, const double *z, int64_t n,
+                          int nvec, double *partial, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(true_residual_kernel, dim3(nblk, nvec), dim3(kBlock), 0, st, (const double2 *)v,
+                     (const double2 *)y, (const double2 *)Ay, z, n, partial, nblk);
+}
+void launch_moments_strided(const void *y, int nsrc, int nshift, const double *c_dev, int nmom, void *s,
+                            int64_t n, int64_t sl, int64_t sk, hipStream_t st) {
+  const dim3 grid(nblocks1d(n), nsrc, (nmom + kMomChunk - 1) / kMomChunk);
+  const size_t shm = (size_t)kMomChunk * nshift * sizeof(double2);
+  hipLaunchKernelGGL(moments_kernel, grid, dim3(kBlock), shm, st, (const double2 *)y, nshift,
+                     (const double2 *)c_dev, nmom, (double2 *)s, n, sl, sk);
+}
+void launch_moments(const void *y, int nsrc, int nshift, const double *c_dev, int nmom, void *s, int64_t n,
+                    hipStream_t st) {
+  launch_moments_strided(y, nsrc, nshift, c_dev, nmom, s, n, nmom, 1, st);
+}
+
+}  // namespace sscg
