@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the Sakurai-Sugiura shifted-CG eigensolver on one MI355X.
+
+One step is one pass of the whole hot path over one set of synthetic inputs that
+are already resident in HBM: quadrature on the two lines, the shifted CG for all
+N nodes and L sources (one seed system per source), the moment sums and the
+Rayleigh-Ritz extraction with acceptance (sscg_ss_eigs). The throughput is
+shift-updates per second: the number of (source, shift) vector updates the
+shifted CG performs, summed over the timed steps, divided by their wall time.
+
+Printed as one JSON line on rank 0. Besides the throughput it carries:
+  roofline      the dominant kernel (by measured time), its algorithmic bytes per
+                launch over its average launch duration from HIP events recorded
+                around every launch inside the timed region, against 8 TB/s;
+                traffic from committed rocprofv3 counter summaries when they match
+                the current kernel source, else null
+  dslash        the same figures for the Wilson dslash
+  cpu_baseline  the FP64 CPU oracle (numpy/scipy) on the host: one source's full
+                shifted CG (all N shifts) on the same workload, bounded in time
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "shift-updates/sec & dslash HBM GB/s (frac of peak), mixed/batched vs FP64 plain"
+HBM_PEAK_GBS = 8000.0
+DEFAULT_CONFIG = "wilson8_fp64"
+STAGES = ["dslash", "seed_alpha", "seed_r_update", "shift_scalars", "shift_update", "reliable_update",
+          "solve_loop"]
+KERNEL_SOURCES = {"shift_update": "paper_1004_0292_amd/csrc/vec.hip",
+                  "dslash": "paper_1004_0292_amd/csrc/dslash.hip"}
+
+
+def source_hash(rel):
+    return hashlib.sha256((ROOT / rel).read_bytes()).hexdigest()[:16]
+
+
+def pmc_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if it still matches."""
+    f = ROOT / "profiles" / f"{kernel}_{workload}_pmc.json"
+    if not f.exists():
+        return None
+    d = json.loads(f.read_text())
+    if d.get("source_sha256_16") != source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s=20.0):
+    """Oracle shifted CG on source 0 (all N shifts), stopped after budget_s seconds."""
+    import numpy as np
+    from oracle import quadrature as quad
+    from oracle import solvers, wilson
+    import synth
+
+    t_setup = time.perf_counter()
+    U = w.gauge()
+    A = wilson.hermitian_wilson(U, w.dims, w.kappa)
+    v = synth.sources(w.V, 1, w.seed).reshape(-1)
+    z, zeta = quad.line_nodes(w.N, w.gamma, w.rho, w.beta)
+    setup = time.perf_counter() - t_setup
+    updates = [0]
+    t0 = time.perf_counter()
+    c0 = time.process_time()
+
+    class Stop(Exception):
+        pass
+
+    def rec(k, st):
+        updates[0] += st["updated"]
+        if time.perf_counter() - t0 > budget_s:
+            raise Stop()
+
+    finished = True
+    try:
+        r = solvers.shifted_cg(lambda x: A @ x, v, z, w.gamma, w.tol, record=rec)
+        iters = r.iters
+    except Stop:
+        finished = False
+        iters = None
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    return {"value": updates[0] / wall, "unit": "shift-updates/s", "cores": max(1, round(cpu / wall)),
+            "kind": "oracle",
+            "sample": (f"source 0 of {w.L}: FP64 shifted CG for all {w.N} shifts on the explicit sparse A "
+                       f"({'to convergence, ' + str(iters) + ' iterations' if finished else 'stopped after ' + str(round(wall, 1)) + ' s'}); "
+                       f"{updates[0]} shift-updates in {wall:.1f} s; sparse matvec and vector updates single-threaded; "
+                       f"matrix assembly ({setup:.1f} s) excluded"),
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default=DEFAULT_CONFIG)
+    ap.add_argument("--method", default="rr", choices=["rr", "hankel"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-events", action="store_true", help="time without per-launch events (graph replay)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy five times (for counter scaling) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is not implemented",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_calibration:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 5}))
+        return
+
+    import paper_1004_0292_amd as S
+    import synth
+
+    w = synth.CONFIGS[args.config]
+    prec = S.MIXED if w.prec == "mixed" else S.FP64
+    U = w.gauge()
+    V = w.sources()
+    ctx = S.Context(w.dims, w.kappa, device=0)
+    ctx.set_gauge(U, w.link_reals)
+    vd = torch.from_numpy(V).to("cuda:0")
+    del V
+    opts = S.default_opts(tol=w.tol, prec=prec, ru_interval=w.ru_interval, switch_tol=w.switch_tol)
+    params = S.default_ss_params(gamma=w.gamma, rho=w.rho, beta=w.beta, N=w.N, M=w.M,
+                                 method=S.RR if args.method == "rr" else S.HANKEL, rank_tol=1e-7,
+                                 spur_tol=1e-6, solve=opts)
+    max_eigs = w.M * w.L
+    ctx.set_profiling(not args.no_events)
+    for _ in range(args.warmup):
+        ctx.ss_eigs(params, vd, max_eigs=max_eigs)
+    torch.cuda.synchronize()
+    stage_ms = np.zeros(8)
+    stage_calls = np.zeros(8, dtype=np.int64)
+    tot = dict(shift_updates=0, shift_updates_fp32=0, seed_iters=0, seed_iters_fp32=0, matvecs=0,
+               t_solve=0.0, t_moments=0.0, t_extract=0.0)
+    link_launches = [0, 0]   # dslash launches doing work in the FP64 and FP32 phases
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.ss_eigs(params, vd, max_eigs=max_eigs)
+        ms, calls = ctx.stage_times()
+        stage_ms += ms
+        stage_calls += calls
+        for k in tot:
+            tot[k] += getattr(out.info, k)
+        sw = out.info.switch_iter if out.info.switch_iter >= 0 else out.info.iters
+        link_launches[0] += min(out.info.iters, sw)
+        link_launches[1] += max(0, out.info.iters - sw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    n = w.n
+    value = tot["shift_updates"] / elapsed
+
+    # algorithmic bytes (compulsory traffic) per kernel over the timed steps
+    su64 = tot["shift_updates"] - tot["shift_updates_fp32"]
+    su32 = tot["shift_updates_fp32"]
+    it64 = tot["seed_iters"] - tot["seed_iters_fp32"]
+    it32 = tot["seed_iters_fp32"]
+    # shift update: read and write x_j and p_j per active (shift, source, entry); seed r
+    # read once and seed p read and written once per (source, entry, iteration)
+    shift_bytes = (su64 * 64 + it64 * 48) * n + (su32 * 32 + it32 * 24) * n
+    # dslash: spinor in and out per (source, site) and the four forward links per site
+    dslash_bytes = (it64 * 48 * 8 + it32 * 48 * 4) * w.V
+    dslash_bytes += (link_launches[0] * 18 * 8 + link_launches[1] * w.link_reals * 4) * 4 * w.V
+    rep = {}
+    for name, idx, b in (("shift_update", 4, shift_bytes), ("dslash", 0, dslash_bytes)):
+        calls = int(stage_calls[idx])
+        if calls == 0 or stage_ms[idx] <= 0:
+            rep[name] = None
+            continue
+        avg_s = stage_ms[idx] / 1e3 / calls
+        per_launch = b / calls
+        ach = per_launch / avg_s / 1e9
+        rep[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(name, w.name),
+                     "kernel": name, "launches": calls, "avg_launch_us": round(avg_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": round(per_launch)}
+    dominant = "shift_update" if stage_ms[4] >= stage_ms[0] else "dslash"
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "shift-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == S.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": list(w.dims), "kappa": w.kappa, "eps": w.eps, "seed": w.seed,
+                   "interval": [w.gamma - w.rho, w.gamma + w.rho], "beta": w.beta, "N": w.N, "L": w.L,
+                   "M": w.M, "tol": w.tol, "prec": w.prec, "link_reals": w.link_reals,
+                   "method": args.method, "parallelism": "single GPU"},
+        "roofline": rep[dominant],
+        "dslash": rep["dslash"],
+        "site_shift_updates_per_s": round(value * w.V, 1),
+        "seed_iters_per_step": tot["seed_iters"] / args.steps / w.L,
+        "eigenpairs_found": int(out.n_found),
+        "stage_ms_per_step": {STAGES[i]: round(stage_ms[i] / args.steps, 3) for i in range(7)},
+        "phase_ms_per_step": {k: round(tot[k] * 1e3 / args.steps, 3) for k in ("t_solve", "t_moments", "t_extract")},
+        "timing": "per-launch HIP events" if not args.no_events else "graph replay",
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -148,6 +148,13 @@ typedef struct {
   int32_t iters;            /* max seed iterations over sources                     */
   int32_t solve_status;     /* status of the shifted-CG stage                       */
   double t_solve, t_moments, t_extract;  /* seconds                                 */
+  int64_t shift_updates;    /* (source, shift) vector updates summed over iterations */
+  int64_t matvecs;          /* applications of A to one vector (solve + extraction)  */
+  int64_t shift_updates_fp32; /* of shift_updates, those made in the FP32 phase       */
+  int64_t seed_iters;       /* seed iterations summed over sources                   */
+  int64_t seed_iters_fp32;  /* of seed_iters, those made in the FP32 phase           */
+  int32_t switch_iter;      /* iteration at which the FP32 phase began, -1 if never  */
+  int32_t pad;
 } sscg_ss_info;
 
 void sscg_default_ss_params(sscg_ss_params *p);

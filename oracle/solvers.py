@@ -141,7 +141,8 @@ def shifted_cg(A_mul, v: np.ndarray, z: np.ndarray, sigma: float, tol: float = 1
         pi_prev, pi_cur = pi_cur, pi_next
         alpha_prev, beta_prev, rho = alpha, beta, rho_next
         if record is not None:
-            record(k, dict(X=X, P=P, r=r, p=p, pi=pi_cur, alpha=alpha, beta=beta, rho=rho))
+            record(k, dict(X=X, P=P, r=r, p=p, pi=pi_cur, alpha=alpha, beta=beta, rho=rho,
+                           updated=act.size, active=active))
         if not active.any():
             status = "ok"
             k += 1

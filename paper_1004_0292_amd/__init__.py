@@ -51,7 +51,9 @@ class SSParams(C.Structure):
 class SSInfo(C.Structure):
     _fields_ = [("rank", C.c_int32), ("n_candidates", C.c_int32), ("iters", C.c_int32),
                 ("solve_status", C.c_int32), ("t_solve", C.c_double), ("t_moments", C.c_double),
-                ("t_extract", C.c_double)]
+                ("t_extract", C.c_double), ("shift_updates", C.c_int64), ("matvecs", C.c_int64),
+                ("shift_updates_fp32", C.c_int64), ("seed_iters", C.c_int64), ("seed_iters_fp32", C.c_int64),
+                ("switch_iter", C.c_int32), ("pad", C.c_int32)]
 
 
 EXPORTS = ["sscg_create", "sscg_destroy", "sscg_last_error", "sscg_global_error", "sscg_set_gauge",

@@ -16,6 +16,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -30,6 +31,13 @@ static constexpr int kEptHost = 2;  // entries per thread of the streaming kerne
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+};
+
+struct Tune {
+  int nr = 2;       // sources per dslash thread
+  int bs = 256;     // sites per dslash block
+  int wbatch = 8;   // shifts per block of the fused shift update
+  int xcd = 1;      // XCD-aware block order in the dslash
 };
 
 enum Stage { ST_DSLASH = 0, ST_ALPHA, ST_RUPD, ST_SCAL, ST_SHIFT, ST_RU, ST_LOOP, ST_N = 8 };
@@ -47,8 +55,11 @@ struct sscg_ctx {
   int link_reals = 18;
   bool have_gauge = false;
   std::string err;
-  // tunables (autotuned or set by the caller through the environment)
-  int nr = 2, wbatch = 8, xcd = 1;
+  // launch shapes: defaults, overridden by SSCG_NR / SSCG_BS / SSCG_WBATCH / SSCG_XCD,
+  // or chosen per problem shape by the autotuner (SSCG_AUTOTUNE=0 disables it)
+  Tune tune;
+  bool autotune = true;
+  std::map<std::string, Tune> tuned;
   // solver workspaces
   DevBuf v64, r64, p64, q64, W, r32, p32, q32, rbase, xpart64, xpart32, tmp, pq_part, rr_part, seed,
       shift, zdev, small, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, apply_in, apply_out;
@@ -138,11 +149,15 @@ int sscg_create(sscg_ctx **out, const int32_t dims[4], double kappa, double r, i
   c->V = (int)V;
   c->n = 12 * V;
   c->kappa = kappa;
-  c->nr = env_int("SSCG_NR", 2);
-  c->wbatch = env_int("SSCG_WBATCH", 8);
-  c->xcd = env_int("SSCG_XCD", 1);
-  if (c->nr != 1 && c->nr != 2 && c->nr != 4) c->nr = 2;
-  if (c->wbatch < 1) c->wbatch = 8;
+  c->tune.nr = env_int("SSCG_NR", 2);
+  c->tune.bs = env_int("SSCG_BS", 256);
+  c->tune.wbatch = env_int("SSCG_WBATCH", 8);
+  c->tune.xcd = env_int("SSCG_XCD", 1);
+  c->autotune = env_int("SSCG_AUTOTUNE", 1) != 0 && !getenv("SSCG_NR") && !getenv("SSCG_BS") &&
+                !getenv("SSCG_WBATCH") && !getenv("SSCG_XCD");
+  if (c->tune.nr != 1 && c->tune.nr != 2 && c->tune.nr != 4) c->tune.nr = 2;
+  if (c->tune.bs != 64 && c->tune.bs != 128 && c->tune.bs != 256) c->tune.bs = 256;
+  if (c->tune.wbatch < 1) c->tune.wbatch = 8;
   *out = c;
   return SSCG_OK;
 }
@@ -225,7 +240,7 @@ int sscg_stage_times(const sscg_ctx *c, double ms[8], int64_t calls[8]) {
 // ---------------------------------------------------------------------------
 // internal helpers
 
-static int nblk_site(const sscg_ctx *c) { return (c->V + kBlock - 1) / kBlock; }
+static int nblk_site(const sscg_ctx *c, int bs) { return (c->V + bs - 1) / bs; }
 static int nblk_vec(const sscg_ctx *c) { return (int)((c->n + kBlock * kEptHost - 1) / (kBlock * kEptHost)); }
 
 // FP64 dslash of nsrc planar vectors: out = A in (mode 0) or sigma in - A in (mode 1)
@@ -243,13 +258,13 @@ static void dslash_plain(sscg_ctx *c, const void *in, void *out, int nsrc, int p
   for (int i = 0; i < 4; ++i) j.dims[i] = c->dims[i];
   j.V = c->V;
   j.nsrc = nsrc;
-  j.nblk_site = nblk_site(c);
+  j.nblk_site = nblk_site(c, c->tune.bs);
   j.block_begin = 0;
-  j.nblocks = j.nblk_site * ((nsrc + c->nr - 1) / c->nr);
+  j.nblocks = j.nblk_site * ((nsrc + c->tune.nr - 1) / c->tune.nr);
   j.mode = mode;
   b.njobs = 1;
   b.total_blocks = j.nblocks;
-  launch_dslash(b, prec, c->nr, prec == 0 ? 18 : c->link_reals, c->xcd, st);
+  launch_dslash(b, prec, c->tune.nr, prec == 0 ? 18 : c->link_reals, c->tune.bs, c->tune.xcd, st);
 }
 
 static int host_sum_partials(sscg_ctx *c, const double *dev_partial, int nvec, int nblk, std::vector<double> &out,
@@ -285,6 +300,7 @@ struct Prob {
   double *true_res = nullptr;
   int32_t *iters = nullptr;
   int status = SSCG_OK;
+  int switch_iter = -1;   // iteration at which the FP32 phase began (output)
 };
 
 struct IterPlan {
@@ -293,15 +309,15 @@ struct IterPlan {
   VecBatch r64, r32, u64, u32, fold_seed, rel;
 };
 
-static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts &o) {
+static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts &o, const Tune &t) {
   memset(&pl, 0, sizeof(pl));
   int bd = 0, bdru = 0, bs = 0, bv = 0, bu = 0;
   const int np = (int)P.size();
   for (int i = 0; i < np; ++i) {
     sscg_ctx *c = P[i].c;
     const int L = P[i].L, N = P[i].N;
-    const int nbs = nblk_site(c), nbv = nblk_vec(c);
-    const int groups = (L + c->nr - 1) / c->nr;
+    const int nbs = nblk_site(c, t.bs), nbv = nblk_vec(c);
+    const int groups = (L + t.nr - 1) / t.nr;
     SeedState *seed = (SeedState *)c->seed.p;
     ShiftState *shift = (ShiftState *)c->shift.p;
     auto mk_d = [&](DslashJob &j, const void *in, void *out, const void *g, double *part, int begin) {
@@ -325,14 +341,14 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
     auto mk_v = [&](VecJob &j, void *a, void *b, void *cc, void *d, int begin, int nblocks) {
       j.a = a; j.b = b; j.c = cc; j.d = d; j.e = nullptr; j.partial = (double *)c->rr_part.p;
       j.seed = seed; j.shift = shift; j.n = c->n; j.nsrc = L; j.nshift = N; j.nblk_vec = nbv;
-      j.block_begin = begin; j.nblocks = nblocks; j.wbatch = c->wbatch;
+      j.block_begin = begin; j.nblocks = nblocks; j.wbatch = t.wbatch;
     };
     mk_v(pl.r64.job[i], c->r64.p, c->q64.p, nullptr, nullptr, bv, L * nbv);
     mk_v(pl.r32.job[i], c->r32.p, c->q32.p, c->xpart32.p, c->p32.p, bv, L * nbv);
     mk_v(pl.fold_seed.job[i], c->xpart64.p, c->xpart32.p, nullptr, nullptr, bv, L * nbv);
     mk_v(pl.rel.job[i], c->rbase.p, c->q64.p, c->r64.p, c->r32.p, bv, L * nbv);
     bv += L * nbv;
-    const int nbatch = (N + c->wbatch - 1) / c->wbatch;
+    const int nbatch = (N + t.wbatch - 1) / t.wbatch;
     mk_v(pl.u64.job[i], P[i].y, c->W.p, c->r64.p, c->p64.p, bu, L * nbatch * nbv);
     mk_v(pl.u32.job[i], P[i].y, c->W.p, c->r32.p, c->p32.p, bu, L * nbatch * nbv);
     bu += L * nbatch * nbv;
@@ -380,10 +396,10 @@ struct Recorder {
   }
 };
 
-static void launch_iteration(const IterPlan &pl, int prec, bool ru, int lr, int nr, int xcd, hipStream_t st,
+static void launch_iteration(const IterPlan &pl, int prec, bool ru, int lr, const Tune &t, hipStream_t st,
                              Recorder &rec) {
   rec.mark(ST_DSLASH);
-  launch_dslash(prec == 0 ? pl.d64 : pl.d32, prec, nr, prec == 0 ? 18 : lr, xcd, st);
+  launch_dslash(prec == 0 ? pl.d64 : pl.d32, prec, t.nr, prec == 0 ? 18 : lr, t.bs, t.xcd, st);
   rec.mark(ST_ALPHA);
   launch_seed_alpha(pl.alpha, st);
   rec.mark(ST_RUPD);
@@ -391,7 +407,7 @@ static void launch_iteration(const IterPlan &pl, int prec, bool ru, int lr, int 
   if (prec == 1 && ru) {
     rec.mark(ST_RU);
     launch_fold_seed(pl.fold_seed, st);
-    launch_dslash(pl.dru, 0, nr, 18, xcd, st);
+    launch_dslash(pl.dru, 0, t.nr, 18, t.bs, t.xcd, st);
     launch_reliable_residual(pl.rel, st);
   }
   rec.mark(ST_SCAL);
@@ -410,7 +426,7 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
   CHK(ensure(c, c->q64, L * vec64));
   CHK(ensure(c, c->W, L * N * vec64));
   CHK(ensure(c, c->tmp, vec64));
-  CHK(ensure(c, c->pq_part, L * nblk_site(c) * sizeof(double)));
+  CHK(ensure(c, c->pq_part, L * nblk_site(c, 64) * sizeof(double)));
   CHK(ensure(c, c->rr_part, std::max<size_t>(L * nblk_vec(c), L * 64) * sizeof(double)));
   CHK(ensure(c, c->seed, L * sizeof(SeedState)));
   CHK(ensure(c, c->shift, L * N * sizeof(ShiftState)));
@@ -435,11 +451,7 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
   launch_pack(p.v, c->v64.p, 0, (int)L, c->V, st);
   HIPCHK(c, hipMemcpyAsync(c->r64.p, c->v64.p, L * vec64, hipMemcpyDeviceToDevice, st));
   HIPCHK(c, hipMemcpyAsync(c->p64.p, c->v64.p, L * vec64, hipMemcpyDeviceToDevice, st));
-  for (size_t l = 0; l < L; ++l)
-    for (size_t j = 0; j < N; ++j)
-      HIPCHK(c, hipMemcpyAsync((char *)c->W.p + (l * N + j) * vec64, (char *)c->v64.p + l * vec64, vec64,
-                               hipMemcpyDeviceToDevice, st));
-  HIPCHK(c, hipMemsetAsync(p.y, 0, L * N * vec64, st));
+  launch_init_shifts(p.y, c->W.p, c->v64.p, (int64_t)n, (int)L, (int)N, st);
   // ||v||
   const int nb = 64;
   launch_norm2_partial(c->v64.p, c->n, (int)L, (double *)c->rr_part.p, nb, st);
@@ -493,6 +505,117 @@ static int switch_to_fp32(Prob &p, hipStream_t st) {
   return SSCG_OK;
 }
 
+// Launch-shape autotuner. Times the dslash over (sources per thread, sites per
+// block, XCD order) and the fused shift update over the shift-batch width on the
+// problem's own buffers, before the first iteration. The shift update is timed
+// as an identity (alpha_j = 0, beta_j = 1, 1/pi_j = 0 leaves x_j and p_j exactly
+// as they are, and the seed p = r + 0 p = v is unchanged at the start), after
+// which the initial solver state is uploaded again. Results are cached per shape.
+static std::string tune_key(const std::vector<Prob> &P, const sscg_solve_opts &o) {
+  std::string k = std::to_string(o.prec);
+  for (const Prob &p : P)
+    k += "|" + std::to_string(p.c->dims[0]) + "x" + std::to_string(p.c->dims[1]) + "x" +
+         std::to_string(p.c->dims[2]) + "x" + std::to_string(p.c->dims[3]) + ":" + std::to_string(p.L) + ":" +
+         std::to_string(p.N);
+  return k;
+}
+
+static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipStream_t st, Tune &best) {
+  sscg_ctx *c0 = P[0].c;
+  const std::string key = tune_key(P, o);
+  auto it = c0->tuned.find(key);
+  if (it != c0->tuned.end()) {
+    best = it->second;
+    return SSCG_OK;
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(c0, hipEventCreate(&e0));
+  HIPCHK(c0, hipEventCreate(&e1));
+  auto time_it = [&](auto &&launch, int reps) -> double {
+    launch();  // warm
+    hipEventRecord(e0, st);
+    for (int r = 0; r < reps; ++r) launch();
+    hipEventRecord(e1, st);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    return ms / reps;
+  };
+  int maxL = 1, maxN = 1;
+  for (Prob &p : P) {
+    maxL = std::max(maxL, p.L);
+    maxN = std::max(maxN, p.N);
+  }
+  // dslash on the FP64 seed buffers (p -> q); its partials are rewritten by the first iteration
+  double tbest = 1e300;
+  Tune cand = best;
+  for (int nr : {1, 2, 4}) {
+    if (nr > 1 && nr > maxL) continue;
+    for (int bs : {64, 128, 256})
+      for (int xcd : {0, 1}) {
+        cand.nr = nr;
+        cand.bs = bs;
+        cand.xcd = xcd;
+        IterPlan pl;
+        build_plan(P, pl, o, cand);
+        const double t = time_it([&] { launch_dslash(pl.d64, 0, nr, 18, bs, xcd, st); }, 5);
+        if (t < tbest) {
+          tbest = t;
+          best.nr = nr;
+          best.bs = bs;
+          best.xcd = xcd;
+        }
+      }
+  }
+  // fused shift update as an identity on the current data
+  for (Prob &p : P) {
+    std::vector<ShiftState> sh((size_t)p.L * p.N);
+    HIPCHK(p.c, hipMemcpy(sh.data(), p.c->shift.p, sh.size() * sizeof(ShiftState), hipMemcpyDeviceToHost));
+    for (ShiftState &h : sh) {
+      h.upd = 1;
+      h.a = make_double2(0.0, 0.0);
+      h.b = make_double2(1.0, 0.0);
+      h.ipi = make_double2(0.0, 0.0);
+    }
+    HIPCHK(p.c, hipMemcpy(p.c->shift.p, sh.data(), sh.size() * sizeof(ShiftState), hipMemcpyHostToDevice));
+    std::vector<SeedState> sd(p.L);
+    HIPCHK(p.c, hipMemcpy(sd.data(), p.c->seed.p, sd.size() * sizeof(SeedState), hipMemcpyDeviceToHost));
+    for (SeedState &x : sd) x.pending = 1;
+    HIPCHK(p.c, hipMemcpy(p.c->seed.p, sd.data(), sd.size() * sizeof(SeedState), hipMemcpyHostToDevice));
+  }
+  tbest = 1e300;
+  cand = best;
+  for (int w : {2, 4, 8, 16, 32}) {
+    if (w > 2 && w / 2 >= maxN) continue;
+    cand.wbatch = w;
+    IterPlan pl;
+    build_plan(P, pl, o, cand);
+    const double t = time_it([&] { launch_shift_update(pl.u64, 0, 0, st); }, 3);
+    if (t < tbest) {
+      tbest = t;
+      best.wbatch = w;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  // restore the initial state
+  for (Prob &p : P) {
+    std::vector<ShiftState> sh((size_t)p.L * p.N);
+    HIPCHK(p.c, hipMemcpy(sh.data(), p.c->shift.p, sh.size() * sizeof(ShiftState), hipMemcpyDeviceToHost));
+    for (ShiftState &h : sh) {
+      h.upd = 0;
+      h.a = h.b = h.ipi = make_double2(0.0, 0.0);
+    }
+    HIPCHK(p.c, hipMemcpy(p.c->shift.p, sh.data(), sh.size() * sizeof(ShiftState), hipMemcpyHostToDevice));
+    std::vector<SeedState> sd(p.L);
+    HIPCHK(p.c, hipMemcpy(sd.data(), p.c->seed.p, sd.size() * sizeof(SeedState), hipMemcpyDeviceToHost));
+    for (SeedState &x : sd) x.pending = 0;
+    HIPCHK(p.c, hipMemcpy(p.c->seed.p, sd.data(), sd.size() * sizeof(SeedState), hipMemcpyHostToDevice));
+  }
+  c0->tuned[key] = best;
+  return SSCG_OK;
+}
+
 static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   sscg_solve_opts o = o_in;
   if (o.poll_every < 1) o.poll_every = 1;
@@ -514,13 +637,16 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       HIPCHK(c0, hipStreamWaitEvent(st, p.c->ev_sync, 0));
     }
   }
-  IterPlan pl;
-  build_plan(P, pl, o);
-  const int nr = c0->nr, xcd = c0->xcd;
   int lr = 18;
   for (Prob &p : P) lr = std::min(lr, p.c->link_reals);
   for (Prob &p : P)
     if (p.c->link_reals != lr) return fail(c0, SSCG_EINVAL, "all problems of a batch must use one link format");
+  Tune tn = c0->tune;
+  if (c0->autotune) {
+    CHK(autotune(P, o, lr, st, tn));
+  }
+  IterPlan pl;
+  build_plan(P, pl, o, tn);
   for (int i = 0; i < ST_N; ++i) {
     c0->stage_ms[i] = 0.0;
     c0->stage_calls[i] = 0;
@@ -534,7 +660,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     Recorder off{c0, st, false, {}};
     HIPCHK(c0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < len; ++k)
-      launch_iteration(pl, prec, prec == 1 && k == len - 1, lr, nr, xcd, st, off);
+      launch_iteration(pl, prec, prec == 1 && k == len - 1, lr, tn, st, off);
     HIPCHK(c0, hipStreamEndCapture(st, &g));
     HIPCHK(c0, hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
     HIPCHK(c0, hipGraphDestroy(g));
@@ -562,7 +688,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       }
     } else {
       for (int kk = 0; kk < chunk; ++kk)
-        launch_iteration(pl, prec, prec == 1 && (kk == chunk - 1) && full, lr, nr, xcd, st, rec);
+        launch_iteration(pl, prec, prec == 1 && (kk == chunk - 1) && full, lr, tn, st, rec);
     }
     k += chunk;
     // poll
@@ -598,6 +724,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       }
       if (rc != SSCG_OK) break;
       prec = 1;
+      for (Prob &p : P) p.switch_iter = k;
     }
   }
   for (auto &g : gexec)
@@ -961,8 +1088,9 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   P[0].z = zd;
   P[0].y = c->Ybuf.p;
   P[0].keep_planar = true;
-  std::vector<int32_t> iters(L);
+  std::vector<int32_t> iters(L), conv((size_t)L * N);
   P[0].iters = iters.data();
+  P[0].conv_iter = conv.data();
   auto t0 = std::chrono::steady_clock::now();
   int rc = run_solve(P, p->solve);
   if (rc != SSCG_OK && rc != SSCG_ENOTCONV) return rc;
@@ -1161,6 +1289,30 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
     info->t_solve = std::chrono::duration<double>(t1 - t0).count();
     info->t_moments = std::chrono::duration<double>(t2 - t1).count();
     info->t_extract = std::chrono::duration<double>(t3 - t2).count();
+    int64_t su = 0, mv = 0;
+    for (int l = 0; l < L; ++l) {
+      mv += iters[l];
+      for (int j = 0; j < N; ++j) {
+        const int ci = conv[(size_t)l * N + j];
+        su += ci >= 0 ? ci : iters[l];
+      }
+    }
+    info->shift_updates = su;
+    info->matvecs = mv + r;  // seed products plus A Q (Rayleigh-Ritz) or A X (Hankel)
+    const int ks = P[0].switch_iter;
+    int64_t su32 = 0, it32 = 0;
+    if (ks >= 0)
+      for (int l = 0; l < L; ++l) {
+        it32 += std::max(0, iters[l] - ks);
+        for (int j = 0; j < N; ++j) {
+          const int ci = conv[(size_t)l * N + j];
+          su32 += std::max(0, (ci >= 0 ? ci : iters[l]) - ks);
+        }
+      }
+    info->shift_updates_fp32 = su32;
+    info->seed_iters = mv;
+    info->seed_iters_fp32 = it32;
+    info->switch_iter = ks;
   }
   HIPCHK(c, hipStreamSynchronize(st));
   return rc == SSCG_ENOTCONV ? SSCG_ENOTCONV : SSCG_OK;

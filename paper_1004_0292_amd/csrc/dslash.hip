@@ -171,10 +171,10 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return t;  // valid in thread 0
 }
 
-template <typename T, int NR, int LR>
-__global__ __launch_bounds__(kBlock) void dslash_kernel(DslashBatch B, int xcd_remap) {
+template <typename T, int NR, int LR, int BS>
+__global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap) {
   using C = V2<T>;
-  __shared__ double red[kBlock / 64];
+  __shared__ double red[BS / 64];
   int b = blockIdx.x;
   if (xcd_remap) b = xcd_remap_block(b, gridDim.x);
   int begins[kMaxJobs];
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void dslash_kernel(DslashBatch B, int xcd_r
     if (all_done) return;
   }
   const int V = J.V;
-  const int s = sblk * kBlock + threadIdx.x;
+  const int s = sblk * BS + threadIdx.x;
   const bool valid = s < V;
   const V2<T> *in = reinterpret_cast<const V2<T> *>(J.in) + (size_t)l0 * 12 * V;
   V2<T> *out = reinterpret_cast<V2<T> *>(J.out) + (size_t)l0 * 12 * V;
@@ -253,32 +253,34 @@ __global__ __launch_bounds__(kBlock) void dslash_kernel(DslashBatch B, int xcd_r
   if (J.partial) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const double tot = block_sum<kBlock / 64>(dot[r], red);
+      const double tot = block_sum<BS / 64>(dot[r], red);
       if (threadIdx.x == 0 && r < nvalid) J.partial[(size_t)(l0 + r) * J.nblk_site + sblk] = tot;
     }
   }
 }
 
 template <typename T, int NR, int LR>
-static void launch_t(const DslashBatch &b, int xcd, hipStream_t st) {
-  hipLaunchKernelGGL((dslash_kernel<T, NR, LR>), dim3(b.total_blocks), dim3(kBlock), 0, st, b, xcd);
+static void launch_t(const DslashBatch &b, int bs, int xcd, hipStream_t st) {
+  if (bs == 64)
+    hipLaunchKernelGGL((dslash_kernel<T, NR, LR, 64>), dim3(b.total_blocks), dim3(64), 0, st, b, xcd);
+  else if (bs == 128)
+    hipLaunchKernelGGL((dslash_kernel<T, NR, LR, 128>), dim3(b.total_blocks), dim3(128), 0, st, b, xcd);
+  else
+    hipLaunchKernelGGL((dslash_kernel<T, NR, LR, 256>), dim3(b.total_blocks), dim3(256), 0, st, b, xcd);
 }
 
-void launch_dslash(const DslashBatch &b, int prec, int nr, int lr, int xcd, hipStream_t st) {
+template <typename T, int LR>
+static void launch_nr(const DslashBatch &b, int nr, int bs, int xcd, hipStream_t st) {
+  if (nr == 1) launch_t<T, 1, LR>(b, bs, xcd, st);
+  else if (nr == 2) launch_t<T, 2, LR>(b, bs, xcd, st);
+  else launch_t<T, 4, LR>(b, bs, xcd, st);
+}
+
+void launch_dslash(const DslashBatch &b, int prec, int nr, int lr, int bs, int xcd, hipStream_t st) {
   if (b.total_blocks <= 0) return;
-  if (prec == 0) {
-    if (nr == 1) launch_t<double, 1, 18>(b, xcd, st);
-    else if (nr == 2) launch_t<double, 2, 18>(b, xcd, st);
-    else launch_t<double, 4, 18>(b, xcd, st);
-  } else if (lr == 18) {
-    if (nr == 1) launch_t<float, 1, 18>(b, xcd, st);
-    else if (nr == 2) launch_t<float, 2, 18>(b, xcd, st);
-    else launch_t<float, 4, 18>(b, xcd, st);
-  } else {
-    if (nr == 1) launch_t<float, 1, 12>(b, xcd, st);
-    else if (nr == 2) launch_t<float, 2, 12>(b, xcd, st);
-    else launch_t<float, 4, 12>(b, xcd, st);
-  }
+  if (prec == 0) launch_nr<double, 18>(b, nr, bs, xcd, st);
+  else if (lr == 18) launch_nr<float, 18>(b, nr, bs, xcd, st);
+  else launch_nr<float, 12>(b, nr, bs, xcd, st);
 }
 
 }  // namespace sscg

@@ -123,7 +123,9 @@ __device__ __forceinline__ int find_job(const int32_t *begins, int njobs, int b)
 
 // ---- launchers (defined in the .hip files) ---------------------------------
 // dslash.hip
-void launch_dslash(const DslashBatch &b, int prec /*0 fp64, 1 fp32*/, int nr, int lr,
+// nr: sources per thread (1, 2, 4); bs: sites per block (64, 128, 256); each
+// job's nblk_site must be ceil(V / bs).
+void launch_dslash(const DslashBatch &b, int prec /*0 fp64, 1 fp32*/, int nr, int lr, int bs,
                    int xcd_remap, hipStream_t st);
 // vec.hip
 void launch_seed_alpha(const ScalarBatch &b, hipStream_t st);
@@ -133,6 +135,7 @@ void launch_shift_update(const VecBatch &b, int prec, int fold, hipStream_t st);
 void launch_reliable_residual(const VecBatch &b, hipStream_t st);
 void launch_fold_seed(const VecBatch &b, hipStream_t st);
 void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st);
+void launch_init_shifts(void *y, void *W, const void *v, int64_t n, int nsrc, int nshift, hipStream_t st);
 void launch_moments_strided(const void *y, int nsrc, int nshift, const double *c_dev, int nmom, void *s,
                             int64_t n, int64_t sl, int64_t sk, hipStream_t st);
 void launch_to_fp32(const void *src64, void *dst32, void *zero32, int64_t n, hipStream_t st);

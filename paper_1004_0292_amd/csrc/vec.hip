@@ -359,6 +359,16 @@ __global__ __launch_bounds__(kBlock) void fold_seed_kernel(VecBatch B) {
   }
 }
 
+// Start of a solve: p_j = v_l and x_j = 0 for every (source, shift) slot.
+__global__ void init_shifts_kernel(double2 *y, double2 *W, const double2 *v, int64_t n, int nshift) {
+  const size_t slot = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t l = slot / nshift;
+  W[slot * n + i] = v[l * n + i];
+  y[slot * n + i] = make_double2(0.0, 0.0);
+}
+
 // End of an FP32 phase: x_j += x_part_j, x_part_j = 0 for every (source, shift)
 // slot; the FP32 partial is the upper half of the slot's workspace.
 __global__ void fold_shifts_kernel(double2 *y, double2 *W, int64_t n) {
@@ -518,6 +528,11 @@ void launch_to_fp32(const void *src64, void *dst32, void *zero32, int64_t n, hip
   if (n <= 0) return;
   hipLaunchKernelGGL(to_fp32_kernel, dim3(nblocks1d(n)), dim3(kBlock), 0, st,
                      (const double2 *)src64, (float2 *)dst32, (float2 *)zero32, n);
+}
+void launch_init_shifts(void *y, void *W, const void *v, int64_t n, int nsrc, int nshift, hipStream_t st) {
+  if (n <= 0 || nsrc * nshift <= 0) return;
+  hipLaunchKernelGGL(init_shifts_kernel, dim3(nblocks1d(n), nsrc * nshift), dim3(kBlock), 0, st, (double2 *)y,
+                     (double2 *)W, (const double2 *)v, n, nshift);
 }
 void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st) {
   if (n <= 0 || nslots <= 0) return;

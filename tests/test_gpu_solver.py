@@ -1,0 +1,182 @@
+"""GPU shifted-CG behaviour: determinism, launch shapes, mixed precision, batching,
+several sources, and the failure paths forced from the host.
+
+Bars:
+  * results must not depend on how often the host polls, on graph replay or on
+    the launch shapes chosen by the autotuner: bitwise equal (reductions are
+    two-stage with a fixed order; launch shapes only change which thread adds
+    which entry when the block size changes, so across block sizes the bar is
+    1e-13 relative);
+  * mixed precision: every shift's FP64 true residual <= 1e-10 (tolerance 1e-12
+    on the implicit residual, FP32 arithmetic after the switch at 1e-6; the
+    residual gap is bounded by ~eps_32 * switch_tol * cond) and the solution
+    within 1e-9 of the FP64 oracle's;
+  * a batched solve equals the single-problem solves of its members to 1e-13
+    (the batch may be tuned to other launch shapes than each member alone).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import quadrature as quad
+from oracle import solvers, wilson
+from tests.helpers import case, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+CFG1 = synth.CONFIGS["wilson4_fp64"]
+
+
+@pytest.fixture(scope="module")
+def prob():
+    U = CFG1.gauge()
+    A = wilson.hermitian_wilson(U, CFG1.dims, CFG1.kappa)
+    V = synth.sources(CFG1.V, 3, 21).reshape(3, -1)
+    z, _ = quad.line_nodes(CFG1.N, CFG1.gamma, CFG1.rho, CFG1.beta)
+    return U, A, V, z
+
+
+def solve(S, U, V, z, sigma=0.0, dims=CFG1.dims, kappa=CFG1.kappa, link_reals=18, **opts):
+    c = S.Context(dims, kappa)
+    c.set_gauge(U, link_reals)
+    L = V.shape[0]
+    y = to_dev(np.zeros((L, len(z), V.shape[1])))
+    r = c.shifted_cg_solve(to_dev(V), z, sigma, y, S.default_opts(**opts))
+    return to_host(y), r
+
+
+def test_poll_and_graph_do_not_change_results(sscg, prob):
+    case("determinism poll/graph")
+    U, A, V, z = prob
+    y0, r0 = solve(sscg, U, V, z, poll_every=50, use_graph=1)
+    y1, r1 = solve(sscg, U, V, z, poll_every=7, use_graph=0)
+    y2, r2 = solve(sscg, U, V, z, poll_every=1000, use_graph=1)
+    assert np.array_equal(y0, y1) and np.array_equal(y0, y2)
+    assert np.array_equal(r0.conv_iter, r1.conv_iter) and np.array_equal(r0.iters, r2.iters)
+
+
+@pytest.mark.parametrize("env", [dict(SSCG_NR="1", SSCG_BS="64", SSCG_WBATCH="3", SSCG_XCD="0"),
+                                 dict(SSCG_NR="4", SSCG_BS="128", SSCG_WBATCH="16", SSCG_XCD="1"),
+                                 dict(SSCG_NR="2", SSCG_BS="256", SSCG_WBATCH="1", SSCG_XCD="1")])
+def test_launch_shapes_agree(sscg, prob, monkeypatch, env):
+    case(f"launch shapes {env}")
+    U, A, V, z = prob
+    y_ref, r_ref = solve(sscg, U, V, z)
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    y, r = solve(sscg, U, V, z)
+    assert rel(y, y_ref) < 1e-13
+    assert np.all(np.abs(r.conv_iter - r_ref.conv_iter) <= 1)
+
+
+def test_several_sources_and_seed_shift(sscg, prob):
+    case("3 sources, seed 0.07")
+    U, A, V, z = prob
+    y, r = solve(sscg, U, V, z, sigma=0.07)
+    assert r.status == sscg.OK
+    for l in range(3):
+        ref = solvers.shifted_cg(lambda x: A @ x, V[l], z, 0.07, 1e-12)
+        assert rel(y[l], ref.Y) < 1e-9
+        assert np.all(np.abs(r.conv_iter[l] - ref.conv_iter) <= 1)
+        assert r.iters[l] == pytest.approx(ref.iters, abs=1)
+    assert r.true_res.max() < 5e-12
+
+
+@pytest.mark.parametrize("link_reals", [18, 12])
+def test_mixed_precision_accuracy(sscg, prob, link_reals):
+    case(f"mixed precision link_reals={link_reals}")
+    U, A, V, z = prob
+    y64, r64 = solve(sscg, U, V, z)
+    y, r = solve(sscg, U, V, z, prec=sscg.MIXED, ru_interval=20, switch_tol=1e-6, link_reals=link_reals)
+    assert r.status == sscg.OK
+    assert r.true_res.max() < 1e-10
+    for l in range(3):
+        tr = solvers.true_residuals(lambda x: A @ x, V[l], z, y[l])
+        assert tr.max() < 1e-10
+    assert rel(y, y64) < 1e-9
+
+
+def test_mixed_precision_with_early_switch(sscg, prob):
+    """Switch to FP32 right away: reliable updates keep the seed residual honest, but the
+    shifted solutions carry the FP32 rounding of the early, large updates (stated bound)."""
+    case("mixed precision switch_tol=1")
+    U, A, V, z = prob
+    y, r = solve(sscg, U, V, z, prec=sscg.MIXED, ru_interval=10, switch_tol=1.0)
+    assert r.status == sscg.OK
+    assert r.true_res.max() < 1e-4
+
+
+def test_batch_equals_single(sscg):
+    case("batched uneven problems")
+    shapes = [((4, 4, 4, 4), 0.12, 16, 2), ((6, 4, 4, 4), 0.125, 12, 1), ((4, 4, 6, 6), 0.13, 8, 3)]
+    ctxs, vs, zs, ys, singles = [], [], [], [], []
+    for i, (dims, kappa, N, L) in enumerate(shapes):
+        U = synth.gauge_field(dims, 0.5, 30 + i)
+        Vh = synth.sources(int(np.prod(dims)), L, 40 + i).reshape(L, -1)
+        z, _ = quad.line_nodes(N, 0.0, 0.2, 0.25)
+        ys_single, r_single = solve(sscg, U, Vh, z, dims=dims, kappa=kappa)
+        singles.append((ys_single, r_single))
+        c = sscg.Context(dims, kappa)
+        c.set_gauge(U)
+        ctxs.append(c)
+        vs.append(to_dev(Vh))
+        zs.append(z)
+        ys.append(to_dev(np.zeros((L, N, Vh.shape[1]))))
+    res = sscg.batch_solve(ctxs, vs, zs, [0.0] * 3, ys)
+    for (ys_single, r_single), y, r in zip(singles, ys, res):
+        assert r.status == sscg.OK
+        assert rel(to_host(y), ys_single) < 1e-13
+        assert np.all(np.abs(r.iters - r_single.iters) <= 1)
+        assert np.all(np.abs(r.conv_iter - r_single.conv_iter) <= 1)
+        assert r.true_res.max() < 5e-12
+
+
+def test_zero_and_nan_sources_rejected(sscg, prob):
+    case("zero / NaN source")
+    U, A, V, z = prob
+    c = sscg.Context(CFG1.dims, CFG1.kappa)
+    c.set_gauge(U)
+    y = to_dev(np.zeros((1, len(z), CFG1.n)))
+    for bad in (np.zeros((1, CFG1.n)), np.full((1, CFG1.n), np.nan)):
+        with pytest.raises(sscg.SSCGError) as e:
+            c.shifted_cg_solve(to_dev(bad.astype(complex)), z, 0.0, y)
+        assert e.value.code == sscg.EINVAL
+
+
+def test_no_gauge_is_a_state_error(sscg, prob):
+    case("no gauge")
+    U, A, V, z = prob
+    c = sscg.Context(CFG1.dims, CFG1.kappa)
+    y = to_dev(np.zeros((1, len(z), CFG1.n)))
+    with pytest.raises(sscg.SSCGError) as e:
+        c.shifted_cg_solve(to_dev(V[:1]), z, 0.0, y)
+    assert e.value.code == sscg.ESTATE
+
+
+def test_maxiter_not_converged(sscg, prob):
+    case("maxiter=1")
+    U, A, V, z = prob
+    y, r = solve(sscg, U, V[:1], z, maxiter=1)
+    assert r.status == sscg.ENOTCONV
+    assert np.all(r.conv_iter == -1) and r.iters[0] == 1
+
+
+def test_breakdown_detected(sscg):
+    case("breakdown B v = 0")
+    dims, kappa = (4, 4, 4, 4), 0.125
+    v = np.zeros((1, 256, 4, 3), dtype=complex)
+    v[0, :, 0, 0] = 1.0
+    y, r = solve(sscg, synth.unit_gauge(dims), v.reshape(1, -1), np.array([0.01j]), dims=dims, kappa=kappa)
+    assert r.status == sscg.EBREAKDOWN
+    assert r.iters[0] == 0
+
+
+def test_shift_on_eigenvalue_only_that_shift_fails(sscg):
+    case("shift on an eigenvalue")
+    dims, kappa = (4, 4, 4, 4), 0.12
+    v = synth.sources(256, 1, 7).reshape(1, -1)
+    z = np.array([0.04 + 0j, 0.04 + 0.05j, -0.1 + 0.05j])
+    y, r = solve(sscg, synth.unit_gauge(dims), v, z, dims=dims, kappa=kappa, maxiter=300)
+    assert r.status == sscg.ENOTCONV
+    assert r.conv_iter[0, 0] == -1 and r.conv_iter[0, 1] > 0 and r.conv_iter[0, 2] > 0
+    assert r.true_res[0, 1] < 5e-12 and r.true_res[0, 2] < 5e-12
