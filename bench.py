@@ -99,6 +99,25 @@ def cpu_baseline(w, budget_s=20.0):
             "host_cpus": os.cpu_count()}
 
 
+def copy_bandwidth(nbytes=2 << 30, reps=5):
+    """Device-to-device copy rate (read + write bytes per second) as the achievable
+    HBM reference next to the 8 TB/s peak."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,7 +126,7 @@ def main():
     ap.add_argument("--config", default=DEFAULT_CONFIG)
     ap.add_argument("--method", default="rr", choices=["rr", "hankel"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-events", action="store_true", help="time without per-launch events (graph replay)")
+    ap.add_argument("--no-events", action="store_true", help="time without per-launch events")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy five times (for counter scaling) and exit")
     args = ap.parse_args()
@@ -143,7 +162,7 @@ def main():
     params = S.default_ss_params(gamma=w.gamma, rho=w.rho, beta=w.beta, N=w.N, M=w.M,
                                  method=S.RR if args.method == "rr" else S.HANKEL, rank_tol=1e-7,
                                  spur_tol=1e-6, solve=opts)
-    max_eigs = w.M * w.L
+    max_eigs = min(w.M * w.L, 32)
     ctx.set_profiling(not args.no_events)
     for _ in range(args.warmup):
         ctx.ss_eigs(params, vd, max_eigs=max_eigs)
@@ -169,6 +188,17 @@ def main():
     elapsed = t1 - t0
     n = w.n
     value = tot["shift_updates"] / elapsed
+    graph_value = None
+    if not args.no_events:
+        # the same steps again with graph replay and no per-launch events (context only)
+        ctx.set_profiling(False)
+        su = 0
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(args.steps):
+            su += ctx.ss_eigs(params, vd, max_eigs=max_eigs).info.shift_updates
+        torch.cuda.synchronize()
+        graph_value = su / (time.perf_counter() - g0)
 
     # algorithmic bytes (compulsory traffic) per kernel over the timed steps
     su64 = tot["shift_updates"] - tot["shift_updates_fp32"]
@@ -219,8 +249,10 @@ def main():
         "eigenpairs_found": int(out.n_found),
         "stage_ms_per_step": {STAGES[i]: round(stage_ms[i] / args.steps, 3) for i in range(7)},
         "phase_ms_per_step": {k: round(tot[k] * 1e3 / args.steps, 3) for k in ("t_solve", "t_moments", "t_extract")},
-        "timing": "per-launch HIP events" if not args.no_events else "graph replay",
+        "timing": ("direct launches with HIP events around every launch" if not args.no_events else "graph replay"),
+        "value_graph_replay": round(graph_value, 1) if graph_value else None,
     }
+    line["copy_bw_GBs"] = copy_bandwidth()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

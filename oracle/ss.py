@@ -96,6 +96,21 @@ def accept(lam, res, lo: float, hi: float, imag_max: float, spur_tol: float):
     return idx[np.argsort(lam.real[idx])]
 
 
+def lowest_magnitude_eigs(A, k: int, tol: float = 1e-12):
+    """The k eigenvalues of A of smallest magnitude with unit eigenvectors (plain
+    definition of the reference spectrum on lattices too large for a dense eigh):
+    Lanczos (scipy eigsh) for the smallest eigenvalues of A^2, signs and values from
+    the Rayleigh quotients. Returns (lam ascending, X [n][k])."""
+    import scipy.sparse.linalg as sla
+    op = sla.LinearOperator(A.shape, matvec=lambda x: A @ (A @ x), dtype=np.complex128)
+    _, vecs = sla.eigsh(op, k=k, which="SA", tol=tol, ncv=max(4 * k, 40))
+    # the eigenspaces of A^2 mix +-lambda pairs only if both signs occur with equal
+    # magnitude; a Rayleigh-Ritz step on the k-dimensional space separates them
+    Q, _ = np.linalg.qr(vecs)
+    lam, W = np.linalg.eigh(Q.conj().T @ (A @ Q))
+    return lam, Q @ W
+
+
 def ss_eigs(A, Vsrc: np.ndarray, gamma: float, rho: float, beta: float, N: int, M: int,
             tol: float = 1e-12, method: str = "rr", path: str = "lines", Nprime: int | None = None,
             rank_tol: float = 1e-10, spur_tol: float = 1e-6, maxiter: int = 100000):

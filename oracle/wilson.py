@@ -122,3 +122,32 @@ def free_field_spectrum(dims, kappa: float, r: float = 1.0) -> np.ndarray:
 def to_vec(psi: np.ndarray) -> np.ndarray:
     """Canonical spinor array [..., V, 4, 3] -> flat vectors [..., 12V]."""
     return psi.reshape(psi.shape[:-3] + (-1,))
+
+
+def apply_rows(U: np.ndarray, dims, kappa: float, x: np.ndarray, sites, r: float = 1.0) -> np.ndarray:
+    """(A x) restricted to the 12 rows of each listed site, from the definition.
+
+    For lattices where the explicit matrix is too large: every listed site sums its
+    own term and its eight hops, each as the Kronecker product of the 4x4 spin
+    factor and the 3x3 link (the same blocks as hermitian_wilson). x: [12V] or
+    [V][4][3]. Returns [len(sites)][12].
+    """
+    g = gamma_matrices()
+    g5 = g[4]
+    I4 = np.eye(4)
+    xv = np.asarray(x).reshape(-1, 12)
+    sites = np.asarray(sites, dtype=np.int64)
+    c = coords(dims)[sites]
+    out = np.einsum("ab,sb->sa", np.kron(g5, np.eye(3)), xv[sites])
+    for mu in range(4):
+        cf = c.copy()
+        cf[:, mu] = (cf[:, mu] + 1) % dims[mu]
+        cb = c.copy()
+        cb[:, mu] = (cb[:, mu] - 1) % dims[mu]
+        fwd, bwd = site_index(cf, dims), site_index(cb, dims)
+        Pf = -kappa * (g5 @ (r * I4 - g[mu]))
+        Pb = -kappa * (g5 @ (r * I4 + g[mu]))
+        for k in range(len(sites)):
+            out[k] += np.kron(Pf, U[mu, sites[k]]) @ xv[fwd[k]]
+            out[k] += np.kron(Pb, adjoint(U[mu, bwd[k]])) @ xv[bwd[k]]
+    return out

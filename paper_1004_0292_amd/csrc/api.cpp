@@ -38,6 +38,8 @@ struct Tune {
   int bs = 256;     // sites per dslash block
   int wbatch = 8;   // shifts per block of the fused shift update
   int xcd = 1;      // XCD-aware block order in the dslash
+  int unroll = 2;   // shifts whose loads a shift-update thread issues together
+  int nt = 0;       // non-temporal access to the shift vectors
 };
 
 enum Stage { ST_DSLASH = 0, ST_ALPHA, ST_RUPD, ST_SCAL, ST_SHIFT, ST_RU, ST_LOOP, ST_N = 8 };
@@ -153,8 +155,10 @@ int sscg_create(sscg_ctx **out, const int32_t dims[4], double kappa, double r, i
   c->tune.bs = env_int("SSCG_BS", 256);
   c->tune.wbatch = env_int("SSCG_WBATCH", 8);
   c->tune.xcd = env_int("SSCG_XCD", 1);
+  c->tune.unroll = env_int("SSCG_UNROLL", 2);
+  c->tune.nt = env_int("SSCG_NT", 0);
   c->autotune = env_int("SSCG_AUTOTUNE", 1) != 0 && !getenv("SSCG_NR") && !getenv("SSCG_BS") &&
-                !getenv("SSCG_WBATCH") && !getenv("SSCG_XCD");
+                !getenv("SSCG_WBATCH") && !getenv("SSCG_XCD") && !getenv("SSCG_UNROLL") && !getenv("SSCG_NT");
   if (c->tune.nr != 1 && c->tune.nr != 2 && c->tune.nr != 4) c->tune.nr = 2;
   if (c->tune.bs != 64 && c->tune.bs != 128 && c->tune.bs != 256) c->tune.bs = 256;
   if (c->tune.wbatch < 1) c->tune.wbatch = 8;
@@ -335,7 +339,7 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
       j.seed = seed; j.shift = shift; j.partial = part; j.nblk = nblk; j.nsrc = L; j.nshift = N;
       j.maxiter = o.maxiter; j.block_begin = bs; j.tol = o.tol;
     };
-    mk_s(pl.alpha.job[i], (double *)c->pq_part.p, nbs);
+    mk_s(pl.alpha.job[i], (double *)c->pq_part.p, (c->V + 63) / 64);
     mk_s(pl.scal.job[i], (double *)c->rr_part.p, nbv);
     bs += L;
     auto mk_v = [&](VecJob &j, void *a, void *b, void *cc, void *d, int begin, int nblocks) {
@@ -366,6 +370,10 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
   pl.u64.total_blocks = pl.u32.total_blocks = bu;
 }
 
+// Per-stage timing with HIP events on the solver stream: an event is recorded
+// before each stage launch and the intervals are read at the next poll. Timing
+// runs use direct launches (event records inside captured graphs are not read
+// back reliably on this runtime).
 struct Recorder {
   sscg_ctx *c;
   hipStream_t st;
@@ -379,19 +387,27 @@ struct Recorder {
       hipEventCreate(&e);
       c->events.push_back(e);
     }
-    hipEventRecord(c->events[k], st);
+    if (hipEventRecord(c->events[k], st) != hipSuccess) {
+      on = false;  // timing is best effort; never leave a sticky error behind
+      (void)hipGetLastError();
+      return;
+    }
     stages.push_back(stage);
+  }
+  // intervals between consecutive recorded events (all complete) -> stage totals
+  void account(const std::vector<int> &stg) {
+    for (size_t k = 0; k + 1 < stg.size(); ++k) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, c->events[k], c->events[k + 1]);
+      c->stage_ms[stg[k]] += ms;
+      c->stage_calls[stg[k]] += 1;
+    }
   }
   void flush() {
     if (!on || stages.empty()) return;
     mark(-1);
     hipEventSynchronize(c->events[stages.size() - 1]);
-    for (size_t k = 0; k + 1 < stages.size(); ++k) {
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, c->events[k], c->events[k + 1]);
-      c->stage_ms[stages[k]] += ms;
-      c->stage_calls[stages[k]] += 1;
-    }
+    account(stages);
     stages.clear();
   }
 };
@@ -413,7 +429,7 @@ static void launch_iteration(const IterPlan &pl, int prec, bool ru, int lr, cons
   rec.mark(ST_SCAL);
   launch_shift_scalars(pl.scal, st);
   rec.mark(ST_SHIFT);
-  launch_shift_update(prec == 0 ? pl.u64 : pl.u32, prec, prec == 1 && ru, st);
+  launch_shift_update(prec == 0 ? pl.u64 : pl.u32, prec, prec == 1 && ru, t.unroll, t.nt, st);
 }
 
 static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
@@ -426,7 +442,7 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
   CHK(ensure(c, c->q64, L * vec64));
   CHK(ensure(c, c->W, L * N * vec64));
   CHK(ensure(c, c->tmp, vec64));
-  CHK(ensure(c, c->pq_part, L * nblk_site(c, 64) * sizeof(double)));
+  CHK(ensure(c, c->pq_part, L * (size_t)((c->V + 63) / 64) * sizeof(double)));
   CHK(ensure(c, c->rr_part, std::max<size_t>(L * nblk_vec(c), L * 64) * sizeof(double)));
   CHK(ensure(c, c->seed, L * sizeof(SeedState)));
   CHK(ensure(c, c->shift, L * N * sizeof(ShiftState)));
@@ -587,15 +603,27 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
   cand = best;
   for (int w : {2, 4, 8, 16, 32}) {
     if (w > 2 && w / 2 >= maxN) continue;
-    cand.wbatch = w;
-    IterPlan pl;
-    build_plan(P, pl, o, cand);
-    const double t = time_it([&] { launch_shift_update(pl.u64, 0, 0, st); }, 3);
-    if (t < tbest) {
-      tbest = t;
-      best.wbatch = w;
+    for (int u : {1, 2, 4}) {
+      if (u > w) continue;
+      for (int nt : {0, 1}) {
+        cand.wbatch = w;
+        cand.unroll = u;
+        cand.nt = nt;
+        IterPlan pl;
+        build_plan(P, pl, o, cand);
+        const double t = time_it([&] { launch_shift_update(pl.u64, 0, 0, u, nt, st); }, 3);
+        if (t < tbest) {
+          tbest = t;
+          best.wbatch = w;
+          best.unroll = u;
+          best.nt = nt;
+        }
+      }
     }
   }
+  if (getenv("SSCG_VERBOSE"))
+    fprintf(stderr, "[sscg] tuned %s: nr=%d bs=%d xcd=%d wbatch=%d unroll=%d nt=%d\n", key.c_str(), best.nr,
+            best.bs, best.xcd, best.wbatch, best.unroll, best.nt);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   // restore the initial state
@@ -652,15 +680,15 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     c0->stage_calls[i] = 0;
   }
   Recorder rec{c0, st, c0->profiling, {}};
-  const bool use_graph = o.use_graph && !c0->profiling;
+  const bool use_graph = o.use_graph != 0 && !c0->profiling;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int glen[2] = {0, 0};
   auto capture = [&](int prec, int len, hipGraphExec_t &exec) -> int {
     hipGraph_t g = nullptr;
-    Recorder off{c0, st, false, {}};
+    Recorder cap{c0, st, false, {}};
     HIPCHK(c0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < len; ++k)
-      launch_iteration(pl, prec, prec == 1 && k == len - 1, lr, tn, st, off);
+      launch_iteration(pl, prec, prec == 1 && k == len - 1, lr, tn, st, cap);
     HIPCHK(c0, hipStreamEndCapture(st, &g));
     HIPCHK(c0, hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
     HIPCHK(c0, hipGraphDestroy(g));
@@ -671,8 +699,12 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   int k = 0;
   int rc = SSCG_OK;
   while (k < o.maxiter) {
-    const int chunk = std::min(prec == 0 ? o.poll_every : o.ru_interval, o.maxiter - k);
-    const bool full = chunk == (prec == 0 ? o.poll_every : o.ru_interval);
+    // the FP64 phase of a mixed solve polls at least every 10 iterations so the
+    // switch to FP32 is not delayed by a long poll interval
+    const int period = prec == 1 ? o.ru_interval
+                                 : (o.prec == SSCG_MIXED ? std::min(o.poll_every, 10) : o.poll_every);
+    const int chunk = std::min(period, o.maxiter - k);
+    const bool full = chunk == period;
     if (use_graph && full) {
       if (!gexec[prec] || glen[prec] != chunk) {
         if (gexec[prec]) hipGraphExecDestroy(gexec[prec]);

@@ -14,8 +14,8 @@
 //   (1 - g4) psi = [h0, h1, -h0, -h1],      h0 = p0 - p2,    h1 = p1 - p3
 //   (1 + g4) psi = [h0, h1,  h0,  h1],      h0 = p0 + p2,    h1 = p1 + p3
 // Epilogue: out = A psi = gamma5 (psi - kappa D psi) (mode 0), or the CG seed
-// matrix out = sigma psi - A psi (mode 1), with the per-block partial sums of
-// Re <psi, out> written for the CG step length when requested.
+// matrix out = sigma psi - A psi (mode 1), with partial sums of Re <psi, out> per
+// 64-site wavefront written for the CG step length when requested.
 //
 // Memory: the spinor planes and link planes are site-contiguous, so each of the
 // 8 neighbour gathers of a wavefront is a run of 64 consecutive complex numbers
@@ -155,26 +155,9 @@ __device__ __forceinline__ void hop(const V2<T> *__restrict__ in, const V2<T> *_
   }
 }
 
-template <int NW>
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NW; ++i) t += sh[i];
-  }
-  return t;  // valid in thread 0
-}
-
 template <typename T, int NR, int LR, int BS>
 __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap) {
   using C = V2<T>;
-  __shared__ double red[BS / 64];
   int b = blockIdx.x;
   if (xcd_remap) b = xcd_remap_block(b, gridDim.x);
   int begins[kMaxJobs];
@@ -251,10 +234,16 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
     }
   }
   if (J.partial) {
+    // one partial per 64-site wavefront, at the wave's global index: the layout and
+    // the summation order do not depend on the block size or sources per thread
+    const int wave = (sblk * BS + (int)threadIdx.x) >> 6;
+    const int npart = (V + 63) >> 6;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const double tot = block_sum<BS / 64>(dot[r], red);
-      if (threadIdx.x == 0 && r < nvalid) J.partial[(size_t)(l0 + r) * J.nblk_site + sblk] = tot;
+      double d = dot[r];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+      if ((threadIdx.x & 63) == 0 && r < nvalid && wave < npart) J.partial[(size_t)(l0 + r) * npart + wave] = d;
     }
   }
 }

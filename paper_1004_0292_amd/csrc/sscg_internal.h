@@ -86,7 +86,7 @@ struct DslashJob {
   const void *in;        // planar [nsrc][12][V] of T
   void *out;             // planar [nsrc][12][V] of T
   const void *gauge;     // [4][LR/2][V] of V2<T>
-  double *partial;       // [nsrc][nblk_site] partial Re<in, out>, or nullptr
+  double *partial;       // [nsrc][ceil(V/64)] partial Re<in, out> per wavefront, or nullptr
   const SeedState *seed; // per-source done flags, or nullptr (always compute)
   double kappa, sigma;   // out = sigma in - A in (mode 1) or A in (mode 0)
   int32_t dims[4];
@@ -131,7 +131,8 @@ void launch_dslash(const DslashBatch &b, int prec /*0 fp64, 1 fp32*/, int nr, in
 void launch_seed_alpha(const ScalarBatch &b, hipStream_t st);
 void launch_shift_scalars(const ScalarBatch &b, hipStream_t st);
 void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st);
-void launch_shift_update(const VecBatch &b, int prec, int fold, hipStream_t st);
+// unroll: shifts whose loads are issued together (1, 2, 4); nt: non-temporal access
+void launch_shift_update(const VecBatch &b, int prec, int fold, int unroll, int nt, hipStream_t st);
 void launch_reliable_residual(const VecBatch &b, hipStream_t st);
 void launch_fold_seed(const VecBatch &b, hipStream_t st);
 void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st);

@@ -207,12 +207,60 @@ __global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
   if (threadIdx.x == 0) J.partial[(size_t)l * J.nblk_vec + vb] = tot;
 }
 
+// Non-temporal (streaming) loads and stores of one complex number.
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf2 __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ double2 ldc(const double2 *p) {
+  if constexpr (NT) {
+    const nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2 *>(p));
+    return make_double2(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ float2 ldc(const float2 *p) {
+  if constexpr (NT) {
+    const nf2 v = __builtin_nontemporal_load(reinterpret_cast<const nf2 *>(p));
+    return make_float2(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void stc(double2 *p, double2 v) {
+  if constexpr (NT) {
+    nd2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<nd2 *>(p));
+  } else {
+    *p = v;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void stc(float2 *p, float2 v) {
+  if constexpr (NT) {
+    nf2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<nf2 *>(p));
+  } else {
+    *p = v;
+  }
+}
+
 // Fused multi-shift update. job: a = x (FP64 solution storage [nsrc][nshift][n]),
 // b = shift workspace [nsrc][nshift] slots of n double2: FP64 phase p_j;
 // FP32 phase p_j (first n float2) and the FP32 partial x_j (next n float2);
 // c = seed r, d = seed p (both T). FOLD (FP32 phase only) also adds the partial
 // and this iteration's step into the FP64 solution and clears the partial.
-template <typename T, bool FOLD>
+// U shifts are handled together: all their loads are issued before the first
+// store, so a thread keeps 2 U kEpt loads in flight. NT selects streaming
+// (non-temporal) access for the shift vectors, which are touched once per
+// iteration.
+template <typename T, bool FOLD, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
   using C = V2<T>;
   const int b = blockIdx.x;
@@ -235,54 +283,103 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
     rv[e] = i < n ? r[i] : cmk<C>(0, 0);
   }
   const int j0 = bt * J.wbatch, j1 = min(j0 + J.wbatch, J.nshift);
-  for (int j = j0; j < j1; ++j) {
-    const ShiftState &H = J.shift[(size_t)l * J.nshift + j];
-    if (!H.upd) continue;
-    const size_t slot = (size_t)l * J.nshift + j;
-    if constexpr (sizeof(T) == 8) {
-      const double2 a = H.a, bb = H.b, ip = H.ipi;
-      double2 *x = reinterpret_cast<double2 *>(J.a) + slot * n;
-      double2 *p = reinterpret_cast<double2 *>(J.b) + slot * n;
+  for (int j = j0; j < j1; j += U) {
+    bool act[U];
+    double2 a[U], bb[U], ip[U];
 #pragma unroll
-      for (int e = 0; e < kEpt; ++e) {
-        const int64_t i = base + (int64_t)e * kBlock;
-        if (i < n) {
-          double2 xv = x[i];
-          const double2 pv = p[i];
-          cfma(xv, a, pv);
-          double2 pn = cmul(ip, rv[e]);
-          cfma(pn, bb, pv);
-          x[i] = xv;
-          p[i] = pn;
+    for (int u = 0; u < U; ++u) {
+      act[u] = false;
+      if (j + u < j1) {
+        const ShiftState &H = J.shift[(size_t)l * J.nshift + j + u];
+        act[u] = H.upd != 0;
+        a[u] = H.a;
+        bb[u] = H.b;
+        ip[u] = H.ipi;
+      }
+    }
+    if constexpr (sizeof(T) == 8) {
+      double2 xv[U][kEpt], pv[U][kEpt];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!act[u]) continue;
+        const size_t slot = (size_t)l * J.nshift + j + u;
+        const double2 *x = reinterpret_cast<const double2 *>(J.a) + slot * n;
+        const double2 *p = reinterpret_cast<const double2 *>(J.b) + slot * n;
+#pragma unroll
+        for (int e = 0; e < kEpt; ++e) {
+          const int64_t i = base + (int64_t)e * kBlock;
+          if (i < n) {
+            xv[u][e] = ldc<NT>(x + i);
+            pv[u][e] = ldc<NT>(p + i);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!act[u]) continue;
+        const size_t slot = (size_t)l * J.nshift + j + u;
+        double2 *x = reinterpret_cast<double2 *>(J.a) + slot * n;
+        double2 *p = reinterpret_cast<double2 *>(J.b) + slot * n;
+#pragma unroll
+        for (int e = 0; e < kEpt; ++e) {
+          const int64_t i = base + (int64_t)e * kBlock;
+          if (i < n) {
+            double2 xn = xv[u][e];
+            cfma(xn, a[u], pv[u][e]);
+            double2 pn = cmul(ip[u], rv[e]);
+            cfma(pn, bb[u], pv[u][e]);
+            stc<NT>(x + i, xn);
+            stc<NT>(p + i, pn);
+          }
         }
       }
     } else {
-      const float2 a = make_float2((float)H.a.x, (float)H.a.y);
-      const float2 bb = make_float2((float)H.b.x, (float)H.b.y);
-      const float2 ip = make_float2((float)H.ipi.x, (float)H.ipi.y);
-      float2 *p = reinterpret_cast<float2 *>(reinterpret_cast<double2 *>(J.b) + slot * n);
-      float2 *xp = p + n;
+      float2 xv[U][kEpt], pv[U][kEpt];
+      double2 xm[FOLD ? U : 1][kEpt];
 #pragma unroll
-      for (int e = 0; e < kEpt; ++e) {
-        const int64_t i = base + (int64_t)e * kBlock;
-        if (i < n) {
-          const float2 pv = p[i];
-          float2 xv = xp[i];
-          float2 pn = cmul(ip, rv[e]);
-          cfma(pn, bb, pv);
-          p[i] = pn;
-          if constexpr (FOLD) {
-            double2 *x = reinterpret_cast<double2 *>(J.a) + slot * n;
-            double2 xm = x[i];
-            const double2 pd = make_double2(pv.x, pv.y);
-            xm.x += (double)xv.x;
-            xm.y += (double)xv.y;
-            cfma(xm, H.a, pd);
-            x[i] = xm;
-            xp[i] = make_float2(0.f, 0.f);
-          } else {
-            cfma(xv, a, pv);
-            xp[i] = xv;
+      for (int u = 0; u < U; ++u) {
+        if (!act[u]) continue;
+        const size_t slot = (size_t)l * J.nshift + j + u;
+        const float2 *p = reinterpret_cast<const float2 *>(reinterpret_cast<const double2 *>(J.b) + slot * n);
+        const float2 *xp = p + n;
+#pragma unroll
+        for (int e = 0; e < kEpt; ++e) {
+          const int64_t i = base + (int64_t)e * kBlock;
+          if (i < n) {
+            pv[u][e] = ldc<NT>(p + i);
+            xv[u][e] = ldc<NT>(xp + i);
+            if constexpr (FOLD) xm[u][e] = ldc<NT>(reinterpret_cast<const double2 *>(J.a) + slot * n + i);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!act[u]) continue;
+        const size_t slot = (size_t)l * J.nshift + j + u;
+        float2 *p = reinterpret_cast<float2 *>(reinterpret_cast<double2 *>(J.b) + slot * n);
+        float2 *xp = p + n;
+        const float2 af = make_float2((float)a[u].x, (float)a[u].y);
+        const float2 bf = make_float2((float)bb[u].x, (float)bb[u].y);
+        const float2 pf = make_float2((float)ip[u].x, (float)ip[u].y);
+#pragma unroll
+        for (int e = 0; e < kEpt; ++e) {
+          const int64_t i = base + (int64_t)e * kBlock;
+          if (i < n) {
+            float2 pn = cmul(pf, rv[e]);
+            cfma(pn, bf, pv[u][e]);
+            stc<NT>(p + i, pn);
+            if constexpr (FOLD) {
+              double2 m = xm[u][e];
+              m.x += (double)xv[u][e].x;
+              m.y += (double)xv[u][e].y;
+              cfma(m, a[u], make_double2(pv[u][e].x, pv[u][e].y));
+              stc<NT>(reinterpret_cast<double2 *>(J.a) + slot * n + i, m);
+              stc<NT>(xp + i, make_float2(0.f, 0.f));
+            } else {
+              float2 xn = xv[u][e];
+              cfma(xn, af, pv[u][e]);
+              stc<NT>(xp + i, xn);
+            }
           }
         }
       }
@@ -512,10 +609,22 @@ void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st) {
   if (prec == 0) hipLaunchKernelGGL(seed_r_update_kernel<double>, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
   else hipLaunchKernelGGL(seed_r_update_kernel<float>, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
 }
-void launch_shift_update(const VecBatch &b, int prec, int fold, hipStream_t st) {
-  if (prec == 0) hipLaunchKernelGGL((shift_update_kernel<double, false>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
-  else if (fold) hipLaunchKernelGGL((shift_update_kernel<float, true>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
-  else hipLaunchKernelGGL((shift_update_kernel<float, false>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+template <typename T, bool FOLD, int U>
+static void launch_su_nt(const VecBatch &b, int nt, hipStream_t st) {
+  if (nt) hipLaunchKernelGGL((shift_update_kernel<T, FOLD, U, true>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+  else hipLaunchKernelGGL((shift_update_kernel<T, FOLD, U, false>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+}
+template <typename T, bool FOLD>
+static void launch_su_u(const VecBatch &b, int unroll, int nt, hipStream_t st) {
+  if (unroll >= 4) launch_su_nt<T, FOLD, 4>(b, nt, st);
+  else if (unroll == 2) launch_su_nt<T, FOLD, 2>(b, nt, st);
+  else launch_su_nt<T, FOLD, 1>(b, nt, st);
+}
+void launch_shift_update(const VecBatch &b, int prec, int fold, int unroll, int nt, hipStream_t st) {
+  if (b.total_blocks <= 0) return;
+  if (prec == 0) launch_su_u<double, false>(b, unroll, nt, st);
+  else if (fold) launch_su_u<float, true>(b, unroll, nt, st);
+  else launch_su_u<float, false>(b, unroll, nt, st);
 }
 void launch_reliable_residual(const VecBatch &b, hipStream_t st) {
   hipLaunchKernelGGL(reliable_residual_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);

@@ -9,7 +9,9 @@ Tolerances:
   * converged solutions: both meet the tolerance 1e-12 on the true residual, so
     they agree to about cond * 1e-12; checked at 1e-9 relative, and the GPU's own
     FP64 true residual at 5e-12.
-  * conv_iter: floating point decides it; identical or off by one.
+  * conv_iter: floating point decides it. With the seed at the centre of a nearly
+    +-symmetric spectrum CG lowers the residual only every second step, so a
+    last-bit difference in the freeze test moves it by 2: identical or within 2.
 """
 import numpy as np
 import pytest
@@ -100,7 +102,7 @@ def test_shifted_cg_converged(sscg, cfg1):
     assert r.status == sscg.OK
     Y = to_host(y).reshape(CFG1.N, -1)
     assert rel(Y, ref.Y) < 1e-9
-    assert np.all(np.abs(r.conv_iter[0] - ref.conv_iter) <= 1)
+    assert np.all(np.abs(r.conv_iter[0] - ref.conv_iter) <= 2)
     assert r.true_res.max() < 5e-12
     tr = solvers.true_residuals(lambda x: A @ x, v[0], z, Y)
     assert tr.max() < 5e-12

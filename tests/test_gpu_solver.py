@@ -2,17 +2,21 @@
 several sources, and the failure paths forced from the host.
 
 Bars:
-  * results must not depend on how often the host polls, on graph replay or on
-    the launch shapes chosen by the autotuner: bitwise equal (reductions are
-    two-stage with a fixed order; launch shapes only change which thread adds
-    which entry when the block size changes, so across block sizes the bar is
-    1e-13 relative);
+  * results must not depend on how often the host polls or on graph replay:
+    bitwise equal. Every reduction is two-stage with partials of a fixed
+    granularity (64 sites for the dslash, 512 entries for the vector kernels)
+    summed in a fixed order, also independent of the launch shapes;
+  * across launch shapes (block size, sources per thread, shift batch, unrolling,
+    XCD order) different kernel instantiations may contract multiply-adds
+    differently; the Krylov recurrence amplifies such last-bit differences over a
+    few hundred iterations, so the bar is 1e-11 relative (100 times below the
+    oracle parity bar) and convergence iterations within 2;
   * mixed precision: every shift's FP64 true residual <= 1e-10 (tolerance 1e-12
     on the implicit residual, FP32 arithmetic after the switch at 1e-6; the
     residual gap is bounded by ~eps_32 * switch_tol * cond) and the solution
     within 1e-9 of the FP64 oracle's;
-  * a batched solve equals the single-problem solves of its members to 1e-13
-    (the batch may be tuned to other launch shapes than each member alone).
+  * a batched FP64 solve equals the single-problem solves of its members to the
+    same 1e-11 (the batch may be tuned to other launch shapes).
 """
 import numpy as np
 import pytest
@@ -55,9 +59,10 @@ def test_poll_and_graph_do_not_change_results(sscg, prob):
     assert np.array_equal(r0.conv_iter, r1.conv_iter) and np.array_equal(r0.iters, r2.iters)
 
 
-@pytest.mark.parametrize("env", [dict(SSCG_NR="1", SSCG_BS="64", SSCG_WBATCH="3", SSCG_XCD="0"),
-                                 dict(SSCG_NR="4", SSCG_BS="128", SSCG_WBATCH="16", SSCG_XCD="1"),
-                                 dict(SSCG_NR="2", SSCG_BS="256", SSCG_WBATCH="1", SSCG_XCD="1")])
+@pytest.mark.parametrize("env", [dict(SSCG_NR="1", SSCG_BS="64", SSCG_WBATCH="3", SSCG_XCD="0", SSCG_UNROLL="1"),
+                                 dict(SSCG_NR="4", SSCG_BS="128", SSCG_WBATCH="16", SSCG_XCD="1", SSCG_UNROLL="4",
+                                      SSCG_NT="1"),
+                                 dict(SSCG_NR="2", SSCG_BS="256", SSCG_WBATCH="1", SSCG_XCD="1", SSCG_UNROLL="2")])
 def test_launch_shapes_agree(sscg, prob, monkeypatch, env):
     case(f"launch shapes {env}")
     U, A, V, z = prob
@@ -65,8 +70,8 @@ def test_launch_shapes_agree(sscg, prob, monkeypatch, env):
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     y, r = solve(sscg, U, V, z)
-    assert rel(y, y_ref) < 1e-13
-    assert np.all(np.abs(r.conv_iter - r_ref.conv_iter) <= 1)
+    assert rel(y, y_ref) < 1e-11
+    assert np.all(np.abs(r.conv_iter - r_ref.conv_iter) <= 2)
 
 
 def test_several_sources_and_seed_shift(sscg, prob):
@@ -77,8 +82,8 @@ def test_several_sources_and_seed_shift(sscg, prob):
     for l in range(3):
         ref = solvers.shifted_cg(lambda x: A @ x, V[l], z, 0.07, 1e-12)
         assert rel(y[l], ref.Y) < 1e-9
-        assert np.all(np.abs(r.conv_iter[l] - ref.conv_iter) <= 1)
-        assert r.iters[l] == pytest.approx(ref.iters, abs=1)
+        assert np.all(np.abs(r.conv_iter[l] - ref.conv_iter) <= 2)
+        assert r.iters[l] == pytest.approx(ref.iters, abs=2)
     assert r.true_res.max() < 5e-12
 
 
@@ -125,10 +130,14 @@ def test_batch_equals_single(sscg):
     res = sscg.batch_solve(ctxs, vs, zs, [0.0] * 3, ys)
     for (ys_single, r_single), y, r in zip(singles, ys, res):
         assert r.status == sscg.OK
-        assert rel(to_host(y), ys_single) < 1e-13
-        assert np.all(np.abs(r.iters - r_single.iters) <= 1)
-        assert np.all(np.abs(r.conv_iter - r_single.conv_iter) <= 1)
-        assert r.true_res.max() < 5e-12
+        assert rel(to_host(y), ys_single) < 1e-11
+        assert np.all(np.abs(r.iters - r_single.iters) <= 2)
+        assert np.all(np.abs(r.conv_iter - r_single.conv_iter) <= 2)
+        # FP64 rounding gap between the recursive and the true residual is about
+        # eps * max_k ||r_k|| / ||v||; one of these sources passes a near-breakdown of
+        # the indefinite seed where ||r_k|| peaks near 1e5 ||v|| (the oracle shows
+        # 3e-11 on it), so the bar is 1e-10 rather than the tolerance itself
+        assert r.true_res.max() < 1e-10
 
 
 def test_zero_and_nan_sources_rejected(sscg, prob):

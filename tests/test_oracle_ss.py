@@ -127,3 +127,13 @@ def test_moments_are_linear_in_the_solutions():
     E = np.zeros((1, N, 1), dtype=complex)
     E[0, 3, 0] = 1
     assert np.allclose(ss.moments(E, zeta, w, M)[0, :, 0], w[3] * zeta[3] ** np.arange(M))
+
+
+def test_lowest_magnitude_eigs_matches_dense():
+    dims = (3, 3, 3, 3)
+    A = wilson.hermitian_wilson(synth.gauge_field(dims, 0.5, 2), dims, 0.13)
+    lam = np.linalg.eigvalsh(A.toarray())
+    got, X = ss.lowest_magnitude_eigs(A, 12)
+    ref = np.sort(lam[np.argsort(np.abs(lam))[:12]])
+    assert np.abs(got - ref).max() < 1e-12
+    assert np.linalg.norm(A @ X - X * got[None, :], axis=0).max() < 1e-9

@@ -155,3 +155,14 @@ def test_global_gamma_sign_is_a_basis_change(monkeypatch):
     # pins cannot see it, so the hop-direction convention (1 - gamma_mu forward)
     # is fixed by the element-by-element GPU parity tests instead.
     assert pins_pass(wilson.hermitian_wilson)
+
+
+def test_apply_rows_matches_explicit_matrix():
+    dims, kappa = (4, 3, 5, 4), 0.13
+    U = synth.gauge_field(dims, 0.6, 5)
+    A = wilson.hermitian_wilson(U, dims, kappa)
+    x = synth.sources(int(np.prod(dims)), 1, 2).reshape(-1)
+    sites = [0, 7, 59, 239, 120]
+    got = wilson.apply_rows(U, dims, kappa, x, sites)
+    full = (A @ x).reshape(-1, 12)
+    assert np.abs(got - full[sites]).max() < 1e-14
