@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default=DEFAULT_CONFIG)
     ap.add_argument("--method", default="rr", choices=["rr", "hankel"])
+    ap.add_argument("--prec", default=None, choices=["fp64", "mixed", "mixed_shifts"],
+                    help="override the workload's precision mode")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-events", action="store_true", help="time without per-launch events")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -151,7 +153,9 @@ def main():
     import synth
 
     w = synth.CONFIGS[args.config]
-    prec = S.MIXED if w.prec == "mixed" else S.FP64
+    mode = args.prec or w.prec
+    prec = {"fp64": S.FP64, "mixed": S.MIXED, "mixed_shifts": S.MIXED_SHIFTS}[mode]
+    seed32 = prec == S.MIXED
     U = w.gauge()
     V = w.sources()
     ctx = S.Context(w.dims, w.kappa, device=0)
@@ -207,10 +211,12 @@ def main():
     it32 = tot["seed_iters_fp32"]
     # shift update: read and write x_j and p_j per active (shift, source, entry); seed r
     # read once and seed p read and written once per (source, entry, iteration)
-    shift_bytes = (su64 * 64 + it64 * 48) * n + (su32 * 32 + it32 * 24) * n
+    # (the seed vectors are FP32 in the FP32 phase only in the "mixed" mode)
+    shift_bytes = (su64 * 64 + it64 * 48) * n + (su32 * 32 + it32 * (24 if seed32 else 48)) * n
     # dslash: spinor in and out per (source, site) and the four forward links per site
-    dslash_bytes = (it64 * 48 * 8 + it32 * 48 * 4) * w.V
-    dslash_bytes += (link_launches[0] * 18 * 8 + link_launches[1] * w.link_reals * 4) * 4 * w.V
+    dslash_bytes = (it64 * 48 * 8 + it32 * 48 * (4 if seed32 else 8)) * w.V
+    dslash_bytes += (link_launches[0] * 18 * 8 +
+                     link_launches[1] * (w.link_reals * 4 if seed32 else 18 * 8)) * 4 * w.V
     rep = {}
     for name, idx, b in (("shift_update", 4, shift_bytes), ("dslash", 0, dslash_bytes)):
         calls = int(stage_calls[idx])
@@ -237,10 +243,11 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == S.FP64 else "f32+f64",
+        "prec_mode": mode,
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.dims), "kappa": w.kappa, "eps": w.eps, "seed": w.seed,
                    "interval": [w.gamma - w.rho, w.gamma + w.rho], "beta": w.beta, "N": w.N, "L": w.L,
-                   "M": w.M, "tol": w.tol, "prec": w.prec, "link_reals": w.link_reals,
+                   "M": w.M, "tol": w.tol, "prec": mode, "link_reals": w.link_reals,
                    "method": args.method, "parallelism": "single GPU"},
         "roofline": rep[dominant],
         "dslash": rep["dslash"],

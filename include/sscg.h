@@ -56,10 +56,14 @@ enum {
 };
 
 enum { SSCG_FP64 = 0,    /* every vector, product and scalar in FP64                 */
-       SSCG_MIXED = 1 }; /* FP64 until the largest active shifted residual falls
-                            below switch_tol, then FP32 dslash and vector updates
-                            with FP64 reliable updates of the seed residual; scalar
-                            recurrences and dot products stay FP64                 */
+       SSCG_MIXED = 1,   /* FP64 until the largest active shifted residual falls
+                            below switch_tol, then FP32 dslash, FP32 seed and shift
+                            vectors, with FP64 reliable updates of the seed residual
+                            every ru_interval iterations; scalar recurrences and dot
+                            products stay FP64                                      */
+       SSCG_MIXED_SHIFTS = 2 }; /* FP64 seed CG throughout; after the switch the
+                            shift vectors x_j, p_j are kept in FP32 and folded into
+                            the FP64 solutions every ru_interval iterations        */
 
 enum { SSCG_PATH_LINES = 0, SSCG_PATH_CIRCLE = 1 };
 enum { SSCG_RR = 0, SSCG_HANKEL = 1 };
@@ -90,7 +94,7 @@ int sscg_apply_A(sscg_ctx *ctx, const void *x, void *y, int32_t nsrc, int32_t pr
 typedef struct {
   double tol;            /* per-shift stop: ||r_j|| <= tol ||v|| (Sec. 4 criterion)   */
   int32_t maxiter;       /* seed iterations at most                                    */
-  int32_t prec;          /* SSCG_FP64 | SSCG_MIXED                                     */
+  int32_t prec;          /* SSCG_FP64 | SSCG_MIXED | SSCG_MIXED_SHIFTS                 */
   int32_t ru_interval;   /* MIXED: reliable update every this many FP32 iterations    */
   int32_t poll_every;    /* host checks the device "all converged" word this often    */
   double switch_tol;     /* MIXED: FP64 -> FP32 switch when max active ||r_j||/||v||

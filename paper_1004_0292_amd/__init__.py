@@ -22,7 +22,7 @@ _PKG = Path(__file__).resolve().parent
 LIB_PATH = Path(os.environ.get("SSCG_LIB", _PKG / "libsscg.so"))
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, ESTATE = 0, -1, -2, -3, -4, -5, -6
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_SHIFTS = 0, 1, 2
 PATH_LINES, PATH_CIRCLE = 0, 1
 RR, HANKEL = 0, 1
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOTCONV: "ENOTCONV",

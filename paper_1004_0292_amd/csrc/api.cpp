@@ -310,7 +310,7 @@ struct Prob {
 struct IterPlan {
   DslashBatch d64, d32, dru;
   ScalarBatch alpha, scal;
-  VecBatch r64, r32, u64, u32, fold_seed, rel;
+  VecBatch r64, r32, u64, u32, u32s, fold_seed, rel;
 };
 
 static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts &o, const Tune &t) {
@@ -355,6 +355,7 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
     const int nbatch = (N + t.wbatch - 1) / t.wbatch;
     mk_v(pl.u64.job[i], P[i].y, c->W.p, c->r64.p, c->p64.p, bu, L * nbatch * nbv);
     mk_v(pl.u32.job[i], P[i].y, c->W.p, c->r32.p, c->p32.p, bu, L * nbatch * nbv);
+    mk_v(pl.u32s.job[i], P[i].y, c->W.p, c->r64.p, c->p64.p, bu, L * nbatch * nbv);
     bu += L * nbatch * nbv;
   }
   pl.d64.njobs = pl.d32.njobs = pl.dru.njobs = np;
@@ -366,8 +367,8 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
     vb->njobs = np;
     vb->total_blocks = bv;
   }
-  pl.u64.njobs = pl.u32.njobs = np;
-  pl.u64.total_blocks = pl.u32.total_blocks = bu;
+  pl.u64.njobs = pl.u32.njobs = pl.u32s.njobs = np;
+  pl.u64.total_blocks = pl.u32.total_blocks = pl.u32s.total_blocks = bu;
 }
 
 // Per-stage timing with HIP events on the solver stream: an event is recorded
@@ -412,15 +413,20 @@ struct Recorder {
   }
 };
 
-static void launch_iteration(const IterPlan &pl, int prec, bool ru, int lr, const Tune &t, hipStream_t st,
-                             Recorder &rec) {
+// One iteration. prec: 0 FP64 phase, 1 FP32 phase; seed32: the FP32 phase also runs
+// the seed in FP32 (SSCG_MIXED) rather than FP64 (SSCG_MIXED_SHIFTS); ru: last
+// iteration of an FP32 chunk (seed reliable update if seed32, fold of the FP32
+// shift partials into the FP64 solutions in both FP32 modes).
+static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru, int lr, const Tune &t,
+                             hipStream_t st, Recorder &rec) {
+  const int sp = (prec == 1 && seed32) ? 1 : 0;  // seed precision
   rec.mark(ST_DSLASH);
-  launch_dslash(prec == 0 ? pl.d64 : pl.d32, prec, t.nr, prec == 0 ? 18 : lr, t.bs, t.xcd, st);
+  launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, st);
   rec.mark(ST_ALPHA);
   launch_seed_alpha(pl.alpha, st);
   rec.mark(ST_RUPD);
-  launch_seed_r_update(prec == 0 ? pl.r64 : pl.r32, prec, st);
-  if (prec == 1 && ru) {
+  launch_seed_r_update(sp == 0 ? pl.r64 : pl.r32, sp, st);
+  if (sp == 1 && ru) {
     rec.mark(ST_RU);
     launch_fold_seed(pl.fold_seed, st);
     launch_dslash(pl.dru, 0, t.nr, 18, t.bs, t.xcd, st);
@@ -429,7 +435,8 @@ static void launch_iteration(const IterPlan &pl, int prec, bool ru, int lr, cons
   rec.mark(ST_SCAL);
   launch_shift_scalars(pl.scal, st);
   rec.mark(ST_SHIFT);
-  launch_shift_update(prec == 0 ? pl.u64 : pl.u32, prec, prec == 1 && ru, t.unroll, t.nt, st);
+  const VecBatch &u = prec == 0 ? pl.u64 : (sp == 1 ? pl.u32 : pl.u32s);
+  launch_shift_update(u, prec, sp, prec == 1 && ru, t.unroll, t.nt, st);
 }
 
 static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
@@ -447,7 +454,7 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
   CHK(ensure(c, c->seed, L * sizeof(SeedState)));
   CHK(ensure(c, c->shift, L * N * sizeof(ShiftState)));
   CHK(ensure(c, c->zdev, N * 2 * sizeof(double)));
-  if (o.prec == SSCG_MIXED) {
+  if (o.prec == SSCG_MIXED) {  // FP32 seed vectors and reliable-update storage
     CHK(ensure(c, c->r32, L * vec32));
     CHK(ensure(c, c->p32, L * vec32));
     CHK(ensure(c, c->q32, L * vec32));
@@ -505,14 +512,16 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
 
 // FP64 -> FP32 switch of one problem: seed vectors, reliable-update base, and the
 // shift directions p_j (rewritten in place through one temporary vector).
-static int switch_to_fp32(Prob &p, hipStream_t st) {
+static int switch_to_fp32(Prob &p, bool seed32, hipStream_t st) {
   sscg_ctx *c = p.c;
   const size_t n = c->n, L = p.L, N = p.N, vec64 = n * sizeof(double2);
-  launch_cast(c->r64.p, 0, c->r32.p, 1, (int64_t)(L * n), st);
-  launch_cast(c->p64.p, 0, c->p32.p, 1, (int64_t)(L * n), st);
-  HIPCHK(c, hipMemcpyAsync(c->rbase.p, c->r64.p, L * vec64, hipMemcpyDeviceToDevice, st));
-  HIPCHK(c, hipMemsetAsync(c->xpart64.p, 0, L * vec64, st));
-  HIPCHK(c, hipMemsetAsync(c->xpart32.p, 0, L * n * sizeof(float2), st));
+  if (seed32) {
+    launch_cast(c->r64.p, 0, c->r32.p, 1, (int64_t)(L * n), st);
+    launch_cast(c->p64.p, 0, c->p32.p, 1, (int64_t)(L * n), st);
+    HIPCHK(c, hipMemcpyAsync(c->rbase.p, c->r64.p, L * vec64, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, hipMemsetAsync(c->xpart64.p, 0, L * vec64, st));
+    HIPCHK(c, hipMemsetAsync(c->xpart32.p, 0, L * n * sizeof(float2), st));
+  }
   for (size_t k = 0; k < L * N; ++k) {
     char *slot = (char *)c->W.p + k * vec64;
     HIPCHK(c, hipMemcpyAsync(c->tmp.p, slot, vec64, hipMemcpyDeviceToDevice, st));
@@ -611,7 +620,7 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
         cand.nt = nt;
         IterPlan pl;
         build_plan(P, pl, o, cand);
-        const double t = time_it([&] { launch_shift_update(pl.u64, 0, 0, u, nt, st); }, 3);
+        const double t = time_it([&] { launch_shift_update(pl.u64, 0, 0, 0, u, nt, st); }, 3);
         if (t < tbest) {
           tbest = t;
           best.wbatch = w;
@@ -681,6 +690,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   }
   Recorder rec{c0, st, c0->profiling, {}};
   const bool use_graph = o.use_graph != 0 && !c0->profiling;
+  const bool seed32 = o.prec == SSCG_MIXED;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int glen[2] = {0, 0};
   auto capture = [&](int prec, int len, hipGraphExec_t &exec) -> int {
@@ -688,7 +698,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     Recorder cap{c0, st, false, {}};
     HIPCHK(c0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < len; ++k)
-      launch_iteration(pl, prec, prec == 1 && k == len - 1, lr, tn, st, cap);
+      launch_iteration(pl, prec, seed32, prec == 1 && k == len - 1, lr, tn, st, cap);
     HIPCHK(c0, hipStreamEndCapture(st, &g));
     HIPCHK(c0, hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
     HIPCHK(c0, hipGraphDestroy(g));
@@ -702,7 +712,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     // the FP64 phase of a mixed solve polls at least every 10 iterations so the
     // switch to FP32 is not delayed by a long poll interval
     const int period = prec == 1 ? o.ru_interval
-                                 : (o.prec == SSCG_MIXED ? std::min(o.poll_every, 10) : o.poll_every);
+                                 : (o.prec != SSCG_FP64 ? std::min(o.poll_every, 10) : o.poll_every);
     const int chunk = std::min(period, o.maxiter - k);
     const bool full = chunk == period;
     if (use_graph && full) {
@@ -720,7 +730,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       }
     } else {
       for (int kk = 0; kk < chunk; ++kk)
-        launch_iteration(pl, prec, prec == 1 && (kk == chunk - 1) && full, lr, tn, st, rec);
+        launch_iteration(pl, prec, seed32, prec == 1 && (kk == chunk - 1) && full, lr, tn, st, rec);
     }
     k += chunk;
     // poll
@@ -749,9 +759,9 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
         }
       }
     if (all_done) break;
-    if (o.prec == SSCG_MIXED && prec == 0 && can_switch) {
+    if (o.prec != SSCG_FP64 && prec == 0 && can_switch) {
       for (Prob &p : P) {
-        rc = switch_to_fp32(p, st);
+        rc = switch_to_fp32(p, seed32, st);
         if (rc != SSCG_OK) break;
       }
       if (rc != SSCG_OK) break;
@@ -913,7 +923,8 @@ static int check_solve_args(sscg_ctx *c, const void *v, int nsrc, const double *
   if (nsrc <= 0 || nshift <= 0) return fail(c, SSCG_EINVAL, "nsrc and nshift must be positive");
   if (nshift > 4096) return fail(c, SSCG_EINVAL, "at most 4096 shifts");
   if (!(o->tol > 0) || o->maxiter <= 0) return fail(c, SSCG_EINVAL, "tol must be > 0 and maxiter > 0");
-  if (o->prec != SSCG_FP64 && o->prec != SSCG_MIXED) return fail(c, SSCG_EINVAL, "bad precision");
+  if (o->prec != SSCG_FP64 && o->prec != SSCG_MIXED && o->prec != SSCG_MIXED_SHIFTS)
+    return fail(c, SSCG_EINVAL, "bad precision");
   for (int j = 0; j < 2 * nshift; ++j)
     if (!std::isfinite(z[j])) return fail(c, SSCG_EINVAL, "non-finite shift");
   return SSCG_OK;

@@ -131,8 +131,10 @@ void launch_dslash(const DslashBatch &b, int prec /*0 fp64, 1 fp32*/, int nr, in
 void launch_seed_alpha(const ScalarBatch &b, hipStream_t st);
 void launch_shift_scalars(const ScalarBatch &b, hipStream_t st);
 void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st);
+// prec: shift vectors (0 FP64, 1 FP32); seed_prec: seed r and p (0 FP64, 1 FP32);
 // unroll: shifts whose loads are issued together (1, 2, 4); nt: non-temporal access
-void launch_shift_update(const VecBatch &b, int prec, int fold, int unroll, int nt, hipStream_t st);
+void launch_shift_update(const VecBatch &b, int prec, int seed_prec, int fold, int unroll, int nt,
+                         hipStream_t st);
 void launch_reliable_residual(const VecBatch &b, hipStream_t st);
 void launch_fold_seed(const VecBatch &b, hipStream_t st);
 void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st);

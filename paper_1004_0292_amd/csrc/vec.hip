@@ -260,9 +260,9 @@ __device__ __forceinline__ void stc(float2 *p, float2 v) {
 // store, so a thread keeps 2 U kEpt loads in flight. NT selects streaming
 // (non-temporal) access for the shift vectors, which are touched once per
 // iteration.
-template <typename T, bool FOLD, int U, bool NT>
+template <typename T, typename TR, bool FOLD, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
-  using C = V2<T>;
+  using C = V2<TR>;  // seed vectors r and p (TR); shift vectors in T
   const int b = blockIdx.x;
   const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
   const int lb = b - J.block_begin;
@@ -359,13 +359,16 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
         float2 *p = reinterpret_cast<float2 *>(reinterpret_cast<double2 *>(J.b) + slot * n);
         float2 *xp = p + n;
         const float2 af = make_float2((float)a[u].x, (float)a[u].y);
+        float2 rf[kEpt];
+#pragma unroll
+        for (int e = 0; e < kEpt; ++e) rf[e] = make_float2((float)rv[e].x, (float)rv[e].y);
         const float2 bf = make_float2((float)bb[u].x, (float)bb[u].y);
         const float2 pf = make_float2((float)ip[u].x, (float)ip[u].y);
 #pragma unroll
         for (int e = 0; e < kEpt; ++e) {
           const int64_t i = base + (int64_t)e * kBlock;
           if (i < n) {
-            float2 pn = cmul(pf, rv[e]);
+            float2 pn = cmul(pf, rf[e]);
             cfma(pn, bf, pv[u][e]);
             stc<NT>(p + i, pn);
             if constexpr (FOLD) {
@@ -386,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
     }
   }
   if (bt == 0) {
-    const T beta = (T)S.beta_prev;
+    const TR beta = (TR)S.beta_prev;
     C *p = reinterpret_cast<C *>(J.d) + (size_t)l * n;
 #pragma unroll
     for (int e = 0; e < kEpt; ++e) {
@@ -609,22 +612,27 @@ void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st) {
   if (prec == 0) hipLaunchKernelGGL(seed_r_update_kernel<double>, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
   else hipLaunchKernelGGL(seed_r_update_kernel<float>, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
 }
-template <typename T, bool FOLD, int U>
+template <typename T, typename TR, bool FOLD, int U>
 static void launch_su_nt(const VecBatch &b, int nt, hipStream_t st) {
-  if (nt) hipLaunchKernelGGL((shift_update_kernel<T, FOLD, U, true>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
-  else hipLaunchKernelGGL((shift_update_kernel<T, FOLD, U, false>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+  if (nt) hipLaunchKernelGGL((shift_update_kernel<T, TR, FOLD, U, true>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+  else hipLaunchKernelGGL((shift_update_kernel<T, TR, FOLD, U, false>), dim3(b.total_blocks), dim3(kBlock), 0, st, b);
 }
-template <typename T, bool FOLD>
+template <typename T, typename TR, bool FOLD>
 static void launch_su_u(const VecBatch &b, int unroll, int nt, hipStream_t st) {
-  if (unroll >= 4) launch_su_nt<T, FOLD, 4>(b, nt, st);
-  else if (unroll == 2) launch_su_nt<T, FOLD, 2>(b, nt, st);
-  else launch_su_nt<T, FOLD, 1>(b, nt, st);
+  if (unroll >= 4) launch_su_nt<T, TR, FOLD, 4>(b, nt, st);
+  else if (unroll == 2) launch_su_nt<T, TR, FOLD, 2>(b, nt, st);
+  else launch_su_nt<T, TR, FOLD, 1>(b, nt, st);
 }
-void launch_shift_update(const VecBatch &b, int prec, int fold, int unroll, int nt, hipStream_t st) {
+void launch_shift_update(const VecBatch &b, int prec, int seed_prec, int fold, int unroll, int nt, hipStream_t st) {
   if (b.total_blocks <= 0) return;
-  if (prec == 0) launch_su_u<double, false>(b, unroll, nt, st);
-  else if (fold) launch_su_u<float, true>(b, unroll, nt, st);
-  else launch_su_u<float, false>(b, unroll, nt, st);
+  if (prec == 0) launch_su_u<double, double, false>(b, unroll, nt, st);
+  else if (seed_prec == 0) {
+    if (fold) launch_su_u<float, double, true>(b, unroll, nt, st);
+    else launch_su_u<float, double, false>(b, unroll, nt, st);
+  } else {
+    if (fold) launch_su_u<float, float, true>(b, unroll, nt, st);
+    else launch_su_u<float, float, false>(b, unroll, nt, st);
+  }
 }
 void launch_reliable_residual(const VecBatch &b, hipStream_t st) {
   hipLaunchKernelGGL(reliable_residual_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);

@@ -87,12 +87,13 @@ def test_several_sources_and_seed_shift(sscg, prob):
     assert r.true_res.max() < 5e-12
 
 
-@pytest.mark.parametrize("link_reals", [18, 12])
-def test_mixed_precision_accuracy(sscg, prob, link_reals):
-    case(f"mixed precision link_reals={link_reals}")
+@pytest.mark.parametrize("mode,link_reals", [("mixed", 18), ("mixed", 12), ("mixed_shifts", 18)])
+def test_mixed_precision_accuracy(sscg, prob, mode, link_reals):
+    case(f"{mode} precision link_reals={link_reals}")
     U, A, V, z = prob
     y64, r64 = solve(sscg, U, V, z)
-    y, r = solve(sscg, U, V, z, prec=sscg.MIXED, ru_interval=20, switch_tol=1e-6, link_reals=link_reals)
+    prec = sscg.MIXED if mode == "mixed" else sscg.MIXED_SHIFTS
+    y, r = solve(sscg, U, V, z, prec=prec, ru_interval=20, switch_tol=1e-6, link_reals=link_reals)
     assert r.status == sscg.OK
     assert r.true_res.max() < 1e-10
     for l in range(3):
@@ -101,12 +102,14 @@ def test_mixed_precision_accuracy(sscg, prob, link_reals):
     assert rel(y, y64) < 1e-9
 
 
-def test_mixed_precision_with_early_switch(sscg, prob):
+@pytest.mark.parametrize("mode", ["mixed", "mixed_shifts"])
+def test_mixed_precision_with_early_switch(sscg, prob, mode):
     """Switch to FP32 right away: reliable updates keep the seed residual honest, but the
     shifted solutions carry the FP32 rounding of the early, large updates (stated bound)."""
-    case("mixed precision switch_tol=1")
+    case(f"{mode} precision switch_tol=1")
     U, A, V, z = prob
-    y, r = solve(sscg, U, V, z, prec=sscg.MIXED, ru_interval=10, switch_tol=1.0)
+    prec = sscg.MIXED if mode == "mixed" else sscg.MIXED_SHIFTS
+    y, r = solve(sscg, U, V, z, prec=prec, ru_interval=10, switch_tol=1.0)
     assert r.status == sscg.OK
     assert r.true_res.max() < 1e-4
 
