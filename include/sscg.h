@@ -144,6 +144,12 @@ typedef struct {
   double rank_tol;          /* numerical rank: keep singular values > rank_tol*max  */
   double spur_tol;          /* report pairs with ||A x - lambda x|| <= spur_tol      */
   sscg_solve_opts solve;
+  int32_t npairs;           /* lines path: number of adjacent line pairs (Sec. 3, end):
+                               pair p+1 is pair p moved by the N'-2 nodes of its
+                               acceptance rectangle, the pairs are centred on gamma
+                               as a group and share nodes, all distinct nodes are
+                               solved by one shifted CG; 1 = a single pair         */
+  int32_t pad;
 } sscg_ss_params;
 
 typedef struct {
@@ -166,7 +172,11 @@ void sscg_default_ss_params(sscg_ss_params *p);
 /* Eigenpairs of A in [gamma - rho, gamma + rho] (Sec. 2-3): line (or circle)
  * quadrature, shifted CG for all nodes, moments eq. (2), Rayleigh-Ritz or block
  * Hankel extraction (Sec. 2.1, block form with nsrc sources), then the acceptance
- * rectangle of Sec. 3 and the residual filter res <= spur_tol.
+ * rectangle of Sec. 3 and the residual filter res <= spur_tol. With npairs > 1 the
+ * interval is covered by adjacent line pairs that reuse nodes (Sec. 3): one shifted
+ * CG over the N + (npairs - 1)(N' - 2) distinct nodes, then moments, extraction and
+ * acceptance per pair (each pair's rectangle is half-open on the right except the
+ * last, so an eigenvalue on a shared edge is reported once).
  *   v       device complex128 [nsrc][n] canonical sources
  *   lambda  host double [max_eigs] (output, ascending)
  *   X       device complex128 [max_eigs][n] canonical unit eigenvectors, or NULL

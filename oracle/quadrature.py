@@ -85,3 +85,31 @@ def acceptance_interval(zeta: np.ndarray, gamma: float, rho: float, Nprime: int)
     order = np.argsort(np.abs(xr))[: Nprime // 2]
     sel = np.sort(xr[order])
     return gamma + rho * sel[0], gamma + rho * sel[-1]
+
+
+def adjacent_pairs(N: int, Nprime: int, P: int, gamma: float, rho: float, beta: float):
+    """P line pairs side by side with shared nodes (Sec. 3, last paragraph).
+
+    Every pair has N nodes, half-width rho and offset beta; pair p + 1 is pair p moved
+    right by the N'-2 nodes (N'/2 - 1 per line) that span its acceptance rectangle,
+    so the rectangles tile [first lo, last hi] and each new pair adds N' - 2 nodes.
+    The pairs are centred on gamma as a group. Returns
+      z_all [N + (P-1)(N'-2)]  distinct nodes, ordered as in line_nodes (even index on
+                               the upper line) along the common grid,
+      offsets [P]              pair p uses z_all[offsets[p] : offsets[p] + N],
+      centres [P]              the pair centres gamma_p,
+    and the per-pair normalised nodes are those of line_nodes(N, 0, 1, beta).
+    """
+    if Nprime < 4 or Nprime % 2 or Nprime > N:
+        raise ValueError("need even 4 <= Nprime <= N")
+    h = 2.0 * rho / (N // 2 - 1)          # node spacing along a line
+    step = (Nprime - 2) // 2              # nodes per line between neighbouring pairs
+    total_x = N // 2 + (P - 1) * step
+    span = (P - 1) * step * h             # distance between the first and last centre
+    x = (gamma - 0.5 * span - rho) + h * np.arange(total_x)
+    z_all = np.empty(2 * total_x, dtype=np.complex128)
+    z_all[0::2] = x + 1j * beta * rho
+    z_all[1::2] = x - 1j * beta * rho
+    offsets = 2 * step * np.arange(P)
+    centres = gamma - 0.5 * span + step * h * np.arange(P)
+    return z_all, offsets, centres

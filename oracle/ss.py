@@ -147,3 +147,32 @@ def ss_eigs(A, Vsrc: np.ndarray, gamma: float, rho: float, beta: float, N: int, 
     idx = accept(lam, res, lo, hi, imag_max, spur_tol)
     return dict(lam=lam[idx], X=X[:, idx], res=res[idx], all_lam=lam, all_res=res,
                 z=z, zeta=zeta, w=w, Y=Y, S=S, runs=runs, lo=lo, hi=hi)
+
+
+def ss_eigs_adjacent(A, Vsrc: np.ndarray, gamma: float, rho: float, beta: float, N: int, M: int,
+                     Nprime: int, P: int, tol: float = 1e-12, rank_tol: float = 1e-10,
+                     spur_tol: float = 1e-6, maxiter: int = 100000):
+    """P adjacent line pairs sharing nodes (Sec. 3): one shifted CG over the distinct nodes,
+    then per pair the moments eq. (2) over its own N nodes, Rayleigh-Ritz, and acceptance in
+    its N' rectangle (half-open [lo, hi) except for the last pair, so an eigenvalue on a
+    shared edge is reported once)."""
+    z_all, offsets, centres = quad.adjacent_pairs(N, Nprime, P, gamma, rho, beta)
+    _, zeta = quad.line_nodes(N, 0.0, 1.0, beta)
+    w = quad.line_weights(zeta)
+    A_mul = lambda x: A @ x
+    runs = [shifted_cg(A_mul, v, z_all, gamma, tol, maxiter) for v in Vsrc]
+    Y_all = np.array([r.Y for r in runs])
+    lams, Xs, ress = [], [], []
+    for p in range(P):
+        Y = Y_all[:, offsets[p]:offsets[p] + N]
+        Sh = s_hat(moments(Y, zeta, w, M))
+        lam, X, res = rayleigh_ritz(Sh, lambda X: A @ X, rank_tol)
+        lo, hi = quad.acceptance_interval(zeta, centres[p], rho, Nprime)
+        keep = (lam >= lo) & ((lam < hi) if p < P - 1 else (lam <= hi)) & (res <= spur_tol)
+        lams.append(lam[keep])
+        Xs.append(X[:, keep])
+        ress.append(res[keep])
+    lam = np.concatenate(lams)
+    order = np.argsort(lam)
+    return dict(lam=lam[order], X=np.concatenate(Xs, axis=1)[:, order], res=np.concatenate(ress)[order],
+                z_all=z_all, offsets=offsets, centres=centres, runs=runs)

@@ -45,7 +45,7 @@ class SSParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("rho", C.c_double), ("beta", C.c_double),
                 ("N", C.c_int32), ("M", C.c_int32), ("Nprime", C.c_int32), ("path", C.c_int32),
                 ("method", C.c_int32), ("rank_tol", C.c_double), ("spur_tol", C.c_double),
-                ("solve", SolveOpts)]
+                ("solve", SolveOpts), ("npairs", C.c_int32), ("pad", C.c_int32)]
 
 
 class SSInfo(C.Structure):

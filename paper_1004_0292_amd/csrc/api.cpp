@@ -64,7 +64,7 @@ struct sscg_ctx {
   std::map<std::string, Tune> tuned;
   // solver workspaces
   DevBuf v64, r64, p64, q64, W, r32, p32, q32, rbase, xpart64, xpart32, tmp, pq_part, rr_part, seed,
-      shift, zdev, small, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, apply_in, apply_out;
+      shift, zdev, small, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out;
   SeedState *seed_host = nullptr;
   int seed_host_cap = 0;
   // profiling
@@ -173,7 +173,7 @@ void sscg_destroy(sscg_ctx *c) {
   DevBuf *bufs[] = {&c->g64, &c->g32, &c->v64, &c->r64, &c->p64, &c->q64, &c->W, &c->r32, &c->p32,
                     &c->q32, &c->rbase, &c->xpart64, &c->xpart32, &c->tmp, &c->pq_part, &c->rr_part,
                     &c->seed, &c->shift, &c->zdev, &c->small, &c->Ybuf, &c->Sbuf, &c->Qbuf, &c->AQbuf,
-                    &c->Xbuf, &c->AXbuf, &c->apply_in, &c->apply_out};
+                    &c->Xbuf, &c->AXbuf, &c->Accbuf, &c->apply_in, &c->apply_out};
   for (DevBuf *b : bufs) release(*b);
   if (c->seed_host) hipHostFree(c->seed_host);
   for (hipEvent_t e : c->events) hipEventDestroy(e);
@@ -1003,6 +1003,7 @@ void sscg_default_ss_params(sscg_ss_params *p) {
   p->method = SSCG_RR;
   p->rank_tol = 1e-7;
   p->spur_tol = 1e-6;
+  p->npairs = 1;
   sscg_default_opts(&p->solve);
 }
 
@@ -1095,13 +1096,132 @@ static int col_residuals(sscg_ctx *c, const void *AX, const void *X, int ncol, c
   return SSCG_OK;
 }
 
+// Rayleigh-Ritz on the columns of S (n x ncol): Q from two Gram passes over the
+// unit-norm columns (the second restores the orthogonality the first loses),
+// keeping directions whose singular value exceeds rank_tol times the largest; then
+// A~ = Q^H (A Q), its eigenpairs, X = Q W and A X = (A Q) W in Xd / AXd.
+static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, void *Xd, void *AXd,
+                      std::vector<double> &lam, int &r, hipStream_t st) {
+  const size_t vec = c->n * sizeof(double2);
+  std::vector<cd> G;
+  CHK(gram(c, S, ncol, S, ncol, G, st));
+  std::vector<double> dsc(ncol);
+  for (int a = 0; a < ncol; ++a) dsc[a] = G[(size_t)a * ncol + a].real() > 0 ? 1.0 / std::sqrt(G[(size_t)a * ncol + a].real()) : 0.0;
+  std::vector<cd> Gs((size_t)ncol * ncol);
+  for (int a = 0; a < ncol; ++a)
+    for (int b = 0; b < ncol; ++b) Gs[(size_t)a * ncol + b] = dsc[a] * G[(size_t)a * ncol + b] * dsc[b];
+  std::vector<double> ev;
+  std::vector<cd> W;
+  eig_rowmajor(ncol, Gs, ev, W);
+  const double emax = ev.back();
+  std::vector<int> keep;
+  for (int k = ncol - 1; k >= 0; --k)
+    if (emax > 0 && ev[k] > rank_tol * rank_tol * emax) keep.push_back(k);
+  r = (int)keep.size();
+  lam.clear();
+  if (r == 0) return SSCG_OK;
+  std::vector<cd> T1((size_t)ncol * r);
+  for (int a = 0; a < ncol; ++a)
+    for (int q = 0; q < r; ++q) T1[(size_t)a * r + q] = dsc[a] * W[(size_t)a * ncol + keep[q]] / std::sqrt(ev[keep[q]]);
+  CHK(ensure(c, c->Qbuf, (size_t)r * vec));
+  CHK(ensure(c, c->AQbuf, (size_t)r * vec));
+  CHK(basis_change(c, S, ncol, T1, r, c->AQbuf.p, st));  // Q1 (held in AQbuf for now)
+  std::vector<cd> G2;
+  CHK(gram(c, c->AQbuf.p, r, c->AQbuf.p, r, G2, st));
+  std::vector<double> ev2;
+  std::vector<cd> W2;
+  eig_rowmajor(r, G2, ev2, W2);
+  std::vector<cd> T2((size_t)r * r);
+  for (int a = 0; a < r; ++a)
+    for (int q = 0; q < r; ++q) T2[(size_t)a * r + q] = W2[(size_t)a * r + q] / std::sqrt(std::max(ev2[q], 1e-300));
+  CHK(basis_change(c, c->AQbuf.p, r, T2, r, c->Qbuf.p, st));  // Q
+  CHK(apply_A_planar(c, c->Qbuf.p, c->AQbuf.p, r, st));         // A Q
+  std::vector<cd> At;
+  CHK(gram(c, c->Qbuf.p, r, c->AQbuf.p, r, At, st));
+  std::vector<cd> Wr;
+  eig_rowmajor(r, At, lam, Wr);
+  CHK(basis_change(c, c->Qbuf.p, r, Wr, r, Xd, st));
+  CHK(basis_change(c, c->AQbuf.p, r, Wr, r, AXd, st));
+  (void)vec;
+  return SSCG_OK;
+}
+
+// Block Hankel on moments mu_k = V^H s_k (k < 2M) built from Gv[a][l N_all + off + j]
+// = <v_a, y_{l, off + j}>: H = [M_{i+j}], H< = [M_{i+j+1}] (L x L blocks). H is
+// Hermitian positive semidefinite for the real filters used here, so the pencil is
+// reduced on H's dominant eigenvectors and solved as a Hermitian problem; the
+// eigenvectors are X = S_hat u (S_hat = first M moments, columns k L + l).
+static int extract_hankel(sscg_ctx *c, const std::vector<cd> &Gv, int L, int Nall, int off, int N, int M,
+                          const std::vector<cd> &zeta, const std::vector<cd> &w, double gamma, double rho,
+                          double rank_tol, const void *S, void *Xd, void *AXd, std::vector<double> &lam, int &r,
+                          hipStream_t st) {
+  const int K = 2 * M;
+  std::vector<cd> mu((size_t)K * L * L, cd(0, 0));
+  for (int k = 0; k < K; ++k)
+    for (int j = 0; j < N; ++j) {
+      const cd cc = w[j] * std::pow(zeta[j], k);
+      for (int a = 0; a < L; ++a)
+        for (int l = 0; l < L; ++l) mu[((size_t)k * L + a) * L + l] += cc * Gv[(size_t)a * L * Nall + (size_t)l * Nall + off + j];
+    }
+  const int m = M * L;
+  std::vector<cd> H((size_t)m * m), Hs((size_t)m * m);
+  for (int bi = 0; bi < M; ++bi)
+    for (int bj = 0; bj < M; ++bj)
+      for (int a = 0; a < L; ++a)
+        for (int l = 0; l < L; ++l) {
+          H[(size_t)(bi * L + a) * m + bj * L + l] = mu[((size_t)(bi + bj) * L + a) * L + l];
+          Hs[(size_t)(bi * L + a) * m + bj * L + l] = mu[((size_t)(bi + bj + 1) * L + a) * L + l];
+        }
+  std::vector<double> ev;
+  std::vector<cd> W;
+  eig_rowmajor(m, H, ev, W);
+  const double emax = ev.back();
+  std::vector<int> keep;
+  for (int k = m - 1; k >= 0; --k)
+    if (emax > 0 && ev[k] > rank_tol * emax) keep.push_back(k);
+  r = (int)keep.size();
+  lam.clear();
+  if (r == 0) return SSCG_OK;
+  std::vector<cd> Wr((size_t)m * r);
+  for (int a = 0; a < m; ++a)
+    for (int q = 0; q < r; ++q) Wr[(size_t)a * r + q] = W[(size_t)a * m + keep[q]] / std::sqrt(ev[keep[q]]);
+  std::vector<cd> red((size_t)r * r, cd(0, 0));
+  for (int q1 = 0; q1 < r; ++q1)
+    for (int q2 = 0; q2 < r; ++q2) {
+      cd acc = 0;
+      for (int a = 0; a < m; ++a) {
+        cd t = 0;
+        for (int b = 0; b < m; ++b) t += Hs[(size_t)a * m + b] * Wr[(size_t)b * r + q2];
+        acc += std::conj(Wr[(size_t)a * r + q1]) * t;
+      }
+      red[(size_t)q1 * r + q2] = acc;
+    }
+  std::vector<double> eta;
+  std::vector<cd> T;
+  eig_rowmajor(r, red, eta, T);
+  lam.resize(r);
+  for (int q = 0; q < r; ++q) lam[q] = gamma + rho * eta[q];
+  std::vector<cd> Tc((size_t)m * r, cd(0, 0));
+  for (int a = 0; a < m; ++a)
+    for (int q = 0; q < r; ++q) {
+      cd acc = 0;
+      for (int b = 0; b < r; ++b) acc += Wr[(size_t)a * r + b] * T[(size_t)b * r + q];
+      Tc[(size_t)a * r + q] = acc;
+    }
+  CHK(basis_change(c, S, m, Tc, r, Xd, st));
+  CHK(apply_A_planar(c, Xd, AXd, r, st));
+  return SSCG_OK;
+}
+
 extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v, int32_t nsrc, int32_t max_eigs,
                             double *lambda, void *X, double *res, int32_t *n_found, sscg_ss_info *info) {
   if (!c || !p || !v || nsrc <= 0 || max_eigs < 0 || (max_eigs > 0 && (!lambda || !res)) || !n_found)
     return fail(c, SSCG_EINVAL, "bad argument");
+  const int P = p->npairs > 1 ? p->npairs : 1;
   if (p->M <= 0 || p->N < 4 || (p->path == SSCG_PATH_LINES && p->N % 2) || !(p->rho > 0) ||
-      (p->path == SSCG_PATH_LINES && !(p->beta > 0)))
+      (p->path == SSCG_PATH_LINES && !(p->beta > 0)) || (p->path != SSCG_PATH_LINES && p->path != SSCG_PATH_CIRCLE))
     return fail(c, SSCG_EINVAL, "bad contour parameters");
+  if (p->method != SSCG_RR && p->method != SSCG_HANKEL) return fail(c, SSCG_EINVAL, "bad extraction method");
   if (p->method == SSCG_HANKEL && 2 * p->M > p->N)
     return fail(c, SSCG_EINVAL, "Hankel needs 2M <= N moments from N nodes");
   if (!(p->rank_tol > 0 && p->rank_tol < 1)) return fail(c, SSCG_EINVAL, "rank_tol must lie in (0, 1)");
@@ -1109,59 +1229,68 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
     return fail(c, SSCG_EINVAL, "at most 512 nodes and M * nsrc <= 256 moment columns");
   const int Np = p->Nprime ? p->Nprime : p->N;
   if (p->path == SSCG_PATH_LINES && (Np < 4 || Np % 2 || Np > p->N)) return fail(c, SSCG_EINVAL, "bad Nprime");
+  if (P > 1 && p->path != SSCG_PATH_LINES) return fail(c, SSCG_EINVAL, "adjacent pairs need the line path");
+  if (P > 64) return fail(c, SSCG_EINVAL, "at most 64 adjacent pairs");
   HIPCHK(c, hipSetDevice(c->device));
   const int N = p->N, M = p->M, L = nsrc;
   const size_t n = c->n, vec = n * sizeof(double2);
-  std::vector<cd> z, zeta, w;
-  if (p->path == SSCG_PATH_LINES) quad_lines_host(N, p->gamma, p->rho, p->beta, z, zeta, w);
-  else quad_circle_host(N, p->gamma, p->rho, z, zeta, w);
-  // shifted CG into the internal (planar) solution buffer
-  CHK(ensure(c, c->Ybuf, (size_t)L * N * vec));
-  std::vector<double> zd(2 * N);
-  for (int j = 0; j < N; ++j) {
-    zd[2 * j] = z[j].real();
-    zd[2 * j + 1] = z[j].imag();
+  // normalised nodes and weights of one pair (identical for every pair)
+  std::vector<cd> zt, zeta, w;
+  if (p->path == SSCG_PATH_LINES) quad_lines_host(N, 0.0, 1.0, p->beta, zt, zeta, w);
+  else quad_circle_host(N, 0.0, 1.0, zt, zeta, w);
+  // distinct nodes of all pairs (Sec. 3: neighbouring pairs share all but N' - 2 nodes)
+  std::vector<cd> z_all;
+  std::vector<int> offsets(P);
+  std::vector<double> centres(P);
+  if (P == 1) {
+    for (int j = 0; j < N; ++j) z_all.push_back(p->gamma + p->rho * zeta[j]);
+    offsets[0] = 0;
+    centres[0] = p->gamma;
+  } else {
+    const double h = 2.0 * p->rho / (N / 2 - 1);
+    const int step = (Np - 2) / 2;
+    const int total_x = N / 2 + (P - 1) * step;
+    const double span = (P - 1) * step * h;
+    for (int i = 0; i < total_x; ++i) {
+      const double x = (p->gamma - 0.5 * span - p->rho) + h * i;
+      z_all.push_back(cd(x, p->beta * p->rho));
+      z_all.push_back(cd(x, -p->beta * p->rho));
+    }
+    for (int q = 0; q < P; ++q) {
+      offsets[q] = 2 * step * q;
+      centres[q] = p->gamma - 0.5 * span + step * h * q;
+    }
   }
-  std::vector<Prob> P(1);
-  P[0].c = c;
-  P[0].v = v;
-  P[0].L = L;
-  P[0].N = N;
-  P[0].sigma = p->gamma;
-  P[0].z = zd;
-  P[0].y = c->Ybuf.p;
-  P[0].keep_planar = true;
-  std::vector<int32_t> iters(L), conv((size_t)L * N);
-  P[0].iters = iters.data();
-  P[0].conv_iter = conv.data();
+  const int Nall = (int)z_all.size();
+  if (Nall > 4096) return fail(c, SSCG_EINVAL, "too many distinct nodes");
+  // one shifted CG for all distinct nodes into the internal (planar) solution buffer
+  CHK(ensure(c, c->Ybuf, (size_t)L * Nall * vec));
+  std::vector<double> zd(2 * Nall);
+  for (int j = 0; j < Nall; ++j) {
+    zd[2 * j] = z_all[j].real();
+    zd[2 * j + 1] = z_all[j].imag();
+  }
+  std::vector<Prob> PP(1);
+  PP[0].c = c;
+  PP[0].v = v;
+  PP[0].L = L;
+  PP[0].N = Nall;
+  PP[0].sigma = p->gamma;
+  PP[0].z = zd;
+  PP[0].y = c->Ybuf.p;
+  PP[0].keep_planar = true;
+  std::vector<int32_t> iters(L), conv((size_t)L * Nall);
+  PP[0].iters = iters.data();
+  PP[0].conv_iter = conv.data();
   auto t0 = std::chrono::steady_clock::now();
-  int rc = run_solve(P, p->solve);
+  int rc = run_solve(PP, p->solve);
   if (rc != SSCG_OK && rc != SSCG_ENOTCONV) return rc;
   hipStream_t st = c->work;
   auto t1 = std::chrono::steady_clock::now();
-  // moments: S planar, column k L + l = s_{k,l} (eq. 2)
-  const int K = (p->method == SSCG_HANKEL) ? 2 * M : M;
+  double t_mom = 0.0;
   const int ncol = M * L;
   CHK(ensure(c, c->Sbuf, (size_t)ncol * vec));
-  {
-    std::vector<double> cf(2 * (size_t)M * N);
-    for (int k = 0; k < M; ++k)
-      for (int j = 0; j < N; ++j) {
-        const cd cc = w[j] * std::pow(zeta[j], k);
-        cf[2 * ((size_t)k * N + j)] = cc.real();
-        cf[2 * ((size_t)k * N + j) + 1] = cc.imag();
-      }
-    CHK(ensure(c, c->small, cf.size() * sizeof(double)));
-    HIPCHK(c, hipMemcpyAsync(c->small.p, cf.data(), cf.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_moments_strided(c->Ybuf.p, L, N, (const double *)c->small.p, M, c->Sbuf.p, (int64_t)n, 1, L, st);
-    HIPCHK(c, hipStreamSynchronize(st));
-  }
-  auto t2 = std::chrono::steady_clock::now();
-  // candidate pairs: coefficients Tc (ncol x r, row-major) with x = S_hat Tc, values lam
-  std::vector<double> lam;
-  std::vector<cd> Tc;
-  int r = 0;
-  // X and AX buffers live in the shift workspace (free after the solve) when it is large enough
+  // X and AX buffers live in the shift workspace (free after the solve) when large enough
   void *Xd = nullptr, *AXd = nullptr;
   if (c->W.bytes >= 2 * (size_t)ncol * vec) {
     Xd = c->W.p;
@@ -1172,183 +1301,130 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
     Xd = c->Xbuf.p;
     AXd = c->AXbuf.p;
   }
-  if (p->method == SSCG_RR) {
-    // Q from S_hat with unit-norm columns: two Gram passes (the second restores
-    // orthogonality lost in the first), keeping directions whose singular value
-    // exceeds rank_tol times the largest.
-    std::vector<cd> G;
-    CHK(gram(c, c->Sbuf.p, ncol, c->Sbuf.p, ncol, G, st));
-    std::vector<double> dsc(ncol);
-    for (int a = 0; a < ncol; ++a) dsc[a] = G[(size_t)a * ncol + a].real() > 0 ? 1.0 / std::sqrt(G[(size_t)a * ncol + a].real()) : 0.0;
-    std::vector<cd> Gs((size_t)ncol * ncol);
-    for (int a = 0; a < ncol; ++a)
-      for (int b = 0; b < ncol; ++b) Gs[(size_t)a * ncol + b] = dsc[a] * G[(size_t)a * ncol + b] * dsc[b];
-    std::vector<double> ev;
-    std::vector<cd> W;
-    eig_rowmajor(ncol, Gs, ev, W);
-    const double emax = ev.back();
-    std::vector<int> keep;
-    for (int k = ncol - 1; k >= 0; --k)
-      if (ev[k] > p->rank_tol * p->rank_tol * emax) keep.push_back(k);
-    r = (int)keep.size();
-    if (r == 0) return fail(c, SSCG_EBREAKDOWN, "moment matrix has rank 0");
-    std::vector<cd> T1((size_t)ncol * r);
-    for (int a = 0; a < ncol; ++a)
-      for (int q = 0; q < r; ++q) T1[(size_t)a * r + q] = dsc[a] * W[(size_t)a * ncol + keep[q]] / std::sqrt(ev[keep[q]]);
-    CHK(ensure(c, c->Qbuf, (size_t)r * vec));
-    CHK(ensure(c, c->AQbuf, (size_t)r * vec));
-    CHK(basis_change(c, c->Sbuf.p, ncol, T1, r, c->AQbuf.p, st));  // Q1 (in AQbuf for now)
-    std::vector<cd> G2;
-    CHK(gram(c, c->AQbuf.p, r, c->AQbuf.p, r, G2, st));
-    std::vector<double> ev2;
-    std::vector<cd> W2;
-    eig_rowmajor(r, G2, ev2, W2);
-    std::vector<cd> T2((size_t)r * r);
-    for (int a = 0; a < r; ++a)
-      for (int q = 0; q < r; ++q) T2[(size_t)a * r + q] = W2[(size_t)a * r + q] / std::sqrt(std::max(ev2[q], 1e-300));
-    CHK(basis_change(c, c->AQbuf.p, r, T2, r, c->Qbuf.p, st));    // Q
-    CHK(apply_A_planar(c, c->Qbuf.p, c->AQbuf.p, r, st));           // A Q
-    std::vector<cd> At;
-    CHK(gram(c, c->Qbuf.p, r, c->AQbuf.p, r, At, st));
-    std::vector<cd> Wr;
-    eig_rowmajor(r, At, lam, Wr);
-    CHK(basis_change(c, c->Qbuf.p, r, Wr, r, Xd, st));
-    CHK(basis_change(c, c->AQbuf.p, r, Wr, r, AXd, st));
-  } else {
-    // block Hankel: M_k = V^H s_k = sum_j w_j zeta_j^k (V^H y_{.,j}) for k < 2M
+  std::vector<cd> Gv;
+  if (p->method == SSCG_HANKEL) {
     CHK(ensure(c, c->v64, (size_t)L * vec));
     launch_pack(v, c->v64.p, 0, L, c->V, st);
-    std::vector<cd> Gv;  // [a][l N + j] = <v_a, y_{l,j}>
-    CHK(gram(c, c->v64.p, L, c->Ybuf.p, L * N, Gv, st));
-    std::vector<cd> mu((size_t)K * L * L, cd(0, 0));
-    for (int k = 0; k < K; ++k)
-      for (int j = 0; j < N; ++j) {
-        const cd cc = w[j] * std::pow(zeta[j], k);
-        for (int a = 0; a < L; ++a)
-          for (int l = 0; l < L; ++l) mu[((size_t)k * L + a) * L + l] += cc * Gv[(size_t)a * L * N + (size_t)l * N + j];
-      }
-    const int m = M * L;
-    std::vector<cd> H((size_t)m * m), Hs((size_t)m * m);
-    for (int bi = 0; bi < M; ++bi)
-      for (int bj = 0; bj < M; ++bj)
-        for (int a = 0; a < L; ++a)
-          for (int l = 0; l < L; ++l) {
-            H[(size_t)(bi * L + a) * m + bj * L + l] = mu[((size_t)(bi + bj) * L + a) * L + l];
-            Hs[(size_t)(bi * L + a) * m + bj * L + l] = mu[((size_t)(bi + bj + 1) * L + a) * L + l];
-          }
-    // H is Hermitian positive semidefinite for a real filter (f_0 > 0 on the real
-    // axis for both paths); reduce on its dominant eigenvectors.
-    std::vector<double> ev;
-    std::vector<cd> W;
-    eig_rowmajor(m, H, ev, W);
-    const double emax = ev.back();
-    std::vector<int> keep;
-    for (int k = m - 1; k >= 0; --k)
-      if (ev[k] > p->rank_tol * emax) keep.push_back(k);
-    r = (int)keep.size();
-    if (r == 0) return fail(c, SSCG_EBREAKDOWN, "Hankel matrix has rank 0");
-    std::vector<cd> Wr((size_t)m * r);
-    for (int a = 0; a < m; ++a)
-      for (int q = 0; q < r; ++q) Wr[(size_t)a * r + q] = W[(size_t)a * m + keep[q]] / std::sqrt(ev[keep[q]]);
-    std::vector<cd> red((size_t)r * r, cd(0, 0));
-    for (int q1 = 0; q1 < r; ++q1)
-      for (int q2 = 0; q2 < r; ++q2) {
-        cd s = 0;
-        for (int a = 0; a < m; ++a) {
-          cd t = 0;
-          for (int b = 0; b < m; ++b) t += Hs[(size_t)a * m + b] * Wr[(size_t)b * r + q2];
-          s += std::conj(Wr[(size_t)a * r + q1]) * t;
-        }
-        red[(size_t)q1 * r + q2] = s;
-      }
-    std::vector<double> eta;
-    std::vector<cd> T;
-    eig_rowmajor(r, red, eta, T);
-    lam.resize(r);
-    for (int q = 0; q < r; ++q) lam[q] = p->gamma + p->rho * eta[q];
-    Tc.assign((size_t)m * r, cd(0, 0));
-    for (int a = 0; a < m; ++a)
-      for (int q = 0; q < r; ++q) {
-        cd s = 0;
-        for (int b = 0; b < r; ++b) s += Wr[(size_t)a * r + b] * T[(size_t)b * r + q];
-        Tc[(size_t)a * r + q] = s;
-      }
-    CHK(basis_change(c, c->Sbuf.p, m, Tc, r, Xd, st));
-    CHK(apply_A_planar(c, Xd, AXd, r, st));
+    CHK(gram(c, c->v64.p, L, c->Ybuf.p, L * Nall, Gv, st));  // [a][l Nall + j] = <v_a, y_{l,j}>
   }
-  std::vector<double> rs, xn;
-  CHK(col_residuals(c, AXd, Xd, r, lam, rs, xn, st));
-  // acceptance (Sec. 3)
-  double lo, hi, imax;
-  if (p->path == SSCG_PATH_LINES) {
-    std::vector<double> xr;
-    for (int j = 0; j < N; j += 2) xr.push_back(zeta[j].real());
-    std::vector<int> ord(xr.size());
-    for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(xr[a]) < std::fabs(xr[b]); });
-    double mn = 1e300, mx = -1e300;
-    for (int i = 0; i < Np / 2; ++i) {
-      mn = std::min(mn, xr[ord[i]]);
-      mx = std::max(mx, xr[ord[i]]);
+  std::vector<double> cf(2 * (size_t)M * N);
+  for (int k = 0; k < M; ++k)
+    for (int j = 0; j < N; ++j) {
+      const cd cc = w[j] * std::pow(zeta[j], k);
+      cf[2 * ((size_t)k * N + j)] = cc.real();
+      cf[2 * ((size_t)k * N + j) + 1] = cc.imag();
     }
-    lo = p->gamma + p->rho * mn;
-    hi = p->gamma + p->rho * mx;
-    imax = p->beta * p->rho;
-  } else {
-    lo = p->gamma - p->rho;
-    hi = p->gamma + p->rho;
-    imax = p->rho;
-  }
-  (void)imax;  // Ritz and Hermitian-Hankel values are real
-  std::vector<int> acc;
-  for (int q = 0; q < r; ++q)
-    if (lam[q] >= lo && lam[q] <= hi && rs[q] <= p->spur_tol) acc.push_back(q);
-  *n_found = (int)acc.size();
-  // keep the max_eigs nearest gamma, report ascending
-  std::vector<int> sel = acc;
-  std::stable_sort(sel.begin(), sel.end(), [&](int a, int b) { return std::fabs(lam[a] - p->gamma) < std::fabs(lam[b] - p->gamma); });
-  if ((int)sel.size() > max_eigs) sel.resize(max_eigs);
-  std::sort(sel.begin(), sel.end(), [&](int a, int b) { return lam[a] < lam[b]; });
-  for (size_t i = 0; i < sel.size(); ++i) {
-    lambda[i] = lam[sel[i]];
-    res[i] = rs[sel[i]];
-    if (X) {
-      // unit-normalised column, canonical layout
-      std::vector<double> one(1, xn[sel[i]] > 0 ? 1.0 / xn[sel[i]] : 1.0);
-      HIPCHK(c, hipMemcpyAsync(c->tmp.p, (const char *)Xd + (size_t)sel[i] * vec, vec, hipMemcpyDeviceToDevice, st));
-      CHK(ensure(c, c->small, sizeof(double)));
-      HIPCHK(c, hipMemcpyAsync(c->small.p, one.data(), sizeof(double), hipMemcpyHostToDevice, st));
-      launch_colscale(c->tmp.p, (int64_t)n, 1, (const double *)c->small.p, (int64_t)n, st);
-      launch_unpack(c->tmp.p, 0, (char *)X + i * vec, 1, c->V, st);
-      HIPCHK(c, hipStreamSynchronize(st));
+  // accepted pairs kept: at most max_eigs nearest gamma, their vectors in Acc slots
+  struct Acc {
+    double lam, res, dist;
+    int slot;
+  };
+  std::vector<Acc> acc;
+  int total_found = 0, rank_max = 0, ncand = 0;
+  if (X && max_eigs > 0) CHK(ensure(c, c->Accbuf, (size_t)max_eigs * vec));
+  for (int q = 0; q < P; ++q) {
+    auto tm0 = std::chrono::steady_clock::now();
+    CHK(ensure(c, c->small, cf.size() * sizeof(double)));
+    HIPCHK(c, hipMemcpyAsync(c->small.p, cf.data(), cf.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_moments_strided2((const char *)c->Ybuf.p + (size_t)offsets[q] * vec, L, N, (int64_t)Nall,
+                            (const double *)c->small.p, M, c->Sbuf.p, (int64_t)n, 1, L, st);
+    HIPCHK(c, hipStreamSynchronize(st));
+    t_mom += std::chrono::duration<double>(std::chrono::steady_clock::now() - tm0).count();
+    std::vector<double> lam;
+    int r = 0;
+    if (p->method == SSCG_RR) {
+      CHK(extract_rr(c, c->Sbuf.p, ncol, p->rank_tol, Xd, AXd, lam, r, st));
+    } else {
+      CHK(extract_hankel(c, Gv, L, Nall, offsets[q], N, M, zeta, w, centres[q], p->rho, p->rank_tol, c->Sbuf.p,
+                         Xd, AXd, lam, r, st));
+    }
+    rank_max = std::max(rank_max, r);
+    ncand += r;
+    if (r == 0) continue;
+    std::vector<double> rs, xn;
+    CHK(col_residuals(c, AXd, Xd, r, lam, rs, xn, st));
+    // acceptance (Sec. 3): the rectangle of the N' nodes nearest this pair's centre;
+    // half-open on the right except for the last pair, so a shared edge counts once
+    double lo, hi;
+    if (p->path == SSCG_PATH_LINES) {
+      std::vector<double> xr;
+      for (int j = 0; j < N; j += 2) xr.push_back(zeta[j].real());
+      std::vector<int> ord(xr.size());
+      for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(xr[a]) < std::fabs(xr[b]); });
+      double mn = 1e300, mx = -1e300;
+      for (int i = 0; i < Np / 2; ++i) {
+        mn = std::min(mn, xr[ord[i]]);
+        mx = std::max(mx, xr[ord[i]]);
+      }
+      lo = centres[q] + p->rho * mn;
+      hi = centres[q] + p->rho * mx;
+    } else {
+      lo = centres[q] - p->rho;
+      hi = centres[q] + p->rho;
+    }
+    for (int k = 0; k < r; ++k) {
+      const bool inside = lam[k] >= lo && (q < P - 1 ? lam[k] < hi : lam[k] <= hi);
+      if (!inside || !(rs[k] <= p->spur_tol)) continue;
+      ++total_found;
+      if (max_eigs == 0) continue;
+      const double dist = std::fabs(lam[k] - p->gamma);
+      int slot = -1;
+      if ((int)acc.size() < max_eigs) {
+        slot = (int)acc.size();
+        acc.push_back({lam[k], rs[k], dist, slot});
+      } else {
+        auto worst = std::max_element(acc.begin(), acc.end(), [](const Acc &a, const Acc &b) { return a.dist < b.dist; });
+        if (worst->dist <= dist) continue;
+        slot = worst->slot;
+        *worst = {lam[k], rs[k], dist, slot};
+      }
+      if (X) {
+        // unit-normalised copy of the candidate's vector into its slot
+        std::vector<double> one(1, xn[k] > 0 ? 1.0 / xn[k] : 1.0);
+        char *dst = (char *)c->Accbuf.p + (size_t)slot * vec;
+        HIPCHK(c, hipMemcpyAsync(dst, (const char *)Xd + (size_t)k * vec, vec, hipMemcpyDeviceToDevice, st));
+        CHK(ensure(c, c->small, sizeof(double)));
+        HIPCHK(c, hipMemcpyAsync(c->small.p, one.data(), sizeof(double), hipMemcpyHostToDevice, st));
+        launch_colscale(dst, (int64_t)n, 1, (const double *)c->small.p, (int64_t)n, st);
+        HIPCHK(c, hipStreamSynchronize(st));
+      }
     }
   }
+  std::sort(acc.begin(), acc.end(), [](const Acc &a, const Acc &b) { return a.lam < b.lam; });
+  *n_found = total_found;
+  for (size_t i = 0; i < acc.size(); ++i) {
+    lambda[i] = acc[i].lam;
+    res[i] = acc[i].res;
+    if (X) launch_unpack((const char *)c->Accbuf.p + (size_t)acc[i].slot * vec, 0, (char *)X + i * vec, 1, c->V, st);
+  }
+  HIPCHK(c, hipStreamSynchronize(st));
   auto t3 = std::chrono::steady_clock::now();
   if (info) {
-    info->rank = r;
-    info->n_candidates = r;
+    info->rank = rank_max;
+    info->n_candidates = ncand;
     info->iters = *std::max_element(iters.begin(), iters.end());
     info->solve_status = rc;
     info->t_solve = std::chrono::duration<double>(t1 - t0).count();
-    info->t_moments = std::chrono::duration<double>(t2 - t1).count();
-    info->t_extract = std::chrono::duration<double>(t3 - t2).count();
+    info->t_moments = t_mom;
+    info->t_extract = std::chrono::duration<double>(t3 - t1).count() - t_mom;
     int64_t su = 0, mv = 0;
     for (int l = 0; l < L; ++l) {
       mv += iters[l];
-      for (int j = 0; j < N; ++j) {
-        const int ci = conv[(size_t)l * N + j];
+      for (int j = 0; j < Nall; ++j) {
+        const int ci = conv[(size_t)l * Nall + j];
         su += ci >= 0 ? ci : iters[l];
       }
     }
     info->shift_updates = su;
-    info->matvecs = mv + r;  // seed products plus A Q (Rayleigh-Ritz) or A X (Hankel)
-    const int ks = P[0].switch_iter;
+    info->matvecs = mv + ncand;  // seed products plus A Q (Rayleigh-Ritz) or A X (Hankel)
+    const int ks = PP[0].switch_iter;
     int64_t su32 = 0, it32 = 0;
     if (ks >= 0)
       for (int l = 0; l < L; ++l) {
         it32 += std::max(0, iters[l] - ks);
-        for (int j = 0; j < N; ++j) {
-          const int ci = conv[(size_t)l * N + j];
+        for (int j = 0; j < Nall; ++j) {
+          const int ci = conv[(size_t)l * Nall + j];
           su32 += std::max(0, (ci >= 0 ? ci : iters[l]) - ks);
         }
       }
@@ -1357,6 +1433,5 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
     info->seed_iters_fp32 = it32;
     info->switch_iter = ks;
   }
-  HIPCHK(c, hipStreamSynchronize(st));
   return rc == SSCG_ENOTCONV ? SSCG_ENOTCONV : SSCG_OK;
 }

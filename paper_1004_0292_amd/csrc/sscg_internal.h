@@ -141,6 +141,9 @@ void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st)
 void launch_init_shifts(void *y, void *W, const void *v, int64_t n, int nsrc, int nshift, hipStream_t st);
 void launch_moments_strided(const void *y, int nsrc, int nshift, const double *c_dev, int nmom, void *s,
                             int64_t n, int64_t sl, int64_t sk, hipStream_t st);
+// y: [nsrc] blocks of y_stride_l vectors, the first nshift of each used
+void launch_moments_strided2(const void *y, int nsrc, int nshift, int64_t y_stride_l, const double *c_dev, int nmom,
+                             void *s, int64_t n, int64_t sl, int64_t sk, hipStream_t st);
 void launch_to_fp32(const void *src64, void *dst32, void *zero32, int64_t n, hipStream_t st);
 void launch_cast(const void *src, int src_prec, void *dst, int dst_prec, int64_t n, hipStream_t st);
 void launch_pack(const void *canon, void *planar, int prec, int nsrc, int V, hipStream_t st);

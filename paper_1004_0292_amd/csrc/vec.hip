@@ -572,8 +572,8 @@ __global__ __launch_bounds__(kBlock) void true_residual_kernel(const double2 *v,
 
 // s_{l,k} = sum_j c[k][j] y_{l,j}; grid (entry blocks, source, moment chunk)
 constexpr int kMomChunk = 8;
-__global__ __launch_bounds__(kBlock) void moments_kernel(const double2 *y, int nshift, const double2 *c,
-                                                         int nmom, double2 *s, int64_t n,
+__global__ __launch_bounds__(kBlock) void moments_kernel(const double2 *y, int nshift, int64_t y_stride_l,
+                                                         const double2 *c, int nmom, double2 *s, int64_t n,
                                                          int64_t s_stride_l, int64_t s_stride_k) {
   extern __shared__ double2 csh[];  // [kMomChunk][nshift]
   const int l = blockIdx.y;
@@ -589,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(const double2 *y, int n
   double2 acc[kMomChunk];
 #pragma unroll
   for (int kk = 0; kk < kMomChunk; ++kk) acc[kk] = make_double2(0, 0);
-  const double2 *yl = y + (size_t)l * nshift * n;
+  const double2 *yl = y + (size_t)l * y_stride_l * n;
   for (int j = 0; j < nshift; ++j) {
     const double2 yv = yl[(size_t)j * n + i];
 #pragma unroll
@@ -687,12 +687,16 @@ void launch_true_residual(const void *v, const void *y, const void *Ay, const do
   hipLaunchKernelGGL(true_residual_kernel, dim3(nblk, nvec), dim3(kBlock), 0, st, (const double2 *)v,
                      (const double2 *)y, (const double2 *)Ay, z, n, partial, nblk);
 }
-void launch_moments_strided(const void *y, int nsrc, int nshift, const double *c_dev, int nmom, void *s,
-                            int64_t n, int64_t sl, int64_t sk, hipStream_t st) {
+void launch_moments_strided2(const void *y, int nsrc, int nshift, int64_t y_stride_l, const double *c_dev, int nmom,
+                             void *s, int64_t n, int64_t sl, int64_t sk, hipStream_t st) {
   const dim3 grid(nblocks1d(n), nsrc, (nmom + kMomChunk - 1) / kMomChunk);
   const size_t shm = (size_t)kMomChunk * nshift * sizeof(double2);
-  hipLaunchKernelGGL(moments_kernel, grid, dim3(kBlock), shm, st, (const double2 *)y, nshift,
+  hipLaunchKernelGGL(moments_kernel, grid, dim3(kBlock), shm, st, (const double2 *)y, nshift, y_stride_l,
                      (const double2 *)c_dev, nmom, (double2 *)s, n, sl, sk);
+}
+void launch_moments_strided(const void *y, int nsrc, int nshift, const double *c_dev, int nmom, void *s,
+                            int64_t n, int64_t sl, int64_t sk, hipStream_t st) {
+  launch_moments_strided2(y, nsrc, nshift, nshift, c_dev, nmom, s, n, sl, sk, st);
 }
 void launch_moments(const void *y, int nsrc, int nshift, const double *c_dev, int nmom, void *s, int64_t n,
                     hipStream_t st) {

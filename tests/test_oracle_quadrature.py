@@ -134,3 +134,18 @@ def test_acceptance_interval():
     assert (lo, hi) == pytest.approx((-7 / 15, 7 / 15))
     with pytest.raises(ValueError):
         quad.acceptance_interval(zeta, 0.0, 1.0, 6 + 1)
+
+
+def test_adjacent_pairs_node_count_and_sharing():
+    # Table 2: six pairs with N = 32, N' = 16 use 32 + 5 * 14 = 102 nodes (128 for four circles of 32)
+    z_all, offsets, centres = quad.adjacent_pairs(32, 16, 6, 0.0, 0.02121, 0.2)
+    assert z_all.size == 102 == 32 + 5 * (16 - 2)
+    for p in range(6):
+        zp = z_all[offsets[p]:offsets[p] + 32]
+        z_ref, _ = quad.line_nodes(32, centres[p], 0.02121, 0.2)
+        assert np.abs(zp - z_ref).max() < 1e-15
+    # neighbouring acceptance rectangles share an edge and tile the whole range
+    _, zeta = quad.line_nodes(32, 0.0, 1.0, 0.2)
+    rects = [quad.acceptance_interval(zeta, c, 0.02121, 16) for c in centres]
+    for (lo1, hi1), (lo2, hi2) in zip(rects, rects[1:]):
+        assert hi1 == pytest.approx(lo2, abs=1e-15)

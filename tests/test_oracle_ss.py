@@ -137,3 +137,25 @@ def test_lowest_magnitude_eigs_matches_dense():
     ref = np.sort(lam[np.argsort(np.abs(lam))[:12]])
     assert np.abs(got - ref).max() < 1e-12
     assert np.linalg.norm(A @ X - X * got[None, :], axis=0).max() < 1e-9
+
+
+def test_adjacent_pairs_equal_separate_runs(spec):
+    """Three adjacent pairs over [0.205, 0.245] on the 4^4 field give, pair by pair, the
+    same accepted eigenvalues as three separate single-pair runs (Sec. 3)."""
+    A, lam, W = spec
+    V = synth.sources(CFG1.V, 2, 5).reshape(2, -1)
+    N, Np, P, rho, beta, M = 16, 8, 3, 0.012, 0.25, 6
+    out = ss.ss_eigs_adjacent(A, V, 0.225, rho, beta, N, M, Np, P, rank_tol=1e-7)
+    sep = []
+    for p, c in enumerate(out["centres"]):
+        o = ss.ss_eigs(A, V, c, rho, beta, N, M, Nprime=Np, rank_tol=1e-7)
+        _, zeta = quad.line_nodes(N, 0.0, 1.0, beta)
+        lo, hi = quad.acceptance_interval(zeta, c, rho, Np)
+        keep = (o["lam"] >= lo) & ((o["lam"] < hi) if p < P - 1 else (o["lam"] <= hi))
+        sep.extend(o["lam"][keep])
+    assert len(out["lam"]) == len(sep) > 0
+    assert np.abs(np.sort(out["lam"]) - np.sort(sep)).max() < 1e-12
+    lo_all = out["centres"][0] - rho * (Np // 2 - 1) / (N // 2 - 1)
+    hi_all = out["centres"][-1] + rho * (Np // 2 - 1) / (N // 2 - 1)
+    truth = lam[(lam >= lo_all) & (lam <= hi_all)]
+    assert np.abs(np.sort(out["lam"]) - truth).max() < 1e-10
