@@ -99,6 +99,86 @@ def cpu_baseline(w, budget_s=20.0):
             "host_cpus": os.cpu_count()}
 
 
+def tts_compare(S, ctx, params, vd, max_eigs, steps):
+    """Time to solution of the whole step in FP64 and in the FP64-seed / FP32-shift mode
+    on the same inputs (graph replay, no per-launch events)."""
+    import copy
+    import torch
+    out = {}
+    ctx.set_profiling(False)
+    for name, prec in (("fp64", S.FP64), ("mixed_shifts", S.MIXED_SHIFTS)):
+        p = copy.copy(params)
+        p.solve = copy.copy(params.solve)
+        p.solve.prec = prec
+        ctx.ss_eigs(p, vd, max_eigs=max_eigs)          # tune for this mode
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = ctx.ss_eigs(p, vd, max_eigs=max_eigs)
+        torch.cuda.synchronize()
+        out[name + "_ms_per_step"] = round((time.perf_counter() - t0) / steps * 1e3, 3)
+        out[name + "_eigs"] = r.lam.round(12).tolist()
+        out[name + "_max_res"] = float(r.res.max()) if len(r.res) else None
+    out["speedup_mixed_vs_fp64"] = round(out["fp64_ms_per_step"] / out["mixed_shifts_ms_per_step"], 3)
+    return out
+
+
+def bench_batch(args):
+    """The batched workload: three lattices (8^4, 12^4, 16^4) with their own intervals,
+    N and 4 sources solved together (one grouped launch per stage, graphs between polls)
+    versus the same three problems solved one after another in plain FP64."""
+    import numpy as np
+    import torch
+    import paper_1004_0292_amd as S
+    import synth
+    ws = [synth.CONFIGS[nm] for nm in synth.BATCH]
+    ctxs, vs, zs, ys = [], [], [], []
+    for w in ws:
+        c = S.Context(w.dims, w.kappa)
+        c.set_gauge(w.gauge())
+        ctxs.append(c)
+        vs.append(torch.from_numpy(w.sources()).to("cuda:0"))
+        z, _, _ = S.quad_lines(w.N, w.gamma, w.rho, w.beta)
+        zs.append(z)
+        ys.append(torch.zeros((w.L, w.N, w.n), dtype=torch.complex128, device="cuda:0"))
+    mixed = S.default_opts(prec=S.MIXED_SHIFTS, ru_interval=50, switch_tol=1e-6)
+    fp64 = S.default_opts(prec=S.FP64)
+
+    def batched():
+        return S.batch_solve(ctxs, vs, zs, [w.gamma for w in ws], ys, mixed, true_res=False)
+
+    def sequential():
+        return [c.shifted_cg_solve(v, z, w.gamma, y, fp64, true_res=False) for c, v, z, w, y in zip(ctxs, vs, zs, ws, ys)]
+
+    res = {}
+    for name, fn in (("batched_mixed", batched), ("sequential_fp64", sequential)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rr = fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        su = sum(int(np.where(r.conv_iter >= 0, r.conv_iter, r.iters[:, None]).sum()) for r in rr)
+        res[name] = {"ms_per_step": round(dt * 1e3, 3), "shift_updates": su, "value": round(su / dt, 1),
+                     "status": [int(r.status) for r in rr]}
+    line = {
+        "metric": METRIC, "value": res["batched_mixed"]["value"], "unit": "shift-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["batched_mixed"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "batch_8_12_16", "problems": [
+            {"lattice": list(w.dims), "kappa": w.kappa, "interval": [w.gamma - w.rho, w.gamma + w.rho], "N": w.N,
+             "L": w.L} for w in ws], "prec": "mixed_shifts", "parallelism": "single GPU, one grouped launch per stage"},
+        "tts": {"batched_mixed_ms": res["batched_mixed"]["ms_per_step"],
+                "sequential_fp64_ms": res["sequential_fp64"]["ms_per_step"],
+                "speedup": round(res["sequential_fp64"]["ms_per_step"] / res["batched_mixed"]["ms_per_step"], 3)},
+        "detail": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def copy_bandwidth(nbytes=2 << 30, reps=5):
     """Device-to-device copy rate (read + write bytes per second) as the achievable
     HBM reference next to the 8 TB/s peak."""
@@ -128,6 +208,7 @@ def main():
     ap.add_argument("--prec", default=None, choices=["fp64", "mixed", "mixed_shifts"],
                     help="override the workload's precision mode")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 vs mixed time-to-solution comparison")
     ap.add_argument("--no-events", action="store_true", help="time without per-launch events")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy five times (for counter scaling) and exit")
@@ -152,6 +233,9 @@ def main():
     import paper_1004_0292_amd as S
     import synth
 
+    if args.config == "batch":
+        bench_batch(args)
+        return
     w = synth.CONFIGS[args.config]
     mode = args.prec or w.prec
     prec = {"fp64": S.FP64, "mixed": S.MIXED, "mixed_shifts": S.MIXED_SHIFTS}[mode]
@@ -259,6 +343,8 @@ def main():
         "timing": ("direct launches with HIP events around every launch" if not args.no_events else "graph replay"),
         "value_graph_replay": round(graph_value, 1) if graph_value else None,
     }
+    if not args.no_compare:
+        line["tts"] = tts_compare(S, ctx, params, vd, max_eigs, args.steps)
     line["copy_bw_GBs"] = copy_bandwidth()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
