@@ -100,16 +100,19 @@ def cpu_baseline(w, budget_s=20.0):
 
 
 def tts_compare(S, ctx, params, vd, max_eigs, steps):
-    """Time to solution of the whole step in FP64 and in the FP64-seed / FP32-shift mode
-    on the same inputs (graph replay, no per-launch events)."""
+    """Time to solution of the whole step in FP64 and in the FP64-seed / FP32-shift mode,
+    each with stored solutions and with the moments summed inside the solve, on the
+    same inputs (graph replay, no per-launch events)."""
     import copy
     import torch
     out = {}
     ctx.set_profiling(False)
-    for name, prec in (("fp64", S.FP64), ("mixed_shifts", S.MIXED_SHIFTS)):
+    for name, prec, in_loop in (("fp64", S.FP64, 0), ("mixed_shifts", S.MIXED_SHIFTS, 0),
+                                ("fp64_inloop", S.FP64, 1), ("mixed_shifts_inloop", S.MIXED_SHIFTS, 1)):
         p = copy.copy(params)
         p.solve = copy.copy(params.solve)
         p.solve.prec = prec
+        p.moments_in_loop = in_loop
         ctx.ss_eigs(p, vd, max_eigs=max_eigs)          # tune for this mode
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -120,6 +123,7 @@ def tts_compare(S, ctx, params, vd, max_eigs, steps):
         out[name + "_eigs"] = r.lam.round(12).tolist()
         out[name + "_max_res"] = float(r.res.max()) if len(r.res) else None
     out["speedup_mixed_vs_fp64"] = round(out["fp64_ms_per_step"] / out["mixed_shifts_ms_per_step"], 3)
+    out["speedup_mixed_inloop_vs_fp64"] = round(out["fp64_ms_per_step"] / out["mixed_shifts_inloop_ms_per_step"], 3)
     return out
 
 
@@ -207,6 +211,9 @@ def main():
     ap.add_argument("--method", default="rr", choices=["rr", "hankel"])
     ap.add_argument("--prec", default=None, choices=["fp64", "mixed", "mixed_shifts"],
                     help="override the workload's precision mode")
+    ap.add_argument("--moments-in-loop", action="store_true",
+                    help="accumulate the moments inside the solve (no stored solutions)")
+    ap.add_argument("--weighted-tol", action="store_true", help="moment-weighted per-shift stopping")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 vs mixed time-to-solution comparison")
     ap.add_argument("--no-events", action="store_true", help="time without per-launch events")
@@ -249,7 +256,8 @@ def main():
     opts = S.default_opts(tol=w.tol, prec=prec, ru_interval=w.ru_interval, switch_tol=w.switch_tol)
     params = S.default_ss_params(gamma=w.gamma, rho=w.rho, beta=w.beta, N=w.N, M=w.M,
                                  method=S.RR if args.method == "rr" else S.HANKEL, rank_tol=1e-7,
-                                 spur_tol=1e-6, solve=opts)
+                                 spur_tol=1e-6, solve=opts, moments_in_loop=int(args.moments_in_loop),
+                                 weighted_tol=int(args.weighted_tol))
     max_eigs = min(w.M * w.L, 32)
     ctx.set_profiling(not args.no_events)
     for _ in range(args.warmup):
@@ -297,6 +305,11 @@ def main():
     # read once and seed p read and written once per (source, entry, iteration)
     # (the seed vectors are FP32 in the FP32 phase only in the "mixed" mode)
     shift_bytes = (su64 * 64 + it64 * 48) * n + (su32 * 32 + it32 * (24 if seed32 else 48)) * n
+    if args.moments_in_loop:
+        # p_j read and written per active (shift, source, entry); per (source, entry,
+        # iteration) the seed r read, the seed p read and written, and the M moments read
+        # and written
+        shift_bytes = (su64 * 32 + su32 * 16 + (it64 + it32) * (48 + 32 * w.M)) * n
     # dslash: spinor in and out per (source, site) and the four forward links per site
     dslash_bytes = (it64 * 48 * 8 + it32 * 48 * (4 if seed32 else 8)) * w.V
     dslash_bytes += (link_launches[0] * 18 * 8 +
@@ -332,7 +345,8 @@ def main():
         "config": {"workload": w.name, "lattice": list(w.dims), "kappa": w.kappa, "eps": w.eps, "seed": w.seed,
                    "interval": [w.gamma - w.rho, w.gamma + w.rho], "beta": w.beta, "N": w.N, "L": w.L,
                    "M": w.M, "tol": w.tol, "prec": mode, "link_reals": w.link_reals,
-                   "method": args.method, "parallelism": "single GPU"},
+                   "method": args.method, "moments_in_loop": bool(args.moments_in_loop),
+                   "weighted_tol": bool(args.weighted_tol), "parallelism": "single GPU"},
         "roofline": rep[dominant],
         "dslash": rep["dslash"],
         "site_shift_updates_per_s": round(value * w.V, 1),

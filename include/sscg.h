@@ -149,6 +149,20 @@ typedef struct {
                                acceptance rectangle, the pairs are centred on gamma
                                as a group and share nodes, all distinct nodes are
                                solved by one shifted CG; 1 = a single pair         */
+  int32_t moments_in_loop;  /* 1: accumulate the moments of eq. (2) inside the solve:
+                               each shift's step alpha_j p_j is added to every
+                               s_k = sum_j w_j zeta_j^k y_j as it is made, so the
+                               solutions y_j are never stored (one fewer vector
+                               read and write per shift and iteration). Needs the
+                               Rayleigh-Ritz method, npairs * M <= 32 and a solve
+                               precision of SSCG_FP64 or SSCG_MIXED_SHIFTS, else
+                               SSCG_EINVAL. 0: solutions stored, moments after the
+                               solve.                                               */
+  int32_t weighted_tol;     /* 1: shift j stops at tol * m / m_j, where m_j is the
+                               largest |w_j zeta_j^k| over the moments (and pairs)
+                               it enters and m the largest m_j: every shift's
+                               contribution to the moments then carries at most the
+                               error of the largest-weight shift at tol. 0: one tol */
   int32_t pad;
 } sscg_ss_params;
 

@@ -70,7 +70,7 @@ class ShiftedCGResult:
 
 
 def shifted_cg(A_mul, v: np.ndarray, z: np.ndarray, sigma: float, tol: float = 1e-12,
-               maxiter: int = 100000, record=None):
+               maxiter: int = 100000, record=None, tol_scale=None):
     """Shifted CG with a real Hermitian seed (Sec. 2.2).
 
     Seed matrix B = sigma I - A (Hermitian because sigma is real); shift j is
@@ -92,7 +92,8 @@ def shifted_cg(A_mul, v: np.ndarray, z: np.ndarray, sigma: float, tol: float = 1
     beta_{-1} = 0.
     Stopping rule (reading of Sec. 4's criterion, applied per shift): after its update
     in iteration k, shift j freezes once sqrt(rho_{k+1}) / |pi_{j,k+1}| <= tol ||v||;
-    conv_iter[j] = k + 1. The run ends when every shift has frozen.
+    conv_iter[j] = k + 1. The run ends when every shift has frozen. tol_scale (one
+    factor per shift) replaces tol by tol * tol_scale[j] for shift j.
 
     A_mul(x) applies A to one vector. record(k, state) is called after every
     iteration when given (used to compare iterates at a fixed k).
@@ -114,6 +115,7 @@ def shifted_cg(A_mul, v: np.ndarray, z: np.ndarray, sigma: float, tol: float = 1
     alpha_prev, beta_prev = 1.0, 0.0
     active = np.ones(N, dtype=bool)
     conv_iter = np.full(N, -1, dtype=np.int64)
+    thr = tol * vnorm * (np.ones(N) if tol_scale is None else np.asarray(tol_scale, dtype=np.float64))
     status = "notconv"
     k = 0
     for k in range(maxiter):
@@ -135,7 +137,7 @@ def shifted_cg(A_mul, v: np.ndarray, z: np.ndarray, sigma: float, tol: float = 1
         X[act] += a_j[act, None] * P[act]
         P[act] = r[None, :] / pi_next[act, None] + b_j[act, None] * P[act]
         p = r + beta * p
-        newly = active & (np.sqrt(rho_next) / np.abs(pi_next) <= tol * vnorm)
+        newly = active & (np.sqrt(rho_next) / np.abs(pi_next) <= thr)
         conv_iter[newly] = k + 1
         active &= ~newly
         pi_prev, pi_cur = pi_cur, pi_next

@@ -111,14 +111,31 @@ def lowest_magnitude_eigs(A, k: int, tol: float = 1e-12):
     return lam, Q @ W
 
 
+def weighted_tol_scale(coefs) -> np.ndarray:
+    """Per-node tolerance multipliers for moment-weighted stopping.
+
+    coefs: one [M][N_nodes] coefficient array c[k][j] = w_j zeta_j^k per pair (zero
+    where a node is not in the pair). The moments use y_j only through c[k][j] y_j,
+    so an error e_j in y_j enters them as |c[k][j]| e_j. Node j may stop at
+    tol * m / m_j with m_j = max over pairs and k of |c[k][j]| and m = max_j m_j: its
+    contribution then carries no more error than the largest-weight node at tol.
+    (Nodes with m_j below 1e-12 m take the factor 1e12.)
+    """
+    m_j = np.max([np.abs(c).max(axis=0) for c in coefs], axis=0)
+    m = m_j.max()
+    return np.where(m_j > 1e-12 * m, m / np.maximum(m_j, 1e-300), 1e12)
+
+
 def ss_eigs(A, Vsrc: np.ndarray, gamma: float, rho: float, beta: float, N: int, M: int,
             tol: float = 1e-12, method: str = "rr", path: str = "lines", Nprime: int | None = None,
-            rank_tol: float = 1e-10, spur_tol: float = 1e-6, maxiter: int = 100000):
+            rank_tol: float = 1e-10, spur_tol: float = 1e-6, maxiter: int = 100000,
+            weighted_tol: bool = False):
     """Full pipeline: quadrature, shifted CG per source, moments, extraction, acceptance.
 
     A: scipy sparse (or anything with @). Vsrc: [L][n]. Returns a dict with the
     accepted eigenvalues, unit eigenvectors (columns), residuals, and the
-    intermediate quantities.
+    intermediate quantities. weighted_tol: per-node stopping tolerances from
+    weighted_tol_scale (the shifted CG then stops each node by its moment weight).
     """
     if path == "lines":
         z, zeta = quad.line_nodes(N, gamma, rho, beta)
@@ -132,7 +149,8 @@ def ss_eigs(A, Vsrc: np.ndarray, gamma: float, rho: float, beta: float, N: int, 
     else:
         raise ValueError(path)
     A_mul = lambda x: A @ x
-    runs = [shifted_cg(A_mul, v, z, gamma, tol, maxiter) for v in Vsrc]
+    ts = weighted_tol_scale([quad.moment_coefficients(zeta, w, M)]) if weighted_tol else None
+    runs = [shifted_cg(A_mul, v, z, gamma, tol, maxiter, tol_scale=ts) for v in Vsrc]
     Y = np.array([r.Y for r in runs])
     S = moments(Y, zeta, w, M)
     Sh = s_hat(S)
@@ -151,7 +169,7 @@ def ss_eigs(A, Vsrc: np.ndarray, gamma: float, rho: float, beta: float, N: int, 
 
 def ss_eigs_adjacent(A, Vsrc: np.ndarray, gamma: float, rho: float, beta: float, N: int, M: int,
                      Nprime: int, P: int, tol: float = 1e-12, rank_tol: float = 1e-10,
-                     spur_tol: float = 1e-6, maxiter: int = 100000):
+                     spur_tol: float = 1e-6, maxiter: int = 100000, weighted_tol: bool = False):
     """P adjacent line pairs sharing nodes (Sec. 3): one shifted CG over the distinct nodes,
     then per pair the moments eq. (2) over its own N nodes, Rayleigh-Ritz, and acceptance in
     its N' rectangle (half-open [lo, hi) except for the last pair, so an eigenvalue on a
@@ -160,7 +178,16 @@ def ss_eigs_adjacent(A, Vsrc: np.ndarray, gamma: float, rho: float, beta: float,
     _, zeta = quad.line_nodes(N, 0.0, 1.0, beta)
     w = quad.line_weights(zeta)
     A_mul = lambda x: A @ x
-    runs = [shifted_cg(A_mul, v, z_all, gamma, tol, maxiter) for v in Vsrc]
+    ts = None
+    if weighted_tol:
+        c = quad.moment_coefficients(zeta, w, M)
+        per_pair = []
+        for p in range(P):
+            cp = np.zeros((M, z_all.size), dtype=np.complex128)
+            cp[:, offsets[p]:offsets[p] + N] = c
+            per_pair.append(cp)
+        ts = weighted_tol_scale(per_pair)
+    runs = [shifted_cg(A_mul, v, z_all, gamma, tol, maxiter, tol_scale=ts) for v in Vsrc]
     Y_all = np.array([r.Y for r in runs])
     lams, Xs, ress = [], [], []
     for p in range(P):

@@ -45,7 +45,8 @@ class SSParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("rho", C.c_double), ("beta", C.c_double),
                 ("N", C.c_int32), ("M", C.c_int32), ("Nprime", C.c_int32), ("path", C.c_int32),
                 ("method", C.c_int32), ("rank_tol", C.c_double), ("spur_tol", C.c_double),
-                ("solve", SolveOpts), ("npairs", C.c_int32), ("pad", C.c_int32)]
+                ("solve", SolveOpts), ("npairs", C.c_int32), ("moments_in_loop", C.c_int32),
+                ("weighted_tol", C.c_int32), ("pad", C.c_int32)]
 
 
 class SSInfo(C.Structure):

@@ -61,10 +61,12 @@ struct sscg_ctx {
   // or chosen per problem shape by the autotuner (SSCG_AUTOTUNE=0 disables it)
   Tune tune;
   bool autotune = true;
+  int px = 0;        // x-piece width of the dslash traversal order (0: lexicographic)
+  int dorder = 1;    // dslash block order (1: all source groups of a site tile adjacent)
   std::map<std::string, Tune> tuned;
   // solver workspaces
   DevBuf v64, r64, p64, q64, W, r32, p32, q32, rbase, xpart64, xpart32, tmp, pq_part, rr_part, seed,
-      shift, zdev, small, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out;
+      shift, zdev, small, cmom, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out;
   SeedState *seed_host = nullptr;
   int seed_host_cap = 0;
   // profiling
@@ -156,6 +158,9 @@ int sscg_create(sscg_ctx **out, const int32_t dims[4], double kappa, double r, i
   c->tune.wbatch = env_int("SSCG_WBATCH", 8);
   c->tune.xcd = env_int("SSCG_XCD", 1);
   c->tune.unroll = env_int("SSCG_UNROLL", 2);
+  c->px = env_int("SSCG_PX", 0);
+  c->dorder = env_int("SSCG_DORDER", 1) ? 1 : 0;
+  if (c->px < 0 || c->px > dims[0] || dims[0] % std::max(c->px, 1) != 0) c->px = 0;
   c->tune.nt = env_int("SSCG_NT", 0);
   c->autotune = env_int("SSCG_AUTOTUNE", 1) != 0 && !getenv("SSCG_NR") && !getenv("SSCG_BS") &&
                 !getenv("SSCG_WBATCH") && !getenv("SSCG_XCD") && !getenv("SSCG_UNROLL") && !getenv("SSCG_NT");
@@ -172,7 +177,7 @@ void sscg_destroy(sscg_ctx *c) {
   hipStreamSynchronize(c->work);
   DevBuf *bufs[] = {&c->g64, &c->g32, &c->v64, &c->r64, &c->p64, &c->q64, &c->W, &c->r32, &c->p32,
                     &c->q32, &c->rbase, &c->xpart64, &c->xpart32, &c->tmp, &c->pq_part, &c->rr_part,
-                    &c->seed, &c->shift, &c->zdev, &c->small, &c->Ybuf, &c->Sbuf, &c->Qbuf, &c->AQbuf,
+                    &c->seed, &c->shift, &c->zdev, &c->small, &c->cmom, &c->Ybuf, &c->Sbuf, &c->Qbuf, &c->AQbuf,
                     &c->Xbuf, &c->AXbuf, &c->Accbuf, &c->apply_in, &c->apply_out};
   for (DevBuf *b : bufs) release(*b);
   if (c->seed_host) hipHostFree(c->seed_host);
@@ -266,6 +271,8 @@ static void dslash_plain(sscg_ctx *c, const void *in, void *out, int nsrc, int p
   j.block_begin = 0;
   j.nblocks = j.nblk_site * ((nsrc + c->tune.nr - 1) / c->tune.nr);
   j.mode = mode;
+  j.px = c->px;
+  j.order = c->dorder;
   b.njobs = 1;
   b.total_blocks = j.nblocks;
   launch_dslash(b, prec, c->tune.nr, prec == 0 ? 18 : c->link_reals, c->tune.bs, c->tune.xcd, st);
@@ -305,17 +312,25 @@ struct Prob {
   int32_t *iters = nullptr;
   int status = SSCG_OK;
   int switch_iter = -1;   // iteration at which the FP32 phase began (output)
+  // moments accumulated inside the solve (y == nullptr then): S device FP64
+  // planar [nmom][L][n] (zeroed by the caller), coefficients device [nmom][N]
+  void *mom = nullptr;
+  const void *mom_coef = nullptr;
+  int nmom = 0;
+  std::vector<double> tscale;  // per-shift tolerance multipliers (empty: all 1)
 };
 
 struct IterPlan {
   DslashBatch d64, d32, dru;
   ScalarBatch alpha, scal;
   VecBatch r64, r32, u64, u32, u32s, fold_seed, rel;
+  VecBatch m64, m32;  // shift update with in-loop moments (FP64 / FP32 shift vectors)
+  int nmom_max;       // 0: the solutions are stored
 };
 
 static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts &o, const Tune &t) {
   memset(&pl, 0, sizeof(pl));
-  int bd = 0, bdru = 0, bs = 0, bv = 0, bu = 0;
+  int bd = 0, bdru = 0, bs = 0, bv = 0, bu = 0, bm = 0;
   const int np = (int)P.size();
   for (int i = 0; i < np; ++i) {
     sscg_ctx *c = P[i].c;
@@ -329,6 +344,8 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
       j.kappa = c->kappa; j.sigma = P[i].sigma;
       for (int k = 0; k < 4; ++k) j.dims[k] = c->dims[k];
       j.V = c->V; j.nsrc = L; j.nblk_site = nbs; j.block_begin = begin; j.nblocks = nbs * groups; j.mode = 1;
+      j.px = c->px;
+      j.order = c->dorder;
     };
     mk_d(pl.d64.job[i], c->p64.p, c->q64.p, c->g64.p, (double *)c->pq_part.p, bd);
     mk_d(pl.d32.job[i], c->p32.p, c->q32.p, c->g32.p, (double *)c->pq_part.p, bd);
@@ -357,7 +374,21 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
     mk_v(pl.u32.job[i], P[i].y, c->W.p, c->r32.p, c->p32.p, bu, L * nbatch * nbv);
     mk_v(pl.u32s.job[i], P[i].y, c->W.p, c->r64.p, c->p64.p, bu, L * nbatch * nbv);
     bu += L * nbatch * nbv;
+    if (P[i].nmom > 0) {
+      const int nbm = (int)((c->n + kMomBlock - 1) / kMomBlock);
+      for (VecBatch *mb : {&pl.m64, &pl.m32}) {
+        VecJob &j = mb->job[i];
+        mk_v(j, P[i].mom, c->W.p, c->r64.p, c->p64.p, bm, L * nbm);
+        j.e = const_cast<void *>(P[i].mom_coef);
+        j.nmom = P[i].nmom;
+        j.nblk_mom = nbm;
+      }
+      bm += L * nbm;
+      pl.nmom_max = std::max(pl.nmom_max, P[i].nmom);
+    }
   }
+  pl.m64.njobs = pl.m32.njobs = np;
+  pl.m64.total_blocks = pl.m32.total_blocks = bm;
   pl.d64.njobs = pl.d32.njobs = pl.dru.njobs = np;
   pl.d64.total_blocks = pl.d32.total_blocks = bd;
   pl.dru.total_blocks = bdru;
@@ -435,6 +466,10 @@ static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru,
   rec.mark(ST_SCAL);
   launch_shift_scalars(pl.scal, st);
   rec.mark(ST_SHIFT);
+  if (pl.nmom_max > 0) {  // FP64 seed in both phases (checked by run_solve)
+    launch_shift_moments(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, st);
+    return;
+  }
   const VecBatch &u = prec == 0 ? pl.u64 : (sp == 1 ? pl.u32 : pl.u32s);
   launch_shift_update(u, prec, sp, prec == 1 && ru, t.unroll, t.nt, st);
 }
@@ -502,6 +537,7 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
       h.pi_prev = h.pi_cur = make_double2(1.0, 0.0);
       h.active = 1;
       h.conv_iter = -1;
+      h.tscale = p.tscale.empty() ? 1.0 : p.tscale[j];
     }
   HIPCHK(c, hipMemcpyAsync(c->seed.p, seeds.data(), L * sizeof(SeedState), hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(c->shift.p, sh.data(), L * N * sizeof(ShiftState), hipMemcpyHostToDevice, st));
@@ -592,8 +628,11 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
         }
       }
   }
-  // fused shift update as an identity on the current data
+  // fused shift update as an identity on the current data (not used, and not
+  // timed, when the moments are accumulated in the loop: there is no y_j)
+  const bool tune_update = P[0].nmom == 0;
   for (Prob &p : P) {
+    if (!tune_update) break;
     std::vector<ShiftState> sh((size_t)p.L * p.N);
     HIPCHK(p.c, hipMemcpy(sh.data(), p.c->shift.p, sh.size() * sizeof(ShiftState), hipMemcpyDeviceToHost));
     for (ShiftState &h : sh) {
@@ -611,6 +650,7 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
   tbest = 1e300;
   cand = best;
   for (int w : {2, 4, 8, 16, 32}) {
+    if (!tune_update) break;
     if (w > 2 && w / 2 >= maxN) continue;
     for (int u : {1, 2, 4}) {
       if (u > w) continue;
@@ -674,6 +714,9 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       HIPCHK(c0, hipStreamWaitEvent(st, p.c->ev_sync, 0));
     }
   }
+  for (Prob &p : P)
+    if ((p.nmom > 0) != (P[0].nmom > 0) || (p.nmom > 0 && (o.prec == SSCG_MIXED || p.nmom > 32 || !p.mom)))
+      return fail(c0, SSCG_EINVAL, "in-loop moments need an FP64 seed, at most 32 moments, and one mode per batch");
   int lr = 18;
   for (Prob &p : P) lr = std::min(lr, p.c->link_reals);
   for (Prob &p : P)
@@ -774,7 +817,8 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   if (rc != SSCG_OK) return rc;
   if (prec == 1) {
     // fold every shift's FP32 partial into its FP64 solution
-    for (Prob &p : P) launch_fold_shifts(p.y, p.c->W.p, p.c->n, p.L * p.N, st);
+    for (Prob &p : P)
+      if (p.y) launch_fold_shifts(p.y, p.c->W.p, p.c->n, p.L * p.N, st);
   }
   HIPCHK(c0, hipStreamSynchronize(st));
   auto t1 = std::chrono::steady_clock::now();
@@ -802,7 +846,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     if (st_p == SSCG_EBREAKDOWN) worst = SSCG_EBREAKDOWN;
     else if (st_p == SSCG_ENOTCONV && worst == SSCG_OK) worst = SSCG_ENOTCONV;
     // FP64 true residuals ||v - (z_j - A) y_j|| / ||v||
-    if (p.true_res) {
+    if (p.true_res && p.y) {
       const size_t n = c->n, vec64 = n * sizeof(double2);
       const int nb = 64;
       for (int l = 0; l < L; ++l) {
@@ -818,7 +862,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
         }
       }
     }
-    if (!p.keep_planar) {
+    if (!p.keep_planar && p.y) {
       const size_t n = c->n, vec64 = n * sizeof(double2);
       for (size_t kk = 0; kk < (size_t)L * N; ++kk) {
         char *slot = (char *)p.y + kk * vec64;
@@ -1004,6 +1048,9 @@ void sscg_default_ss_params(sscg_ss_params *p) {
   p->rank_tol = 1e-7;
   p->spur_tol = 1e-6;
   p->npairs = 1;
+  p->moments_in_loop = 0;
+  p->weighted_tol = 0;
+  p->pad = 0;
   sscg_default_opts(&p->solve);
 }
 
@@ -1263,8 +1310,46 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   }
   const int Nall = (int)z_all.size();
   if (Nall > 4096) return fail(c, SSCG_EINVAL, "too many distinct nodes");
-  // one shifted CG for all distinct nodes into the internal (planar) solution buffer
-  CHK(ensure(c, c->Ybuf, (size_t)L * Nall * vec));
+  const bool in_loop = p->moments_in_loop != 0;
+  if (in_loop && (p->method != SSCG_RR || P * M > 32 || p->solve.prec == SSCG_MIXED))
+    return fail(c, SSCG_EINVAL, "in-loop moments need Rayleigh-Ritz, npairs * M <= 32 and an FP64 seed");
+  const int ncol = M * L;
+  // moment coefficients c[k][j] = w_j zeta_j^k of one pair (eq. 2)
+  std::vector<double> cf(2 * (size_t)M * N);
+  for (int k = 0; k < M; ++k)
+    for (int j = 0; j < N; ++j) {
+      const cd cc = w[j] * std::pow(zeta[j], k);
+      cf[2 * ((size_t)k * N + j)] = cc.real();
+      cf[2 * ((size_t)k * N + j) + 1] = cc.imag();
+    }
+  hipStream_t st = c->work;
+  // largest moment coefficient per distinct node over every pair it belongs to
+  std::vector<double> cmax(Nall, 0.0);
+  for (int q = 0; q < P; ++q)
+    for (int k = 0; k < M; ++k)
+      for (int j = 0; j < N; ++j)
+        cmax[offsets[q] + j] = std::max(cmax[offsets[q] + j], std::hypot(cf[2 * ((size_t)k * N + j)],
+                                                                           cf[2 * ((size_t)k * N + j) + 1]));
+  if (in_loop) {
+    // pair q's moments are rows q M .. q M + M - 1 of one [P M][Nall] coefficient
+    // matrix over the distinct nodes (zero outside the pair's N nodes), so the
+    // moment sums of every pair are accumulated by the one solve
+    std::vector<double> cm(2 * (size_t)P * M * Nall, 0.0);
+    for (int q = 0; q < P; ++q)
+      for (int k = 0; k < M; ++k)
+        for (int j = 0; j < N; ++j) {
+          const size_t dst = 2 * ((size_t)(q * M + k) * Nall + offsets[q] + j);
+          cm[dst] = cf[2 * ((size_t)k * N + j)];
+          cm[dst + 1] = cf[2 * ((size_t)k * N + j) + 1];
+        }
+    CHK(ensure(c, c->cmom, cm.size() * sizeof(double)));
+    CHK(ensure(c, c->Sbuf, (size_t)P * ncol * vec));
+    HIPCHK(c, hipMemcpyAsync(c->cmom.p, cm.data(), cm.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemsetAsync(c->Sbuf.p, 0, (size_t)P * ncol * vec, st));
+  } else {
+    // one shifted CG for all distinct nodes into the internal (planar) solution buffer
+    CHK(ensure(c, c->Ybuf, (size_t)L * Nall * vec));
+  }
   std::vector<double> zd(2 * Nall);
   for (int j = 0; j < Nall; ++j) {
     zd[2 * j] = z_all[j].real();
@@ -1277,19 +1362,27 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   PP[0].N = Nall;
   PP[0].sigma = p->gamma;
   PP[0].z = zd;
-  PP[0].y = c->Ybuf.p;
+  PP[0].y = in_loop ? nullptr : c->Ybuf.p;
   PP[0].keep_planar = true;
+  if (p->weighted_tol) {
+    const double m = *std::max_element(cmax.begin(), cmax.end());
+    PP[0].tscale.resize(Nall);
+    for (int j = 0; j < Nall; ++j) PP[0].tscale[j] = cmax[j] > m * 1e-12 ? m / cmax[j] : 1e12;
+  }
+  if (in_loop) {
+    PP[0].mom = c->Sbuf.p;
+    PP[0].mom_coef = c->cmom.p;
+    PP[0].nmom = P * M;
+  }
   std::vector<int32_t> iters(L), conv((size_t)L * Nall);
   PP[0].iters = iters.data();
   PP[0].conv_iter = conv.data();
   auto t0 = std::chrono::steady_clock::now();
   int rc = run_solve(PP, p->solve);
   if (rc != SSCG_OK && rc != SSCG_ENOTCONV) return rc;
-  hipStream_t st = c->work;
   auto t1 = std::chrono::steady_clock::now();
   double t_mom = 0.0;
-  const int ncol = M * L;
-  CHK(ensure(c, c->Sbuf, (size_t)ncol * vec));
+  if (!in_loop) CHK(ensure(c, c->Sbuf, (size_t)ncol * vec));
   // X and AX buffers live in the shift workspace (free after the solve) when large enough
   void *Xd = nullptr, *AXd = nullptr;
   if (c->W.bytes >= 2 * (size_t)ncol * vec) {
@@ -1307,13 +1400,6 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
     launch_pack(v, c->v64.p, 0, L, c->V, st);
     CHK(gram(c, c->v64.p, L, c->Ybuf.p, L * Nall, Gv, st));  // [a][l Nall + j] = <v_a, y_{l,j}>
   }
-  std::vector<double> cf(2 * (size_t)M * N);
-  for (int k = 0; k < M; ++k)
-    for (int j = 0; j < N; ++j) {
-      const cd cc = w[j] * std::pow(zeta[j], k);
-      cf[2 * ((size_t)k * N + j)] = cc.real();
-      cf[2 * ((size_t)k * N + j) + 1] = cc.imag();
-    }
   // accepted pairs kept: at most max_eigs nearest gamma, their vectors in Acc slots
   struct Acc {
     double lam, res, dist;
@@ -1323,17 +1409,22 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   int total_found = 0, rank_max = 0, ncand = 0;
   if (X && max_eigs > 0) CHK(ensure(c, c->Accbuf, (size_t)max_eigs * vec));
   for (int q = 0; q < P; ++q) {
-    auto tm0 = std::chrono::steady_clock::now();
-    CHK(ensure(c, c->small, cf.size() * sizeof(double)));
-    HIPCHK(c, hipMemcpyAsync(c->small.p, cf.data(), cf.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_moments_strided2((const char *)c->Ybuf.p + (size_t)offsets[q] * vec, L, N, (int64_t)Nall,
-                            (const double *)c->small.p, M, c->Sbuf.p, (int64_t)n, 1, L, st);
-    HIPCHK(c, hipStreamSynchronize(st));
-    t_mom += std::chrono::duration<double>(std::chrono::steady_clock::now() - tm0).count();
+    const void *Sq = c->Sbuf.p;
+    if (in_loop) {
+      Sq = (const char *)c->Sbuf.p + (size_t)q * ncol * vec;
+    } else {
+      auto tm0 = std::chrono::steady_clock::now();
+      CHK(ensure(c, c->small, cf.size() * sizeof(double)));
+      HIPCHK(c, hipMemcpyAsync(c->small.p, cf.data(), cf.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      launch_moments_strided2((const char *)c->Ybuf.p + (size_t)offsets[q] * vec, L, N, (int64_t)Nall,
+                              (const double *)c->small.p, M, c->Sbuf.p, (int64_t)n, 1, L, st);
+      HIPCHK(c, hipStreamSynchronize(st));
+      t_mom += std::chrono::duration<double>(std::chrono::steady_clock::now() - tm0).count();
+    }
     std::vector<double> lam;
     int r = 0;
     if (p->method == SSCG_RR) {
-      CHK(extract_rr(c, c->Sbuf.p, ncol, p->rank_tol, Xd, AXd, lam, r, st));
+      CHK(extract_rr(c, Sq, ncol, p->rank_tol, Xd, AXd, lam, r, st));
     } else {
       CHK(extract_hankel(c, Gv, L, Nall, offsets[q], N, M, zeta, w, centres[q], p->rho, p->rank_tol, c->Sbuf.p,
                          Xd, AXd, lam, r, st));

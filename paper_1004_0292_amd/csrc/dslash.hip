@@ -166,7 +166,18 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
   const int ji = find_job(begins, B.njobs, b);
   const DslashJob &J = B.job[ji];
   const int lb = b - J.block_begin;
-  const int group = lb / J.nblk_site, sblk = lb - group * J.nblk_site;
+  // site-major order (J.order = 1): the source groups of one site tile are adjacent
+  // blocks, so after the XCD renumbering one XCD serves all sources of a lattice
+  // region and fetches its links once; group-major (0): one source at a time
+  const int groups = (J.nsrc + NR - 1) / NR;
+  int group, sblk;
+  if (J.order) {
+    sblk = lb / groups;
+    group = lb - sblk * groups;
+  } else {
+    group = lb / J.nblk_site;
+    sblk = lb - group * J.nblk_site;
+  }
   const int l0 = group * NR;
   const int nvalid = min(NR, J.nsrc - l0);
   if (J.seed) {
@@ -175,8 +186,25 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
     if (all_done) return;
   }
   const int V = J.V;
-  const int s = sblk * BS + threadIdx.x;
-  const bool valid = s < V;
+  const int ii = sblk * BS + threadIdx.x;  // position in the traversal order
+  const bool valid = ii < V;
+  // Traversal order: with px > 0 the lattice is walked in x-pieces of width px
+  // (order: piece, t, z, y, x within the piece), which shortens the distance between
+  // a site and its t- and z-neighbours in the order the blocks run; otherwise
+  // lexicographic. The data layout itself is lexicographic either way.
+  int s = ii;
+  if (J.px > 0 && valid) {
+    const int px = J.px, Ly = J.dims[1], Lz = J.dims[2], Lt = J.dims[3];
+    const int xl = ii % px;
+    int r2 = ii / px;
+    const int yy = r2 % Ly;
+    r2 /= Ly;
+    const int zz = r2 % Lz;
+    r2 /= Lz;
+    const int tt = r2 % Lt;
+    const int pc = r2 / Lt;
+    s = pc * px + xl + J.dims[0] * (yy + Ly * (zz + Lz * tt));
+  }
   const V2<T> *in = reinterpret_cast<const V2<T> *>(J.in) + (size_t)l0 * 12 * V;
   V2<T> *out = reinterpret_cast<V2<T> *>(J.out) + (size_t)l0 * 12 * V;
   const V2<T> *gauge = reinterpret_cast<const V2<T> *>(J.gauge);
@@ -236,7 +264,7 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
   if (J.partial) {
     // one partial per 64-site wavefront, at the wave's global index: the layout and
     // the summation order do not depend on the block size or sources per thread
-    const int wave = (sblk * BS + (int)threadIdx.x) >> 6;
+    const int wave = ii >> 6;
     const int npart = (V + 63) >> 6;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {

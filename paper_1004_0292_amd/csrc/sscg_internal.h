@@ -77,6 +77,8 @@ struct ShiftState {
   int32_t upd;               // apply the update of the current iteration
   int32_t conv_iter;         // iteration after which it froze, -1 if not yet
   int32_t pad;
+  double tscale;             // this shift's tolerance multiplier (1: the common tol)
+  double pad2;
 };
 
 // ---- job tables -------------------------------------------------------------
@@ -91,6 +93,8 @@ struct DslashJob {
   double kappa, sigma;   // out = sigma in - A in (mode 1) or A in (mode 0)
   int32_t dims[4];
   int32_t V, nsrc, nblk_site, block_begin, nblocks, mode;
+  int32_t px;            // x-piece width of the traversal order (0: lexicographic)
+  int32_t order;         // block order: 0 source groups outermost, 1 sites outermost
 };
 struct DslashBatch { DslashJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
 
@@ -102,6 +106,8 @@ struct VecJob {
   ShiftState *shift;     // [nsrc][nshift]
   int64_t n;             // complex entries per vector (12 V)
   int32_t nsrc, nshift, nblk_vec, block_begin, nblocks, wbatch;
+  int32_t nmom;          // moments accumulated inside the solve (0: none)
+  int32_t nblk_mom;      // blocks per source of the in-loop moment kernel
 };
 struct VecBatch { VecJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
 
@@ -136,6 +142,11 @@ void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st);
 void launch_shift_update(const VecBatch &b, int prec, int seed_prec, int fold, int unroll, int nt,
                          hipStream_t st);
 void launch_reliable_residual(const VecBatch &b, hipStream_t st);
+// Shift update with the moment sums accumulated in the loop (no stored x_j).
+// job: a = moments S (column k L + l of n entries), b = shift slots (p_j),
+// c = seed r, d = seed p (FP64), e = coefficients c[k][j] (device, [nmom][nshift]).
+constexpr int kMomBlock = 128;
+void launch_shift_moments(const VecBatch &b, int prec, int nmom_max, hipStream_t st);
 void launch_fold_seed(const VecBatch &b, hipStream_t st);
 void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st);
 void launch_init_shifts(void *y, void *W, const void *v, int64_t n, int nsrc, int nshift, hipStream_t st);

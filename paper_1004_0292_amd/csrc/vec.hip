@@ -129,7 +129,8 @@ __global__ __launch_bounds__(kBlock) void shift_scalars_kernel(ScalarBatch B) {
       H.pi_prev = pc;
       H.pi_cur = pn;
       H.upd = 1;
-      const double res = sq / hypot(pn.x, pn.y);
+      // residual in units of this shift's own tolerance scale
+      const double res = sq / hypot(pn.x, pn.y) / H.tscale;
       if (res <= thr) {
         H.active = 0;
         H.conv_iter = it + 1;
@@ -404,6 +405,81 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
   }
 }
 
+// Fused shift update with in-loop moment sums (eq. 2 accumulated as the solve runs):
+// for every shift updated in this iteration, the step alpha_j p_j that would be added
+// to x_j is instead added to every moment, s_{k,l} += c[k][j] alpha_j p_j, and p_j is
+// advanced as usual. One thread owns one entry of one source and loops over all
+// shifts, so each moment entry has a single writer; the shift vectors x_j are never
+// stored. Shift vectors are FP64 (T = double) or FP32 (after the FP32 switch); the
+// seed and the moments stay FP64.
+template <typename T, int MM>
+__global__ __launch_bounds__(kMomBlock) void shift_moments_kernel(VecBatch B) {
+  constexpr int JC = 64;  // shifts whose coefficients are staged in LDS at once
+  __shared__ double2 cs[MM * JC];
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int lb = b - J.block_begin;
+  const int l = lb / J.nblk_mom, vb = lb - l * J.nblk_mom;
+  const SeedState &S = J.seed[l];
+  if (!S.pending) return;
+  const int64_t n = J.n;
+  const int M = J.nmom, N = J.nshift;
+  const int64_t i = (int64_t)vb * kMomBlock + threadIdx.x;
+  const bool valid = i < n;
+  const double2 rv = valid ? reinterpret_cast<const double2 *>(J.c)[(size_t)l * n + i] : make_double2(0, 0);
+  double2 acc[MM];
+#pragma unroll
+  for (int k = 0; k < MM; ++k) acc[k] = make_double2(0, 0);
+  const double2 *cf = reinterpret_cast<const double2 *>(J.e);
+  for (int j0 = 0; j0 < N; j0 += JC) {
+    const int jn = min(JC, N - j0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < MM * JC; t += kMomBlock) {
+      const int k = t / JC, jj = t - k * JC;
+      cs[t] = (k < M && jj < jn) ? cf[(size_t)k * N + j0 + jj] : make_double2(0, 0);
+    }
+    __syncthreads();
+    for (int jj = 0; jj < jn; ++jj) {
+      const int j = j0 + jj;
+      const ShiftState &H = J.shift[(size_t)l * N + j];
+      if (!H.upd || !valid) continue;
+      const size_t slot = (size_t)l * N + j;
+      double2 pv;
+      if constexpr (sizeof(T) == 8) pv = reinterpret_cast<const double2 *>(J.b)[slot * n + i];
+      else {
+        const float2 pf = reinterpret_cast<const float2 *>(reinterpret_cast<const double2 *>(J.b) + slot * n)[i];
+        pv = make_double2(pf.x, pf.y);
+      }
+      const double2 d = cmul(H.a, pv);  // alpha_j p_j
+#pragma unroll
+      for (int k = 0; k < MM; ++k)
+        if (k < M) cfma(acc[k], cs[k * JC + jj], d);
+      double2 pn = cmul(H.ipi, rv);
+      cfma(pn, H.b, pv);
+      if constexpr (sizeof(T) == 8) reinterpret_cast<double2 *>(J.b)[slot * n + i] = pn;
+      else reinterpret_cast<float2 *>(reinterpret_cast<double2 *>(J.b) + slot * n)[i] = make_float2((float)pn.x, (float)pn.y);
+    }
+  }
+  if (!valid) return;
+  double2 *Sm = reinterpret_cast<double2 *>(J.a);
+#pragma unroll
+  for (int k = 0; k < MM; ++k) {
+    if (k < M) {
+      double2 *sp = Sm + ((size_t)k * J.nsrc + l) * n + i;
+      double2 v = *sp;
+      v.x += acc[k].x;
+      v.y += acc[k].y;
+      *sp = v;
+    }
+  }
+  // seed direction p <- r + beta p
+  double2 *p = reinterpret_cast<double2 *>(J.d) + (size_t)l * n;
+  double2 pv = p[i];
+  pv.x = rv.x + S.beta_prev * pv.x;
+  pv.y = rv.y + S.beta_prev * pv.y;
+  p[i] = pv;
+}
+
 // Reliable update: r64 = r_base - B x_part (q = B x_part already computed in FP64),
 // r32 = (float) r64, partial <r64, r64>. job: a = r_base, b = q64, c = r64, d = r32.
 __global__ __launch_bounds__(kBlock) void reliable_residual_kernel(VecBatch B) {
@@ -466,7 +542,7 @@ __global__ void init_shifts_kernel(double2 *y, double2 *W, const double2 *v, int
   if (i >= n) return;
   const size_t l = slot / nshift;
   W[slot * n + i] = v[l * n + i];
-  y[slot * n + i] = make_double2(0.0, 0.0);
+  if (y) y[slot * n + i] = make_double2(0.0, 0.0);
 }
 
 // End of an FP32 phase: x_j += x_part_j, x_part_j = 0 for every (source, shift)
@@ -633,6 +709,18 @@ void launch_shift_update(const VecBatch &b, int prec, int seed_prec, int fold, i
     if (fold) launch_su_u<float, float, true>(b, unroll, nt, st);
     else launch_su_u<float, float, false>(b, unroll, nt, st);
   }
+}
+template <typename T>
+static void launch_sm(const VecBatch &b, int mm, hipStream_t st) {
+  if (mm <= 8) hipLaunchKernelGGL((shift_moments_kernel<T, 8>), dim3(b.total_blocks), dim3(kMomBlock), 0, st, b);
+  else if (mm <= 16) hipLaunchKernelGGL((shift_moments_kernel<T, 16>), dim3(b.total_blocks), dim3(kMomBlock), 0, st, b);
+  else if (mm <= 24) hipLaunchKernelGGL((shift_moments_kernel<T, 24>), dim3(b.total_blocks), dim3(kMomBlock), 0, st, b);
+  else hipLaunchKernelGGL((shift_moments_kernel<T, 32>), dim3(b.total_blocks), dim3(kMomBlock), 0, st, b);
+}
+void launch_shift_moments(const VecBatch &b, int prec, int nmom_max, hipStream_t st) {
+  if (b.total_blocks <= 0) return;
+  if (prec == 0) launch_sm<double>(b, nmom_max, st);
+  else launch_sm<float>(b, nmom_max, st);
 }
 void launch_reliable_residual(const VecBatch &b, hipStream_t st) {
   hipLaunchKernelGGL(reliable_residual_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);

@@ -97,3 +97,30 @@ def test_create_rejects_bad_lattice(sscg):
     with pytest.raises(sscg.SSCGError) as e:
         sscg.Context((4, 4, 4, 4), 0.12, r=0.5)
     assert e.value.code == sscg.EINVAL
+
+
+def test_struct_layouts_match_header(sscg, tmp_path):
+    """The ctypes mirrors of the option, parameter and info structs have the size and
+    field offsets the C header gives them (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"sscg_solve_opts": sscg.SolveOpts, "sscg_ss_params": sscg.SSParams, "sscg_ss_info": sscg.SSInfo}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

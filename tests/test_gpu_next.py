@@ -106,3 +106,68 @@ def test_rr_more_accurate_than_hankel(sscg, f4):
     for out in (rr, hk):
         for l, r_ in zip(out.lam, out.res):
             assert np.abs(lam - l).min() <= r_ + 1e-13
+
+
+@pytest.mark.parametrize("prec,P", [("fp64", 1), ("mixed_shifts", 1), ("fp64", 3)])
+def test_moments_in_loop(sscg, f4, prec, P):
+    """Moments summed inside the solve (no stored y_j) equal the stored-solution path
+    and the oracle: same count, eigenvalues within 1e-10 relative, residuals below 1e-8
+    (or twice the oracle's where N = 16, M = 8 leave the oracle itself above it)."""
+    case(f"in-loop moments {prec} P={P}")
+    U, A, lam, c = f4
+    V = synth.sources(CFG1.V, 2, 8).reshape(2, -1)
+    pr = {"fp64": sscg.FP64, "mixed_shifts": sscg.MIXED_SHIFTS}[prec]
+    opts = sscg.default_opts(prec=pr, switch_tol=1e-6, ru_interval=20)
+    if P == 1:
+        kw = dict(gamma=0.225, rho=0.03, beta=0.25, N=16, M=8, rank_tol=1e-7)
+        ref = ss.ss_eigs(A, V, kw["gamma"], kw["rho"], kw["beta"], kw["N"], kw["M"], rank_tol=1e-7)
+    else:
+        kw = dict(gamma=0.225, rho=0.012, beta=0.25, N=16, M=6, Nprime=8, npairs=3, rank_tol=1e-7)
+        ref = ss.ss_eigs_adjacent(A, V, 0.225, 0.012, 0.25, 16, 6, 8, 3, rank_tol=1e-7)
+    stored = c.ss_eigs(sscg.default_ss_params(solve=opts, **kw), to_dev(V), max_eigs=32)
+    fused = c.ss_eigs(sscg.default_ss_params(solve=opts, moments_in_loop=1, **kw), to_dev(V), max_eigs=32)
+    assert fused.n_found == stored.n_found == len(ref["lam"]) > 0
+    assert np.all(np.abs(fused.lam - stored.lam) <= 1e-11 * np.abs(stored.lam))
+    assert np.all(np.abs(fused.lam - np.real(ref["lam"])) <= 1e-10 * np.abs(fused.lam))
+    # residual bar as for the circle: 1e-8 where the FP64 oracle meets it, else twice its own
+    assert np.all(fused.res <= np.maximum(1e-8, 2 * ref["res"]))
+    assert fused.info.iters == stored.info.iters
+    assert fused.info.shift_updates == stored.info.shift_updates
+    # eigenvectors agree up to phase
+    Xf, Xs = to_host(fused.X), to_host(stored.X)
+    for k in range(fused.n_found):
+        ov = abs(np.vdot(Xf[k].ravel(), Xs[k].ravel()))
+        assert ov > 1 - 1e-9
+
+
+def test_moments_in_loop_rejects(sscg, f4):
+    case("in-loop moments argument errors")
+    U, A, lam, c = f4
+    V = to_dev(synth.sources(CFG1.V, 2, 8).reshape(2, -1))
+    base = dict(gamma=0.225, rho=0.03, N=16, M=8, moments_in_loop=1)
+    for kw in (dict(method=sscg.HANKEL), dict(M=33), dict(M=12, npairs=3, Nprime=8),
+               dict(solve=sscg.default_opts(prec=sscg.MIXED))):
+        with pytest.raises(sscg.SSCGError) as e:
+            c.ss_eigs(sscg.default_ss_params(**{**base, **kw}), V, max_eigs=8)
+        assert e.value.code == sscg.EINVAL
+
+
+@pytest.mark.parametrize("in_loop", [0, 1])
+def test_weighted_tolerance(sscg, f4, in_loop):
+    """Moment-weighted stopping on the GPU equals the oracle's: the same shift-update
+    count (each node's convergence iteration within 2), eigenvalues within 1e-10."""
+    case(f"weighted tolerance in_loop={in_loop}")
+    U, A, lam, c = f4
+    V = synth.sources(CFG1.V, 2, 9).reshape(2, -1)
+    kw = dict(gamma=0.225, rho=0.03, beta=0.25, N=16, M=8, rank_tol=1e-7)
+    ref = ss.ss_eigs(A, V, kw["gamma"], kw["rho"], kw["beta"], kw["N"], kw["M"], rank_tol=1e-7,
+                     weighted_tol=True)
+    out = c.ss_eigs(sscg.default_ss_params(weighted_tol=1, moments_in_loop=in_loop, **kw), to_dev(V),
+                    max_eigs=32)
+    su_ref = sum(int(np.where(r.conv_iter >= 0, r.conv_iter, r.iters).sum()) for r in ref["runs"])
+    assert abs(out.info.shift_updates - su_ref) <= 2 * kw["N"] * 2
+    plain = c.ss_eigs(sscg.default_ss_params(**kw), to_dev(V), max_eigs=32)
+    assert out.info.shift_updates < plain.info.shift_updates
+    assert out.n_found == len(ref["lam"]) > 0
+    assert np.all(np.abs(out.lam - np.real(ref["lam"])) <= 1e-10 * np.abs(out.lam))
+    assert np.all(out.res <= np.maximum(1e-8, 2 * ref["res"]))

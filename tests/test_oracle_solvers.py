@@ -161,3 +161,33 @@ def test_shift_on_an_eigenvalue_never_converges():
     r = solvers.shifted_cg(lambda x: A @ x, v, z, 0.0, 1e-12, maxiter=300)
     assert r.status == "notconv"
     assert r.conv_iter[0] == -1 and r.conv_iter[1] > 0 and r.conv_iter[2] > 0
+
+
+def test_per_shift_tolerance(cfg1_spec):
+    """tol_scale[j] moves shift j's stopping point and nothing else: each shift freezes
+    at the first iteration where its implicit residual is below tol * tol_scale[j]
+    ||v||, its true residual (dense spectral solve) is at that level, and the shifts
+    with scale 1 are bitwise those of the unscaled run."""
+    A, lam, W = cfg1_spec
+    v = CFG1.sources().reshape(-1)
+    z, _ = quad.line_nodes(CFG1.N, CFG1.gamma, CFG1.rho, CFG1.beta)
+    scale = np.ones(z.size)
+    scale[:4] = 1e4
+    hist = []
+    r1 = solvers.shifted_cg(lambda x: A @ x, v, z, CFG1.gamma, 1e-12, tol_scale=scale,
+                            record=lambda k, st: hist.append(np.sqrt(st["rho"]) / np.abs(st["pi"])))
+    r0 = solvers.shifted_cg(lambda x: A @ x, v, z, CFG1.gamma, 1e-12)
+    assert r1.status == r0.status == "ok"
+    hist = np.array(hist)
+    vn = np.linalg.norm(v)
+    for j in range(z.size):
+        first = np.nonzero(hist[:, j] <= 1e-12 * scale[j] * vn)[0][0] + 1
+        assert r1.conv_iter[j] == first
+    assert np.all(r1.conv_iter[:4] < r0.conv_iter[:4])
+    assert np.array_equal(r1.Y[4:], r0.Y[4:])
+    Y = spectral_solve(lam, W, z, v)
+    err = np.linalg.norm(r1.Y - Y, axis=1)
+    res = solvers.true_residuals(lambda x: A @ x, v, z, r1.Y)
+    assert np.all(res[:4] <= 1e-8 * 1.5) and np.all(res[:4] > 1e-12)
+    assert np.all(res[4:] < 2e-12)
+    assert np.all(err[:4] > err[4:].max())

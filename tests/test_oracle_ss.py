@@ -159,3 +159,30 @@ def test_adjacent_pairs_equal_separate_runs(spec):
     hi_all = out["centres"][-1] + rho * (Np // 2 - 1) / (N // 2 - 1)
     truth = lam[(lam >= lo_all) & (lam <= hi_all)]
     assert np.abs(np.sort(out["lam"]) - truth).max() < 1e-10
+
+
+def test_weighted_tolerance_keeps_the_moments(spec):
+    """Moment-weighted stopping (each node stops at tol * m / m_j): fewer shift updates,
+    the moments stay within a few times the uniform-tolerance error of the exact
+    moments from dense spectral solves, and the eigenpairs are unchanged."""
+    A, lam, W = spec
+    V = synth.sources(CFG1.V, 2, 9).reshape(2, -1)
+    gamma, rho, beta, N, M = 0.225, 0.03, 0.25, 16, 8
+    z, zeta = quad.line_nodes(N, gamma, rho, beta)
+    w = quad.line_weights(zeta)
+    c = quad.moment_coefficients(zeta, w, M)
+    ts = ss.weighted_tol_scale([c])
+    m_j = np.abs(c).max(axis=0)
+    assert np.allclose(ts * m_j, m_j.max()) and ts.min() == 1.0
+    Yx = np.array([[W @ ((W.conj().T @ v) / (zj - lam)) for zj in z] for v in V])
+    Sx = ss.moments(Yx, zeta, w, M)
+    u = ss.ss_eigs(A, V, gamma, rho, beta, N, M, rank_tol=1e-7)
+    g = ss.ss_eigs(A, V, gamma, rho, beta, N, M, rank_tol=1e-7, weighted_tol=True)
+    su = lambda out: sum(int(np.where(r.conv_iter >= 0, r.conv_iter, r.iters).sum()) for r in out["runs"])
+    assert su(g) < su(u)
+    eu = np.abs(u["S"] - Sx).max()
+    eg = np.abs(g["S"] - Sx).max()
+    assert eg <= 10 * max(eu, 1e-13 * np.abs(Sx).max())
+    assert len(g["lam"]) == len(u["lam"]) > 0
+    assert np.all(np.abs(g["lam"] - u["lam"]) <= 1e-10 * np.abs(u["lam"]))
+    assert g["res"].max() < 1e-8
