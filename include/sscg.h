@@ -239,7 +239,8 @@ int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs);
  * context's stream, in milliseconds summed over the solve; counts in calls.
  * stage: 0 dslash, 1 seed alpha scalars, 2 seed residual update, 3 shift scalars,
  * 4 fused shift update, 5 reliable update, 6 whole iteration loop.
- * Timing is recorded only when enabled with sscg_set_profiling(ctx, 1). */
+ * Timing is recorded only when enabled with sscg_set_profiling(ctx, 1); then
+ * sscg_apply_A also adds its dslash time to stage 0 (and blocks until it ends). */
 int sscg_set_profiling(sscg_ctx *ctx, int32_t on);
 int sscg_stage_times(const sscg_ctx *ctx, double ms[8], int64_t calls[8]);
 

@@ -40,6 +40,8 @@ struct Tune {
   int xcd = 1;      // XCD-aware block order in the dslash
   int unroll = 2;   // shifts whose loads a shift-update thread issues together
   int nt = 0;       // non-temporal access to the shift vectors
+  int ct = 0;       // t-slices per block of the tile dslash (0: site-parallel kernel)
+  int tbs = 0;      // sites (threads) per tile of the tile dslash
 };
 
 enum Stage { ST_DSLASH = 0, ST_ALPHA, ST_RUPD, ST_SCAL, ST_SHIFT, ST_RU, ST_LOOP, ST_N = 8 };
@@ -61,8 +63,8 @@ struct sscg_ctx {
   // or chosen per problem shape by the autotuner (SSCG_AUTOTUNE=0 disables it)
   Tune tune;
   bool autotune = true;
-  int px = 0;        // x-piece width of the dslash traversal order (0: lexicographic)
   int dorder = 1;    // dslash block order (1: all source groups of a site tile adjacent)
+  int max_lds = 65536;  // dynamic LDS limit per block (bytes)
   std::map<std::string, Tune> tuned;
   // solver workspaces
   DevBuf v64, r64, p64, q64, W, r32, p32, q32, rbase, xpart64, xpart32, tmp, pq_part, rr_part, seed,
@@ -150,6 +152,13 @@ int sscg_create(sscg_ctx **out, const int32_t dims[4], double kappa, double r, i
     return fail(nullptr, SSCG_EDEVICE, "stream creation failed");
   }
   for (int i = 0; i < 4; ++i) c->dims[i] = dims[i];
+  {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && v > 0)
+      c->max_lds = v;
+    else
+      (void)hipGetLastError();
+  }
   c->V = (int)V;
   c->n = 12 * V;
   c->kappa = kappa;
@@ -158,12 +167,15 @@ int sscg_create(sscg_ctx **out, const int32_t dims[4], double kappa, double r, i
   c->tune.wbatch = env_int("SSCG_WBATCH", 8);
   c->tune.xcd = env_int("SSCG_XCD", 1);
   c->tune.unroll = env_int("SSCG_UNROLL", 2);
-  c->px = env_int("SSCG_PX", 0);
-  c->dorder = env_int("SSCG_DORDER", 1) ? 1 : 0;
-  if (c->px < 0 || c->px > dims[0] || dims[0] % std::max(c->px, 1) != 0) c->px = 0;
+  c->tune.ct = env_int("SSCG_CT", 0);
+  c->tune.tbs = env_int("SSCG_TBS", 256);
+  c->dorder = env_int("SSCG_DORDER", 1);
+  if (c->dorder < 0 || c->dorder > 2) c->dorder = 1;
+  if (c->tune.ct < 0) c->tune.ct = 0;
   c->tune.nt = env_int("SSCG_NT", 0);
   c->autotune = env_int("SSCG_AUTOTUNE", 1) != 0 && !getenv("SSCG_NR") && !getenv("SSCG_BS") &&
-                !getenv("SSCG_WBATCH") && !getenv("SSCG_XCD") && !getenv("SSCG_UNROLL") && !getenv("SSCG_NT");
+                !getenv("SSCG_WBATCH") && !getenv("SSCG_XCD") && !getenv("SSCG_UNROLL") && !getenv("SSCG_NT") && !getenv("SSCG_CT") &&
+                !getenv("SSCG_TBS");
   if (c->tune.nr != 1 && c->tune.nr != 2 && c->tune.nr != 4) c->tune.nr = 2;
   if (c->tune.bs != 64 && c->tune.bs != 128 && c->tune.bs != 256) c->tune.bs = 256;
   if (c->tune.wbatch < 1) c->tune.wbatch = 8;
@@ -249,7 +261,37 @@ int sscg_stage_times(const sscg_ctx *c, double ms[8], int64_t calls[8]) {
 // ---------------------------------------------------------------------------
 // internal helpers
 
-static int nblk_site(const sscg_ctx *c, int bs) { return (c->V + bs - 1) / bs; }
+// Tile of tbs sites for the tile dslash on this lattice: whole x-rows, ty | Ly,
+// tz | Lz, Lx ty tz = tbs (a multiple of 64, at most 1024), LDS for nr sources of
+// FP64 or FP32 spinors within the device limit; among the shapes, the one with the
+// fewest face sites. Returns false if there is none.
+static bool tile_shape(const sscg_ctx *c, int tbs, int nr, int prec, int &ty, int &tz) {
+  const int Lx = c->dims[0], Ly = c->dims[1], Lz = c->dims[2];
+  if (tbs < 64 || tbs > 1024 || tbs % 64 || tbs % Lx) return false;
+  const size_t lds = (size_t)nr * 12 * tbs * (prec == 0 ? 16 : 8);
+  if (lds > (size_t)c->max_lds) return false;
+  const int k = tbs / Lx;
+  double best = 1e30;
+  for (int a = 1; a <= Ly && a <= k; ++a) {
+    if (Ly % a || k % a) continue;
+    const int bz = k / a;
+    if (bz > Lz || Lz % bz) continue;
+    const double f = (a == Ly ? 0.0 : 1.0 / a) + (bz == Lz ? 0.0 : 1.0 / bz);
+    if (f < best) {
+      best = f;
+      ty = a;
+      tz = bz;
+    }
+  }
+  return best < 1e29;
+}
+// site blocks per source group of the dslash: one thread per site (ct = 0) or
+// tiles times t-ranges of the tile kernel (ct > 0)
+static int nblk_site(const sscg_ctx *c, int bs, int ct, int ty, int tz) {
+  if (ct <= 0) return (c->V + bs - 1) / bs;
+  const int Lt = c->dims[3];
+  return (c->dims[1] / ty) * (c->dims[2] / tz) * ((Lt + ct - 1) / ct);
+}
 static int nblk_vec(const sscg_ctx *c) { return (int)((c->n + kBlock * kEptHost - 1) / (kBlock * kEptHost)); }
 
 // FP64 dslash of nsrc planar vectors: out = A in (mode 0) or sigma in - A in (mode 1)
@@ -267,15 +309,19 @@ static void dslash_plain(sscg_ctx *c, const void *in, void *out, int nsrc, int p
   for (int i = 0; i < 4; ++i) j.dims[i] = c->dims[i];
   j.V = c->V;
   j.nsrc = nsrc;
-  j.nblk_site = nblk_site(c, c->tune.bs);
+  int ct = c->tune.ct, ty = 0, tz = 0;
+  if (ct > 0 && !tile_shape(c, c->tune.tbs, c->tune.nr, prec, ty, tz)) ct = 0;
+  j.nblk_site = nblk_site(c, c->tune.bs, ct, ty, tz);
   j.block_begin = 0;
   j.nblocks = j.nblk_site * ((nsrc + c->tune.nr - 1) / c->tune.nr);
   j.mode = mode;
-  j.px = c->px;
+  j.ct = ct;
+  j.ty = ty;
+  j.tz = tz;
   j.order = c->dorder;
   b.njobs = 1;
   b.total_blocks = j.nblocks;
-  launch_dslash(b, prec, c->tune.nr, prec == 0 ? 18 : c->link_reals, c->tune.bs, c->tune.xcd, st);
+  launch_dslash(b, prec, c->tune.nr, prec == 0 ? 18 : c->link_reals, c->tune.bs, c->tune.xcd, ct, st);
 }
 
 static int host_sum_partials(sscg_ctx *c, const double *dev_partial, int nvec, int nblk, std::vector<double> &out,
@@ -326,16 +372,23 @@ struct IterPlan {
   VecBatch r64, r32, u64, u32, u32s, fold_seed, rel;
   VecBatch m64, m32;  // shift update with in-loop moments (FP64 / FP32 shift vectors)
   int nmom_max;       // 0: the solutions are stored
+  int ct;             // dslash kernel: t-slices per block (0: site-parallel)
 };
 
 static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts &o, const Tune &t) {
   memset(&pl, 0, sizeof(pl));
   int bd = 0, bdru = 0, bs = 0, bv = 0, bu = 0, bm = 0;
   const int np = (int)P.size();
+  // the tile kernel needs a tile of t.tbs sites on every lattice of the batch, with
+  // LDS for FP64 spinors (the FP64 phase and the reliable updates use it too)
+  pl.ct = t.ct;
+  std::vector<int> tys(np, 0), tzs(np, 0);
+  for (int i = 0; i < np; ++i)
+    if (pl.ct > 0 && !tile_shape(P[i].c, t.tbs, t.nr, 0, tys[i], tzs[i])) pl.ct = 0;
   for (int i = 0; i < np; ++i) {
     sscg_ctx *c = P[i].c;
     const int L = P[i].L, N = P[i].N;
-    const int nbs = nblk_site(c, t.bs), nbv = nblk_vec(c);
+    const int nbs = nblk_site(c, t.bs, pl.ct, tys[i], tzs[i]), nbv = nblk_vec(c);
     const int groups = (L + t.nr - 1) / t.nr;
     SeedState *seed = (SeedState *)c->seed.p;
     ShiftState *shift = (ShiftState *)c->shift.p;
@@ -344,7 +397,9 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
       j.kappa = c->kappa; j.sigma = P[i].sigma;
       for (int k = 0; k < 4; ++k) j.dims[k] = c->dims[k];
       j.V = c->V; j.nsrc = L; j.nblk_site = nbs; j.block_begin = begin; j.nblocks = nbs * groups; j.mode = 1;
-      j.px = c->px;
+      j.ct = pl.ct;
+      j.ty = tys[i];
+      j.tz = tzs[i];
       j.order = c->dorder;
     };
     mk_d(pl.d64.job[i], c->p64.p, c->q64.p, c->g64.p, (double *)c->pq_part.p, bd);
@@ -452,7 +507,7 @@ static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru,
                              hipStream_t st, Recorder &rec) {
   const int sp = (prec == 1 && seed32) ? 1 : 0;  // seed precision
   rec.mark(ST_DSLASH);
-  launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, st);
+  launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, pl.ct, st);
   rec.mark(ST_ALPHA);
   launch_seed_alpha(pl.alpha, st);
   rec.mark(ST_RUPD);
@@ -460,7 +515,7 @@ static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru,
   if (sp == 1 && ru) {
     rec.mark(ST_RU);
     launch_fold_seed(pl.fold_seed, st);
-    launch_dslash(pl.dru, 0, t.nr, 18, t.bs, t.xcd, st);
+    launch_dslash(pl.dru, 0, t.nr, 18, t.bs, t.xcd, pl.ct, st);
     launch_reliable_residual(pl.rel, st);
   }
   rec.mark(ST_SCAL);
@@ -607,25 +662,48 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
     maxL = std::max(maxL, p.L);
     maxN = std::max(maxN, p.N);
   }
-  // dslash on the FP64 seed buffers (p -> q); its partials are rewritten by the first iteration
+  // dslash on the seed buffers (p -> q) in the precision most iterations use (FP32
+  // when the seed switches to FP32, then on a copy of p); its partials are
+  // rewritten by the first iteration
+  const int dprec = o.prec == SSCG_MIXED ? 1 : 0;
+  if (dprec == 1)
+    for (Prob &p : P) launch_cast(p.c->p64.p, 0, p.c->p32.p, 1, (int64_t)p.L * p.c->n, st);
   double tbest = 1e300;
   Tune cand = best;
+  // site-parallel kernel: sources per thread, sites per block, XCD order
+  auto try_shape = [&](const Tune &cd) {
+    IterPlan pl;
+    build_plan(P, pl, o, cd);
+    if (cd.ct > 0 && pl.ct == 0) return;  // no tile of this size on some lattice
+    const double t = time_it([&] {
+      launch_dslash(dprec ? pl.d32 : pl.d64, dprec, cd.nr, dprec ? lr : 18, cd.bs, cd.xcd, pl.ct, st);
+    }, 5);
+    if (t < tbest) {
+      tbest = t;
+      best.nr = cd.nr;
+      best.bs = cd.bs;
+      best.xcd = cd.xcd;
+      best.ct = cd.ct;
+      best.tbs = cd.tbs;
+    }
+  };
   for (int nr : {1, 2, 4}) {
     if (nr > 1 && nr > maxL) continue;
+    cand.nr = nr;
+    cand.ct = 0;
     for (int bs : {64, 128, 256})
       for (int xcd : {0, 1}) {
-        cand.nr = nr;
         cand.bs = bs;
         cand.xcd = xcd;
-        IterPlan pl;
-        build_plan(P, pl, o, cand);
-        const double t = time_it([&] { launch_dslash(pl.d64, 0, nr, 18, bs, xcd, st); }, 5);
-        if (t < tbest) {
-          tbest = t;
-          best.nr = nr;
-          best.bs = bs;
-          best.xcd = xcd;
-        }
+        try_shape(cand);
+      }
+    // tile kernel: t-slices per block and tile size
+    cand.xcd = 1;
+    for (int ct : {2, 4, 8, 16})
+      for (int tbs = 64; tbs <= 1024; tbs += 64) {
+        cand.ct = ct;
+        cand.tbs = tbs;
+        try_shape(cand);
       }
   }
   // fused shift update as an identity on the current data (not used, and not
@@ -671,8 +749,8 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
     }
   }
   if (getenv("SSCG_VERBOSE"))
-    fprintf(stderr, "[sscg] tuned %s: nr=%d bs=%d xcd=%d wbatch=%d unroll=%d nt=%d\n", key.c_str(), best.nr,
-            best.bs, best.xcd, best.wbatch, best.unroll, best.nt);
+    fprintf(stderr, "[sscg] tuned %s: nr=%d bs=%d xcd=%d ct=%d tbs=%d wbatch=%d unroll=%d nt=%d\n",
+            key.c_str(), best.nr, best.bs, best.xcd, best.ct, best.tbs, best.wbatch, best.unroll, best.nt);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   // restore the initial state
@@ -954,7 +1032,24 @@ int sscg_apply_A(sscg_ctx *c, const void *x, void *y, int32_t nsrc, int32_t prec
   CHK(ensure(c, c->apply_out, (size_t)nsrc * c->n * es));
   hipStream_t st = c->user;
   launch_pack(x, c->apply_in.p, prec, nsrc, c->V, st);
-  dslash_plain(c, c->apply_in.p, c->apply_out.p, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
+  if (c->profiling) {
+    // time the dslash alone (blocking) and add it to the dslash stage
+    while (c->events.size() < 2) {
+      hipEvent_t e;
+      HIPCHK(c, hipEventCreate(&e));
+      c->events.push_back(e);
+    }
+    HIPCHK(c, hipEventRecord(c->events[0], st));
+    dslash_plain(c, c->apply_in.p, c->apply_out.p, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
+    HIPCHK(c, hipEventRecord(c->events[1], st));
+    HIPCHK(c, hipEventSynchronize(c->events[1]));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->events[0], c->events[1]));
+    c->stage_ms[ST_DSLASH] += ms;
+    c->stage_calls[ST_DSLASH] += 1;
+  } else {
+    dslash_plain(c, c->apply_in.p, c->apply_out.p, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
+  }
   launch_unpack(c->apply_out.p, prec, y, nsrc, c->V, st);
   HIPCHK(c, hipGetLastError());
   return SSCG_OK;

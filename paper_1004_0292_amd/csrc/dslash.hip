@@ -171,7 +171,7 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
   // region and fetches its links once; group-major (0): one source at a time
   const int groups = (J.nsrc + NR - 1) / NR;
   int group, sblk;
-  if (J.order) {
+  if (J.order == 1) {
     sblk = lb / groups;
     group = lb - sblk * groups;
   } else {
@@ -186,25 +186,8 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
     if (all_done) return;
   }
   const int V = J.V;
-  const int ii = sblk * BS + threadIdx.x;  // position in the traversal order
-  const bool valid = ii < V;
-  // Traversal order: with px > 0 the lattice is walked in x-pieces of width px
-  // (order: piece, t, z, y, x within the piece), which shortens the distance between
-  // a site and its t- and z-neighbours in the order the blocks run; otherwise
-  // lexicographic. The data layout itself is lexicographic either way.
-  int s = ii;
-  if (J.px > 0 && valid) {
-    const int px = J.px, Ly = J.dims[1], Lz = J.dims[2], Lt = J.dims[3];
-    const int xl = ii % px;
-    int r2 = ii / px;
-    const int yy = r2 % Ly;
-    r2 /= Ly;
-    const int zz = r2 % Lz;
-    r2 /= Lz;
-    const int tt = r2 % Lt;
-    const int pc = r2 / Lt;
-    s = pc * px + xl + J.dims[0] * (yy + Ly * (zz + Lz * tt));
-  }
+  const int s = sblk * BS + threadIdx.x;
+  const bool valid = s < V;
   const V2<T> *in = reinterpret_cast<const V2<T> *>(J.in) + (size_t)l0 * 12 * V;
   V2<T> *out = reinterpret_cast<V2<T> *>(J.out) + (size_t)l0 * 12 * V;
   const V2<T> *gauge = reinterpret_cast<const V2<T> *>(J.gauge);
@@ -264,7 +247,7 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
   if (J.partial) {
     // one partial per 64-site wavefront, at the wave's global index: the layout and
     // the summation order do not depend on the block size or sources per thread
-    const int wave = ii >> 6;
+    const int wave = s >> 6;
     const int npart = (V + 63) >> 6;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -274,6 +257,277 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
       if ((threadIdx.x & 63) == 0 && r < nvalid && wave < npart) J.partial[(size_t)(l0 + r) * npart + wave] = d;
     }
   }
+}
+
+// One spatial direction of the tile kernel: a neighbour inside the block's tile is
+// read from the block's LDS copy of the current slice (local index lf / lb >= 0),
+// one outside it from memory (site sf / sb).
+template <typename T, int NR, int LR, int MU>
+__device__ __forceinline__ void hop_tile(const V2<T> *__restrict__ in, const V2<T> *__restrict__ gauge,
+                                         const V2<T> *lds, int V, int BS, int s, int sf, int sb, int lf, int lb,
+                                         int nvalid, V2<T> (&acc)[NR][12]) {
+  using C = V2<T>;
+  C u[9];
+  load_link<T, LR>(gauge, V, MU, s, u);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r < nvalid) {
+      C p[12];
+      if (lf >= 0) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = lds[(r * 12 + c) * BS + lf];
+      } else {
+        const C *src = in + (size_t)r * 12 * V + sf;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = src[(size_t)c * V];
+      }
+      C h0[3], h1[3], g0[3], g1[3];
+      project<MU, -1>(p, h0, h1);
+      su3_mul(u, h0, g0);
+      su3_mul(u, h1, g1);
+      reconstruct<MU, -1>(acc[r], g0, g1);
+    }
+  }
+  load_link<T, LR>(gauge, V, MU, sb, u);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r < nvalid) {
+      C p[12];
+      if (lb >= 0) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = lds[(r * 12 + c) * BS + lb];
+      } else {
+        const C *src = in + (size_t)r * 12 * V + sb;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = src[(size_t)c * V];
+      }
+      C h0[3], h1[3], g0[3], g1[3];
+      project<MU, 1>(p, h0, h1);
+      su3_mul_adj(u, h0, g0);
+      su3_mul_adj(u, h1, g1);
+      reconstruct<MU, 1>(acc[r], g0, g1);
+    }
+  }
+}
+
+// local index of a neighbour inside the tile, or -1; the tile spans the whole
+// lattice in that direction when T == L (then the neighbour wraps inside it)
+__device__ __forceinline__ int tile_nb(int tid, int l, int T, int L, int stride, bool fwd) {
+  if (T == L) return fwd ? tid + (l == T - 1 ? (1 - T) * stride : stride) : tid + (l == 0 ? (T - 1) * stride : -stride);
+  if (fwd) return l < T - 1 ? tid + stride : -1;
+  return l > 0 ? tid - stride : -1;
+}
+
+// Tile-marching variant (J.ct > 0). A block owns a spatial tile of whole x-rows,
+// Lx x ty x tz sites with one thread per site, and walks it through ct
+// consecutive time slices:
+//  * t-hops from registers: the spinor of slice t+1 loaded for the forward hop is
+//    the centre spinor of the next step, and the backward hop into slice t+1,
+//    U_t(x, t)^H (1 + gamma_4) psi(x, t), is formed while slice t is current, with
+//    the t-link already loaded for the forward hop of slice t;
+//  * x, y, z hops from LDS: each step the block stores its centre spinors of the
+//    current slice in LDS, and neighbours inside the tile are read from there;
+//    only the faces of the tile (1/ty and 1/tz of the sites per direction) read
+//    their neighbours from memory.
+// So every spinor is read from memory about once per block, plus the two slices
+// bounding the t-range and the tile faces. Needs ty | Ly, tz | Lz and Lx ty tz a
+// multiple of 64 (at most 1024); dynamic LDS of nr * 12 * Lx ty tz complex numbers.
+// Partials of Re <psi, out>: one per 64-site wavefront, indexed by (slice, tile,
+// wavefront), V / 64 of them as in the site-parallel kernel.
+template <typename T, int NR, int LR, int MAXBS>
+__global__ __launch_bounds__(MAXBS) void dslash_tile_kernel(DslashBatch B, int xcd_remap) {
+  using C = V2<T>;
+  extern __shared__ __align__(16) unsigned char dslash_lds[];
+  C *lds = reinterpret_cast<C *>(dslash_lds);
+  int b = blockIdx.x;
+  if (xcd_remap) b = xcd_remap_block(b, gridDim.x);
+  int begins[kMaxJobs];
+#pragma unroll
+  for (int k = 0; k < kMaxJobs; ++k) begins[k] = B.job[k].block_begin;
+  const int ji = find_job(begins, B.njobs, b);
+  const DslashJob &J = B.job[ji];
+  const int lb = b - J.block_begin;
+  const int Lx = J.dims[0], Ly = J.dims[1], Lz = J.dims[2], Lt = J.dims[3];
+  const int Ty = J.ty, Tz = J.tz;
+  const int BS = Lx * Ty * Tz;
+  const int nty = Ly / Ty, ntile = nty * (Lz / Tz);
+  const int nrange = (Lt + J.ct - 1) / J.ct;
+  const int groups = (J.nsrc + NR - 1) / NR;
+  // block order (J.order): 1 = source groups innermost, then tiles, then t-ranges
+  // (one XCD serves all sources of a region, links fetched once); 0 = source
+  // groups outermost; 2 = source groups outermost, t-ranges innermost
+  int group, range, tile;
+  if (J.order == 1) {
+    const int sg = lb / groups;
+    group = lb - sg * groups;
+    range = sg / ntile;
+    tile = sg - range * ntile;
+  } else {
+    const int per = ntile * nrange;
+    group = lb / per;
+    const int sg = lb - group * per;
+    if (J.order == 0) {
+      range = sg / ntile;
+      tile = sg - range * ntile;
+    } else {
+      tile = sg / nrange;
+      range = sg - tile * nrange;
+    }
+  }
+  const int t0 = range * J.ct, t1 = min(t0 + J.ct, Lt);
+  const int l0 = group * NR;
+  const int nvalid = min(NR, J.nsrc - l0);
+  if (J.seed) {
+    bool all_done = true;
+    for (int r = 0; r < nvalid; ++r) all_done &= (J.seed[l0 + r].done != 0);
+    if (all_done) return;  // uniform over the block, before any barrier
+  }
+  const int V = J.V;
+  const int Vs = Lx * Ly * Lz;
+  const int tid = threadIdx.x;
+  const int lx = tid % Lx, q = tid / Lx, ly = q % Ty, lz = q / Ty;
+  const int x = lx, y = (tile % nty) * Ty + ly, z = (tile / nty) * Tz + lz;
+  const int sp = x + Lx * (y + Ly * z);
+  const int sxy = Lx * Ly;
+  const int fx = sp + (x == Lx - 1 ? 1 - Lx : 1), bx = sp + (x == 0 ? Lx - 1 : -1);
+  const int fy = sp + (y == Ly - 1 ? (1 - Ly) * Lx : Lx), by = sp + (y == 0 ? (Ly - 1) * Lx : -Lx);
+  const int fz = sp + (z == Lz - 1 ? (1 - Lz) * sxy : sxy), bz = sp + (z == 0 ? (Lz - 1) * sxy : -sxy);
+  const int lfx = tile_nb(tid, lx, Lx, Lx, 1, true), lbx = tile_nb(tid, lx, Lx, Lx, 1, false);
+  const int lfy = tile_nb(tid, ly, Ty, Ly, Lx, true), lby = tile_nb(tid, ly, Ty, Ly, Lx, false);
+  const int lfz = tile_nb(tid, lz, Tz, Lz, Lx * Ty, true), lbz = tile_nb(tid, lz, Tz, Lz, Lx * Ty, false);
+  const V2<T> *in = reinterpret_cast<const V2<T> *>(J.in) + (size_t)l0 * 12 * V;
+  V2<T> *out = reinterpret_cast<V2<T> *>(J.out) + (size_t)l0 * 12 * V;
+  const V2<T> *gauge = reinterpret_cast<const V2<T> *>(J.gauge);
+  const int npart = V >> 6;
+  const int wpt = BS >> 6;
+
+  C bw0[NR][3], bw1[NR][3];
+  C u[9];
+  {
+    // backward t-hop into slice t0; the centre spinors of slice t0 go to LDS
+    const int sprev = sp + Vs * (t0 == 0 ? Lt - 1 : t0 - 1);
+    load_link<T, LR>(gauge, V, 3, sprev, u);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r < nvalid) {
+        const C *src = in + (size_t)r * 12 * V + sprev;
+        C p[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = src[(size_t)c * V];
+        C h0[3], h1[3];
+        project<3, 1>(p, h0, h1);
+        su3_mul_adj(u, h0, bw0[r]);
+        su3_mul_adj(u, h1, bw1[r]);
+        const C *cs = in + (size_t)r * 12 * V + sp + Vs * t0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) lds[(r * 12 + c) * BS + tid] = cs[(size_t)c * V];
+      }
+    }
+  }
+  const T kap = (T)J.kappa;
+  const T sig = (T)J.sigma;
+  for (int t = t0; t < t1; ++t) {
+    const int ofs = Vs * t;
+    const int s = sp + ofs;
+    const int sn = sp + Vs * (t == Lt - 1 ? 0 : t + 1);
+    // spinors of slice t+1 (forward t-hop now, the centre of the next step)
+    C nxt[NR][12];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r < nvalid) {
+        const C *src = in + (size_t)r * 12 * V + sn;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) nxt[r][c] = src[(size_t)c * V];
+      }
+    }
+    __syncthreads();  // slice t of the tile is in LDS
+    C acc[NR][12];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[r][c] = cmk<C>(0, 0);
+    hop_tile<T, NR, LR, 0>(in, gauge, lds, V, BS, s, fx + ofs, bx + ofs, lfx, lbx, nvalid, acc);
+    hop_tile<T, NR, LR, 1>(in, gauge, lds, V, BS, s, fy + ofs, by + ofs, lfy, lby, nvalid, acc);
+    hop_tile<T, NR, LR, 2>(in, gauge, lds, V, BS, s, fz + ofs, bz + ofs, lfz, lbz, nvalid, acc);
+    load_link<T, LR>(gauge, V, 3, s, u);
+    double dot[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      dot[r] = 0.0;
+      if (r < nvalid) {
+        C h0[3], h1[3], g0[3], g1[3];
+        project<3, -1>(nxt[r], h0, h1);
+        su3_mul(u, h0, g0);
+        su3_mul(u, h1, g1);
+        reconstruct<3, -1>(acc[r], g0, g1);
+        reconstruct<3, 1>(acc[r], bw0[r], bw1[r]);
+        C cur[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) cur[c] = lds[(r * 12 + c) * BS + tid];
+        if (t + 1 < t1) {
+          project<3, 1>(cur, h0, h1);
+          su3_mul_adj(u, h0, bw0[r]);
+          su3_mul_adj(u, h1, bw1[r]);
+        }
+        C *dst = out + (size_t)r * 12 * V + s;
+        double d = 0.0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const C p = cur[c];
+          const C a = acc[r][c];
+          C o;
+          if (J.mode == 1) {
+            if (c < 6) { o.x = (sig - (T)1) * p.x + kap * a.x; o.y = (sig - (T)1) * p.y + kap * a.y; }
+            else       { o.x = (sig + (T)1) * p.x - kap * a.x; o.y = (sig + (T)1) * p.y - kap * a.y; }
+          } else {
+            if (c < 6) { o.x = p.x - kap * a.x; o.y = p.y - kap * a.y; }
+            else       { o.x = kap * a.x - p.x; o.y = kap * a.y - p.y; }
+          }
+          dst[(size_t)c * V] = o;
+          d += (double)p.x * (double)o.x + (double)p.y * (double)o.y;
+        }
+        dot[r] = d;
+      }
+    }
+    if (J.partial) {
+      const int wave = (t * ntile + tile) * wpt + (tid >> 6);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        double d = dot[r];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+        if ((tid & 63) == 0 && r < nvalid) J.partial[(size_t)(l0 + r) * npart + wave] = d;
+      }
+    }
+    __syncthreads();  // every read of slice t is done: slice t+1 replaces it
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (r < nvalid)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) lds[(r * 12 + c) * BS + tid] = nxt[r][c];
+  }
+}
+
+template <typename T, int NR, int LR, int MAXBS>
+static void launch_tile(const DslashBatch &b, int bs, size_t shm, int xcd, hipStream_t st) {
+  static bool raised = false;  // allow more than the default dynamic LDS once per kernel
+  if (shm > 65536 && !raised) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&dslash_tile_kernel<T, NR, LR, MAXBS>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    raised = true;
+  }
+  hipLaunchKernelGGL((dslash_tile_kernel<T, NR, LR, MAXBS>), dim3(b.total_blocks), dim3(bs), shm, st, b, xcd);
+}
+
+template <typename T, int NR, int LR>
+static void launch_m(const DslashBatch &b, int xcd, hipStream_t st) {
+  const DslashJob &j = b.job[0];
+  const int bs = j.dims[0] * j.ty * j.tz;
+  const size_t shm = (size_t)NR * 12 * bs * sizeof(V2<T>);
+  if (bs <= 256) launch_tile<T, NR, LR, 256>(b, bs, shm, xcd, st);
+  else if (bs <= 512) launch_tile<T, NR, LR, 512>(b, bs, shm, xcd, st);
+  else if (bs <= 768) launch_tile<T, NR, LR, 768>(b, bs, shm, xcd, st);
+  else launch_tile<T, NR, LR, 1024>(b, bs, shm, xcd, st);
 }
 
 template <typename T, int NR, int LR>
@@ -287,17 +541,24 @@ static void launch_t(const DslashBatch &b, int bs, int xcd, hipStream_t st) {
 }
 
 template <typename T, int LR>
-static void launch_nr(const DslashBatch &b, int nr, int bs, int xcd, hipStream_t st) {
+static void launch_nr(const DslashBatch &b, int nr, int bs, int xcd, bool march, hipStream_t st) {
+  if (march) {
+    if (nr == 1) launch_m<T, 1, LR>(b, xcd, st);
+    else if (nr == 2) launch_m<T, 2, LR>(b, xcd, st);
+    else launch_m<T, 4, LR>(b, xcd, st);
+    return;
+  }
   if (nr == 1) launch_t<T, 1, LR>(b, bs, xcd, st);
   else if (nr == 2) launch_t<T, 2, LR>(b, bs, xcd, st);
   else launch_t<T, 4, LR>(b, bs, xcd, st);
 }
 
-void launch_dslash(const DslashBatch &b, int prec, int nr, int lr, int bs, int xcd, hipStream_t st) {
+void launch_dslash(const DslashBatch &b, int prec, int nr, int lr, int bs, int xcd, int ct, hipStream_t st) {
   if (b.total_blocks <= 0) return;
-  if (prec == 0) launch_nr<double, 18>(b, nr, bs, xcd, st);
-  else if (lr == 18) launch_nr<float, 18>(b, nr, bs, xcd, st);
-  else launch_nr<float, 12>(b, nr, bs, xcd, st);
+  const bool march = ct > 0;
+  if (prec == 0) launch_nr<double, 18>(b, nr, bs, xcd, march, st);
+  else if (lr == 18) launch_nr<float, 18>(b, nr, bs, xcd, march, st);
+  else launch_nr<float, 12>(b, nr, bs, xcd, march, st);
 }
 
 }  // namespace sscg

@@ -93,7 +93,8 @@ struct DslashJob {
   double kappa, sigma;   // out = sigma in - A in (mode 1) or A in (mode 0)
   int32_t dims[4];
   int32_t V, nsrc, nblk_site, block_begin, nblocks, mode;
-  int32_t px;            // x-piece width of the traversal order (0: lexicographic)
+  int32_t ct;            // t-slices per block of the tile kernel (0: one site per thread)
+  int32_t ty, tz;        // tile kernel: tile of Lx x ty x tz sites (one thread per site)
   int32_t order;         // block order: 0 source groups outermost, 1 sites outermost
 };
 struct DslashBatch { DslashJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
@@ -129,10 +130,13 @@ __device__ __forceinline__ int find_job(const int32_t *begins, int njobs, int b)
 
 // ---- launchers (defined in the .hip files) ---------------------------------
 // dslash.hip
-// nr: sources per thread (1, 2, 4); bs: sites per block (64, 128, 256); each
-// job's nblk_site must be ceil(V / bs).
+// nr: sources per thread (1, 2, 4); bs: sites per block (64, 128, 256).
+// ct = 0: one thread per site, each job's nblk_site = ceil(V / bs); ct > 0: the
+// tile kernel with every job's (ct, ty, tz) equal (ty | Ly, tz | Lz, Lx ty tz a
+// multiple of 64 up to 1024, bs unused), nblk_site = (Ly / ty)(Lz / tz) ceil(Lt / ct).
+// Blocks per job: nblk_site * ceil(nsrc / nr).
 void launch_dslash(const DslashBatch &b, int prec /*0 fp64, 1 fp32*/, int nr, int lr, int bs,
-                   int xcd_remap, hipStream_t st);
+                   int xcd_remap, int ct, hipStream_t st);
 // vec.hip
 void launch_seed_alpha(const ScalarBatch &b, hipStream_t st);
 void launch_shift_scalars(const ScalarBatch &b, hipStream_t st);

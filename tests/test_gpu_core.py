@@ -56,6 +56,38 @@ def test_apply_A_fp64(sscg, dims, nsrc):
     assert rel(y, ref) < 1e-14
 
 
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 2, 5), (8, 8, 8, 8), (3, 5, 7, 2)])
+@pytest.mark.parametrize("ct,nr,tbs", [(1, 1, 64), (2, 2, 256), (3, 4, 64), (16, 1, 512), (5, 2, 128)])
+def test_apply_A_tile_kernel(sscg, monkeypatch, dims, ct, nr, tbs):
+    """The tile dslash (tiles of tbs sites marching through ct time slices, a ragged
+    last t-range, tiles with faces in y and z or spanning the lattice) equals the
+    sparse A in FP64 and the site-parallel kernel in FP64 and FP32 (18- and 12-real
+    links); where no tile of tbs sites fits the lattice the site-parallel kernel runs."""
+    case(f"apply_A tile kernel dims={dims} ct={ct} nr={nr} tbs={tbs}")
+    U = synth.gauge_field(dims, 0.5, 13)
+    A = wilson.hermitian_wilson(U, dims, 0.13)
+    V = int(np.prod(dims))
+    nsrc = 3
+    x = synth.sources(V, nsrc, 14)
+    ref = np.array([A @ xv for xv in x.reshape(nsrc, -1)])
+    out = {}
+    for k in ("plain", "march"):
+        monkeypatch.setenv("SSCG_NR", str(nr))
+        monkeypatch.setenv("SSCG_TBS", str(tbs))
+        monkeypatch.setenv("SSCG_CT", "0" if k == "plain" else str(ct))
+        for prec, lr in ((sscg.FP64, 18), (sscg.MIXED, 18), (sscg.MIXED, 12)):
+            c = make_ctx(sscg, dims, 0.13, U, lr)
+            yd = to_dev(np.zeros_like(x))
+            c.apply_A(to_dev(x), yd, prec=prec)
+            out[k, prec, lr] = to_host(yd).reshape(nsrc, -1)
+            c.close()
+    assert rel(out["march", sscg.FP64, 18], ref) < 1e-14
+    assert rel(out["march", sscg.FP64, 18], out["plain", sscg.FP64, 18]) < 1e-15
+    for lr in (18, 12):
+        assert rel(out["march", sscg.MIXED, lr], out["plain", sscg.MIXED, lr]) < 1e-6
+        assert rel(out["march", sscg.MIXED, lr], ref) < 2e-6
+
+
 @pytest.mark.parametrize("link_reals", [18, 12])
 def test_apply_A_fp32(sscg, cfg1, link_reals):
     case(f"apply_A fp32 link_reals={link_reals}")

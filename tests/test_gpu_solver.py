@@ -62,7 +62,9 @@ def test_poll_and_graph_do_not_change_results(sscg, prob):
 @pytest.mark.parametrize("env", [dict(SSCG_NR="1", SSCG_BS="64", SSCG_WBATCH="3", SSCG_XCD="0", SSCG_UNROLL="1"),
                                  dict(SSCG_NR="4", SSCG_BS="128", SSCG_WBATCH="16", SSCG_XCD="1", SSCG_UNROLL="4",
                                       SSCG_NT="1"),
-                                 dict(SSCG_NR="2", SSCG_BS="256", SSCG_WBATCH="1", SSCG_XCD="1", SSCG_UNROLL="2")])
+                                 dict(SSCG_NR="2", SSCG_BS="256", SSCG_WBATCH="1", SSCG_XCD="1", SSCG_UNROLL="2"),
+                                 dict(SSCG_NR="2", SSCG_TBS="64", SSCG_CT="3", SSCG_XCD="1"),
+                                 dict(SSCG_NR="1", SSCG_TBS="64", SSCG_CT="1", SSCG_XCD="0", SSCG_DORDER="2")])
 def test_launch_shapes_agree(sscg, prob, monkeypatch, env):
     case(f"launch shapes {env}")
     U, A, V, z = prob
