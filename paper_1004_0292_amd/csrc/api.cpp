@@ -68,7 +68,7 @@ struct sscg_ctx {
   std::map<std::string, Tune> tuned;
   // solver workspaces
   DevBuf v64, r64, p64, q64, W, r32, p32, q32, rbase, xpart64, xpart32, tmp, pq_part, rr_part, seed,
-      shift, zdev, small, cmom, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out;
+      shift, zdev, small, cmom, mgbuf, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out;
   SeedState *seed_host = nullptr;
   int seed_host_cap = 0;
   // profiling
@@ -189,7 +189,7 @@ void sscg_destroy(sscg_ctx *c) {
   hipStreamSynchronize(c->work);
   DevBuf *bufs[] = {&c->g64, &c->g32, &c->v64, &c->r64, &c->p64, &c->q64, &c->W, &c->r32, &c->p32,
                     &c->q32, &c->rbase, &c->xpart64, &c->xpart32, &c->tmp, &c->pq_part, &c->rr_part,
-                    &c->seed, &c->shift, &c->zdev, &c->small, &c->cmom, &c->Ybuf, &c->Sbuf, &c->Qbuf, &c->AQbuf,
+                    &c->seed, &c->shift, &c->zdev, &c->small, &c->cmom, &c->mgbuf, &c->Ybuf, &c->Sbuf, &c->Qbuf, &c->AQbuf,
                     &c->Xbuf, &c->AXbuf, &c->Accbuf, &c->apply_in, &c->apply_out};
   for (DevBuf *b : bufs) release(*b);
   if (c->seed_host) hipHostFree(c->seed_host);
@@ -413,6 +413,11 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
     };
     mk_s(pl.alpha.job[i], (double *)c->pq_part.p, (c->V + 63) / 64);
     mk_s(pl.scal.job[i], (double *)c->rr_part.p, nbv);
+    if (P[i].nmom > 0) {
+      pl.scal.job[i].mcoef = (const double2 *)P[i].mom_coef;
+      pl.scal.job[i].mg = (double2 *)c->mgbuf.p;
+      pl.scal.job[i].nmom = P[i].nmom;
+    }
     bs += L;
     auto mk_v = [&](VecJob &j, void *a, void *b, void *cc, void *d, int begin, int nblocks) {
       j.a = a; j.b = b; j.c = cc; j.d = d; j.e = nullptr; j.partial = (double *)c->rr_part.p;
@@ -434,7 +439,7 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
       for (VecBatch *mb : {&pl.m64, &pl.m32}) {
         VecJob &j = mb->job[i];
         mk_v(j, P[i].mom, c->W.p, c->r64.p, c->p64.p, bm, L * nbm);
-        j.e = const_cast<void *>(P[i].mom_coef);
+        j.e = c->mgbuf.p;
         j.nmom = P[i].nmom;
         j.nblk_mom = nbm;
       }
@@ -544,6 +549,10 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
   CHK(ensure(c, c->seed, L * sizeof(SeedState)));
   CHK(ensure(c, c->shift, L * N * sizeof(ShiftState)));
   CHK(ensure(c, c->zdev, N * 2 * sizeof(double)));
+  if (p.nmom > 0) {  // g of the in-loop moments; rows from nmom on stay zero
+    CHK(ensure(c, c->mgbuf, L * kMomRows * N * sizeof(double2)));
+    HIPCHK(c, hipMemsetAsync(c->mgbuf.p, 0, L * kMomRows * N * sizeof(double2), c->work));
+  }
   if (o.prec == SSCG_MIXED) {  // FP32 seed vectors and reliable-update storage
     CHK(ensure(c, c->r32, L * vec32));
     CHK(ensure(c, c->p32, L * vec32));

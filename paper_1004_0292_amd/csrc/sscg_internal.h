@@ -11,6 +11,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -38,12 +40,15 @@ template <typename C> __host__ __device__ __forceinline__ C cmulc(C a, C b) {
   C c; c.x = a.x * b.x + a.y * b.y; c.y = a.x * b.y - a.y * b.x; return c;
 }
 // acc += a * b
+// (written as chains of fused multiply-adds: four per complex product)
 template <typename C> __host__ __device__ __forceinline__ void cfma(C &acc, C a, C b) {
-  acc.x += a.x * b.x - a.y * b.y; acc.y += a.x * b.y + a.y * b.x;
+  acc.x = fma(a.x, b.x, acc.x); acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y); acc.y = fma(a.y, b.x, acc.y);
 }
 // acc += conj(a) * b
 template <typename C> __host__ __device__ __forceinline__ void cfmac(C &acc, C a, C b) {
-  acc.x += a.x * b.x + a.y * b.y; acc.y += a.x * b.y - a.y * b.x;
+  acc.x = fma(a.x, b.x, acc.x); acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y); acc.y = fma(-a.y, b.x, acc.y);
 }
 template <typename C> __host__ __device__ __forceinline__ C cscale(C a, decltype(C{}.x) s) { C c; c.x = a.x * s; c.y = a.y * s; return c; }
 // i * a
@@ -119,7 +124,13 @@ struct ScalarJob {
   int32_t nblk;          // partials per source
   int32_t nsrc, nshift, maxiter, block_begin;
   double tol;
+  // in-loop moments (shift scalars only): g[l][k][j] = mcoef[k][j] alpha_j for the
+  // shifts updated this iteration, 0 otherwise; rows k < nmom of [nsrc][32][nshift]
+  const double2 *mcoef;
+  double2 *mg;
+  int32_t nmom, pad;
 };
+constexpr int kMomRows = 32;  // rows of g per source (the largest moment count)
 struct ScalarBatch { ScalarJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
 
 __device__ __forceinline__ int find_job(const int32_t *begins, int njobs, int b) {
@@ -148,8 +159,10 @@ void launch_shift_update(const VecBatch &b, int prec, int seed_prec, int fold, i
 void launch_reliable_residual(const VecBatch &b, hipStream_t st);
 // Shift update with the moment sums accumulated in the loop (no stored x_j).
 // job: a = moments S (column k L + l of n entries), b = shift slots (p_j),
-// c = seed r, d = seed p (FP64), e = coefficients c[k][j] (device, [nmom][nshift]).
-constexpr int kMomBlock = 128;
+// c = seed r, d = seed p (FP64), e = g[l][k][j] = c[k][j] alpha_j of this
+// iteration ([nsrc][kMomRows][nshift], written by the shift-scalar kernel; rows
+// from nmom on stay zero).
+constexpr int kMomBlock = 256;   // entries (threads) per block of the in-loop moment kernel
 void launch_shift_moments(const VecBatch &b, int prec, int nmom_max, hipStream_t st);
 void launch_fold_seed(const VecBatch &b, hipStream_t st);
 void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st);

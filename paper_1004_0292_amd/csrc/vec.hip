@@ -142,6 +142,16 @@ __global__ __launch_bounds__(kBlock) void shift_scalars_kernel(ScalarBatch B) {
       H.upd = 0;
     }
   }
+  if (J.nmom > 0) {
+    // g[k][j] = c[k][j] alpha_j for the in-loop moments (zero for frozen shifts)
+    __syncthreads();
+    double2 *g = J.mg + (size_t)l * kMomRows * J.nshift;
+    for (int t = threadIdx.x; t < J.nmom * J.nshift; t += kBlock) {
+      const int j = t % J.nshift;
+      const ShiftState &H = J.shift[(size_t)l * J.nshift + j];
+      g[t] = H.upd ? cmul(J.mcoef[t], H.a) : make_double2(0.0, 0.0);
+    }
+  }
   const double na = block_sum_all<kBlock / 64>(nact, red);
   const double mr = block_max_all<kBlock / 64>(maxres, red);
   if (threadIdx.x == 0) {
@@ -411,11 +421,29 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
 // advanced as usual. One thread owns one entry of one source and loops over all
 // shifts, so each moment entry has a single writer; the shift vectors x_j are never
 // stored. Shift vectors are FP64 (T = double) or FP32 (after the FP32 switch); the
-// seed and the moments stay FP64.
+// seed and the moments stay FP64. g[k][j] = c[k][j] alpha_j (from the shift-scalar
+// kernel) and the shifts' beta_j, 1/pi_j are staged in LDS per chunk of shifts, and
+// the loads of several shifts are issued together.
+// shift slots: an FP64 p_j fills its slot of n double2, an FP32 one the first half
+template <typename T>
+__device__ __forceinline__ double2 ld_shift(const void *base, size_t slot, int64_t n, int64_t i) {
+  if constexpr (sizeof(T) == 8) return reinterpret_cast<const double2 *>(base)[slot * n + i];
+  const float2 f = reinterpret_cast<const float2 *>(reinterpret_cast<const double2 *>(base) + slot * n)[i];
+  return make_double2(f.x, f.y);
+}
+template <typename T>
+__device__ __forceinline__ void st_shift(void *base, size_t slot, int64_t n, int64_t i, double2 v) {
+  if constexpr (sizeof(T) == 8) reinterpret_cast<double2 *>(base)[slot * n + i] = v;
+  else reinterpret_cast<float2 *>(reinterpret_cast<double2 *>(base) + slot * n)[i] = make_float2((float)v.x, (float)v.y);
+}
+
 template <typename T, int MM>
 __global__ __launch_bounds__(kMomBlock) void shift_moments_kernel(VecBatch B) {
-  constexpr int JC = 64;  // shifts whose coefficients are staged in LDS at once
-  __shared__ double2 cs[MM * JC];
+  constexpr int JC = 32;  // shifts staged in LDS at once
+  constexpr int UB = 8;   // shifts whose loads are issued together
+  __shared__ double2 gs[MM][JC];       // g[k][j] of the chunk (zero rows from M on)
+  __shared__ double2 bs[JC], ips[JC];  // beta_j and 1/pi_j of the chunk
+  __shared__ int ups[JC];              // shift updated this iteration
   const int b = blockIdx.x;
   const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
   const int lb = b - J.block_begin;
@@ -426,38 +454,51 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_kernel(VecBatch B) {
   const int M = J.nmom, N = J.nshift;
   const int64_t i = (int64_t)vb * kMomBlock + threadIdx.x;
   const bool valid = i < n;
-  const double2 rv = valid ? reinterpret_cast<const double2 *>(J.c)[(size_t)l * n + i] : make_double2(0, 0);
+  const int64_t ii = valid ? i : 0;  // invalid lanes read entry 0 and store nothing
+  const double2 rv = reinterpret_cast<const double2 *>(J.c)[(size_t)l * n + ii];
+  const ShiftState *sh = J.shift + (size_t)l * N;
+  const size_t slot0 = (size_t)l * N;
+  const double2 *G = reinterpret_cast<const double2 *>(J.e) + (size_t)l * kMomRows * N;
   double2 acc[MM];
 #pragma unroll
   for (int k = 0; k < MM; ++k) acc[k] = make_double2(0, 0);
-  const double2 *cf = reinterpret_cast<const double2 *>(J.e);
   for (int j0 = 0; j0 < N; j0 += JC) {
     const int jn = min(JC, N - j0);
     __syncthreads();
     for (int t = threadIdx.x; t < MM * JC; t += kMomBlock) {
       const int k = t / JC, jj = t - k * JC;
-      cs[t] = (k < M && jj < jn) ? cf[(size_t)k * N + j0 + jj] : make_double2(0, 0);
+      gs[k][jj] = (k < M && jj < jn) ? G[(size_t)k * N + j0 + jj] : make_double2(0, 0);
+    }
+    for (int jj = threadIdx.x; jj < JC; jj += kMomBlock) {
+      const bool in = jj < jn;
+      ups[jj] = in ? sh[j0 + jj].upd : 0;
+      bs[jj] = in ? sh[j0 + jj].b : make_double2(0, 0);
+      ips[jj] = in ? sh[j0 + jj].ipi : make_double2(0, 0);
     }
     __syncthreads();
-    for (int jj = 0; jj < jn; ++jj) {
-      const int j = j0 + jj;
-      const ShiftState &H = J.shift[(size_t)l * N + j];
-      if (!H.upd || !valid) continue;
-      const size_t slot = (size_t)l * N + j;
-      double2 pv;
-      if constexpr (sizeof(T) == 8) pv = reinterpret_cast<const double2 *>(J.b)[slot * n + i];
-      else {
-        const float2 pf = reinterpret_cast<const float2 *>(reinterpret_cast<const double2 *>(J.b) + slot * n)[i];
-        pv = make_double2(pf.x, pf.y);
-      }
-      const double2 d = cmul(H.a, pv);  // alpha_j p_j
+    for (int u0 = 0; u0 < JC; u0 += UB) {
+      double2 pv[UB];
+      bool up[UB];
 #pragma unroll
-      for (int k = 0; k < MM; ++k)
-        if (k < M) cfma(acc[k], cs[k * JC + jj], d);
-      double2 pn = cmul(H.ipi, rv);
-      cfma(pn, H.b, pv);
-      if constexpr (sizeof(T) == 8) reinterpret_cast<double2 *>(J.b)[slot * n + i] = pn;
-      else reinterpret_cast<float2 *>(reinterpret_cast<double2 *>(J.b) + slot * n)[i] = make_float2((float)pn.x, (float)pn.y);
+      for (int uu = 0; uu < UB; ++uu) {
+        const int jj = u0 + uu;
+        up[uu] = ups[jj] != 0;
+        if (up[uu]) pv[uu] = ld_shift<T>(J.b, slot0 + j0 + jj, n, ii);
+      }
+#pragma unroll
+      for (int uu = 0; uu < UB; ++uu) {
+        const int jj = u0 + uu;
+        // (rows k >= M of g are zero: no branch per moment)
+        if (up[uu]) {
+#pragma unroll
+          for (int k = 0; k < MM; ++k) cfma(acc[k], gs[k][jj], pv[uu]);
+        }
+        if (up[uu] && valid) {
+          double2 pn = cmul(ips[jj], rv);
+          cfma(pn, bs[jj], pv[uu]);
+          st_shift<T>(J.b, slot0 + j0 + jj, n, i, pn);
+        }
+      }
     }
   }
   if (!valid) return;
@@ -466,10 +507,10 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_kernel(VecBatch B) {
   for (int k = 0; k < MM; ++k) {
     if (k < M) {
       double2 *sp = Sm + ((size_t)k * J.nsrc + l) * n + i;
-      double2 v = *sp;
-      v.x += acc[k].x;
-      v.y += acc[k].y;
-      *sp = v;
+      double2 o = *sp;
+      o.x += acc[k].x;
+      o.y += acc[k].y;
+      *sp = o;
     }
   }
   // seed direction p <- r + beta p
@@ -712,10 +753,11 @@ void launch_shift_update(const VecBatch &b, int prec, int seed_prec, int fold, i
 }
 template <typename T>
 static void launch_sm(const VecBatch &b, int mm, hipStream_t st) {
-  if (mm <= 8) hipLaunchKernelGGL((shift_moments_kernel<T, 8>), dim3(b.total_blocks), dim3(kMomBlock), 0, st, b);
-  else if (mm <= 16) hipLaunchKernelGGL((shift_moments_kernel<T, 16>), dim3(b.total_blocks), dim3(kMomBlock), 0, st, b);
-  else if (mm <= 24) hipLaunchKernelGGL((shift_moments_kernel<T, 24>), dim3(b.total_blocks), dim3(kMomBlock), 0, st, b);
-  else hipLaunchKernelGGL((shift_moments_kernel<T, 32>), dim3(b.total_blocks), dim3(kMomBlock), 0, st, b);
+  const dim3 g(b.total_blocks), t(kMomBlock);
+  if (mm <= 8) hipLaunchKernelGGL((shift_moments_kernel<T, 8>), g, t, 0, st, b);
+  else if (mm <= 16) hipLaunchKernelGGL((shift_moments_kernel<T, 16>), g, t, 0, st, b);
+  else if (mm <= 24) hipLaunchKernelGGL((shift_moments_kernel<T, 24>), g, t, 0, st, b);
+  else hipLaunchKernelGGL((shift_moments_kernel<T, 32>), g, t, 0, st, b);
 }
 void launch_shift_moments(const VecBatch &b, int prec, int nmom_max, hipStream_t st) {
   if (b.total_blocks <= 0) return;
