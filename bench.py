@@ -15,6 +15,10 @@ Printed as one JSON line on rank 0. Besides the throughput it carries:
                 traffic from committed rocprofv3 counter summaries when they match
                 the current kernel source, else null
   dslash        the same figures for the Wilson dslash
+  dslash_24x48  the dslash alone on the 24^3 x 48 lattice with 8 sources (FP32 with
+                12-real links, FP64 with 18-real links), autotuned launch shape
+  tts           time to solution of the step in FP64 and FP64-seed / FP32-shift
+                precision, with stored solutions and with in-loop moments
   cpu_baseline  the FP64 CPU oracle (numpy/scipy) on the host: one source's full
                 shifted CG (all N shifts) on the same workload, bounded in time
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
@@ -57,7 +61,8 @@ def pmc_traffic(kernel, workload):
 
 
 def cpu_baseline(w, budget_s=20.0):
-    """Oracle shifted CG on source 0 (all N shifts), stopped after budget_s seconds."""
+    """Oracle shifted CG (all N shifts) on the workload's sources, one after another,
+    stopped after budget_s seconds of wall time."""
     import numpy as np
     from oracle import quadrature as quad
     from oracle import solvers, wilson
@@ -66,7 +71,7 @@ def cpu_baseline(w, budget_s=20.0):
     t_setup = time.perf_counter()
     U = w.gauge()
     A = wilson.hermitian_wilson(U, w.dims, w.kappa)
-    v = synth.sources(w.V, 1, w.seed).reshape(-1)
+    V = w.sources().reshape(w.L, -1)
     z, zeta = quad.line_nodes(w.N, w.gamma, w.rho, w.beta)
     setup = time.perf_counter() - t_setup
     updates = [0]
@@ -81,20 +86,21 @@ def cpu_baseline(w, budget_s=20.0):
         if time.perf_counter() - t0 > budget_s:
             raise Stop()
 
-    finished = True
+    done = 0
     try:
-        r = solvers.shifted_cg(lambda x: A @ x, v, z, w.gamma, w.tol, record=rec)
-        iters = r.iters
+        for l in range(w.L):
+            solvers.shifted_cg(lambda x: A @ x, V[l], z, w.gamma, w.tol, record=rec)
+            done += 1
     except Stop:
-        finished = False
-        iters = None
+        pass
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
     return {"value": updates[0] / wall, "unit": "shift-updates/s", "cores": max(1, round(cpu / wall)),
             "kind": "oracle",
-            "sample": (f"source 0 of {w.L}: FP64 shifted CG for all {w.N} shifts on the explicit sparse A "
-                       f"({'to convergence, ' + str(iters) + ' iterations' if finished else 'stopped after ' + str(round(wall, 1)) + ' s'}); "
-                       f"{updates[0]} shift-updates in {wall:.1f} s; sparse matvec and vector updates single-threaded; "
+            "sample": (f"FP64 shifted CG for all {w.N} shifts on the explicit sparse A (scipy CSR), sources "
+                       f"solved one after another: {done} of {w.L} to convergence"
+                       f"{'' if done == w.L else ', the next stopped at the time limit'}; "
+                       f"{updates[0]} shift-updates in {wall:.1f} s; cores = process CPU time / wall time; "
                        f"matrix assembly ({setup:.1f} s) excluded"),
             "host_cpus": os.cpu_count()}
 
@@ -183,6 +189,38 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def dslash_large(S, reps=10):
+    """The Wilson dslash alone on the large single-GPU lattice (24^3 x 48, 8 sources):
+    FP32 spinors with 12-real links and FP64 spinors with 18-real links, in the launch
+    shape the library's autotuner picks, timed with HIP events around every launch,
+    against its compulsory HBM bytes (spinors in and out once, links once)."""
+    import torch
+    import synth
+    w = synth.CONFIGS["wilson24x48_mixed12"]
+    U = w.gauge()
+    x = torch.from_numpy(w.sources()).to("cuda:0")
+    y = torch.empty_like(x)
+    out = {"lattice": list(w.dims), "sources": w.L}
+    for name, prec, lr, wb in (("fp32_links12", S.MIXED, 12, 4), ("fp64_links18", S.FP64, 18, 8)):
+        c = S.Context(w.dims, w.kappa)
+        c.set_gauge(U, lr)
+        c.apply_A(x, y, prec)            # chooses the launch shape
+        c.set_profiling(True)
+        for _ in range(reps):
+            c.apply_A(x, y, prec)
+        ms, calls = c.stage_times()
+        avg_s = ms[0] / 1e3 / calls[0]
+        nbytes = w.L * w.V * 24 * wb * 2 + w.V * 4 * lr * wb
+        ach = nbytes / avg_s / 1e9
+        out[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": nbytes, "launches": int(calls[0])}
+        c.close()
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(nbytes=2 << 30, reps=5):
     """Device-to-device copy rate (read + write bytes per second) as the achievable
     HBM reference next to the 8 TB/s peak."""
@@ -215,6 +253,8 @@ def main():
                     help="accumulate the moments inside the solve (no stored solutions)")
     ap.add_argument("--weighted-tol", action="store_true", help="moment-weighted per-shift stopping")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dslash-large", action="store_true",
+                    help="skip the dslash-only measurement on the 24^3 x 48 lattice")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 vs mixed time-to-solution comparison")
     ap.add_argument("--no-events", action="store_true", help="time without per-launch events")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -360,6 +400,8 @@ def main():
     if not args.no_compare:
         line["tts"] = tts_compare(S, ctx, params, vd, max_eigs, args.steps)
     line["copy_bw_GBs"] = copy_bandwidth()
+    if not args.no_dslash_large:
+        line["dslash_24x48"] = dslash_large(S)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

@@ -295,8 +295,8 @@ static int nblk_site(const sscg_ctx *c, int bs, int ct, int ty, int tz) {
 static int nblk_vec(const sscg_ctx *c) { return (int)((c->n + kBlock * kEptHost - 1) / (kBlock * kEptHost)); }
 
 // FP64 dslash of nsrc planar vectors: out = A in (mode 0) or sigma in - A in (mode 1)
-static void dslash_plain(sscg_ctx *c, const void *in, void *out, int nsrc, int prec, int mode, double sigma,
-                         double *partial, const SeedState *seed, hipStream_t st) {
+static void dslash_with(sscg_ctx *c, const Tune &t, const void *in, void *out, int nsrc, int prec, int mode,
+                        double sigma, double *partial, const SeedState *seed, hipStream_t st) {
   DslashBatch b{};
   DslashJob &j = b.job[0];
   j.in = in;
@@ -309,11 +309,11 @@ static void dslash_plain(sscg_ctx *c, const void *in, void *out, int nsrc, int p
   for (int i = 0; i < 4; ++i) j.dims[i] = c->dims[i];
   j.V = c->V;
   j.nsrc = nsrc;
-  int ct = c->tune.ct, ty = 0, tz = 0;
-  if (ct > 0 && !tile_shape(c, c->tune.tbs, c->tune.nr, prec, ty, tz)) ct = 0;
-  j.nblk_site = nblk_site(c, c->tune.bs, ct, ty, tz);
+  int ct = t.ct, ty = 0, tz = 0;
+  if (ct > 0 && !tile_shape(c, t.tbs, t.nr, prec, ty, tz)) ct = 0;
+  j.nblk_site = nblk_site(c, t.bs, ct, ty, tz);
   j.block_begin = 0;
-  j.nblocks = j.nblk_site * ((nsrc + c->tune.nr - 1) / c->tune.nr);
+  j.nblocks = j.nblk_site * ((nsrc + t.nr - 1) / t.nr);
   j.mode = mode;
   j.ct = ct;
   j.ty = ty;
@@ -321,8 +321,76 @@ static void dslash_plain(sscg_ctx *c, const void *in, void *out, int nsrc, int p
   j.order = c->dorder;
   b.njobs = 1;
   b.total_blocks = j.nblocks;
-  launch_dslash(b, prec, c->tune.nr, prec == 0 ? 18 : c->link_reals, c->tune.bs, c->tune.xcd, ct, st);
+  launch_dslash(b, prec, t.nr, prec == 0 ? 18 : c->link_reals, t.bs, t.xcd, ct, st);
 }
+
+// Mean duration (ms) of reps launches after one warm-up launch, from HIP events.
+template <typename F>
+static double time_launches(hipStream_t st, F &&launch, int reps) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 1e300;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return 1e300;
+  }
+  launch();
+  hipEventRecord(e0, st);
+  for (int r = 0; r < reps; ++r) launch();
+  hipEventRecord(e1, st);
+  hipEventSynchronize(e1);
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return ms / reps;
+}
+
+// Dslash launch shape for out = A in on nsrc vectors outside a solve (apply_A, true
+// residuals, Rayleigh-Ritz products): with autotuning on, every shape of the
+// site-parallel and tile kernels is timed once on the caller's buffers (out is
+// rewritten by the real launch that follows) and the fastest is kept per
+// (precision, nsrc).
+static Tune apply_tune(sscg_ctx *c, const void *in, void *out, int nsrc, int prec, hipStream_t st) {
+  if (!c->autotune) return c->tune;
+  const std::string key = "apply|" + std::to_string(prec) + "|" + std::to_string(nsrc);
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) return it->second;
+  Tune best = c->tune, cand = c->tune;
+  double tbest = 1e300;
+  auto try_shape = [&](const Tune &cd) {
+    int ty, tz;
+    if (cd.ct > 0 && !tile_shape(c, cd.tbs, cd.nr, prec, ty, tz)) return;
+    const double t = time_launches(st, [&] { dslash_with(c, cd, in, out, nsrc, prec, 0, 0.0, nullptr, nullptr, st); }, 3);
+    if (t < tbest) {
+      tbest = t;
+      best = cd;
+    }
+  };
+  for (int nr : {1, 2, 4}) {
+    if (nr > 1 && nr > nsrc) continue;
+    cand.nr = nr;
+    cand.ct = 0;
+    for (int bs : {64, 128, 256})
+      for (int xcd : {0, 1}) {
+        cand.bs = bs;
+        cand.xcd = xcd;
+        try_shape(cand);
+      }
+    cand.xcd = 1;
+    for (int ct : {2, 4, 8, 16})
+      for (int tbs = 64; tbs <= 1024; tbs += 64) {
+        cand.ct = ct;
+        cand.tbs = tbs;
+        try_shape(cand);
+      }
+  }
+  if (getenv("SSCG_VERBOSE"))
+    fprintf(stderr, "[sscg] tuned %s: nr=%d bs=%d xcd=%d ct=%d tbs=%d\n", key.c_str(), best.nr, best.bs, best.xcd,
+            best.ct, best.tbs);
+  c->tuned[key] = best;
+  return best;
+}
+
 
 static int host_sum_partials(sscg_ctx *c, const double *dev_partial, int nvec, int nblk, std::vector<double> &out,
                              hipStream_t st) {
@@ -940,7 +1008,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
         for (int j0 = 0; j0 < N; j0 += L) {
           const int cnt = std::min(L, N - j0);
           const char *yj = (const char *)p.y + ((size_t)l * N + j0) * vec64;
-          dslash_plain(c, yj, c->q64.p, cnt, 0, 0, 0.0, nullptr, nullptr, st);
+          dslash_with(c, apply_tune(c, yj, c->q64.p, cnt, 0, st), yj, c->q64.p, cnt, 0, 0, 0.0, nullptr, nullptr, st);
           launch_true_residual((const char *)c->v64.p + l * vec64, yj, c->q64.p, (const double *)c->zdev.p + 2 * j0,
                                (int64_t)n, cnt, (double *)c->rr_part.p, nb, st);
           std::vector<double> r2;
@@ -1048,8 +1116,9 @@ int sscg_apply_A(sscg_ctx *c, const void *x, void *y, int32_t nsrc, int32_t prec
       HIPCHK(c, hipEventCreate(&e));
       c->events.push_back(e);
     }
+    const Tune t = apply_tune(c, c->apply_in.p, c->apply_out.p, nsrc, prec, st);
     HIPCHK(c, hipEventRecord(c->events[0], st));
-    dslash_plain(c, c->apply_in.p, c->apply_out.p, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
+    dslash_with(c, t, c->apply_in.p, c->apply_out.p, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
     HIPCHK(c, hipEventRecord(c->events[1], st));
     HIPCHK(c, hipEventSynchronize(c->events[1]));
     float ms = 0.f;
@@ -1057,7 +1126,8 @@ int sscg_apply_A(sscg_ctx *c, const void *x, void *y, int32_t nsrc, int32_t prec
     c->stage_ms[ST_DSLASH] += ms;
     c->stage_calls[ST_DSLASH] += 1;
   } else {
-    dslash_plain(c, c->apply_in.p, c->apply_out.p, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
+    const Tune t = apply_tune(c, c->apply_in.p, c->apply_out.p, nsrc, prec, st);
+    dslash_with(c, t, c->apply_in.p, c->apply_out.p, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
   }
   launch_unpack(c->apply_out.p, prec, y, nsrc, c->V, st);
   HIPCHK(c, hipGetLastError());
@@ -1216,7 +1286,9 @@ static int apply_A_planar(sscg_ctx *c, const void *X, void *AX, int ncol, hipStr
   const size_t vec = c->n * sizeof(double2);
   for (int k = 0; k < ncol; k += 8) {
     const int cnt = std::min(8, ncol - k);
-    dslash_plain(c, (const char *)X + k * vec, (char *)AX + k * vec, cnt, 0, 0, 0.0, nullptr, nullptr, st);
+    const void *xin = (const char *)X + k * vec;
+    void *xout = (char *)AX + k * vec;
+    dslash_with(c, apply_tune(c, xin, xout, cnt, 0, st), xin, xout, cnt, 0, 0, 0.0, nullptr, nullptr, st);
   }
   return SSCG_OK;
 }
