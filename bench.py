@@ -42,7 +42,9 @@ DEFAULT_CONFIG = "wilson8_fp64"
 STAGES = ["dslash", "seed_alpha", "seed_r_update", "shift_scalars", "shift_update", "reliable_update",
           "solve_loop"]
 KERNEL_SOURCES = {"shift_update": "paper_1004_0292_amd/csrc/vec.hip",
-                  "dslash": "paper_1004_0292_amd/csrc/dslash.hip"}
+                  "dslash": "paper_1004_0292_amd/csrc/dslash.hip",
+                  "dslash_fp32_links12": "paper_1004_0292_amd/csrc/dslash.hip",
+                  "dslash_fp64_links18": "paper_1004_0292_amd/csrc/dslash.hip"}
 
 
 def source_hash(rel):
@@ -51,7 +53,7 @@ def source_hash(rel):
 
 def pmc_traffic(kernel, workload):
     """HBM bytes per launch from the committed counter summary, if it still matches."""
-    f = ROOT / "profiles" / f"{kernel}_{workload}_pmc.json"
+    f = ROOT / "profiles" / f"{kernel}_{workload}_pmc.txt"
     if not f.exists():
         return None
     d = json.loads(f.read_text())
@@ -213,7 +215,8 @@ def dslash_large(S, reps=10):
         nbytes = w.L * w.V * 24 * wb * 2 + w.V * 4 * lr * wb
         ach = nbytes / avg_s / 1e9
         out[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg_s * 1e6, 2),
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": pmc_traffic("dslash_" + name, w.name), "avg_launch_us": round(avg_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": nbytes, "launches": int(calls[0])}
         c.close()
     del x, y
