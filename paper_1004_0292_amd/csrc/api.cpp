@@ -441,7 +441,9 @@ struct IterPlan {
   VecBatch m64, m32;  // shift update with in-loop moments (FP64 / FP32 shift vectors)
   int nmom_max;       // 0: the solutions are stored
   int ct;             // dslash kernel: t-slices per block (0: site-parallel)
+  bool fuse_alpha;    // the residual update forms the seed step length itself
 };
+constexpr int kFuseAlphaMax = 1024;  // <p, Bp> partials per source up to which the step length is fused
 
 static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts &o, const Tune &t) {
   memset(&pl, 0, sizeof(pl));
@@ -450,6 +452,11 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
   // the tile kernel needs a tile of t.tbs sites on every lattice of the batch, with
   // LDS for FP64 spinors (the FP64 phase and the reliable updates use it too)
   pl.ct = t.ct;
+  // small lattices: the seed step length is formed inside the residual update from
+  // the few <p, Bp> partials (one launch less per iteration)
+  pl.fuse_alpha = env_int("SSCG_FUSE_ALPHA", 1) != 0;
+  for (int i = 0; i < np; ++i)
+    if ((P[i].c->V + 63) / 64 > kFuseAlphaMax) pl.fuse_alpha = false;
   std::vector<int> tys(np, 0), tzs(np, 0);
   for (int i = 0; i < np; ++i)
     if (pl.ct > 0 && !tile_shape(P[i].c, t.tbs, t.nr, 0, tys[i], tzs[i])) pl.ct = 0;
@@ -494,6 +501,11 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
     };
     mk_v(pl.r64.job[i], c->r64.p, c->q64.p, nullptr, nullptr, bv, L * nbv);
     mk_v(pl.r32.job[i], c->r32.p, c->q32.p, c->xpart32.p, c->p32.p, bv, L * nbv);
+    if (pl.fuse_alpha)
+      for (VecJob *rj : {&pl.r64.job[i], &pl.r32.job[i]}) {
+        rj->npq = (c->V + 63) / 64;
+        rj->pq_partial = (const double *)c->pq_part.p;
+      }
     mk_v(pl.fold_seed.job[i], c->xpart64.p, c->xpart32.p, nullptr, nullptr, bv, L * nbv);
     mk_v(pl.rel.job[i], c->rbase.p, c->q64.p, c->r64.p, c->r32.p, bv, L * nbv);
     bv += L * nbv;
@@ -581,8 +593,10 @@ static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru,
   const int sp = (prec == 1 && seed32) ? 1 : 0;  // seed precision
   rec.mark(ST_DSLASH);
   launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, pl.ct, st);
-  rec.mark(ST_ALPHA);
-  launch_seed_alpha(pl.alpha, st);
+  if (!pl.fuse_alpha) {
+    rec.mark(ST_ALPHA);
+    launch_seed_alpha(pl.alpha, st);
+  }
   rec.mark(ST_RUPD);
   launch_seed_r_update(sp == 0 ? pl.r64 : pl.r32, sp, st);
   if (sp == 1 && ru) {

@@ -114,6 +114,10 @@ struct VecJob {
   int32_t nsrc, nshift, nblk_vec, block_begin, nblocks, wbatch;
   int32_t nmom;          // moments accumulated inside the solve (0: none)
   int32_t nblk_mom;      // blocks per source of the in-loop moment kernel
+  // seed residual update only: > 0 = the step length is formed in the kernel from
+  // this many <p, Bp> partials per source at pq_partial (no separate alpha kernel)
+  int32_t npq;
+  const double *pq_partial;
 };
 struct VecBatch { VecJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
 

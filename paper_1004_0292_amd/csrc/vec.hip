@@ -187,8 +187,37 @@ __global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
   const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
   const int lb = b - J.block_begin;
   const int l = lb / J.nblk_vec, vb = lb - l * J.nblk_vec;
-  if (J.seed[l].done) return;
-  const T alpha = (T)J.seed[l].alpha;
+  SeedState &S = J.seed[l];
+  if (S.done) {
+    // (the alpha kernel clears the flag of a finished source; without it, this does)
+    if (J.npq > 0 && vb == 0 && threadIdx.x == 0) S.pending = 0;
+    return;
+  }
+  double alpha64;
+  if (J.npq > 0) {
+    // the step length of the alpha kernel, formed by every block from the same
+    // partials in the same order (so every block gets the same value); the first
+    // block of the source also writes the seed state
+    double v = 0.0;
+    const double *pp = J.pq_partial + (size_t)l * J.npq;
+    for (int t = threadIdx.x; t < J.npq; t += kBlock) v += pp[t];
+    const double pq = block_sum_all<kBlock / 64>(v, red);
+    const bool broke = pq == 0.0 || !isfinite(pq);
+    alpha64 = broke ? 0.0 : S.rho / pq;
+    if (vb == 0 && threadIdx.x == 0) {
+      S.pending = 0;
+      if (broke) {
+        S.status = -5;  // SSCG_EBREAKDOWN
+        S.done = 1;
+      } else {
+        S.alpha = alpha64;
+      }
+    }
+    if (broke) return;
+  } else {
+    alpha64 = S.alpha;
+  }
+  const T alpha = (T)alpha64;
   C *r = reinterpret_cast<C *>(J.a) + (size_t)l * J.n;
   const C *q = reinterpret_cast<const C *>(J.b) + (size_t)l * J.n;
   C *xp = J.c ? reinterpret_cast<C *>(J.c) + (size_t)l * J.n : nullptr;
