@@ -598,8 +598,9 @@ static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru,
     launch_seed_alpha(pl.alpha, st);
   }
   rec.mark(ST_RUPD);
+  const bool ru_now = sp == 1 && ru;
   launch_seed_r_update(sp == 0 ? pl.r64 : pl.r32, sp, st);
-  if (sp == 1 && ru) {
+  if (ru_now) {
     rec.mark(ST_RU);
     launch_fold_seed(pl.fold_seed, st);
     launch_dslash(pl.dru, 0, t.nr, 18, t.bs, t.xcd, pl.ct, st);

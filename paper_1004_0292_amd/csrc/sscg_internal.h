@@ -104,6 +104,19 @@ struct DslashJob {
 };
 struct DslashBatch { DslashJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
 
+struct ScalarJob {
+  SeedState *seed; ShiftState *shift;
+  const double *partial; // partial sums to reduce (pq or rr)
+  int32_t nblk;          // partials per source
+  int32_t nsrc, nshift, maxiter, block_begin;
+  double tol;
+  // in-loop moments (shift scalars only): g[l][k][j] = mcoef[k][j] alpha_j for the
+  // shifts updated this iteration, 0 otherwise; rows k < nmom of [nsrc][32][nshift]
+  const double2 *mcoef;
+  double2 *mg;
+  int32_t nmom, pad;
+};
+constexpr int kMomRows = 32;  // rows of g per source (the largest moment count)
 // Element-wise pass over nsrc vectors of n complex entries of one problem.
 struct VecJob {
   void *a; void *b; void *c; void *d; void *e;   // meaning depends on the kernel
@@ -122,19 +135,6 @@ struct VecJob {
 struct VecBatch { VecJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
 
 // Scalar kernels: one block per (job, source).
-struct ScalarJob {
-  SeedState *seed; ShiftState *shift;
-  const double *partial; // partial sums to reduce (pq or rr)
-  int32_t nblk;          // partials per source
-  int32_t nsrc, nshift, maxiter, block_begin;
-  double tol;
-  // in-loop moments (shift scalars only): g[l][k][j] = mcoef[k][j] alpha_j for the
-  // shifts updated this iteration, 0 otherwise; rows k < nmom of [nsrc][32][nshift]
-  const double2 *mcoef;
-  double2 *mg;
-  int32_t nmom, pad;
-};
-constexpr int kMomRows = 32;  // rows of g per source (the largest moment count)
 struct ScalarBatch { ScalarJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
 
 __device__ __forceinline__ int find_job(const int32_t *begins, int njobs, int b) {

@@ -94,11 +94,10 @@ __global__ __launch_bounds__(kBlock) void seed_alpha_kernel(ScalarBatch B) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void shift_scalars_kernel(ScalarBatch B) {
-  __shared__ double red[kBlock / 64];
-  const int b = blockIdx.x;
-  const ScalarJob &J = B.job[job_of(B.job, B.njobs, b)];
-  const int l = b - J.block_begin;
+// Seed and shift scalars of one source after its residual update (one block):
+// rho_{k+1}, beta_k, the pi recurrences, alpha_j, beta_j, 1/pi_j, freezing, and the
+// seed state the host polls.
+__device__ void shift_scalars_body(const ScalarJob &J, int l, double *red) {
   SeedState &S = J.seed[l];
   if (S.done) return;
   double v = 0.0;
@@ -174,6 +173,13 @@ __global__ __launch_bounds__(kBlock) void shift_scalars_kernel(ScalarBatch B) {
       S.status = -4;  // SSCG_ENOTCONV
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void shift_scalars_kernel(ScalarBatch B) {
+  __shared__ double red[kBlock / 64];
+  const int b = blockIdx.x;
+  const ScalarJob &J = B.job[job_of(B.job, B.njobs, b)];
+  shift_scalars_body(J, b - J.block_begin, red);
 }
 
 // ---------------------------------------------------------------------------

@@ -62,18 +62,21 @@ def test_poll_and_graph_do_not_change_results(sscg, prob):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_fused_step_length_is_bitwise_the_same(sscg, prob, monkeypatch, prec):
     """The seed step length formed inside the residual update (small lattices) equals
-    the separate alpha kernel's bit for bit: same partials, same summation order."""
+    the separate alpha kernel's bit for bit: same partials, same summation order. The
+    mixed case includes reliable-update iterations."""
     case(f"fused alpha {prec}")
     U, A, V, z = prob
     kw = dict(prec=sscg.MIXED, ru_interval=20, switch_tol=1e-6) if prec == "mixed" else {}
-    monkeypatch.setenv("SSCG_NR", "2")           # one fixed launch shape for both runs
-    monkeypatch.setenv("SSCG_FUSE_ALPHA", "1")
-    y1, r1 = solve(sscg, U, V, z, **kw)
-    monkeypatch.setenv("SSCG_FUSE_ALPHA", "0")
-    y0, r0 = solve(sscg, U, V, z, **kw)
-    assert r1.status == r0.status == sscg.OK
-    assert np.array_equal(y0, y1)
-    assert np.array_equal(r0.conv_iter, r1.conv_iter) and np.array_equal(r0.iters, r1.iters)
+    monkeypatch.setenv("SSCG_NR", "2")           # one fixed launch shape for every run
+    out = []
+    for fa in ("0", "1"):
+        monkeypatch.setenv("SSCG_FUSE_ALPHA", fa)
+        out.append(solve(sscg, U, V, z, **kw))
+    (y0, r0) = out[0]
+    for y1, r1 in out[1:]:
+        assert r1.status == r0.status == sscg.OK
+        assert np.array_equal(y0, y1)
+        assert np.array_equal(r0.conv_iter, r1.conv_iter) and np.array_equal(r0.iters, r1.iters)
 
 
 @pytest.mark.parametrize("env", [dict(SSCG_NR="1", SSCG_BS="64", SSCG_WBATCH="3", SSCG_XCD="0", SSCG_UNROLL="1"),
