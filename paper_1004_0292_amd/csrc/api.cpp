@@ -171,7 +171,7 @@ int sscg_create(sscg_ctx **out, const int32_t dims[4], double kappa, double r, i
   c->tune.tbs = env_int("SSCG_TBS", 256);
   c->dorder = env_int("SSCG_DORDER", 1);
   if (c->dorder < 0 || c->dorder > 2) c->dorder = 1;
-  if (c->tune.ct < 0) c->tune.ct = 0;
+  if (c->tune.ct < -1) c->tune.ct = 0;
   c->tune.nt = env_int("SSCG_NT", 0);
   c->autotune = env_int("SSCG_AUTOTUNE", 1) != 0 && !getenv("SSCG_NR") && !getenv("SSCG_BS") &&
                 !getenv("SSCG_WBATCH") && !getenv("SSCG_XCD") && !getenv("SSCG_UNROLL") && !getenv("SSCG_NT") && !getenv("SSCG_CT") &&
@@ -285,10 +285,12 @@ static bool tile_shape(const sscg_ctx *c, int tbs, int nr, int prec, int &ty, in
   }
   return best < 1e29;
 }
-// site blocks per source group of the dslash: one thread per site (ct = 0) or
-// tiles times t-ranges of the tile kernel (ct > 0)
+// site blocks per source group of the dslash: 64-site blocks of the direction-split
+// kernel (ct < 0), one thread per site (ct = 0), or tiles times t-ranges of the tile
+// kernel (ct > 0)
 static int nblk_site(const sscg_ctx *c, int bs, int ct, int ty, int tz) {
-  if (ct <= 0) return (c->V + bs - 1) / bs;
+  if (ct < 0) return (c->V + 63) / 64;
+  if (ct == 0) return (c->V + bs - 1) / bs;
   const int Lt = c->dims[3];
   return (c->dims[1] / ty) * (c->dims[2] / tz) * ((Lt + ct - 1) / ct);
 }
@@ -311,6 +313,7 @@ static void dslash_with(sscg_ctx *c, const Tune &t, const void *in, void *out, i
   j.nsrc = nsrc;
   int ct = t.ct, ty = 0, tz = 0;
   if (ct > 0 && !tile_shape(c, t.tbs, t.nr, prec, ty, tz)) ct = 0;
+  if (ct < 0 && t.nr > 2) ct = 0;
   j.nblk_site = nblk_site(c, t.bs, ct, ty, tz);
   j.block_begin = 0;
   j.nblocks = j.nblk_site * ((nsrc + t.nr - 1) / t.nr);
@@ -377,6 +380,10 @@ static Tune apply_tune(sscg_ctx *c, const void *in, void *out, int nsrc, int pre
         try_shape(cand);
       }
     cand.xcd = 1;
+    if (nr <= 2) {
+      cand.ct = -1;
+      try_shape(cand);
+    }
     for (int ct : {2, 4, 8, 16})
       for (int tbs = 64; tbs <= 1024; tbs += 64) {
         cand.ct = ct;
@@ -460,6 +467,7 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
   std::vector<int> tys(np, 0), tzs(np, 0);
   for (int i = 0; i < np; ++i)
     if (pl.ct > 0 && !tile_shape(P[i].c, t.tbs, t.nr, 0, tys[i], tzs[i])) pl.ct = 0;
+  if (pl.ct < 0 && t.nr > 2) pl.ct = 0;
   for (int i = 0; i < np; ++i) {
     sscg_ctx *c = P[i].c;
     const int L = P[i].L, N = P[i].N;
@@ -766,7 +774,7 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
   auto try_shape = [&](const Tune &cd) {
     IterPlan pl;
     build_plan(P, pl, o, cd);
-    if (cd.ct > 0 && pl.ct == 0) return;  // no tile of this size on some lattice
+    if (cd.ct != 0 && pl.ct == 0) return;  // no tile of this size on some lattice
     const double t = time_it([&] {
       launch_dslash(dprec ? pl.d32 : pl.d64, dprec, cd.nr, dprec ? lr : 18, cd.bs, cd.xcd, pl.ct, st);
     }, 5);
@@ -789,8 +797,13 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
         cand.xcd = xcd;
         try_shape(cand);
       }
-    // tile kernel: t-slices per block and tile size
+    // direction-split kernel (small lattices)
     cand.xcd = 1;
+    if (nr <= 2) {
+      cand.ct = -1;
+      try_shape(cand);
+    }
+    // tile kernel: t-slices per block and tile size
     for (int ct : {2, 4, 8, 16})
       for (int tbs = 64; tbs <= 1024; tbs += 64) {
         cand.ct = ct;

@@ -259,6 +259,117 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
   }
 }
 
+// Direction-split variant for small lattices (latency-bound: too few sites to fill
+// the chip with one thread per site). A block owns 64 sites and NR sources; each of
+// its 4 wavefronts takes one direction mu (forward and backward hop), the four
+// 12-component results are added in LDS in a fixed order, and wavefront w then
+// finishes output components 3w .. 3w+2. One partial of Re <psi, out> per 64 sites,
+// as in the other kernels.
+template <typename T, int NR, int LR>
+__global__ __launch_bounds__(256) void dslash_split_kernel(DslashBatch B, int xcd_remap) {
+  using C = V2<T>;
+  __shared__ C red[4][NR * 12][64];
+  __shared__ double dsum[4][NR];
+  int b = blockIdx.x;
+  if (xcd_remap) b = xcd_remap_block(b, gridDim.x);
+  int begins[kMaxJobs];
+#pragma unroll
+  for (int k = 0; k < kMaxJobs; ++k) begins[k] = B.job[k].block_begin;
+  const int ji = find_job(begins, B.njobs, b);
+  const DslashJob &J = B.job[ji];
+  const int lb = b - J.block_begin;
+  const int groups = (J.nsrc + NR - 1) / NR;
+  const int sblk = lb / groups, group = lb - sblk * groups;
+  const int l0 = group * NR;
+  const int nvalid = min(NR, J.nsrc - l0);
+  if (J.seed) {
+    bool all_done = true;
+    for (int r = 0; r < nvalid; ++r) all_done &= (J.seed[l0 + r].done != 0);
+    if (all_done) return;  // uniform over the block, before any barrier
+  }
+  const int V = J.V;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int s = sblk * 64 + lane;
+  const bool valid = s < V;
+  const V2<T> *in = reinterpret_cast<const V2<T> *>(J.in) + (size_t)l0 * 12 * V;
+  V2<T> *out = reinterpret_cast<V2<T> *>(J.out) + (size_t)l0 * 12 * V;
+  const V2<T> *gauge = reinterpret_cast<const V2<T> *>(J.gauge);
+  C acc[NR][12];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[r][c] = cmk<C>(0, 0);
+  if (valid) {
+    const int Lx = J.dims[0], Ly = J.dims[1], Lz = J.dims[2], Lt = J.dims[3];
+    const int x = s % Lx, t1 = s / Lx, y = t1 % Ly, t2 = t1 / Ly, z = t2 % Lz, t = t2 / Lz;
+    if (wv == 0) {
+      hop<T, NR, LR, 0>(in, gauge, V, s, s + (x == Lx - 1 ? 1 - Lx : 1), s + (x == 0 ? Lx - 1 : -1), nvalid, acc);
+    } else if (wv == 1) {
+      const int sy = Lx;
+      hop<T, NR, LR, 1>(in, gauge, V, s, s + (y == Ly - 1 ? (1 - Ly) * sy : sy), s + (y == 0 ? (Ly - 1) * sy : -sy),
+                        nvalid, acc);
+    } else if (wv == 2) {
+      const int sz = Lx * Ly;
+      hop<T, NR, LR, 2>(in, gauge, V, s, s + (z == Lz - 1 ? (1 - Lz) * sz : sz), s + (z == 0 ? (Lz - 1) * sz : -sz),
+                        nvalid, acc);
+    } else {
+      const int st = Lx * Ly * Lz;
+      hop<T, NR, LR, 3>(in, gauge, V, s, s + (t == Lt - 1 ? (1 - Lt) * st : st), s + (t == 0 ? (Lt - 1) * st : -st),
+                        nvalid, acc);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) red[wv][r * 12 + c][lane] = acc[r][c];
+  __syncthreads();
+  const T kap = (T)J.kappa;
+  const T sig = (T)J.sigma;
+  double dot[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    dot[r] = 0.0;
+    if (r < nvalid && valid) {
+      const C *src = in + (size_t)r * 12 * V + s;
+      C *dst = out + (size_t)r * 12 * V + s;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        const int c = 3 * wv + cc;
+        C a = red[0][r * 12 + c][lane];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) a = a + red[w][r * 12 + c][lane];
+        const C p = src[(size_t)c * V];
+        C o;
+        if (J.mode == 1) {
+          if (c < 6) { o.x = (sig - (T)1) * p.x + kap * a.x; o.y = (sig - (T)1) * p.y + kap * a.y; }
+          else       { o.x = (sig + (T)1) * p.x - kap * a.x; o.y = (sig + (T)1) * p.y - kap * a.y; }
+        } else {
+          if (c < 6) { o.x = p.x - kap * a.x; o.y = p.y - kap * a.y; }
+          else       { o.x = kap * a.x - p.x; o.y = kap * a.y - p.y; }
+        }
+        dst[(size_t)c * V] = o;
+        dot[r] += (double)p.x * (double)o.x + (double)p.y * (double)o.y;
+      }
+    }
+  }
+  if (J.partial) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      double d = dot[r];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+      if (lane == 0) dsum[wv][r] = d;
+    }
+    __syncthreads();
+    const int npart = (V + 63) >> 6;
+    if (threadIdx.x < NR && (int)threadIdx.x < nvalid) {
+      const int r = threadIdx.x;
+      J.partial[(size_t)(l0 + r) * npart + sblk] = ((dsum[0][r] + dsum[1][r]) + dsum[2][r]) + dsum[3][r];
+    }
+  }
+}
+
 // One spatial direction of the tile kernel: a neighbour inside the block's tile is
 // read from the block's LDS copy of the current slice (local index lf / lb >= 0),
 // one outside it from memory (site sf / sb).
@@ -541,8 +652,15 @@ static void launch_t(const DslashBatch &b, int bs, int xcd, hipStream_t st) {
 }
 
 template <typename T, int LR>
-static void launch_nr(const DslashBatch &b, int nr, int bs, int xcd, bool march, hipStream_t st) {
-  if (march) {
+static void launch_nr(const DslashBatch &b, int nr, int bs, int xcd, int ct, hipStream_t st) {
+  if (ct < 0) {
+    if (nr == 1)
+      hipLaunchKernelGGL((dslash_split_kernel<T, 1, LR>), dim3(b.total_blocks), dim3(256), 0, st, b, xcd);
+    else
+      hipLaunchKernelGGL((dslash_split_kernel<T, 2, LR>), dim3(b.total_blocks), dim3(256), 0, st, b, xcd);
+    return;
+  }
+  if (ct > 0) {
     if (nr == 1) launch_m<T, 1, LR>(b, xcd, st);
     else if (nr == 2) launch_m<T, 2, LR>(b, xcd, st);
     else launch_m<T, 4, LR>(b, xcd, st);
@@ -555,10 +673,9 @@ static void launch_nr(const DslashBatch &b, int nr, int bs, int xcd, bool march,
 
 void launch_dslash(const DslashBatch &b, int prec, int nr, int lr, int bs, int xcd, int ct, hipStream_t st) {
   if (b.total_blocks <= 0) return;
-  const bool march = ct > 0;
-  if (prec == 0) launch_nr<double, 18>(b, nr, bs, xcd, march, st);
-  else if (lr == 18) launch_nr<float, 18>(b, nr, bs, xcd, march, st);
-  else launch_nr<float, 12>(b, nr, bs, xcd, march, st);
+  if (prec == 0) launch_nr<double, 18>(b, nr, bs, xcd, ct, st);
+  else if (lr == 18) launch_nr<float, 18>(b, nr, bs, xcd, ct, st);
+  else launch_nr<float, 12>(b, nr, bs, xcd, ct, st);
 }
 
 }  // namespace sscg

@@ -146,7 +146,8 @@ __device__ __forceinline__ int find_job(const int32_t *begins, int njobs, int b)
 // ---- launchers (defined in the .hip files) ---------------------------------
 // dslash.hip
 // nr: sources per thread (1, 2, 4); bs: sites per block (64, 128, 256).
-// ct = 0: one thread per site, each job's nblk_site = ceil(V / bs); ct > 0: the
+// ct = -1: the direction-split kernel (64 sites per block, nr <= 2), nblk_site =
+// ceil(V / 64); ct = 0: one thread per site, each job's nblk_site = ceil(V / bs); ct > 0: the
 // tile kernel with every job's (ct, ty, tz) equal (ty | Ly, tz | Lz, Lx ty tz a
 // multiple of 64 up to 1024, bs unused), nblk_site = (Ly / ty)(Lz / tz) ceil(Lt / ct).
 // Blocks per job: nblk_site * ceil(nsrc / nr).

@@ -57,12 +57,15 @@ def test_apply_A_fp64(sscg, dims, nsrc):
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 2, 5), (8, 8, 8, 8), (3, 5, 7, 2)])
-@pytest.mark.parametrize("ct,nr,tbs", [(1, 1, 64), (2, 2, 256), (3, 4, 64), (16, 1, 512), (5, 2, 128)])
+@pytest.mark.parametrize("ct,nr,tbs", [(1, 1, 64), (2, 2, 256), (3, 4, 64), (16, 1, 512), (5, 2, 128),
+                                       (-1, 1, 0), (-1, 2, 0)])
 def test_apply_A_tile_kernel(sscg, monkeypatch, dims, ct, nr, tbs):
     """The tile dslash (tiles of tbs sites marching through ct time slices, a ragged
-    last t-range, tiles with faces in y and z or spanning the lattice) equals the
-    sparse A in FP64 and the site-parallel kernel in FP64 and FP32 (18- and 12-real
-    links); where no tile of tbs sites fits the lattice the site-parallel kernel runs."""
+    last t-range, tiles with faces in y and z or spanning the lattice) and the
+    direction-split dslash (ct = -1: one wavefront per direction, 64-site blocks with a
+    ragged last block) equal the sparse A in FP64 and the site-parallel kernel in FP64
+    and FP32 (18- and 12-real links); where no tile of tbs sites fits the lattice the
+    site-parallel kernel runs."""
     case(f"apply_A tile kernel dims={dims} ct={ct} nr={nr} tbs={tbs}")
     U = synth.gauge_field(dims, 0.5, 13)
     A = wilson.hermitian_wilson(U, dims, 0.13)
