@@ -70,7 +70,7 @@ class ShiftedCGResult:
 
 
 def shifted_cg(A_mul, v: np.ndarray, z: np.ndarray, sigma: float, tol: float = 1e-12,
-               maxiter: int = 100000, record=None, tol_scale=None):
+               maxiter: int = 100000, record=None, tol_scale=None, fp32_switch=None, fold_every=50):
     """Shifted CG with a real Hermitian seed (Sec. 2.2).
 
     Seed matrix B = sigma I - A (Hermitian because sigma is real); shift j is
@@ -95,6 +95,14 @@ def shifted_cg(A_mul, v: np.ndarray, z: np.ndarray, sigma: float, tol: float = 1
     conv_iter[j] = k + 1. The run ends when every shift has frozen. tol_scale (one
     factor per shift) replaces tol by tol * tol_scale[j] for shift j.
 
+    fp32_switch (precision emulation, not in the paper): once every active shift's
+    relative residual sqrt(rho)/|pi_j|/||v|| is below fp32_switch, the shift vectors
+    p_j are held in complex64 and updated in complex64 arithmetic (with the FP64
+    scalars rounded to complex64), their steps alpha_j p_j are summed into a complex64
+    partial solution, and that partial is added to the FP64 solution every fold_every
+    iterations and at the end. The seed stays FP64. This is the precision schedule
+    whose errors the FP32-shift mode of the GPU path has to stay within.
+
     A_mul(x) applies A to one vector. record(k, state) is called after every
     iteration when given (used to compare iterates at a fixed k).
     """
@@ -115,6 +123,9 @@ def shifted_cg(A_mul, v: np.ndarray, z: np.ndarray, sigma: float, tol: float = 1
     alpha_prev, beta_prev = 1.0, 0.0
     active = np.ones(N, dtype=bool)
     conv_iter = np.full(N, -1, dtype=np.int64)
+    P32 = None           # complex64 shift vectors once switched
+    X32 = None           # complex64 partial solutions
+    since = 0            # iterations since the last fold
     thr = tol * vnorm * (np.ones(N) if tol_scale is None else np.asarray(tol_scale, dtype=np.float64))
     status = "notconv"
     k = 0
@@ -134,14 +145,31 @@ def shifted_cg(A_mul, v: np.ndarray, z: np.ndarray, sigma: float, tol: float = 1
         a_j = alpha * ratio
         b_j = ratio ** 2 * beta
         act = np.nonzero(active)[0]
-        X[act] += a_j[act, None] * P[act]
-        P[act] = r[None, :] / pi_next[act, None] + b_j[act, None] * P[act]
+        if P32 is None:
+            X[act] += a_j[act, None] * P[act]
+            P[act] = r[None, :] / pi_next[act, None] + b_j[act, None] * P[act]
+        else:
+            a32 = a_j.astype(np.complex64)
+            b32 = b_j.astype(np.complex64)
+            ipi32 = (1.0 / pi_next).astype(np.complex64)
+            r32 = r.astype(np.complex64)
+            X32[act] += a32[act, None] * P32[act]
+            P32[act] = ipi32[act, None] * r32[None, :] + b32[act, None] * P32[act]
+            since += 1
+            if since == fold_every:
+                X += X32.astype(np.complex128)
+                X32[:] = 0
+                since = 0
         p = r + beta * p
         newly = active & (np.sqrt(rho_next) / np.abs(pi_next) <= thr)
         conv_iter[newly] = k + 1
         active &= ~newly
         pi_prev, pi_cur = pi_cur, pi_next
         alpha_prev, beta_prev, rho = alpha, beta, rho_next
+        if (fp32_switch is not None and P32 is None and active.any()
+                and np.max(np.sqrt(rho) / np.abs(pi_cur[active])) / vnorm < fp32_switch):
+            P32 = P.astype(np.complex64)
+            X32 = np.zeros_like(P32)
         if record is not None:
             record(k, dict(X=X, P=P, r=r, p=p, pi=pi_cur, alpha=alpha, beta=beta, rho=rho,
                            updated=act.size, active=active))
@@ -155,6 +183,8 @@ def shifted_cg(A_mul, v: np.ndarray, z: np.ndarray, sigma: float, tol: float = 1
             break
     else:
         k = maxiter
+    if X32 is not None:
+        X += X32.astype(np.complex128)
     return ShiftedCGResult(X, conv_iter, k, status)
 
 

@@ -157,3 +157,33 @@ def test_batched_workload_equals_single_runs(sscg):
         sites = np.random.default_rng(5 + i).choice(w.V, 6, replace=False)
         worst = sampled_shift_residuals(Us[i], w.dims, w.kappa, Vs[i][0], zs[i], to_host(ys[i])[0], sites)
         assert worst <= 2e-10 * np.linalg.norm(Vs[i][0]), nm
+
+
+def test_batched_fp64_is_bitwise_the_single_runs(sscg, monkeypatch):
+    """With one fixed launch shape, each problem of an FP64 batch (two lattices of
+    different size, own intervals and shift counts) gives exactly the bits of its run
+    alone: the grouped launches share kernels and reductions do not depend on the
+    batch."""
+    case("batched FP64 bitwise vs single")
+    for k, v in dict(SSCG_NR="2", SSCG_BS="128", SSCG_WBATCH="4", SSCG_UNROLL="2", SSCG_XCD="1",
+                     SSCG_CT="0").items():
+        monkeypatch.setenv(k, v)
+    probs = []
+    for dims, kappa, seed, (gamma, rho), N in (((4, 4, 4, 4), 0.12, 31, (0.0, 0.2), 16),
+                                               ((6, 4, 4, 6), 0.125, 32, (0.05, 0.1), 12)):
+        U = synth.gauge_field(dims, 0.5, seed)
+        V = synth.sources(int(np.prod(dims)), 2, seed).reshape(2, -1)
+        z, _ = quad.line_nodes(N, gamma, rho, 0.25)
+        c = sscg.Context(dims, kappa)
+        c.set_gauge(U)
+        probs.append((c, V, z, gamma))
+    opts = sscg.default_opts()
+    ys = [to_dev(np.zeros((2, len(z), V.shape[1]))) for c, V, z, g in probs]
+    res = sscg.batch_solve([p[0] for p in probs], [to_dev(p[1]) for p in probs], [p[2] for p in probs],
+                           [p[3] for p in probs], ys, opts)
+    for (c, V, z, g), yb, rb in zip(probs, ys, res):
+        y1 = to_dev(np.zeros((2, len(z), V.shape[1])))
+        r1 = c.shifted_cg_solve(to_dev(V), z, g, y1, opts)
+        assert rb.status == r1.status == sscg.OK
+        assert np.array_equal(to_host(yb), to_host(y1))
+        assert np.array_equal(rb.conv_iter, r1.conv_iter)

@@ -125,6 +125,25 @@ def test_mixed_precision_accuracy(sscg, prob, mode, link_reals):
     assert rel(y, y64) < 1e-9
 
 
+def test_mixed_shifts_matches_fp32_emulation(sscg, prob):
+    """The FP32-shift mode against the oracle's emulation of the same precision
+    schedule (complex64 shift vectors after the switch at 1e-6, FP64 seed): both land
+    within 1e-10 of the dense spectral solution and within 1e-10 of each other."""
+    case("mixed_shifts vs oracle FP32 emulation")
+    U, A, V, z = prob
+    lam, W = np.linalg.eigh(A.toarray())
+    y, r = solve(sscg, U, V, z, prec=sscg.MIXED_SHIFTS, ru_interval=20, switch_tol=1e-6)
+    assert r.status == sscg.OK
+    for l in range(V.shape[0]):
+        emu = solvers.shifted_cg(lambda x: A @ x, V[l], z, 0.0, 1e-12, fp32_switch=1e-6, fold_every=20)
+        c = W.conj().T @ V[l]
+        exact = np.array([W @ (c / (zj - lam)) for zj in z])
+        for Y in (y[l], emu.Y):
+            err = np.linalg.norm(Y - exact, axis=1) / np.linalg.norm(exact, axis=1)
+            assert err.max() < 1e-10
+        assert rel(y[l], emu.Y) < 1e-10
+
+
 @pytest.mark.parametrize("mode", ["mixed", "mixed_shifts"])
 def test_mixed_precision_with_early_switch(sscg, prob, mode):
     """Switch to FP32 right away: reliable updates keep the seed residual honest, but the

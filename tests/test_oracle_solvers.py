@@ -191,3 +191,28 @@ def test_per_shift_tolerance(cfg1_spec):
     assert np.all(res[:4] <= 1e-8 * 1.5) and np.all(res[:4] > 1e-12)
     assert np.all(res[4:] < 2e-12)
     assert np.all(err[:4] > err[4:].max())
+
+
+def test_fp32_shift_emulation(cfg1_spec):
+    """The FP32-shift precision schedule: never switching reproduces the FP64 run bit
+    for bit; switching at 1e-6 keeps every shifted solution within 1e-10 of the dense
+    spectral solution (true residual below 1e-10); switching at the start (planted
+    mistake: FP32 from iteration 0) leaves errors above 1e-8, so the emulation is
+    really rounding to complex64."""
+    A, lam, W = cfg1_spec
+    v = CFG1.sources().reshape(-1)
+    z, _ = quad.line_nodes(CFG1.N, CFG1.gamma, CFG1.rho, CFG1.beta)
+    Amul = lambda x: A @ x
+    exact = spectral_solve(lam, W, z, v)
+    r64 = solvers.shifted_cg(Amul, v, z, CFG1.gamma, 1e-12)
+    rnone = solvers.shifted_cg(Amul, v, z, CFG1.gamma, 1e-12, fp32_switch=0.0)
+    assert np.array_equal(r64.Y, rnone.Y)
+    rsw = solvers.shifted_cg(Amul, v, z, CFG1.gamma, 1e-12, fp32_switch=1e-6, fold_every=20)
+    assert rsw.status == "ok"
+    err = np.linalg.norm(rsw.Y - exact, axis=1) / np.linalg.norm(exact, axis=1)
+    assert err.max() < 1e-10
+    assert solvers.true_residuals(Amul, v, z, rsw.Y).max() < 1e-10
+    assert np.abs(rsw.conv_iter - r64.conv_iter).max() <= 4
+    r0 = solvers.shifted_cg(Amul, v, z, CFG1.gamma, 1e-12, fp32_switch=10.0, maxiter=2000)
+    err0 = np.linalg.norm(r0.Y - exact, axis=1) / np.linalg.norm(exact, axis=1)
+    assert err0.max() > 1e-8
