@@ -62,6 +62,16 @@ def pmc_traffic(kernel, workload):
     return d.get("hbm_bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, budget_s=20.0):
     """Oracle shifted CG (all N shifts) on the workload's sources, one after another,
     stopped after budget_s seconds of wall time."""
@@ -104,7 +114,7 @@ def cpu_baseline(w, budget_s=20.0):
                        f"{'' if done == w.L else ', the next stopped at the time limit'}; "
                        f"{updates[0]} shift-updates in {wall:.1f} s; cores = process CPU time / wall time; "
                        f"matrix assembly ({setup:.1f} s) excluded"),
-            "host_cpus": os.cpu_count()}
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def tts_compare(S, ctx, params, vd, max_eigs, steps):
