@@ -33,6 +33,15 @@
  *            exception or abort crosses the ABI. On error the outputs are
  *            undefined and sscg_last_error() holds a message. One context must not
  *            be used from two host threads at once.
+ *  Launch    kernel launch shapes (dslash kernel, sources per thread, block or tile
+ *  shapes    size, t-slices per block, XCD order; shift batch width, load unroll,
+ *            streaming stores) are chosen by timing on first use of each problem
+ *            shape. Timing noise can make two processes pick different shapes, so
+ *            results agree to rounding, not bit for bit, across processes. The
+ *            environment variable SSCG_AUTOTUNE=0, or any of SSCG_NR, SSCG_BS,
+ *            SSCG_XCD, SSCG_CT, SSCG_TBS, SSCG_WBATCH, SSCG_UNROLL, SSCG_NT set,
+ *            fixes the shapes (read at sscg_create); with fixed shapes a solve is
+ *            bitwise reproducible (the reductions do not depend on the schedule).
  */
 #ifndef SSCG_H
 #define SSCG_H
