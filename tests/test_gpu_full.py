@@ -187,3 +187,56 @@ def test_batched_fp64_is_bitwise_the_single_runs(sscg, monkeypatch):
         assert rb.status == r1.status == sscg.OK
         assert np.array_equal(to_host(yb), to_host(y1))
         assert np.array_equal(rb.conv_iter, r1.conv_iter)
+
+
+@pytest.fixture(scope="module")
+def w24(sscg):
+    w = synth.CONFIGS["wilson24x48_mixed12"]
+    return w, w.gauge()
+
+
+@pytest.mark.parametrize("prec,link_reals,bound", [("fp32", 12, 2e-6), ("fp64", 18, 1e-13)])
+def test_wilson24x48_dslash_sampled_rows(sscg, w24, prec, link_reals, bound):
+    """The dslash at the large workload's full size (24^3 x 48, 8 sources), in the
+    launch shape the autotuner picks for apply_A (as the benchmark times it): sampled
+    rows of A x against the oracle's row-wise matrix."""
+    w, U = w24
+    case(f"24^3x48 apply_A {prec} links={link_reals}")
+    c = sscg.Context(w.dims, w.kappa)
+    c.set_gauge(U, link_reals)
+    X = w.sources().reshape(w.L, -1)
+    xd = to_dev(X)
+    yd = to_dev(np.zeros_like(X))
+    c.apply_A(xd, yd, prec=sscg.MIXED if prec == "fp32" else sscg.FP64)
+    Y = to_host(yd)
+    sites = np.random.default_rng(6).choice(w.V, 24, replace=False)
+    for l in (0, 5, 7):
+        rows = wilson.apply_rows(U, w.dims, w.kappa, X[l], sites)
+        got = Y[l].reshape(-1, 12)[sites]
+        assert np.abs(got - rows).max() <= bound * np.abs(rows).max()
+    c.close()
+
+
+def test_wilson24x48_mixed_shifts_solve(sscg, w24):
+    """A shifted-CG solve at the large workload's size (24^3 x 48, 64 shifts on lines
+    around [-0.05, 0.05] with beta = 0.4, two of the eight sources, FP32 shift vectors
+    after the switch, 12-real links): every true residual below 1e-10 and sampled
+    rows of v - (z_j - A) y_j below 2e-10 ||v|| with the oracle's row-wise matrix."""
+    w, U = w24
+    case("24^3x48 mixed_shifts solve, two sources")
+    c = sscg.Context(w.dims, w.kappa)
+    c.set_gauge(U, w.link_reals)
+    V = w.sources().reshape(w.L, -1)[:2]
+    z, _ = quad.line_nodes(w.N, w.gamma, w.rho, w.beta)
+    y = to_dev(np.zeros((2, w.N, w.n)))
+    r = c.shifted_cg_solve(to_dev(V), z, w.gamma, y,
+                           sscg.default_opts(prec=sscg.MIXED_SHIFTS, ru_interval=w.ru_interval, switch_tol=w.switch_tol))
+    assert r.status == sscg.OK
+    assert r.true_res.max() < 1e-10
+    Y = to_host(y)
+    del y
+    sites = np.random.default_rng(7).choice(w.V, 6, replace=False)
+    for l in range(2):
+        worst = sampled_shift_residuals(U, w.dims, w.kappa, V[l], z, Y[l], sites)
+        assert worst <= 2e-10 * np.linalg.norm(V[l])
+    c.close()
