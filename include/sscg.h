@@ -162,11 +162,12 @@ typedef struct {
                                each shift's step alpha_j p_j is added to every
                                s_k = sum_j w_j zeta_j^k y_j as it is made, so the
                                solutions y_j are never stored (one fewer vector
-                               read and write per shift and iteration). Needs the
-                               Rayleigh-Ritz method, npairs * M <= 32 and a solve
-                               precision of SSCG_FP64 or SSCG_MIXED_SHIFTS, else
-                               SSCG_EINVAL. 0: solutions stored, moments after the
-                               solve.                                               */
+                               read and write per shift and iteration). Rayleigh-
+                               Ritz sums M moments per pair, Hankel 2M (its block
+                               moments V^H s_k run to k = 2M - 1); needs npairs
+                               times that <= 32 and a solve precision of SSCG_FP64
+                               or SSCG_MIXED_SHIFTS, else SSCG_EINVAL. 0: solutions
+                               stored, moments after the solve.                     */
   int32_t weighted_tol;     /* 1: shift j stops at tol * m / m_j, where m_j is the
                                largest |w_j zeta_j^k| over the moments (and pairs)
                                it enters and m the largest m_j: every shift's

@@ -1402,10 +1402,10 @@ static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, voi
 // Hermitian positive semidefinite for the real filters used here, so the pencil is
 // reduced on H's dominant eigenvectors and solved as a Hermitian problem; the
 // eigenvectors are X = S_hat u (S_hat = first M moments, columns k L + l).
-static int extract_hankel(sscg_ctx *c, const std::vector<cd> &Gv, int L, int Nall, int off, int N, int M,
-                          const std::vector<cd> &zeta, const std::vector<cd> &w, double gamma, double rho,
-                          double rank_tol, const void *S, void *Xd, void *AXd, std::vector<double> &lam, int &r,
-                          hipStream_t st) {
+// Block moments mu_k = V^H s_k (k < 2M, L x L blocks, [k][a][l]) from the Gram
+// entries <v_a, y_{l,j}> of the stored solutions of one pair (nodes off .. off+N-1).
+static std::vector<cd> block_moments_from_solutions(const std::vector<cd> &Gv, int L, int Nall, int off, int N,
+                                                    int M, const std::vector<cd> &zeta, const std::vector<cd> &w) {
   const int K = 2 * M;
   std::vector<cd> mu((size_t)K * L * L, cd(0, 0));
   for (int k = 0; k < K; ++k)
@@ -1414,6 +1414,14 @@ static int extract_hankel(sscg_ctx *c, const std::vector<cd> &Gv, int L, int Nal
       for (int a = 0; a < L; ++a)
         for (int l = 0; l < L; ++l) mu[((size_t)k * L + a) * L + l] += cc * Gv[(size_t)a * L * Nall + (size_t)l * Nall + off + j];
     }
+  return mu;
+}
+
+// Block Hankel extraction from the block moments mu ([2M][L][L]) and the moment
+// vectors S (columns k L + l, k < M).
+static int extract_hankel(sscg_ctx *c, const std::vector<cd> &mu, int L, int M, double gamma, double rho,
+                          double rank_tol, const void *S, void *Xd, void *AXd, std::vector<double> &lam, int &r,
+                          hipStream_t st) {
   const int m = M * L;
   std::vector<cd> H((size_t)m * m), Hs((size_t)m * m);
   for (int bi = 0; bi < M; ++bi)
@@ -1515,12 +1523,15 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   const int Nall = (int)z_all.size();
   if (Nall > 4096) return fail(c, SSCG_EINVAL, "too many distinct nodes");
   const bool in_loop = p->moments_in_loop != 0;
-  if (in_loop && (p->method != SSCG_RR || P * M > 32 || p->solve.prec == SSCG_MIXED))
-    return fail(c, SSCG_EINVAL, "in-loop moments need Rayleigh-Ritz, npairs * M <= 32 and an FP64 seed");
+  // moments per pair: M for Rayleigh-Ritz; 2M for Hankel when they are summed in the
+  // loop (its block moments V^H s_k run to k = 2M - 1)
+  const int K = (in_loop && p->method == SSCG_HANKEL) ? 2 * M : M;
+  if (in_loop && (P * K > 32 || p->solve.prec == SSCG_MIXED))
+    return fail(c, SSCG_EINVAL, "in-loop moments need npairs * M (2M for Hankel) <= 32 and an FP64 seed");
   const int ncol = M * L;
-  // moment coefficients c[k][j] = w_j zeta_j^k of one pair (eq. 2)
-  std::vector<double> cf(2 * (size_t)M * N);
-  for (int k = 0; k < M; ++k)
+  // moment coefficients c[k][j] = w_j zeta_j^k of one pair (eq. 2), k < K
+  std::vector<double> cf(2 * (size_t)K * N);
+  for (int k = 0; k < K; ++k)
     for (int j = 0; j < N; ++j) {
       const cd cc = w[j] * std::pow(zeta[j], k);
       cf[2 * ((size_t)k * N + j)] = cc.real();
@@ -1530,26 +1541,26 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   // largest moment coefficient per distinct node over every pair it belongs to
   std::vector<double> cmax(Nall, 0.0);
   for (int q = 0; q < P; ++q)
-    for (int k = 0; k < M; ++k)
+    for (int k = 0; k < K; ++k)
       for (int j = 0; j < N; ++j)
         cmax[offsets[q] + j] = std::max(cmax[offsets[q] + j], std::hypot(cf[2 * ((size_t)k * N + j)],
                                                                            cf[2 * ((size_t)k * N + j) + 1]));
   if (in_loop) {
-    // pair q's moments are rows q M .. q M + M - 1 of one [P M][Nall] coefficient
+    // pair q's moments are rows q K .. q K + K - 1 of one [P K][Nall] coefficient
     // matrix over the distinct nodes (zero outside the pair's N nodes), so the
     // moment sums of every pair are accumulated by the one solve
-    std::vector<double> cm(2 * (size_t)P * M * Nall, 0.0);
+    std::vector<double> cm(2 * (size_t)P * K * Nall, 0.0);
     for (int q = 0; q < P; ++q)
-      for (int k = 0; k < M; ++k)
+      for (int k = 0; k < K; ++k)
         for (int j = 0; j < N; ++j) {
-          const size_t dst = 2 * ((size_t)(q * M + k) * Nall + offsets[q] + j);
+          const size_t dst = 2 * ((size_t)(q * K + k) * Nall + offsets[q] + j);
           cm[dst] = cf[2 * ((size_t)k * N + j)];
           cm[dst + 1] = cf[2 * ((size_t)k * N + j) + 1];
         }
     CHK(ensure(c, c->cmom, cm.size() * sizeof(double)));
-    CHK(ensure(c, c->Sbuf, (size_t)P * ncol * vec));
+    CHK(ensure(c, c->Sbuf, (size_t)P * K * L * vec));
     HIPCHK(c, hipMemcpyAsync(c->cmom.p, cm.data(), cm.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemsetAsync(c->Sbuf.p, 0, (size_t)P * ncol * vec, st));
+    HIPCHK(c, hipMemsetAsync(c->Sbuf.p, 0, (size_t)P * K * L * vec, st));
   } else {
     // one shifted CG for all distinct nodes into the internal (planar) solution buffer
     CHK(ensure(c, c->Ybuf, (size_t)L * Nall * vec));
@@ -1576,7 +1587,7 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   if (in_loop) {
     PP[0].mom = c->Sbuf.p;
     PP[0].mom_coef = c->cmom.p;
-    PP[0].nmom = P * M;
+    PP[0].nmom = P * K;
   }
   std::vector<int32_t> iters(L), conv((size_t)L * Nall);
   PP[0].iters = iters.data();
@@ -1599,7 +1610,7 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
     AXd = c->AXbuf.p;
   }
   std::vector<cd> Gv;
-  if (p->method == SSCG_HANKEL) {
+  if (p->method == SSCG_HANKEL && !in_loop) {
     CHK(ensure(c, c->v64, (size_t)L * vec));
     launch_pack(v, c->v64.p, 0, L, c->V, st);
     CHK(gram(c, c->v64.p, L, c->Ybuf.p, L * Nall, Gv, st));  // [a][l Nall + j] = <v_a, y_{l,j}>
@@ -1615,7 +1626,7 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   for (int q = 0; q < P; ++q) {
     const void *Sq = c->Sbuf.p;
     if (in_loop) {
-      Sq = (const char *)c->Sbuf.p + (size_t)q * ncol * vec;
+      Sq = (const char *)c->Sbuf.p + (size_t)q * K * L * vec;
     } else {
       auto tm0 = std::chrono::steady_clock::now();
       CHK(ensure(c, c->small, cf.size() * sizeof(double)));
@@ -1630,8 +1641,19 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
     if (p->method == SSCG_RR) {
       CHK(extract_rr(c, Sq, ncol, p->rank_tol, Xd, AXd, lam, r, st));
     } else {
-      CHK(extract_hankel(c, Gv, L, Nall, offsets[q], N, M, zeta, w, centres[q], p->rho, p->rank_tol, c->Sbuf.p,
-                         Xd, AXd, lam, r, st));
+      std::vector<cd> mu;
+      if (in_loop) {
+        // mu_k = V^H s_k from the 2M moment vectors summed in the loop
+        std::vector<cd> Gs;
+        CHK(gram(c, c->v64.p, L, Sq, K * L, Gs, st));  // [a][k L + l]
+        mu.assign((size_t)K * L * L, cd(0, 0));
+        for (int k = 0; k < K; ++k)
+          for (int a = 0; a < L; ++a)
+            for (int l = 0; l < L; ++l) mu[((size_t)k * L + a) * L + l] = Gs[(size_t)a * K * L + (size_t)k * L + l];
+      } else {
+        mu = block_moments_from_solutions(Gv, L, Nall, offsets[q], N, M, zeta, w);
+      }
+      CHK(extract_hankel(c, mu, L, M, centres[q], p->rho, p->rank_tol, Sq, Xd, AXd, lam, r, st));
     }
     rank_max = std::max(rank_max, r);
     ncand += r;

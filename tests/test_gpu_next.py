@@ -145,7 +145,7 @@ def test_moments_in_loop_rejects(sscg, f4):
     U, A, lam, c = f4
     V = to_dev(synth.sources(CFG1.V, 2, 8).reshape(2, -1))
     base = dict(gamma=0.225, rho=0.03, N=16, M=8, moments_in_loop=1)
-    for kw in (dict(method=sscg.HANKEL), dict(M=33), dict(M=12, npairs=3, Nprime=8),
+    for kw in (dict(method=sscg.HANKEL, N=48, M=20), dict(M=33), dict(M=12, npairs=3, Nprime=8),
                dict(solve=sscg.default_opts(prec=sscg.MIXED))):
         with pytest.raises(sscg.SSCGError) as e:
             c.ss_eigs(sscg.default_ss_params(**{**base, **kw}), V, max_eigs=8)
@@ -171,3 +171,19 @@ def test_weighted_tolerance(sscg, f4, in_loop):
     assert out.n_found == len(ref["lam"]) > 0
     assert np.all(np.abs(out.lam - np.real(ref["lam"])) <= 1e-10 * np.abs(out.lam))
     assert np.all(out.res <= np.maximum(1e-8, 2 * ref["res"]))
+
+
+def test_hankel_with_moments_in_loop(sscg, f4):
+    """Hankel extraction from 2M moments summed inside the solve (block moments
+    V^H s_k formed from them) equals the stored-solution Hankel and the oracle's."""
+    case("Hankel with in-loop moments")
+    U, A, lam, c = f4
+    V = synth.sources(CFG1.V, 2, 7).reshape(2, -1)
+    kw = dict(gamma=0.225, rho=0.03, beta=0.25, N=16, M=8, rank_tol=1e-7, method=sscg.HANKEL)
+    ref = ss.ss_eigs(A, V, 0.225, 0.03, 0.25, 16, 8, method="hankel", rank_tol=1e-7)
+    stored = c.ss_eigs(sscg.default_ss_params(**kw), to_dev(V), max_eigs=16)
+    fused = c.ss_eigs(sscg.default_ss_params(moments_in_loop=1, **kw), to_dev(V), max_eigs=16)
+    assert fused.n_found == stored.n_found == len(ref["lam"]) > 0
+    assert np.all(np.abs(fused.lam - stored.lam) <= 1e-10 * np.abs(stored.lam))
+    assert np.all(np.abs(fused.lam - np.real(ref["lam"])) <= 1e-10 * np.abs(fused.lam))
+    assert np.all(fused.res <= np.maximum(1e-8, 2 * ref["res"]))
