@@ -42,6 +42,7 @@ struct Tune {
   int nt = 0;       // non-temporal access to the shift vectors
   int ct = 0;       // t-slices per block of the tile dslash (0: site-parallel kernel)
   int tbs = 0;      // sites (threads) per tile of the tile dslash
+  int border = 0;   // shift-update block order (1: the shift batches of an entry chunk adjacent)
 };
 
 enum Stage { ST_DSLASH = 0, ST_ALPHA, ST_RUPD, ST_SCAL, ST_SHIFT, ST_RU, ST_LOOP, ST_N = 8 };
@@ -169,13 +170,14 @@ int sscg_create(sscg_ctx **out, const int32_t dims[4], double kappa, double r, i
   c->tune.unroll = env_int("SSCG_UNROLL", 2);
   c->tune.ct = env_int("SSCG_CT", 0);
   c->tune.tbs = env_int("SSCG_TBS", 256);
+  c->tune.border = env_int("SSCG_BORDER", 0) ? 1 : 0;
   c->dorder = env_int("SSCG_DORDER", 1);
   if (c->dorder < 0 || c->dorder > 2) c->dorder = 1;
   if (c->tune.ct < -1) c->tune.ct = 0;
   c->tune.nt = env_int("SSCG_NT", 0);
   c->autotune = env_int("SSCG_AUTOTUNE", 1) != 0 && !getenv("SSCG_NR") && !getenv("SSCG_BS") &&
                 !getenv("SSCG_WBATCH") && !getenv("SSCG_XCD") && !getenv("SSCG_UNROLL") && !getenv("SSCG_NT") && !getenv("SSCG_CT") &&
-                !getenv("SSCG_TBS");
+                !getenv("SSCG_TBS") && !getenv("SSCG_BORDER");
   if (c->tune.nr != 1 && c->tune.nr != 2 && c->tune.nr != 4) c->tune.nr = 2;
   if (c->tune.bs != 64 && c->tune.bs != 128 && c->tune.bs != 256) c->tune.bs = 256;
   if (c->tune.wbatch < 1) c->tune.wbatch = 8;
@@ -505,7 +507,7 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
     auto mk_v = [&](VecJob &j, void *a, void *b, void *cc, void *d, int begin, int nblocks) {
       j.a = a; j.b = b; j.c = cc; j.d = d; j.e = nullptr; j.partial = (double *)c->rr_part.p;
       j.seed = seed; j.shift = shift; j.n = c->n; j.nsrc = L; j.nshift = N; j.nblk_vec = nbv;
-      j.block_begin = begin; j.nblocks = nblocks; j.wbatch = t.wbatch;
+      j.block_begin = begin; j.nblocks = nblocks; j.wbatch = t.wbatch; j.border = t.border;
     };
     mk_v(pl.r64.job[i], c->r64.p, c->q64.p, nullptr, nullptr, bv, L * nbv);
     mk_v(pl.r32.job[i], c->r32.p, c->q32.p, c->xpart32.p, c->p32.p, bv, L * nbv);
@@ -837,25 +839,28 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
     if (w > 2 && w / 2 >= maxN) continue;
     for (int u : {1, 2, 4}) {
       if (u > w) continue;
-      for (int nt : {0, 1}) {
-        cand.wbatch = w;
-        cand.unroll = u;
-        cand.nt = nt;
-        IterPlan pl;
-        build_plan(P, pl, o, cand);
-        const double t = time_it([&] { launch_shift_update(pl.u64, 0, 0, 0, u, nt, st); }, 3);
-        if (t < tbest) {
-          tbest = t;
-          best.wbatch = w;
-          best.unroll = u;
-          best.nt = nt;
+      for (int nt : {0, 1})
+        for (int bo : {0, 1}) {
+          cand.wbatch = w;
+          cand.unroll = u;
+          cand.nt = nt;
+          cand.border = bo;
+          IterPlan pl;
+          build_plan(P, pl, o, cand);
+          const double t = time_it([&] { launch_shift_update(pl.u64, 0, 0, 0, u, nt, st); }, 3);
+          if (t < tbest) {
+            tbest = t;
+            best.wbatch = w;
+            best.unroll = u;
+            best.nt = nt;
+            best.border = bo;
+          }
         }
-      }
     }
   }
   if (getenv("SSCG_VERBOSE"))
-    fprintf(stderr, "[sscg] tuned %s: nr=%d bs=%d xcd=%d ct=%d tbs=%d wbatch=%d unroll=%d nt=%d\n",
-            key.c_str(), best.nr, best.bs, best.xcd, best.ct, best.tbs, best.wbatch, best.unroll, best.nt);
+    fprintf(stderr, "[sscg] tuned %s: nr=%d bs=%d xcd=%d ct=%d tbs=%d wbatch=%d unroll=%d nt=%d border=%d\n",
+            key.c_str(), best.nr, best.bs, best.xcd, best.ct, best.tbs, best.wbatch, best.unroll, best.nt, best.border);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   // restore the initial state

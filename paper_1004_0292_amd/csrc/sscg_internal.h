@@ -125,6 +125,7 @@ struct VecJob {
   ShiftState *shift;     // [nsrc][nshift]
   int64_t n;             // complex entries per vector (12 V)
   int32_t nsrc, nshift, nblk_vec, block_begin, nblocks, wbatch;
+  int32_t border;        // fused shift update: 0 shift batches outermost, 1 entry chunks outermost
   int32_t nmom;          // moments accumulated inside the solve (0: none)
   int32_t nblk_mom;      // blocks per source of the in-loop moment kernel
   // seed residual update only: > 0 = the step length is formed in the kernel from

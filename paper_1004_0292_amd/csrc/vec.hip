@@ -316,7 +316,17 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
   const int per_src = nbatch * J.nblk_vec;
   const int l = lb / per_src;
   const int rem = lb - l * per_src;
-  const int bt = rem / J.nblk_vec, vb = rem - bt * J.nblk_vec;
+  // block order: shift batches outermost (border 0) or entry chunks outermost
+  // (border 1: the batches of one chunk are neighbouring blocks, so the chunk of the
+  // seed residual they all read stays in L2)
+  int bt, vb;
+  if (J.border) {
+    vb = rem / nbatch;
+    bt = rem - vb * nbatch;
+  } else {
+    bt = rem / J.nblk_vec;
+    vb = rem - bt * J.nblk_vec;
+  }
   const SeedState &S = J.seed[l];
   if (!S.pending) return;
   const int64_t n = J.n;

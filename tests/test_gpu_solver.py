@@ -85,7 +85,8 @@ def test_fused_step_length_is_bitwise_the_same(sscg, prob, monkeypatch, prec):
                                  dict(SSCG_NR="2", SSCG_BS="256", SSCG_WBATCH="1", SSCG_XCD="1", SSCG_UNROLL="2"),
                                  dict(SSCG_NR="2", SSCG_TBS="64", SSCG_CT="3", SSCG_XCD="1"),
                                  dict(SSCG_NR="1", SSCG_TBS="64", SSCG_CT="1", SSCG_XCD="0", SSCG_DORDER="2"),
-                                 dict(SSCG_NR="2", SSCG_CT="-1", SSCG_XCD="1")])
+                                 dict(SSCG_NR="2", SSCG_CT="-1", SSCG_XCD="1"),
+                                 dict(SSCG_WBATCH="4", SSCG_UNROLL="2", SSCG_BORDER="1", SSCG_NT="1")])
 def test_launch_shapes_agree(sscg, prob, monkeypatch, env):
     case(f"launch shapes {env}")
     U, A, V, z = prob
