@@ -19,6 +19,8 @@ Printed as one JSON line on rank 0. Besides the throughput it carries:
                 12-real links, FP64 with 18-real links), autotuned launch shape
   tts           time to solution of the step in FP64 and FP64-seed / FP32-shift
                 precision, with stored solutions and with in-loop moments
+  tts_window    the same comparison on a window of the field's spectrum that holds
+                eigenvalues, with both modes' eigenvalues and residuals
   cpu_baseline  the FP64 CPU oracle (numpy/scipy) on the host: one source's full
                 shifted CG (all N shifts) on the same workload, bounded in time
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
@@ -142,6 +144,45 @@ def tts_compare(S, ctx, params, vd, max_eigs, steps):
         out[name + "_max_res"] = float(r.res.max()) if len(r.res) else None
     out["speedup_mixed_vs_fp64"] = round(out["fp64_ms_per_step"] / out["mixed_shifts_ms_per_step"], 3)
     out["speedup_mixed_inloop_vs_fp64"] = round(out["fp64_ms_per_step"] / out["mixed_shifts_inloop_ms_per_step"], 3)
+    return out
+
+
+# Eigenvalue windows that do contain eigenvalues of a workload's field (from its
+# reference spectrum), for the time-to-solution comparison at equal accuracy.
+WINDOWS = {"wilson8_fp64": dict(lo=0.3700, hi=0.3735, beta=0.5, N=32, M=8)}
+
+
+def tts_window(S, ctx, w, vd, steps):
+    """Time to solution and accuracy of FP64 against the FP32-shift mode on a window
+    with eigenvalues: per-step time, the eigenvalues and residuals of each mode, and
+    the largest relative eigenvalue difference between the two."""
+    import numpy as np
+    import torch
+    win = WINDOWS.get(w.name)
+    if win is None:
+        return None
+    gamma, rho = 0.5 * (win["lo"] + win["hi"]), 0.5 * (win["hi"] - win["lo"])
+    out = {"window": [win["lo"], win["hi"]], "beta": win["beta"], "N": win["N"], "M": win["M"]}
+    ctx.set_profiling(False)
+    lams = {}
+    for name, prec in (("fp64", S.FP64), ("mixed_shifts", S.MIXED_SHIFTS)):
+        opts = S.default_opts(tol=w.tol, prec=prec, ru_interval=w.ru_interval, switch_tol=w.switch_tol)
+        p = S.default_ss_params(gamma=gamma, rho=rho, beta=win["beta"], N=win["N"], M=win["M"], rank_tol=1e-7,
+                                spur_tol=1e-6, solve=opts)
+        ctx.ss_eigs(p, vd, max_eigs=32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = ctx.ss_eigs(p, vd, max_eigs=32)
+        torch.cuda.synchronize()
+        out[name + "_ms_per_step"] = round((time.perf_counter() - t0) / steps * 1e3, 3)
+        out[name + "_eigs"] = r.lam.round(13).tolist()
+        out[name + "_max_res"] = float(r.res.max()) if len(r.res) else None
+        lams[name] = r.lam
+    a, b = lams["fp64"], lams["mixed_shifts"]
+    out["eigs_found"] = [len(a), len(b)]
+    out["max_rel_eig_diff"] = float(np.max(np.abs(a - b) / np.abs(a))) if len(a) == len(b) and len(a) else None
+    out["speedup_mixed_vs_fp64"] = round(out["fp64_ms_per_step"] / out["mixed_shifts_ms_per_step"], 3)
     return out
 
 
@@ -412,6 +453,9 @@ def main():
     }
     if not args.no_compare:
         line["tts"] = tts_compare(S, ctx, params, vd, max_eigs, args.steps)
+        tw = tts_window(S, ctx, w, vd, args.steps)
+        if tw is not None:
+            line["tts_window"] = tw
     line["copy_bw_GBs"] = copy_bandwidth()
     if not args.no_dslash_large:
         line["dslash_24x48"] = dslash_large(S)
