@@ -249,9 +249,17 @@ int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs);
  * context's stream, in milliseconds summed over the solve; counts in calls.
  * stage: 0 dslash, 1 seed alpha scalars, 2 seed residual update, 3 shift scalars,
  * 4 fused shift update, 5 reliable update, 6 whole iteration loop.
- * Timing is recorded only when enabled with sscg_set_profiling(ctx, 1); then
- * sscg_apply_A also adds its dslash time to stage 0 (and blocks until it ends). */
-int sscg_set_profiling(sscg_ctx *ctx, int32_t on);
+ * Timing is recorded only when enabled with sscg_set_profiling(ctx, level):
+ *   level 0  off (the default);
+ *   level 1  every launch of the solve loop is bracketed by events, and the loop runs
+ *            its launches directly (no graph replay);
+ *   level k > 1  graph replay stays on, and the dslash (stage 0) and the shift update
+ *            (stage 4) of every k-th iteration of each poll interval are bracketed by
+ *            event-record nodes in the graph; the other stages are not timed. Stage
+ *            averages are then over that sample, at a small cost to the loop.
+ * A level below 0 is SSCG_EINVAL. When timing is on, sscg_apply_A also adds its dslash
+ * time to stage 0 (and blocks until it ends). */
+int sscg_set_profiling(sscg_ctx *ctx, int32_t level);
 int sscg_stage_times(const sscg_ctx *ctx, double ms[8], int64_t calls[8]);
 
 #ifdef __cplusplus

@@ -287,8 +287,12 @@ class Context:
         return EigResult(rc, lam[:k].copy(), res[:k].copy(), int(nf[0]),
                          X[:k] if X is not None else None, info)
 
-    def set_profiling(self, on=True):
-        lib().sscg_set_profiling(self._h, 1 if on else 0)
+    def set_profiling(self, level=1):
+        """0 off; 1 every launch timed (direct launches); k > 1 the dslash and shift
+        update of every k-th iteration timed with graph replay kept on."""
+        rc = lib().sscg_set_profiling(self._h, int(level))
+        if rc:
+            self._raise(rc)
 
     def stage_times(self):
         ms = np.zeros(8)

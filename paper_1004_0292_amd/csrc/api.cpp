@@ -73,7 +73,7 @@ struct sscg_ctx {
   SeedState *seed_host = nullptr;
   int seed_host_cap = 0;
   // profiling
-  bool profiling = false;
+  int profiling = 0;  // 0 off, 1 every launch, k > 1 every k-th iteration in graphs
   double stage_ms[ST_N] = {};
   int64_t stage_calls[ST_N] = {};
   std::vector<hipEvent_t> events;
@@ -246,7 +246,8 @@ int sscg_set_gauge(sscg_ctx *c, const double *U, int32_t link_reals) {
 
 int sscg_set_profiling(sscg_ctx *c, int32_t on) {
   if (!c) return SSCG_EINVAL;
-  c->profiling = on != 0;
+  if (on < 0) return fail(c, SSCG_EINVAL, "profiling level must be >= 0");
+  c->profiling = on;
   return SSCG_OK;
 }
 int sscg_stage_times(const sscg_ctx *c, double ms[8], int64_t calls[8]) {
@@ -556,53 +557,87 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
 // before each stage launch and the intervals are read at the next poll. Timing
 // runs use direct launches (event records inside captured graphs are not read
 // back reliably on this runtime).
+// Inside a captured graph the marks are event-record nodes, so the same
+// events are rewritten by every replay and read after it (graph replay keeps its
+// timing); the marks of direct launches are read and cleared at every poll.
 struct Recorder {
   sscg_ctx *c;
   hipStream_t st;
   bool on;
   std::vector<int> stages;
+  std::vector<hipEvent_t> *evs;  // event pool (nullptr: the context's)
+  bool in_graph = false;
+  std::vector<hipEvent_t> &pool() { return evs ? *evs : c->events; }
+  // event-record node appended to the capture by hand (after the nodes captured so
+  // far; the next captured launch depends on it)
+  hipError_t record_node(hipEvent_t e) {
+    hipStreamCaptureStatus cs;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t *deps = nullptr;
+    size_t nd = 0;
+    hipError_t r = hipStreamGetCaptureInfo_v2(st, &cs, nullptr, &g, &deps, &nd);
+    if (r != hipSuccess) return r;
+    if (cs != hipStreamCaptureStatusActive || !g) return hipErrorIllegalState;
+    hipGraphNode_t node = nullptr;
+    r = hipGraphAddEventRecordNode(&node, g, deps, nd, e);
+    if (r != hipSuccess) return r;
+    return hipStreamUpdateCaptureDependencies(st, &node, 1, hipStreamSetCaptureDependencies);
+  }
   void mark(int stage) {
     if (!on) return;
     const size_t k = stages.size();
-    if (k >= c->events.size()) {
+    std::vector<hipEvent_t> &ev = pool();
+    if (k >= ev.size()) {
       hipEvent_t e;
-      hipEventCreate(&e);
-      c->events.push_back(e);
+      if (hipEventCreate(&e) != hipSuccess) {
+        on = false;
+        (void)hipGetLastError();
+        return;
+      }
+      ev.push_back(e);
     }
-    if (hipEventRecord(c->events[k], st) != hipSuccess) {
+    const hipError_t r = in_graph ? record_node(ev[k]) : hipEventRecord(ev[k], st);
+    if (r != hipSuccess) {
       on = false;  // timing is best effort; never leave a sticky error behind
       (void)hipGetLastError();
+      fprintf(stderr, "sscg: stage timing off (%s event record: %s)\n", in_graph ? "graph" : "stream",
+              hipGetErrorString(r));
       return;
     }
     stages.push_back(stage);
   }
-  // intervals between consecutive recorded events (all complete) -> stage totals
-  void account(const std::vector<int> &stg) {
-    for (size_t k = 0; k + 1 < stg.size(); ++k) {
+  // intervals between consecutive recorded events (all complete) -> stage totals;
+  // an interval that starts at a stop mark (-1) is not counted
+  void account() {
+    std::vector<hipEvent_t> &ev = pool();
+    for (size_t k = 0; k + 1 < stages.size(); ++k) {
+      if (stages[k] < 0) continue;
       float ms = 0.f;
-      hipEventElapsedTime(&ms, c->events[k], c->events[k + 1]);
-      c->stage_ms[stg[k]] += ms;
-      c->stage_calls[stg[k]] += 1;
+      const hipError_t r = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      if (r != hipSuccess) {
+        (void)hipGetLastError();
+        fprintf(stderr, "sscg: stage timing off (elapsed time: %s)\n", hipGetErrorString(r));
+        on = false;
+        return;
+      }
+      c->stage_ms[stages[k]] += ms;
+      c->stage_calls[stages[k]] += 1;
     }
   }
   void flush() {
     if (!on || stages.empty()) return;
     mark(-1);
-    hipEventSynchronize(c->events[stages.size() - 1]);
-    account(stages);
+    hipEventSynchronize(pool()[stages.size() - 1]);
+    account();
     stages.clear();
   }
 };
 
-// One iteration. prec: 0 FP64 phase, 1 FP32 phase; seed32: the FP32 phase also runs
-// the seed in FP32 (SSCG_MIXED) rather than FP64 (SSCG_MIXED_SHIFTS); ru: last
-// iteration of an FP32 chunk (seed reliable update if seed32, fold of the FP32
-// shift partials into the FP64 solutions in both FP32 modes).
-static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru, int lr, const Tune &t,
-                             hipStream_t st, Recorder &rec) {
+// The iteration after its dslash: step length, seed residual, shift scalars, shift
+// update. rec marks every stage; smp (when given) brackets the shift update alone.
+static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, bool ru, int lr, const Tune &t,
+                                  hipStream_t st, Recorder &rec, Recorder *smp) {
   const int sp = (prec == 1 && seed32) ? 1 : 0;  // seed precision
-  rec.mark(ST_DSLASH);
-  launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, pl.ct, st);
   if (!pl.fuse_alpha) {
     rec.mark(ST_ALPHA);
     launch_seed_alpha(pl.alpha, st);
@@ -619,12 +654,39 @@ static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru,
   rec.mark(ST_SCAL);
   launch_shift_scalars(pl.scal, st);
   rec.mark(ST_SHIFT);
+  if (smp) smp->mark(ST_SHIFT);
   if (pl.nmom_max > 0) {  // FP64 seed in both phases (checked by run_solve)
     launch_shift_moments(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, st);
+  } else {
+    const VecBatch &u = prec == 0 ? pl.u64 : (sp == 1 ? pl.u32 : pl.u32s);
+    launch_shift_update(u, prec, sp, prec == 1 && ru, t.unroll, t.nt, st);
+  }
+  if (smp) smp->mark(-1);
+}
+
+// One iteration. prec: 0 FP64 phase, 1 FP32 phase; seed32: the FP32 phase also runs
+// the seed in FP32 (SSCG_MIXED) rather than FP64 (SSCG_MIXED_SHIFTS); ru: last
+// iteration of an FP32 chunk (seed reliable update if seed32, fold of the FP32
+// shift partials into the FP64 solutions in both FP32 modes).
+// Timing marks: with every == 1 each launch is bracketed (the marks chain, one
+// interval per stage); with every == k > 1 only the dslash and the shift update of
+// iterations it % k == 0 are bracketed (start and stop marks).
+static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru, int lr, const Tune &t,
+                             hipStream_t st, Recorder &rec, int it = 0, int every = 1) {
+  const int sp = (prec == 1 && seed32) ? 1 : 0;  // seed precision
+  if (every > 1) {
+    const bool smp = it % every == 0;
+    Recorder off{rec.c, st, false, {}, nullptr};
+    if (smp) rec.mark(ST_DSLASH);
+    launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, pl.ct, st);
+    if (smp) rec.mark(-1);
+    // the rest of the iteration untimed up to the shift update
+    launch_iteration_tail(pl, prec, seed32, ru, lr, t, st, off, smp ? &rec : nullptr);
     return;
   }
-  const VecBatch &u = prec == 0 ? pl.u64 : (sp == 1 ? pl.u32 : pl.u32s);
-  launch_shift_update(u, prec, sp, prec == 1 && ru, t.unroll, t.nt, st);
+  rec.mark(ST_DSLASH);
+  launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, pl.ct, st);
+  launch_iteration_tail(pl, prec, seed32, ru, lr, t, st, rec, nullptr);
 }
 
 static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
@@ -919,17 +981,37 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     c0->stage_ms[i] = 0.0;
     c0->stage_calls[i] = 0;
   }
-  Recorder rec{c0, st, c0->profiling, {}};
-  const bool use_graph = o.use_graph != 0 && !c0->profiling;
+  Recorder rec{c0, st, c0->profiling > 0, {}, nullptr};
+  // profiling level 1 times every launch and runs them directly (an event-record node
+  // in a graph costs more than the launch gap it would hide); a level k > 1 samples
+  // every k-th iteration and keeps graph replay
+  const int every = c0->profiling > 1 ? c0->profiling : 1;
+  const bool use_graph = o.use_graph != 0 && c0->profiling != 1;
   const bool seed32 = o.prec == SSCG_MIXED;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int glen[2] = {0, 0};
+  // per-graph timing marks (profiling): events owned here, rewritten by each replay
+  std::vector<hipEvent_t> gev[2];
+  Recorder grec[2] = {{c0, st, false, {}, &gev[0]}, {c0, st, false, {}, &gev[1]}};
   auto capture = [&](int prec, int len, hipGraphExec_t &exec) -> int {
     hipGraph_t g = nullptr;
-    Recorder cap{c0, st, false, {}};
+    Recorder &cap = grec[prec];
+    cap.on = c0->profiling > 0;
+    cap.in_graph = true;
+    cap.stages.clear();
+    while (cap.on && gev[prec].size() < (size_t)len * (ST_N + 1) + 1) {  // events exist before capture
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        cap.on = false;
+        break;
+      }
+      gev[prec].push_back(e);
+    }
     HIPCHK(c0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < len; ++k)
-      launch_iteration(pl, prec, seed32, prec == 1 && k == len - 1, lr, tn, st, cap);
+      launch_iteration(pl, prec, seed32, prec == 1 && k == len - 1, lr, tn, st, cap, k, every);
+    if (every == 1) cap.mark(-1);
     HIPCHK(c0, hipStreamEndCapture(st, &g));
     HIPCHK(c0, hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
     HIPCHK(c0, hipGraphDestroy(g));
@@ -961,7 +1043,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       }
     } else {
       for (int kk = 0; kk < chunk; ++kk)
-        launch_iteration(pl, prec, seed32, prec == 1 && (kk == chunk - 1) && full, lr, tn, st, rec);
+        launch_iteration(pl, prec, seed32, prec == 1 && (kk == chunk - 1) && full, lr, tn, st, rec, kk, every);
     }
     k += chunk;
     // poll
@@ -981,6 +1063,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       break;
     }
     rec.flush();
+    if (use_graph && full && grec[prec].on) grec[prec].account();
     for (Prob &p : P)
       for (int l = 0; l < p.L; ++l) {
         const SeedState &s = p.c->seed_host[l];
@@ -1002,6 +1085,8 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   }
   for (auto &g : gexec)
     if (g) hipGraphExecDestroy(g);
+  for (auto &v : gev)
+    for (hipEvent_t e : v) hipEventDestroy(e);
   if (rc != SSCG_OK) return rc;
   if (prec == 1) {
     // fold every shift's FP32 partial into its FP64 solution

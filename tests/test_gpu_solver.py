@@ -59,6 +59,41 @@ def test_poll_and_graph_do_not_change_results(sscg, prob):
     assert np.array_equal(r0.conv_iter, r1.conv_iter) and np.array_equal(r0.iters, r2.iters)
 
 
+def test_profiling_levels(sscg, prob):
+    """Level 1 times every launch (direct launches); level 5 keeps graph replay and
+    times the dslash and shift update of every 5th iteration. Neither changes the
+    results (bitwise), and the sampled launch averages agree with the full ones."""
+    case("profiling levels")
+    U, A, V, z = prob
+    y_ref, r_ref = solve(sscg, U, V, z, poll_every=50, use_graph=1)
+    out = {}
+    for level in (1, 5):
+        c = sscg.Context(CFG1.dims, CFG1.kappa)
+        c.set_gauge(U, 18)
+        c.set_profiling(level)
+        y = to_dev(np.zeros((V.shape[0], len(z), V.shape[1])))
+        r = c.shifted_cg_solve(to_dev(V), z, 0.0, y, sscg.default_opts(poll_every=50, use_graph=1))
+        ms, calls = c.stage_times()
+        assert np.array_equal(to_host(y), y_ref) and np.array_equal(r.iters, r_ref.iters)
+        out[level] = (np.array(ms), np.array(calls))
+        c.close()
+    (ms1, calls1), (ms5, calls5) = out[1], out[5]
+    launched = calls1[0]            # one dslash per launched iteration
+    assert launched >= int(np.max(r_ref.iters)) and calls1[4] == launched
+    assert np.all(calls1[[2, 3]] == launched) and np.all(ms1[[0, 2, 3, 4]] > 0)
+    # every 5th iteration of each 50-iteration poll interval
+    assert calls5[0] == calls5[4] == launched // 5 and np.all(calls5[[1, 2, 3, 5]] == 0)
+    for s in (0, 4):
+        a1, a5 = ms1[s] / calls1[s], ms5[s] / calls5[s]
+        assert 0.3 < a5 / a1 < 3.0, (s, a1, a5)
+    with pytest.raises(sscg.SSCGError):
+        c = sscg.Context(CFG1.dims, CFG1.kappa)
+        try:
+            c.set_profiling(-1)
+        finally:
+            c.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_fused_step_length_is_bitwise_the_same(sscg, prob, monkeypatch, prec):
     """The seed step length formed inside the residual update (small lattices) equals
