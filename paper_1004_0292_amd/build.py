@@ -1,7 +1,8 @@
 """Build the sscg HIP library (libsscg.so) in-tree for gfx950.
 
 Every source under csrc/ is compiled by hipcc and linked into one shared
-library next to this file. Usable as `python -m paper_1004_0292_amd.build`.
+library next to this file (sources named *_host.cpp hold host code only and are
+compiled as plain C++). Usable as `python -m paper_1004_0292_amd.build`.
 """
 from __future__ import annotations
 
@@ -30,7 +31,9 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 def _compile(src: Path) -> Path:
     obj = BUILD / (src.name + ".o")
     cmd = [HIPCC, *COMMON, *DEVICE, "-c", str(src), "-o", str(obj)]
-    if src.suffix == ".cpp":
+    if src.name.endswith("_host.cpp"):  # host code only: plain C++, no device pass
+        cmd = [HIPCC, *COMMON, "-x", "c++", "-c", str(src), "-o", str(obj)]
+    elif src.suffix == ".cpp":
         cmd = [HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", str(src), "-o", str(obj)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -77,6 +77,16 @@ struct sscg_ctx {
   double stage_ms[ST_N] = {};
   int64_t stage_calls[ST_N] = {};
   std::vector<hipEvent_t> events;
+  // solve-loop graphs kept across solves (FP64 and FP32 phase), with the bytes of
+  // everything the capture depended on; a solve of the same shape on the same
+  // buffers replays them without capturing again
+  struct CachedGraph {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> ev;  // timing marks recorded by the graph (profiling)
+    std::vector<int> stages;
+    bool timed = false;
+  } graphs[2];
 };
 
 static int fail(sscg_ctx *c, int code, const std::string &msg) {
@@ -196,6 +206,10 @@ void sscg_destroy(sscg_ctx *c) {
   for (DevBuf *b : bufs) release(*b);
   if (c->seed_host) hipHostFree(c->seed_host);
   for (hipEvent_t e : c->events) hipEventDestroy(e);
+  for (auto &g : c->graphs) {
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    for (hipEvent_t e : g.ev) hipEventDestroy(e);
+  }
   hipEventDestroy(c->ev_sync);
   hipStreamDestroy(c->work);
   delete c;
@@ -988,35 +1002,60 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   const int every = c0->profiling > 1 ? c0->profiling : 1;
   const bool use_graph = o.use_graph != 0 && c0->profiling != 1;
   const bool seed32 = o.prec == SSCG_MIXED;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  int glen[2] = {0, 0};
-  // per-graph timing marks (profiling): events owned here, rewritten by each replay
-  std::vector<hipEvent_t> gev[2];
-  Recorder grec[2] = {{c0, st, false, {}, &gev[0]}, {c0, st, false, {}, &gev[1]}};
-  auto capture = [&](int prec, int len, hipGraphExec_t &exec) -> int {
+  // timing marks of the graphs: events owned by the context, rewritten by each replay
+  Recorder grec[2] = {{c0, st, false, {}, &c0->graphs[0].ev}, {c0, st, false, {}, &c0->graphs[1].ev}};
+  // everything a captured chunk depends on: the launch plan (kernel arguments and
+  // buffer addresses), the launch shapes, the phase, the length, the timing level
+  auto graph_key = [&](int prec, int len) {
+    std::string key(reinterpret_cast<const char *>(&pl), sizeof(pl));
+    const int64_t v[] = {prec, len, lr, every, c0->profiling, seed32 ? 1 : 0, tn.nr, tn.bs, tn.wbatch, tn.xcd,
+                         tn.unroll, tn.nt, tn.ct, tn.tbs, tn.border, (int64_t)(intptr_t)st};
+    key.append(reinterpret_cast<const char *>(v), sizeof(v));
+    return key;
+  };
+  auto capture = [&](int prec, int len) -> int {
+    sscg_ctx::CachedGraph &cg = c0->graphs[prec];
+    const std::string key = graph_key(prec, len);
+    if (cg.exec && cg.key == key) {  // replay the graph of an earlier solve
+      grec[prec].on = cg.timed;
+      grec[prec].in_graph = true;
+      grec[prec].stages = cg.stages;
+      return SSCG_OK;
+    }
+    if (cg.exec) hipGraphExecDestroy(cg.exec);
+    cg.exec = nullptr;
+    cg.key.clear();
     hipGraph_t g = nullptr;
     Recorder &cap = grec[prec];
     cap.on = c0->profiling > 0;
     cap.in_graph = true;
     cap.stages.clear();
-    while (cap.on && gev[prec].size() < (size_t)len * (ST_N + 1) + 1) {  // events exist before capture
+    while (cap.on && cg.ev.size() < (size_t)len * (ST_N + 1) + 1) {  // events exist before capture
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) {
         (void)hipGetLastError();
         cap.on = false;
         break;
       }
-      gev[prec].push_back(e);
+      cg.ev.push_back(e);
     }
     HIPCHK(c0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < len; ++k)
       launch_iteration(pl, prec, seed32, prec == 1 && k == len - 1, lr, tn, st, cap, k, every);
     if (every == 1) cap.mark(-1);
     HIPCHK(c0, hipStreamEndCapture(st, &g));
-    HIPCHK(c0, hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
-    HIPCHK(c0, hipGraphDestroy(g));
+    const hipError_t ie = hipGraphInstantiate(&cg.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      cg.exec = nullptr;
+      return fail(c0, SSCG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    cg.key = key;
+    cg.stages = cap.stages;
+    cg.timed = cap.on;
     return SSCG_OK;
   };
+  bool ready[2] = {false, false};  // graph of this phase checked against this solve
   auto t0 = std::chrono::steady_clock::now();
   int prec = 0;
   int k = 0;
@@ -1029,14 +1068,12 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     const int chunk = std::min(period, o.maxiter - k);
     const bool full = chunk == period;
     if (use_graph && full) {
-      if (!gexec[prec] || glen[prec] != chunk) {
-        if (gexec[prec]) hipGraphExecDestroy(gexec[prec]);
-        gexec[prec] = nullptr;
-        rc = capture(prec, chunk, gexec[prec]);
+      if (!ready[prec]) {
+        rc = capture(prec, chunk);
         if (rc != SSCG_OK) break;
-        glen[prec] = chunk;
+        ready[prec] = true;
       }
-      hipError_t e = hipGraphLaunch(gexec[prec], st);
+      hipError_t e = hipGraphLaunch(c0->graphs[prec].exec, st);
       if (e != hipSuccess) {
         rc = fail(c0, SSCG_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
         break;
@@ -1083,10 +1120,6 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       for (Prob &p : P) p.switch_iter = k;
     }
   }
-  for (auto &g : gexec)
-    if (g) hipGraphExecDestroy(g);
-  for (auto &v : gev)
-    for (hipEvent_t e : v) hipEventDestroy(e);
   if (rc != SSCG_OK) return rc;
   if (prec == 1) {
     // fold every shift's FP32 partial into its FP64 solution

@@ -14,7 +14,10 @@
 //   4. Eigenvectors of A are the columns of Q D Z.
 //
 // Matrices are column-major, complex as interleaved doubles: element (i, j) is
-// A[2 (i + n j)] + i A[2 (i + n j) + 1].
+// A[2 (i + n j)] + i A[2 (i + n j) + 1]. Internally the real and imaginary parts
+// are held in separate arrays, and the eigenvectors are back-transformed in
+// row-major order, so that every inner loop runs over contiguous memory without a
+// reduction (the loops vectorise).
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -24,106 +27,105 @@
 namespace sscg {
 
 namespace {
-struct cpx {
-  double re, im;
-};
-inline cpx cadd(cpx a, cpx b) { return {a.re + b.re, a.im + b.im}; }
-inline cpx csub(cpx a, cpx b) { return {a.re - b.re, a.im - b.im}; }
-inline cpx cmul(cpx a, cpx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-inline cpx cmulc(cpx a, cpx b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }  // conj(a) b
-inline cpx cscal(cpx a, double s) { return {a.re * s, a.im * s}; }
-inline double cabs(cpx a) { return std::hypot(a.re, a.im); }
+// sqrt(a^2 + b^2), without the cost of std::hypot where the squares cannot over- or
+// underflow
+inline double hyp(double a, double b) {
+  const double m = std::fmax(std::fabs(a), std::fabs(b));
+  if (m > 1e-150 && m < 1e150) return std::sqrt(a * a + b * b);
+  return std::hypot(a, b);
+}
 }  // namespace
 
-void herm_eig(int n, const double *Ain, double *evals, double *evecs) {
+// Built twice, for AVX2 with FMA and for plain x86-64; the loader picks the first at
+// run time where the processor has it.
+__attribute__((target_clones("arch=x86-64-v3", "default"))) void herm_eig(int n, const double *Ain, double *evals,
+                                                                          double *evecs) {
   if (n <= 0) return;
-  std::vector<cpx> A((size_t)n * n);
-  auto a = [&](int i, int j) -> cpx & { return A[(size_t)i + (size_t)n * j]; };
+  const size_t nn = (size_t)n * n;
+  std::vector<double> Ar(nn), Ai(nn);  // column-major, split real / imaginary parts
   // Hermitian part of the input
+  auto id = [n](int i, int j) { return (size_t)i + (size_t)n * j; };
   for (int j = 0; j < n; ++j)
-    for (int i = 0; i < n; ++i) a(i, j) = {Ain[2 * ((size_t)i + (size_t)n * j)], Ain[2 * ((size_t)i + (size_t)n * j) + 1]};
+    for (int i = 0; i < n; ++i) {
+      Ar[id(i, j)] = Ain[2 * id(i, j)];
+      Ai[id(i, j)] = Ain[2 * id(i, j) + 1];
+    }
   for (int j = 0; j < n; ++j) {
-    a(j, j).im = 0.0;
+    Ai[id(j, j)] = 0.0;
     for (int i = j + 1; i < n; ++i) {
-      const cpx lo = a(i, j), up = a(j, i);
-      const cpx h = {0.5 * (lo.re + up.re), 0.5 * (lo.im - up.im)};
-      a(i, j) = h;
-      a(j, i) = {h.re, -h.im};
+      const double hr = 0.5 * (Ar[id(i, j)] + Ar[id(j, i)]), hi = 0.5 * (Ai[id(i, j)] - Ai[id(j, i)]);
+      Ar[id(i, j)] = hr; Ai[id(i, j)] = hi;
+      Ar[id(j, i)] = hr; Ai[id(j, i)] = -hi;
     }
   }
-  // 1. Householder tridiagonalisation
-  std::vector<cpx> V((size_t)n * n, {0.0, 0.0});  // reflector k stored in column k, rows k+1..n-1
-  std::vector<double> beta(n, 0.0);
-  std::vector<cpx> p(n), w(n);
-  std::vector<double> d(n, 0.0), e(n, 0.0);
-  std::vector<cpx> sub(n, {0.0, 0.0});  // complex sub-diagonal T[k+1][k]
+  // 1. Householder tridiagonalisation: reflector k in column k of V, rows k+1..n-1;
+  // (sr, si) the complex sub-diagonal T[k+1][k]
+  std::vector<double> Vr(nn, 0.0), Vi(nn, 0.0), beta(n, 0.0);
+  std::vector<double> pr(n), pi(n), wr(n), wi(n), d(n, 0.0), e(n, 0.0), sr(n, 0.0), si(n, 0.0);
   for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;  // length of x = A[k+1.., k]
+    const int m = n - k - 1;
+    const double *xr = &Ar[id(k + 1, k)], *xi = &Ai[id(k + 1, k)];
     double sig2 = 0.0;
-    for (int i = 0; i < m; ++i) {
-      const cpx x = a(k + 1 + i, k);
-      sig2 += x.re * x.re + x.im * x.im;
-    }
+    for (int i = 0; i < m; ++i) sig2 += xr[i] * xr[i] + xi[i] * xi[i];
     const double sig = std::sqrt(sig2);
-    const cpx x0 = a(k + 1, k);
-    const double ax0 = cabs(x0);
-    if (sig == 0.0) {
-      sub[k] = {0.0, 0.0};
-      continue;
-    }
-    const cpx ph = ax0 > 0 ? cpx{x0.re / ax0, x0.im / ax0} : cpx{1.0, 0.0};
-    const cpx alpha = cscal(ph, -sig);
-    cpx *v = &V[(size_t)n * k + k + 1];
-    for (int i = 0; i < m; ++i) v[i] = a(k + 1 + i, k);
-    v[0] = csub(v[0], alpha);
+    const double x0r = xr[0], x0i = xi[0];
+    const double ax0 = hyp(x0r, x0i);
+    if (sig == 0.0) { sr[k] = si[k] = 0.0; continue; }
+    const double phr = ax0 > 0 ? x0r / ax0 : 1.0, phi = ax0 > 0 ? x0i / ax0 : 0.0;
+    const double alr = -sig * phr, ali = -sig * phi;
+    double *vr = &Vr[id(k + 1, k)], *vi = &Vi[id(k + 1, k)];
+    for (int i = 0; i < m; ++i) { vr[i] = xr[i]; vi[i] = xi[i]; }
+    vr[0] -= alr; vi[0] -= ali;
     double vv = 0.0;
-    for (int i = 0; i < m; ++i) vv += v[i].re * v[i].re + v[i].im * v[i].im;
-    if (vv == 0.0) {
-      sub[k] = x0;
-      continue;
-    }
+    for (int i = 0; i < m; ++i) vv += vr[i] * vr[i] + vi[i] * vi[i];
+    if (vv == 0.0) { sr[k] = x0r; si[k] = x0i; continue; }
     const double b = 2.0 / vv;
     beta[k] = b;
-    // p = b A22 v, A22 = A[k+1.., k+1..]
-    for (int i = 0; i < m; ++i) p[i] = {0.0, 0.0};
+    // p = b A22 v with A22 = A[k+1.., k+1..]
+    for (int i = 0; i < m; ++i) pr[i] = pi[i] = 0.0;
     for (int j = 0; j < m; ++j) {
-      const cpx vj = v[j];
-      const cpx *col = &A[(size_t)(k + 1) + (size_t)n * (k + 1 + j)];
-      for (int i = 0; i < m; ++i) p[i] = cadd(p[i], cmul(col[i], vj));
-    }
-    cpx vp = {0.0, 0.0};
-    for (int i = 0; i < m; ++i) {
-      p[i] = cscal(p[i], b);
-      vp = cadd(vp, cmulc(v[i], p[i]));
-    }
-    // w = p - (b/2) (v^H p) v ; A22 <- A22 - v w^H - w v^H
-    const double K = 0.5 * b * vp.re;
-    for (int i = 0; i < m; ++i) w[i] = csub(p[i], cscal(v[i], K));
-    for (int j = 0; j < m; ++j) {
-      const cpx wj = w[j], vj = v[j];
-      cpx *col = &A[(size_t)(k + 1) + (size_t)n * (k + 1 + j)];
+      const double vjr = vr[j], vji = vi[j];
+      const double *cr = &Ar[id(k + 1, k + 1 + j)], *ci = &Ai[id(k + 1, k + 1 + j)];
       for (int i = 0; i < m; ++i) {
-        // v_i conj(w_j) + w_i conj(v_j)
-        const cpx t1 = {v[i].re * wj.re + v[i].im * wj.im, v[i].im * wj.re - v[i].re * wj.im};
-        const cpx t2 = {w[i].re * vj.re + w[i].im * vj.im, w[i].im * vj.re - w[i].re * vj.im};
-        col[i] = csub(col[i], cadd(t1, t2));
+        pr[i] += cr[i] * vjr - ci[i] * vji;
+        pi[i] += cr[i] * vji + ci[i] * vjr;
       }
     }
-    sub[k] = alpha;
+    double vpr = 0.0;
+    for (int i = 0; i < m; ++i) {
+      pr[i] *= b; pi[i] *= b;
+      vpr += vr[i] * pr[i] + vi[i] * pi[i];
+    }
+    // w = p - (b/2) (v^H p) v ; A22 <- A22 - v w^H - w v^H
+    const double K = 0.5 * b * vpr;
+    for (int i = 0; i < m; ++i) { wr[i] = pr[i] - K * vr[i]; wi[i] = pi[i] - K * vi[i]; }
+    for (int j = 0; j < m; ++j) {
+      const double wjr = wr[j], wji = wi[j], vjr = vr[j], vji = vi[j];
+      double *cr = &Ar[id(k + 1, k + 1 + j)], *ci = &Ai[id(k + 1, k + 1 + j)];
+      for (int i = 0; i < m; ++i) {
+        cr[i] -= (vr[i] * wjr + vi[i] * wji) + (wr[i] * vjr + wi[i] * vji);
+        ci[i] -= (vi[i] * wjr - vr[i] * wji) + (wi[i] * vjr - wr[i] * vji);
+      }
+    }
+    sr[k] = alr; si[k] = ali;
   }
-  for (int k = 0; k < n; ++k) d[k] = a(k, k).re;
-  if (n >= 2) sub[n - 2] = a(n - 1, n - 2);
-  // 2. real sub-diagonal through phases delta_{k+1} = delta_k e_k / |e_k|
-  std::vector<cpx> delta(n, {1.0, 0.0});
+  for (int k = 0; k < n; ++k) d[k] = Ar[id(k, k)];
+  if (n >= 2) { sr[n - 2] = Ar[id(n - 1, n - 2)]; si[n - 2] = Ai[id(n - 1, n - 2)]; }
+  // 2. real sub-diagonal through the phases delta_{k+1} = delta_k e_k / |e_k|
+  std::vector<double> dr(n, 1.0), di(n, 0.0);
   for (int k = 0; k + 1 < n; ++k) {
-    const double ae = cabs(sub[k]);
+    const double ae = hyp(sr[k], si[k]);
     e[k] = ae;
-    delta[k + 1] = ae > 0 ? cmul(delta[k], cpx{sub[k].re / ae, sub[k].im / ae}) : delta[k];
+    if (ae > 0) {
+      const double ur = sr[k] / ae, ui = si[k] / ae;
+      dr[k + 1] = dr[k] * ur - di[k] * ui;
+      di[k + 1] = dr[k] * ui + di[k] * ur;
+    } else { dr[k + 1] = dr[k]; di[k + 1] = di[k]; }
   }
   e[n - 1] = 0.0;
   // 3. implicit QL on (d, e); Z accumulates the rotations (column-major n x n)
-  std::vector<double> Z((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) Z[(size_t)i + (size_t)n * i] = 1.0;
+  std::vector<double> Z(nn, 0.0);
+  for (int i = 0; i < n; ++i) Z[id(i, i)] = 1.0;
   const double eps = std::numeric_limits<double>::epsilon();
   for (int l = 0; l < n; ++l) {
     int iter = 0;
@@ -137,39 +139,30 @@ void herm_eig(int n, const double *Ain, double *evals, double *evecs) {
       if (++iter > 60) break;  // does not happen for Hermitian input; guards the loop
       // shift from the leading 2x2 block of the unreduced part
       double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = std::hypot(g, 1.0);
+      double r = hyp(g, 1.0);
       g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
       double s = 1.0, c = 1.0, pp = 0.0;
-      int i = m - 1;
       bool deflated = false;
-      for (; i >= l; --i) {
+      for (int i = m - 1; i >= l; --i) {
         const double f = s * e[i], bb = c * e[i];
-        r = std::hypot(f, g);
+        r = hyp(f, g);
         e[i + 1] = r;
-        if (r == 0.0) {
-          d[i + 1] -= pp;
-          e[m] = 0.0;
-          deflated = true;
-          break;
-        }
-        s = f / r;
-        c = g / r;
+        if (r == 0.0) { d[i + 1] -= pp; e[m] = 0.0; deflated = true; break; }
+        s = f / r; c = g / r;
         g = d[i + 1] - pp;
         r = (d[i] - g) * s + 2.0 * c * bb;
         pp = s * r;
         d[i + 1] = g + pp;
         g = c * r - bb;
-        double *zi = &Z[(size_t)n * i], *zi1 = &Z[(size_t)n * (i + 1)];
-        for (int k = 0; k < n; ++k) {
-          const double t = zi1[k];
-          zi1[k] = s * zi[k] + c * t;
-          zi[k] = c * zi[k] - s * t;
+        double *zi = &Z[id(0, i)], *zi1 = &Z[id(0, i + 1)];
+        for (int q = 0; q < n; ++q) {
+          const double t = zi1[q];
+          zi1[q] = s * zi[q] + c * t;
+          zi[q] = c * zi[q] - s * t;
         }
       }
       if (deflated) continue;
-      d[l] -= pp;
-      e[l] = g;
-      e[m] = 0.0;
+      d[l] -= pp; e[l] = g; e[m] = 0.0;
     }
   }
   std::vector<int> order(n);
@@ -177,29 +170,43 @@ void herm_eig(int n, const double *Ain, double *evals, double *evecs) {
   std::sort(order.begin(), order.end(), [&](int x, int y) { return d[x] < d[y]; });
   for (int k = 0; k < n; ++k) evals[k] = d[order[k]];
   if (!evecs) return;
-  // 4. eigenvectors: X = Q D Z (columns in ascending eigenvalue order)
-  std::vector<cpx> X((size_t)n * n);
-  for (int k = 0; k < n; ++k) {
-    const double *zc = &Z[(size_t)n * order[k]];
-    cpx *xc = &X[(size_t)n * k];
-    for (int i = 0; i < n; ++i) xc[i] = cscal(delta[i], zc[i]);
-  }
+  // 4. eigenvectors X = Q D Z (columns in ascending eigenvalue order), held
+  // row-major (X[i][c] at i n + c) so the reflector sums run over contiguous columns
+  std::vector<double> Xr(nn), Xi(nn), tr(n), ti(n);
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < n; ++c) {
+      const double z = Z[id(i, order[c])];
+      Xr[(size_t)i * n + c] = dr[i] * z;
+      Xi[(size_t)i * n + c] = di[i] * z;
+    }
   for (int k = n - 3; k >= 0; --k) {
     if (beta[k] == 0.0) continue;
     const int m = n - k - 1;
-    const cpx *v = &V[(size_t)n * k + k + 1];
-    for (int c = 0; c < n; ++c) {
-      cpx *xc = &X[(size_t)n * c + k + 1];
-      cpx s = {0.0, 0.0};
-      for (int i = 0; i < m; ++i) s = cadd(s, cmulc(v[i], xc[i]));
-      s = cscal(s, beta[k]);
-      for (int i = 0; i < m; ++i) xc[i] = csub(xc[i], cmul(v[i], s));
+    const double *vr = &Vr[id(k + 1, k)], *vi = &Vi[id(k + 1, k)];
+    for (int c = 0; c < n; ++c) tr[c] = ti[c] = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double a = vr[i], bq = vi[i];
+      const double *xr = &Xr[(size_t)(k + 1 + i) * n], *xi = &Xi[(size_t)(k + 1 + i) * n];
+      for (int c = 0; c < n; ++c) {  // t += conj(v_i) x_i
+        tr[c] += a * xr[c] + bq * xi[c];
+        ti[c] += a * xi[c] - bq * xr[c];
+      }
+    }
+    const double b = beta[k];
+    for (int c = 0; c < n; ++c) { tr[c] *= b; ti[c] *= b; }
+    for (int i = 0; i < m; ++i) {
+      const double a = vr[i], bq = vi[i];
+      double *xr = &Xr[(size_t)(k + 1 + i) * n], *xi = &Xi[(size_t)(k + 1 + i) * n];
+      for (int c = 0; c < n; ++c) {  // x_i -= v_i t
+        xr[c] -= a * tr[c] - bq * ti[c];
+        xi[c] -= a * ti[c] + bq * tr[c];
+      }
     }
   }
-  for (size_t t = 0; t < (size_t)n * n; ++t) {
-    evecs[2 * t] = X[t].re;
-    evecs[2 * t + 1] = X[t].im;
-  }
+  for (int c = 0; c < n; ++c)
+    for (int i = 0; i < n; ++i) {
+      evecs[2 * id(i, c)] = Xr[(size_t)i * n + c];
+      evecs[2 * id(i, c) + 1] = Xi[(size_t)i * n + c];
+    }
 }
-
 }  // namespace sscg

@@ -74,6 +74,17 @@ def test_herm_eig(sscg, n):
     assert np.abs(V.conj().T @ V - np.eye(n)).max() < 1e-12
 
 
+@pytest.mark.parametrize("scale", [1e-100, 1e100])
+def test_herm_eig_scaled(sscg, scale):
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((24, 24)) + 1j * rng.standard_normal((24, 24))
+    A = (B + B.conj().T) * scale
+    ev, V = sscg.herm_eig(A)
+    ref = np.linalg.eigvalsh(A)
+    assert np.abs(ev - ref).max() < 1e-12 * np.abs(ref).max()
+    assert np.abs(V.conj().T @ V - np.eye(24)).max() < 1e-12
+
+
 def test_herm_eig_degenerate(sscg):
     A = np.diag([1.0, 1.0, 2.0, 2.0, 2.0]).astype(complex)
     Q, _ = np.linalg.qr(np.random.default_rng(1).standard_normal((5, 5)) + 0j)

@@ -59,6 +59,28 @@ def test_poll_and_graph_do_not_change_results(sscg, prob):
     assert np.array_equal(r0.conv_iter, r1.conv_iter) and np.array_equal(r0.iters, r2.iters)
 
 
+def test_graphs_kept_across_solves(sscg, prob, monkeypatch):
+    """A context keeps its solve-loop graphs between solves and replays them when the
+    launch plan is the same; solves of other shifts, source counts and options on one
+    context give bitwise what fresh contexts give (fixed launch shapes, so that every
+    context runs the same kernels)."""
+    case("graph reuse across solves")
+    monkeypatch.setenv("SSCG_AUTOTUNE", "0")
+    U, A, V, z = prob
+    z2 = z * 0.5 + 0.01
+    c = sscg.Context(CFG1.dims, CFG1.kappa)
+    c.set_gauge(U, 18)
+    runs = [(V, z, {}), (V, z2, {}), (V, z, {}), (V[:1], z, {}), (V, z, dict(poll_every=30)),
+            (V, z, dict(prec=sscg.MIXED_SHIFTS)), (V, z, {})]
+    for Vk, zk, kw in runs:
+        y = to_dev(np.zeros((Vk.shape[0], len(zk), Vk.shape[1])))
+        r = c.shifted_cg_solve(to_dev(Vk), zk, 0.0, y, sscg.default_opts(**kw))
+        y_ref, r_ref = solve(sscg, U, Vk, zk, **kw)
+        assert np.array_equal(to_host(y), y_ref), kw
+        assert np.array_equal(r.conv_iter, r_ref.conv_iter) and np.array_equal(r.iters, r_ref.iters)
+    c.close()
+
+
 def test_profiling_levels(sscg, prob):
     """Level 1 times every launch (direct launches); level 5 keeps graph replay and
     times the dslash and shift update of every 5th iteration. Neither changes the
