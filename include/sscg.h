@@ -247,8 +247,9 @@ int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs);
 
 /* Per-stage timing of the last solve on this context, from HIP events on the
  * context's stream, in milliseconds summed over the solve; counts in calls.
- * stage: 0 dslash, 1 seed alpha scalars, 2 seed residual update, 3 shift scalars,
- * 4 fused shift update, 5 reliable update, 6 whole iteration loop.
+ * stage: 0 dslash, 1 seed alpha scalars, 2 seed residual update, 3 (not used: the
+ * shift scalars are formed inside the shift update), 4 fused shift update, 5 reliable
+ * update, 6 whole iteration loop (wall clock; its count is the iterations launched).
  * Timing is recorded only when enabled with sscg_set_profiling(ctx, level):
  *   level 0  off (the default);
  *   level 1  every launch of the solve loop is bracketed by events, and the loop runs

@@ -69,7 +69,7 @@ struct sscg_ctx {
   std::map<std::string, Tune> tuned;
   // solver workspaces
   DevBuf v64, r64, p64, q64, W, r32, p32, q32, rbase, xpart64, xpart32, tmp, pq_part, rr_part, seed,
-      shift, zdev, small, cmom, mgbuf, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out;
+      shift, zdev, small, cmom, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out;
   SeedState *seed_host = nullptr;
   int seed_host_cap = 0;
   // profiling
@@ -191,6 +191,7 @@ int sscg_create(sscg_ctx **out, const int32_t dims[4], double kappa, double r, i
   if (c->tune.nr != 1 && c->tune.nr != 2 && c->tune.nr != 4) c->tune.nr = 2;
   if (c->tune.bs != 64 && c->tune.bs != 128 && c->tune.bs != 256) c->tune.bs = 256;
   if (c->tune.wbatch < 1) c->tune.wbatch = 8;
+  if (c->tune.wbatch > kMaxWBatch) c->tune.wbatch = kMaxWBatch;  // the update kernel stages a batch in LDS
   *out = c;
   return SSCG_OK;
 }
@@ -201,7 +202,7 @@ void sscg_destroy(sscg_ctx *c) {
   hipStreamSynchronize(c->work);
   DevBuf *bufs[] = {&c->g64, &c->g32, &c->v64, &c->r64, &c->p64, &c->q64, &c->W, &c->r32, &c->p32,
                     &c->q32, &c->rbase, &c->xpart64, &c->xpart32, &c->tmp, &c->pq_part, &c->rr_part,
-                    &c->seed, &c->shift, &c->zdev, &c->small, &c->cmom, &c->mgbuf, &c->Ybuf, &c->Sbuf, &c->Qbuf, &c->AQbuf,
+                    &c->seed, &c->shift, &c->zdev, &c->small, &c->cmom, &c->Ybuf, &c->Sbuf, &c->Qbuf, &c->AQbuf,
                     &c->Xbuf, &c->AXbuf, &c->Accbuf, &c->apply_in, &c->apply_out};
   for (DevBuf *b : bufs) release(*b);
   if (c->seed_host) hipHostFree(c->seed_host);
@@ -322,7 +323,7 @@ static void dslash_with(sscg_ctx *c, const Tune &t, const void *in, void *out, i
   j.out = out;
   j.gauge = prec == 0 ? c->g64.p : c->g32.p;
   j.partial = partial;
-  j.seed = seed;
+  j.seed = const_cast<SeedState *>(seed);  // read only: no shift table, so no commit
   j.kappa = c->kappa;
   j.sigma = sigma;
   for (int i = 0; i < 4; ++i) j.dims[i] = c->dims[i];
@@ -460,7 +461,7 @@ struct Prob {
 
 struct IterPlan {
   DslashBatch d64, d32, dru;
-  ScalarBatch alpha, scal;
+  ScalarBatch alpha;
   VecBatch r64, r32, u64, u32, u32s, fold_seed, rel;
   VecBatch m64, m32;  // shift update with in-loop moments (FP64 / FP32 shift vectors)
   int nmom_max;       // 0: the solutions are stored
@@ -505,24 +506,27 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
     mk_d(pl.d64.job[i], c->p64.p, c->q64.p, c->g64.p, (double *)c->pq_part.p, bd);
     mk_d(pl.d32.job[i], c->p32.p, c->q32.p, c->g32.p, (double *)c->pq_part.p, bd);
     mk_d(pl.dru.job[i], c->xpart64.p, c->q64.p, c->g64.p, nullptr, bdru);
+    // the iteration's first launch commits the staged state of the previous one
+    for (DslashJob *dj : {&pl.d64.job[i], &pl.d32.job[i]}) {
+      dj->shift = shift;
+      dj->nshift = N;
+    }
     bd += nbs * groups;
     bdru += nbs * groups;
-    auto mk_s = [&](ScalarJob &j, const double *part, int nblk) {
-      j.seed = seed; j.shift = shift; j.partial = part; j.nblk = nblk; j.nsrc = L; j.nshift = N;
-      j.maxiter = o.maxiter; j.block_begin = bs; j.tol = o.tol;
-    };
-    mk_s(pl.alpha.job[i], (double *)c->pq_part.p, (c->V + 63) / 64);
-    mk_s(pl.scal.job[i], (double *)c->rr_part.p, nbv);
-    if (P[i].nmom > 0) {
-      pl.scal.job[i].mcoef = (const double2 *)P[i].mom_coef;
-      pl.scal.job[i].mg = (double2 *)c->mgbuf.p;
-      pl.scal.job[i].nmom = P[i].nmom;
+    {
+      ScalarJob &j = pl.alpha.job[i];
+      j.seed = seed;
+      j.partial = (const double *)c->pq_part.p;
+      j.nblk = (c->V + 63) / 64;
+      j.nsrc = L;
+      j.block_begin = bs;
     }
     bs += L;
     auto mk_v = [&](VecJob &j, void *a, void *b, void *cc, void *d, int begin, int nblocks) {
       j.a = a; j.b = b; j.c = cc; j.d = d; j.e = nullptr; j.partial = (double *)c->rr_part.p;
       j.seed = seed; j.shift = shift; j.n = c->n; j.nsrc = L; j.nshift = N; j.nblk_vec = nbv;
       j.block_begin = begin; j.nblocks = nblocks; j.wbatch = t.wbatch; j.border = t.border;
+      j.rr_partial = (const double *)c->rr_part.p; j.nrr = nbv; j.tol = o.tol;
     };
     mk_v(pl.r64.job[i], c->r64.p, c->q64.p, nullptr, nullptr, bv, L * nbv);
     mk_v(pl.r32.job[i], c->r32.p, c->q32.p, c->xpart32.p, c->p32.p, bv, L * nbv);
@@ -544,7 +548,7 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
       for (VecBatch *mb : {&pl.m64, &pl.m32}) {
         VecJob &j = mb->job[i];
         mk_v(j, P[i].mom, c->W.p, c->r64.p, c->p64.p, bm, L * nbm);
-        j.e = c->mgbuf.p;
+        j.mcoef = (const double2 *)P[i].mom_coef;
         j.nmom = P[i].nmom;
         j.nblk_mom = nbm;
       }
@@ -557,8 +561,8 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
   pl.d64.njobs = pl.d32.njobs = pl.dru.njobs = np;
   pl.d64.total_blocks = pl.d32.total_blocks = bd;
   pl.dru.total_blocks = bdru;
-  pl.alpha.njobs = pl.scal.njobs = np;
-  pl.alpha.total_blocks = pl.scal.total_blocks = bs;
+  pl.alpha.njobs = np;
+  pl.alpha.total_blocks = bs;
   for (VecBatch *vb : {&pl.r64, &pl.r32, &pl.fold_seed, &pl.rel}) {
     vb->njobs = np;
     vb->total_blocks = bv;
@@ -665,8 +669,6 @@ static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, boo
     launch_dslash(pl.dru, 0, t.nr, 18, t.bs, t.xcd, pl.ct, st);
     launch_reliable_residual(pl.rel, st);
   }
-  rec.mark(ST_SCAL);
-  launch_shift_scalars(pl.scal, st);
   rec.mark(ST_SHIFT);
   if (smp) smp->mark(ST_SHIFT);
   if (pl.nmom_max > 0) {  // FP64 seed in both phases (checked by run_solve)
@@ -718,10 +720,6 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
   CHK(ensure(c, c->seed, L * sizeof(SeedState)));
   CHK(ensure(c, c->shift, L * N * sizeof(ShiftState)));
   CHK(ensure(c, c->zdev, N * 2 * sizeof(double)));
-  if (p.nmom > 0) {  // g of the in-loop moments; rows from nmom on stay zero
-    CHK(ensure(c, c->mgbuf, L * kMomRows * N * sizeof(double2)));
-    HIPCHK(c, hipMemsetAsync(c->mgbuf.p, 0, L * kMomRows * N * sizeof(double2), c->work));
-  }
   if (o.prec == SSCG_MIXED) {  // FP32 seed vectors and reliable-update storage
     CHK(ensure(c, c->r32, L * vec32));
     CHK(ensure(c, c->p32, L * vec32));
@@ -760,6 +758,7 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
     s.vnorm = std::sqrt(vn2[l]);
     s.maxres = 1.0;
     s.nactive = (int)N;
+    s.maxiter = o.maxiter;
   }
   std::vector<ShiftState> sh(L * N);
   for (size_t l = 0; l < L; ++l)
@@ -889,20 +888,12 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
         try_shape(cand);
       }
   }
-  // fused shift update as an identity on the current data (not used, and not
-  // timed, when the moments are accumulated in the loop: there is no y_j)
+  // fused shift update as an identity on the current data (identity jobs: every
+  // shift updated with alpha_j = 0, beta_j = 1, 1/pi_j = 0, no state written; not
+  // used, and not timed, when the moments are accumulated in the loop: there is no y_j)
   const bool tune_update = P[0].nmom == 0;
   for (Prob &p : P) {
     if (!tune_update) break;
-    std::vector<ShiftState> sh((size_t)p.L * p.N);
-    HIPCHK(p.c, hipMemcpy(sh.data(), p.c->shift.p, sh.size() * sizeof(ShiftState), hipMemcpyDeviceToHost));
-    for (ShiftState &h : sh) {
-      h.upd = 1;
-      h.a = make_double2(0.0, 0.0);
-      h.b = make_double2(1.0, 0.0);
-      h.ipi = make_double2(0.0, 0.0);
-    }
-    HIPCHK(p.c, hipMemcpy(p.c->shift.p, sh.data(), sh.size() * sizeof(ShiftState), hipMemcpyHostToDevice));
     std::vector<SeedState> sd(p.L);
     HIPCHK(p.c, hipMemcpy(sd.data(), p.c->seed.p, sd.size() * sizeof(SeedState), hipMemcpyDeviceToHost));
     for (SeedState &x : sd) x.pending = 1;
@@ -923,6 +914,7 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
           cand.border = bo;
           IterPlan pl;
           build_plan(P, pl, o, cand);
+          for (int i = 0; i < pl.u64.njobs; ++i) pl.u64.job[i].identity = 1;
           const double t = time_it([&] { launch_shift_update(pl.u64, 0, 0, 0, u, nt, st); }, 3);
           if (t < tbest) {
             tbest = t;
@@ -941,13 +933,6 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
   hipEventDestroy(e1);
   // restore the initial state
   for (Prob &p : P) {
-    std::vector<ShiftState> sh((size_t)p.L * p.N);
-    HIPCHK(p.c, hipMemcpy(sh.data(), p.c->shift.p, sh.size() * sizeof(ShiftState), hipMemcpyDeviceToHost));
-    for (ShiftState &h : sh) {
-      h.upd = 0;
-      h.a = h.b = h.ipi = make_double2(0.0, 0.0);
-    }
-    HIPCHK(p.c, hipMemcpy(p.c->shift.p, sh.data(), sh.size() * sizeof(ShiftState), hipMemcpyHostToDevice));
     std::vector<SeedState> sd(p.L);
     HIPCHK(p.c, hipMemcpy(sd.data(), p.c->seed.p, sd.size() * sizeof(SeedState), hipMemcpyDeviceToHost));
     for (SeedState &x : sd) x.pending = 0;
@@ -1083,7 +1068,9 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
         launch_iteration(pl, prec, seed32, prec == 1 && (kk == chunk - 1) && full, lr, tn, st, rec, kk, every);
     }
     k += chunk;
-    // poll
+    // poll: commit the last iteration's staged state, then read the seed states
+    if (!(use_graph && full)) rec.mark(-1);
+    launch_commit(pl.d64, st);
     bool all_done = true, can_switch = true;
     for (Prob &p : P) {
       hipError_t e = hipMemcpyAsync(p.c->seed_host, p.c->seed.p, p.L * sizeof(SeedState),
@@ -1121,6 +1108,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     }
   }
   if (rc != SSCG_OK) return rc;
+  launch_commit(pl.d64, st);  // (every chunk ends with a commit; kept for a loop left early)
   if (prec == 1) {
     // fold every shift's FP32 partial into its FP64 solution
     for (Prob &p : P)

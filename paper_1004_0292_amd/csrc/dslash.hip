@@ -180,6 +180,10 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
   }
   const int l0 = group * NR;
   const int nvalid = min(NR, J.nsrc - l0);
+  // the first block of a solve-loop launch commits the previous iteration's staged
+  // state (the other blocks read only the done flags: at worst they compute a
+  // finished source once more, whose result is not used)
+  if (lb == 0 && J.shift) commit_states(J.seed, J.shift, J.nsrc, J.nshift);
   if (J.seed) {
     bool all_done = true;
     for (int r = 0; r < nvalid; ++r) all_done &= (J.seed[l0 + r].done != 0);
@@ -282,6 +286,10 @@ __global__ __launch_bounds__(256) void dslash_split_kernel(DslashBatch B, int xc
   const int sblk = lb / groups, group = lb - sblk * groups;
   const int l0 = group * NR;
   const int nvalid = min(NR, J.nsrc - l0);
+  // the first block of a solve-loop launch commits the previous iteration's staged
+  // state (the other blocks read only the done flags: at worst they compute a
+  // finished source once more, whose result is not used)
+  if (lb == 0 && J.shift) commit_states(J.seed, J.shift, J.nsrc, J.nshift);
   if (J.seed) {
     bool all_done = true;
     for (int r = 0; r < nvalid; ++r) all_done &= (J.seed[l0 + r].done != 0);
@@ -488,6 +496,10 @@ __global__ __launch_bounds__(MAXBS) void dslash_tile_kernel(DslashBatch B, int x
   const int t0 = range * J.ct, t1 = min(t0 + J.ct, Lt);
   const int l0 = group * NR;
   const int nvalid = min(NR, J.nsrc - l0);
+  // the first block of a solve-loop launch commits the previous iteration's staged
+  // state (the other blocks read only the done flags: at worst they compute a
+  // finished source once more, whose result is not used)
+  if (lb == 0 && J.shift) commit_states(J.seed, J.shift, J.nsrc, J.nshift);
   if (J.seed) {
     bool all_done = true;
     for (int r = 0; r < nvalid; ++r) all_done &= (J.seed[l0 + r].done != 0);

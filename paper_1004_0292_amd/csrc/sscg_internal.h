@@ -58,6 +58,11 @@ template <typename C> __host__ __device__ __forceinline__ C cmi(C a) { C c; c.x 
 template <typename C> __host__ __device__ __forceinline__ C cneg(C a) { C c; c.x = -a.x; c.y = -a.y; return c; }
 
 // ---- solver state (device memory) ------------------------------------------
+// The shift update kernel forms the scalars of its iteration itself (every block
+// from the same inputs, so every block gets the same values) and may not change
+// what its other blocks read; it stages the new values ("_n" fields), and the first
+// block of the next iteration's dslash commits them (commit_states below), or a
+// commit launch does before the host reads the state.
 // Per source: the seed CG scalars of (sigma I - A) x = v.
 struct SeedState {
   double rho;        // <r_k, r_k>
@@ -66,25 +71,126 @@ struct SeedState {
   double beta_prev;  // beta_{k-1} (0 before the first iteration)
   double vnorm;      // ||v||
   double maxres;     // max over active shifts of ||r_j|| / ||v|| after the last update
+  double rho_n;      // staged: rho_{k+1}
+  double beta_n;     // staged: beta_k
   int32_t iters;     // completed iterations
   int32_t done;      // 1: no more work for this source
   int32_t status;    // SSCG_OK / SSCG_ENOTCONV / SSCG_EBREAKDOWN
   int32_t nactive;   // shifts still iterating
-  int32_t pending;   // 1: shift update of the current iteration still to apply
-  int32_t pad;
+  int32_t pending;   // 1: alpha_k of the current iteration is set (no breakdown)
+  int32_t staged;    // 1: the _n fields hold an update not yet committed
+  int32_t brk_n;     // staged: rho_{k+1} or beta_k not finite
+  int32_t maxiter;   // iteration limit
 };
 // Per (source, shift): the scalars of shift j (s_j = z_j - sigma).
 struct ShiftState {
   double2 s;
   double2 pi_prev, pi_cur;   // pi_{j,k-1}, pi_{j,k}
-  double2 a, b, ipi;         // alpha_{j,k}, beta_{j,k}, 1/pi_{j,k+1}
+  double2 pi_n;              // staged: pi_{j,k+1}
+  double res_n;              // staged: sqrt(rho_{k+1}) / |pi_{j,k+1}| / tscale
+  double tscale;             // this shift's tolerance multiplier (1: the common tol)
   int32_t active;            // still iterating (before this iteration's decision)
-  int32_t upd;               // apply the update of the current iteration
+  int32_t frz_n;             // staged: freezes after this iteration's update
   int32_t conv_iter;         // iteration after which it froze, -1 if not yet
   int32_t pad;
-  double tscale;             // this shift's tolerance multiplier (1: the common tol)
-  double pad2;
 };
+
+// Scalars of one shift in iteration k (Sec. 2.2): from alpha_k, beta_k,
+// c = alpha_k beta_{k-1} / alpha_{k-1}, sqrt(rho_{k+1}) and the committed pi values,
+//   pi_{j,k+1} = (1 + c + alpha_k s_j) pi_{j,k} - c pi_{j,k-1},
+//   alpha_{j,k} = alpha_k pi_{j,k}/pi_{j,k+1},  beta_{j,k} = (pi_{j,k}/pi_{j,k+1})^2 beta_k,
+// and the freeze test sqrt(rho_{k+1}) / |pi_{j,k+1}| / tscale <= thr. A frozen shift
+// (inactive) gets upd = 0 and zero coefficients.
+struct ShiftStep {
+  double2 a, b, ipi, pn;
+  double res;
+  int upd, frz;
+};
+__device__ __forceinline__ double2 cdiv_smith(double2 a, double2 b) {  // Smith's division a / b
+  if (fabs(b.x) >= fabs(b.y)) {
+    const double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  } else {
+    const double r = b.x / b.y, d = b.x * r + b.y;
+    return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+  }
+}
+__device__ __forceinline__ ShiftStep shift_step(const ShiftState &H, double alpha, double beta, double c, double sq,
+                                                double thr) {
+  ShiftStep o;
+  o.a = o.b = o.ipi = o.pn = make_double2(0.0, 0.0);
+  o.res = 0.0;
+  o.upd = o.frz = 0;
+  if (!H.active) return o;
+  const double2 pc = H.pi_cur, pp = H.pi_prev, s = H.s;
+  const double2 f = make_double2(1.0 + c + alpha * s.x, alpha * s.y);
+  double2 pn = cmul(f, pc);
+  pn.x -= c * pp.x;
+  pn.y -= c * pp.y;
+  const double2 ratio = cdiv_smith(pc, pn);
+  o.a = make_double2(alpha * ratio.x, alpha * ratio.y);
+  const double2 r2 = cmul(ratio, ratio);
+  o.b = make_double2(beta * r2.x, beta * r2.y);
+  o.ipi = cdiv_smith(make_double2(1.0, 0.0), pn);
+  o.pn = pn;
+  o.res = sq / hypot(pn.x, pn.y) / H.tscale;
+  o.upd = 1;
+  o.frz = o.res <= thr;
+  return o;
+}
+
+// Commit of the staged iteration of every source of a problem, run by one block
+// (one wavefront per source; full wavefronts only): pi_{j,k-1} <- pi_{j,k} <-
+// pi_{j,k+1} for the shifts that were active, freezing, the seed scalars, the count
+// of active shifts and the largest active residual, and the end of the source's run
+// (all shifts frozen, breakdown, or the iteration limit).
+__device__ inline void commit_states(SeedState *seed, ShiftState *shift, int nsrc, int nshift) {
+  const int nw = blockDim.x / 64, w = threadIdx.x / 64, lane = threadIdx.x & 63;
+  if (w >= nw) return;
+  for (int l = w; l < nsrc; l += nw) {
+    SeedState &S = seed[l];
+    if (!S.staged) continue;  // uniform over the wavefront
+    int nact = 0;
+    double mr = 0.0;
+    for (int j = lane; j < nshift; j += 64) {
+      ShiftState &H = shift[(size_t)l * nshift + j];
+      if (!H.active) continue;
+      H.pi_prev = H.pi_cur;
+      H.pi_cur = H.pi_n;
+      if (H.frz_n) {
+        H.active = 0;
+      } else {
+        nact += 1;
+        mr = fmax(mr, H.res_n / S.vnorm);
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      nact += __shfl_xor(nact, off, 64);
+      mr = fmax(mr, __shfl_xor(mr, off, 64));
+    }
+    if (lane == 0) {
+      S.alpha_prev = S.alpha;
+      S.beta_prev = S.beta_n;
+      S.rho = S.rho_n;
+      S.iters += 1;
+      S.nactive = nact;
+      S.maxres = mr;
+      S.pending = 0;
+      if (S.brk_n) {
+        S.status = -5;  // SSCG_EBREAKDOWN
+        S.done = 1;
+      } else if (nact == 0) {
+        S.status = 0;
+        S.done = 1;
+      } else if (S.iters >= S.maxiter) {
+        S.status = -4;  // SSCG_ENOTCONV
+        S.done = 1;
+      }
+      S.staged = 0;
+    }
+  }
+}
 
 // ---- job tables -------------------------------------------------------------
 // A grouped launch covers up to kMaxJobs problems; block b belongs to the job
@@ -94,7 +200,9 @@ struct DslashJob {
   void *out;             // planar [nsrc][12][V] of T
   const void *gauge;     // [4][LR/2][V] of V2<T>
   double *partial;       // [nsrc][ceil(V/64)] partial Re<in, out> per wavefront, or nullptr
-  const SeedState *seed; // per-source done flags, or nullptr (always compute)
+  SeedState *seed;       // per-source done flags, or nullptr (always compute)
+  ShiftState *shift;     // solve loop: the first block commits the staged states (or nullptr)
+  int32_t nshift, pad0;
   double kappa, sigma;   // out = sigma in - A in (mode 1) or A in (mode 0)
   int32_t dims[4];
   int32_t V, nsrc, nblk_site, block_begin, nblocks, mode;
@@ -104,19 +212,15 @@ struct DslashJob {
 };
 struct DslashBatch { DslashJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
 
+// Step length kernel (large lattices): one block per (job, source).
 struct ScalarJob {
-  SeedState *seed; ShiftState *shift;
-  const double *partial; // partial sums to reduce (pq or rr)
+  SeedState *seed;
+  const double *partial; // <p, Bp> partials to reduce
   int32_t nblk;          // partials per source
-  int32_t nsrc, nshift, maxiter, block_begin;
-  double tol;
-  // in-loop moments (shift scalars only): g[l][k][j] = mcoef[k][j] alpha_j for the
-  // shifts updated this iteration, 0 otherwise; rows k < nmom of [nsrc][32][nshift]
-  const double2 *mcoef;
-  double2 *mg;
-  int32_t nmom, pad;
+  int32_t nsrc, block_begin, pad;
 };
-constexpr int kMomRows = 32;  // rows of g per source (the largest moment count)
+constexpr int kMomRows = 32;  // largest moment count accumulated inside the solve
+constexpr int kMaxWBatch = 64;  // largest shift batch of the fused shift update
 // Element-wise pass over nsrc vectors of n complex entries of one problem.
 struct VecJob {
   void *a; void *b; void *c; void *d; void *e;   // meaning depends on the kernel
@@ -132,6 +236,15 @@ struct VecJob {
   // this many <p, Bp> partials per source at pq_partial (no separate alpha kernel)
   int32_t npq;
   const double *pq_partial;
+  // shift update (and its in-loop moment form): the scalars of the iteration are
+  // formed from the nrr <r, r> partials per source at rr_partial; tol is the
+  // common tolerance; mcoef[k][j] the moment coefficients c_kj; identity = 1 runs
+  // the update with alpha_j = 0, beta_j = 1, 1/pi_j = 0 and writes no state
+  // (launch-shape timing)
+  const double *rr_partial;
+  const double2 *mcoef;
+  double tol;
+  int32_t nrr, identity;
 };
 struct VecBatch { VecJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
 
@@ -156,7 +269,8 @@ void launch_dslash(const DslashBatch &b, int prec /*0 fp64, 1 fp32*/, int nr, in
                    int xcd_remap, int ct, hipStream_t st);
 // vec.hip
 void launch_seed_alpha(const ScalarBatch &b, hipStream_t st);
-void launch_shift_scalars(const ScalarBatch &b, hipStream_t st);
+// commit of the staged states of every job with a shift table (one block per job)
+void launch_commit(const DslashBatch &b, hipStream_t st);
 void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st);
 // prec: shift vectors (0 FP64, 1 FP32); seed_prec: seed r and p (0 FP64, 1 FP32);
 // unroll: shifts whose loads are issued together (1, 2, 4); nt: non-temporal access
@@ -165,9 +279,7 @@ void launch_shift_update(const VecBatch &b, int prec, int seed_prec, int fold, i
 void launch_reliable_residual(const VecBatch &b, hipStream_t st);
 // Shift update with the moment sums accumulated in the loop (no stored x_j).
 // job: a = moments S (column k L + l of n entries), b = shift slots (p_j),
-// c = seed r, d = seed p (FP64), e = g[l][k][j] = c[k][j] alpha_j of this
-// iteration ([nsrc][kMomRows][nshift], written by the shift-scalar kernel; rows
-// from nmom on stay zero).
+// c = seed r, d = seed p (FP64); mcoef [nmom][nshift].
 constexpr int kMomBlock = 256;   // entries (threads) per block of the in-loop moment kernel
 void launch_shift_moments(const VecBatch &b, int prec, int nmom_max, hipStream_t st);
 void launch_fold_seed(const VecBatch &b, hipStream_t st);
@@ -199,8 +311,9 @@ void launch_resid_cols(const void *AX, const void *X, int64_t ld, int ncol, cons
                        int64_t n, double *partial, int nchunk, hipStream_t st);
 void launch_reduce_partials(const double *partial, int nchunk, int nout, double *out, hipStream_t st);
 
-// dense_host.cpp: Hermitian eigen-decomposition (cyclic Jacobi), column-major
-// complex matrices as interleaved doubles. Eigenvalues ascending.
+// dense_host.cpp: Hermitian eigen-decomposition (Householder tridiagonalisation and
+// implicit QL), column-major complex matrices as interleaved doubles. Eigenvalues
+// ascending.
 void herm_eig(int n, const double *A, double *evals, double *evecs);
 
 }  // namespace sscg

@@ -2,18 +2,22 @@
 // sums (eq. 2).
 //
 // Per iteration k of the seed system B x = v, B = sigma I - A, for every source:
-//   dslash        q = B p, partial Re<p, q>                      (dslash.hip)
-//   seed_alpha    alpha_k = rho_k / <p, q>                       (one block per source)
+//   dslash        q = B p, partial Re<p, q>; its first block commits the state
+//                 staged by the previous iteration                (dslash.hip)
+//   seed_alpha    alpha_k = rho_k / <p, q> (large lattices; on small ones the
+//                 residual update forms it itself)
 //   seed_r_update r <- r - alpha_k q, partial <r, r>
-//   shift_scalars rho_{k+1}, beta_k and, per shift j with s_j = z_j - sigma,
+//   shift_update  every block forms rho_{k+1}, beta_k and, for the shifts of its
+//                 batch (s_j = z_j - sigma),
 //                 pi_{j,k+1} = (1 + c + alpha_k s_j) pi_{j,k} - c pi_{j,k-1},
 //                 c = alpha_k beta_{k-1} / alpha_{k-1},
 //                 alpha_{j,k} = alpha_k pi_{j,k}/pi_{j,k+1},
 //                 beta_{j,k} = (pi_{j,k}/pi_{j,k+1})^2 beta_k,
-//                 and the freeze test sqrt(rho_{k+1}) / |pi_{j,k+1}| <= tol ||v||
-//   shift_update  x_j += alpha_{j,k} p_j, p_j <- r/pi_{j,k+1} + beta_{j,k} p_j for
-//                 every shift updated this iteration, and p <- r + beta_k p; the
-//                 seed residual r is read once per batch of shifts.
+//                 and the freeze test sqrt(rho_{k+1}) / |pi_{j,k+1}| <= tol ||v||;
+//                 then x_j += alpha_{j,k} p_j, p_j <- r/pi_{j,k+1} + beta_{j,k} p_j
+//                 for every shift active in this iteration, and p <- r + beta_k p;
+//                 the seed residual r is read once per batch of shifts. The new
+//                 scalars are staged for the commit.
 // Every reduction writes one partial per block and the consumer sums them in a
 // fixed order, so results do not depend on scheduling.
 #include "sscg_internal.h"
@@ -58,17 +62,6 @@ __device__ __forceinline__ int job_of(const J *jobs, int njobs, int b) {
   return j;
 }
 
-// Smith's complex division a / b (no overflow for large |b|).
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-  if (fabs(b.x) >= fabs(b.y)) {
-    const double r = b.y / b.x, d = b.x + b.y * r;
-    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
-  } else {
-    const double r = b.x / b.y, d = b.x * r + b.y;
-    return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
-  }
-}
-
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void seed_alpha_kernel(ScalarBatch B) {
   __shared__ double red[kBlock / 64];
@@ -90,96 +83,16 @@ __global__ __launch_bounds__(kBlock) void seed_alpha_kernel(ScalarBatch B) {
       S.done = 1;
     } else {
       S.alpha = S.rho / pq;
+      S.pending = 1;
     }
   }
 }
 
-// Seed and shift scalars of one source after its residual update (one block):
-// rho_{k+1}, beta_k, the pi recurrences, alpha_j, beta_j, 1/pi_j, freezing, and the
-// seed state the host polls.
-__device__ void shift_scalars_body(const ScalarJob &J, int l, double *red) {
-  SeedState &S = J.seed[l];
-  if (S.done) return;
-  double v = 0.0;
-  const double *p = J.partial + (size_t)l * J.nblk;
-  for (int i = threadIdx.x; i < J.nblk; i += kBlock) v += p[i];
-  const double rho_new = block_sum_all<kBlock / 64>(v, red);
-  const double alpha = S.alpha, alpha_prev = S.alpha_prev, beta_prev = S.beta_prev;
-  const double beta = rho_new / S.rho;
-  const double c = alpha * beta_prev / alpha_prev;
-  const double sq = sqrt(rho_new);
-  const double thr = J.tol * S.vnorm;
-  const int it = S.iters;
-  double nact = 0.0, maxres = 0.0;
-  for (int j = threadIdx.x; j < J.nshift; j += kBlock) {
-    ShiftState &H = J.shift[(size_t)l * J.nshift + j];
-    if (H.active) {
-      const double2 pc = H.pi_cur, pp = H.pi_prev, s = H.s;
-      // (1 + c + alpha s) pi_cur - c pi_prev
-      const double2 f = make_double2(1.0 + c + alpha * s.x, alpha * s.y);
-      double2 pn = cmul(f, pc);
-      pn.x -= c * pp.x;
-      pn.y -= c * pp.y;
-      const double2 ratio = cdiv(pc, pn);
-      H.a = make_double2(alpha * ratio.x, alpha * ratio.y);
-      const double2 r2 = cmul(ratio, ratio);
-      H.b = make_double2(beta * r2.x, beta * r2.y);
-      H.ipi = cdiv(make_double2(1.0, 0.0), pn);
-      H.pi_prev = pc;
-      H.pi_cur = pn;
-      H.upd = 1;
-      // residual in units of this shift's own tolerance scale
-      const double res = sq / hypot(pn.x, pn.y) / H.tscale;
-      if (res <= thr) {
-        H.active = 0;
-        H.conv_iter = it + 1;
-      } else {
-        nact += 1.0;
-        maxres = fmax(maxres, res / S.vnorm);
-      }
-    } else {
-      H.upd = 0;
-    }
-  }
-  if (J.nmom > 0) {
-    // g[k][j] = c[k][j] alpha_j for the in-loop moments (zero for frozen shifts)
-    __syncthreads();
-    double2 *g = J.mg + (size_t)l * kMomRows * J.nshift;
-    for (int t = threadIdx.x; t < J.nmom * J.nshift; t += kBlock) {
-      const int j = t % J.nshift;
-      const ShiftState &H = J.shift[(size_t)l * J.nshift + j];
-      g[t] = H.upd ? cmul(J.mcoef[t], H.a) : make_double2(0.0, 0.0);
-    }
-  }
-  const double na = block_sum_all<kBlock / 64>(nact, red);
-  const double mr = block_max_all<kBlock / 64>(maxres, red);
-  if (threadIdx.x == 0) {
-    S.alpha_prev = alpha;
-    S.beta_prev = beta;
-    S.rho = rho_new;
-    S.iters = it + 1;
-    S.nactive = (int)na;
-    S.maxres = mr;
-    S.pending = 1;
-    if (!isfinite(rho_new) || !isfinite(beta)) {
-      S.status = -5;
-      S.done = 1;
-      S.pending = 0;
-    } else if (na == 0.0) {
-      S.done = 1;
-      S.status = 0;
-    } else if (it + 1 >= J.maxiter) {
-      S.done = 1;
-      S.status = -4;  // SSCG_ENOTCONV
-    }
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void shift_scalars_kernel(ScalarBatch B) {
-  __shared__ double red[kBlock / 64];
-  const int b = blockIdx.x;
-  const ScalarJob &J = B.job[job_of(B.job, B.njobs, b)];
-  shift_scalars_body(J, b - J.block_begin, red);
+// Commit of the staged states outside the solve loop's dslash (before the host
+// reads them): block b commits job b.
+__global__ __launch_bounds__(kBlock) void commit_kernel(DslashBatch B) {
+  const DslashJob &J = B.job[blockIdx.x];
+  if (J.shift && J.seed) commit_states(J.seed, J.shift, J.nsrc, J.nshift);
 }
 
 // ---------------------------------------------------------------------------
@@ -194,11 +107,7 @@ __global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
   const int lb = b - J.block_begin;
   const int l = lb / J.nblk_vec, vb = lb - l * J.nblk_vec;
   SeedState &S = J.seed[l];
-  if (S.done) {
-    // (the alpha kernel clears the flag of a finished source; without it, this does)
-    if (J.npq > 0 && vb == 0 && threadIdx.x == 0) S.pending = 0;
-    return;
-  }
+  if (S.done) return;
   double alpha64;
   if (J.npq > 0) {
     // the step length of the alpha kernel, formed by every block from the same
@@ -211,12 +120,12 @@ __global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
     const bool broke = pq == 0.0 || !isfinite(pq);
     alpha64 = broke ? 0.0 : S.rho / pq;
     if (vb == 0 && threadIdx.x == 0) {
-      S.pending = 0;
       if (broke) {
         S.status = -5;  // SSCG_EBREAKDOWN
         S.done = 1;
       } else {
         S.alpha = alpha64;
+        S.pending = 1;
       }
     }
     if (broke) return;
@@ -306,9 +215,15 @@ __device__ __forceinline__ void stc(float2 *p, float2 v) {
 // store, so a thread keeps 2 U kEpt loads in flight. NT selects streaming
 // (non-temporal) access for the shift vectors, which are touched once per
 // iteration.
+// The block first forms the scalars of the iteration for the shifts of its batch
+// (shift_step, in LDS); the first entry chunk's block of each batch stages them
+// for the commit, and the first block of the source stages rho_{k+1} and beta_k.
 template <typename T, typename TR, bool FOLD, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
   using C = V2<TR>;  // seed vectors r and p (TR); shift vectors in T
+  __shared__ double red[kBlock / 64];
+  __shared__ double2 s_a[kMaxWBatch], s_b[kMaxWBatch], s_ip[kMaxWBatch];
+  __shared__ int s_up[kMaxWBatch];
   const int b = blockIdx.x;
   const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
   const int lb = b - J.block_begin;
@@ -327,8 +242,8 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
     bt = rem / J.nblk_vec;
     vb = rem - bt * J.nblk_vec;
   }
-  const SeedState &S = J.seed[l];
-  if (!S.pending) return;
+  SeedState &S = J.seed[l];
+  if (S.done || !S.pending) return;  // uniform over the block
   const int64_t n = J.n;
   const C *r = reinterpret_cast<const C *>(J.c) + (size_t)l * n;
   const int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x;
@@ -339,6 +254,50 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
     rv[e] = i < n ? r[i] : cmk<C>(0, 0);
   }
   const int j0 = bt * J.wbatch, j1 = min(j0 + J.wbatch, J.nshift);
+  double beta64 = 0.0;
+  bool bad = false;
+  if (J.identity) {
+    for (int jj = threadIdx.x; jj < j1 - j0; jj += kBlock) {
+      s_a[jj] = s_ip[jj] = make_double2(0.0, 0.0);
+      s_b[jj] = make_double2(1.0, 0.0);
+      s_up[jj] = 1;
+    }
+  } else {
+    double v = 0.0;
+    const double *pr = J.rr_partial + (size_t)l * J.nrr;
+    for (int t = threadIdx.x; t < J.nrr; t += kBlock) v += pr[t];
+    const double rho_new = block_sum_all<kBlock / 64>(v, red);
+    const double alpha = S.alpha;
+    beta64 = rho_new / S.rho;
+    const double c = alpha * S.beta_prev / S.alpha_prev;
+    const double sq = sqrt(rho_new);
+    const double thr = J.tol * S.vnorm;
+    const int it = S.iters;
+    bad = !isfinite(rho_new) || !isfinite(beta64);
+    const bool writer = vb == 0 && !bad;
+    for (int jj = threadIdx.x; jj < j1 - j0; jj += kBlock) {
+      ShiftState &H = J.shift[(size_t)l * J.nshift + j0 + jj];
+      const ShiftStep o = shift_step(H, alpha, beta64, c, sq, thr);
+      s_a[jj] = o.a;
+      s_b[jj] = o.b;
+      s_ip[jj] = o.ipi;
+      s_up[jj] = o.upd;
+      if (writer && o.upd) {
+        H.pi_n = o.pn;
+        H.res_n = o.res;
+        H.frz_n = o.frz;
+        if (o.frz) H.conv_iter = it + 1;
+      }
+    }
+    if (vb == 0 && bt == 0 && threadIdx.x == 0) {
+      S.rho_n = rho_new;
+      S.beta_n = beta64;
+      S.brk_n = bad ? 1 : 0;
+      S.staged = 1;
+    }
+  }
+  __syncthreads();
+  if (bad) return;  // uniform: the commit ends this source's run
   for (int j = j0; j < j1; j += U) {
     bool act[U];
     double2 a[U], bb[U], ip[U];
@@ -346,11 +305,11 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
     for (int u = 0; u < U; ++u) {
       act[u] = false;
       if (j + u < j1) {
-        const ShiftState &H = J.shift[(size_t)l * J.nshift + j + u];
-        act[u] = H.upd != 0;
-        a[u] = H.a;
-        bb[u] = H.b;
-        ip[u] = H.ipi;
+        const int jj = j - j0 + u;
+        act[u] = s_up[jj] != 0;
+        a[u] = s_a[jj];
+        bb[u] = s_b[jj];
+        ip[u] = s_ip[jj];
       }
     }
     if constexpr (sizeof(T) == 8) {
@@ -445,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
     }
   }
   if (bt == 0) {
-    const TR beta = (TR)S.beta_prev;
+    const TR beta = (TR)beta64;
     C *p = reinterpret_cast<C *>(J.d) + (size_t)l * n;
 #pragma unroll
     for (int e = 0; e < kEpt; ++e) {
@@ -466,9 +425,10 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
 // advanced as usual. One thread owns one entry of one source and loops over all
 // shifts, so each moment entry has a single writer; the shift vectors x_j are never
 // stored. Shift vectors are FP64 (T = double) or FP32 (after the FP32 switch); the
-// seed and the moments stay FP64. g[k][j] = c[k][j] alpha_j (from the shift-scalar
-// kernel) and the shifts' beta_j, 1/pi_j are staged in LDS per chunk of shifts, and
-// the loads of several shifts are issued together.
+// seed and the moments stay FP64. Per chunk of shifts the block forms the shifts'
+// scalars (shift_step) and g[k][j] = c[k][j] alpha_j in LDS (the first block of the
+// source stages the new scalars for the commit), and the loads of several shifts
+// are issued together.
 // shift slots: an FP64 p_j fills its slot of n double2, an FP32 one the first half
 template <typename T>
 __device__ __forceinline__ double2 ld_shift(const void *base, size_t slot, int64_t n, int64_t i) {
@@ -487,38 +447,72 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_kernel(VecBatch B) {
   constexpr int JC = 32;  // shifts staged in LDS at once
   constexpr int UB = 8;   // shifts whose loads are issued together
   __shared__ double2 gs[MM][JC];       // g[k][j] of the chunk (zero rows from M on)
-  __shared__ double2 bs[JC], ips[JC];  // beta_j and 1/pi_j of the chunk
+  __shared__ double2 as[JC], bs[JC], ips[JC];  // alpha_j, beta_j and 1/pi_j of the chunk
   __shared__ int ups[JC];              // shift updated this iteration
+  __shared__ double red[kMomBlock / 64];
   const int b = blockIdx.x;
   const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
   const int lb = b - J.block_begin;
   const int l = lb / J.nblk_mom, vb = lb - l * J.nblk_mom;
-  const SeedState &S = J.seed[l];
-  if (!S.pending) return;
+  SeedState &S = J.seed[l];
+  if (S.done || !S.pending) return;  // uniform over the block
   const int64_t n = J.n;
   const int M = J.nmom, N = J.nshift;
   const int64_t i = (int64_t)vb * kMomBlock + threadIdx.x;
   const bool valid = i < n;
   const int64_t ii = valid ? i : 0;  // invalid lanes read entry 0 and store nothing
   const double2 rv = reinterpret_cast<const double2 *>(J.c)[(size_t)l * n + ii];
-  const ShiftState *sh = J.shift + (size_t)l * N;
+  ShiftState *sh = J.shift + (size_t)l * N;
   const size_t slot0 = (size_t)l * N;
-  const double2 *G = reinterpret_cast<const double2 *>(J.e) + (size_t)l * kMomRows * N;
+  // seed scalars of the iteration (every block, the same partials in the same order)
+  double v = 0.0;
+  const double *pr = J.rr_partial + (size_t)l * J.nrr;
+  for (int t = threadIdx.x; t < J.nrr; t += kMomBlock) v += pr[t];
+  const double rho_new = block_sum_all<kMomBlock / 64>(v, red);
+  const double alpha = S.alpha;
+  const double beta = rho_new / S.rho;
+  const double cc = alpha * S.beta_prev / S.alpha_prev;
+  const double sq = sqrt(rho_new);
+  const double thr = J.tol * S.vnorm;
+  const int it = S.iters;
+  const bool bad = !isfinite(rho_new) || !isfinite(beta);
+  if (vb == 0 && threadIdx.x == 0) {
+    S.rho_n = rho_new;
+    S.beta_n = beta;
+    S.brk_n = bad ? 1 : 0;
+    S.staged = 1;
+  }
+  if (bad) return;  // uniform: the commit ends this source's run
   double2 acc[MM];
 #pragma unroll
   for (int k = 0; k < MM; ++k) acc[k] = make_double2(0, 0);
   for (int j0 = 0; j0 < N; j0 += JC) {
     const int jn = min(JC, N - j0);
     __syncthreads();
+    for (int jj = threadIdx.x; jj < JC; jj += kMomBlock) {
+      ShiftStep o;
+      if (jj < jn) {
+        ShiftState &H = sh[j0 + jj];
+        o = shift_step(H, alpha, beta, cc, sq, thr);
+        if (vb == 0 && o.upd) {
+          H.pi_n = o.pn;
+          H.res_n = o.res;
+          H.frz_n = o.frz;
+          if (o.frz) H.conv_iter = it + 1;
+        }
+      } else {
+        o.a = o.b = o.ipi = make_double2(0, 0);
+        o.upd = 0;
+      }
+      ups[jj] = o.upd;
+      as[jj] = o.a;
+      bs[jj] = o.b;
+      ips[jj] = o.ipi;
+    }
+    __syncthreads();
     for (int t = threadIdx.x; t < MM * JC; t += kMomBlock) {
       const int k = t / JC, jj = t - k * JC;
-      gs[k][jj] = (k < M && jj < jn) ? G[(size_t)k * N + j0 + jj] : make_double2(0, 0);
-    }
-    for (int jj = threadIdx.x; jj < JC; jj += kMomBlock) {
-      const bool in = jj < jn;
-      ups[jj] = in ? sh[j0 + jj].upd : 0;
-      bs[jj] = in ? sh[j0 + jj].b : make_double2(0, 0);
-      ips[jj] = in ? sh[j0 + jj].ipi : make_double2(0, 0);
+      gs[k][jj] = (k < M && jj < jn && ups[jj]) ? cmul(J.mcoef[(size_t)k * N + j0 + jj], as[jj]) : make_double2(0, 0);
     }
     __syncthreads();
     for (int u0 = 0; u0 < JC; u0 += UB) {
@@ -561,8 +555,8 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_kernel(VecBatch B) {
   // seed direction p <- r + beta p
   double2 *p = reinterpret_cast<double2 *>(J.d) + (size_t)l * n;
   double2 pv = p[i];
-  pv.x = rv.x + S.beta_prev * pv.x;
-  pv.y = rv.y + S.beta_prev * pv.y;
+  pv.x = rv.x + beta * pv.x;
+  pv.y = rv.y + beta * pv.y;
   p[i] = pv;
 }
 
@@ -767,8 +761,9 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(const double2 *y, int n
 void launch_seed_alpha(const ScalarBatch &b, hipStream_t st) {
   hipLaunchKernelGGL(seed_alpha_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
 }
-void launch_shift_scalars(const ScalarBatch &b, hipStream_t st) {
-  hipLaunchKernelGGL(shift_scalars_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+void launch_commit(const DslashBatch &b, hipStream_t st) {
+  if (b.njobs <= 0) return;
+  hipLaunchKernelGGL(commit_kernel, dim3(b.njobs), dim3(kBlock), 0, st, b);
 }
 void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st) {
   if (prec == 0) hipLaunchKernelGGL(seed_r_update_kernel<double>, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
