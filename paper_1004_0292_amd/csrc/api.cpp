@@ -77,6 +77,7 @@ struct sscg_ctx {
   double stage_ms[ST_N] = {};
   int64_t stage_calls[ST_N] = {};
   std::vector<hipEvent_t> events;
+  std::vector<double> hstage;  // host staging of small matrices sent to the device
   // solve-loop graphs kept across solves (FP64 and FP32 phase), with the bytes of
   // everything the capture depended on; a solve of the same shape on the same
   // buffers replays them without capturing again
@@ -1389,18 +1390,26 @@ static int gram(sscg_ctx *c, const void *A, int na, const void *B, int nb, std::
   return SSCG_OK;
 }
 
-// C = A T with T (na x nb) row-major host complex
+// C = A T (and C2 = A2 T when A2 is given) with T (na x nb) row-major host complex.
+// Stream-ordered: T goes through the context's host staging vector, which the next
+// call only rewrites after a synchronisation (every caller reads a Gram matrix or
+// residuals back between two calls).
 static int basis_change(sscg_ctx *c, const void *A, int na, const std::vector<cd> &T, int nb, void *C,
-                        hipStream_t st) {
-  CHK(ensure(c, c->tmp, std::max<size_t>(c->tmp.bytes, (size_t)na * nb * sizeof(double2))));
-  std::vector<double> h(2 * (size_t)na * nb);
+                        hipStream_t st, const void *A2 = nullptr, void *C2 = nullptr) {
+  const size_t need = (size_t)na * nb * sizeof(double2);
+  if (c->tmp.bytes < need) {  // a kernel still reading the old buffer finishes first
+    HIPCHK(c, hipStreamSynchronize(st));
+    CHK(ensure(c, c->tmp, need));
+  }
+  std::vector<double> &h = c->hstage;
+  h.resize(2 * (size_t)na * nb);
   for (size_t k = 0; k < (size_t)na * nb; ++k) {
     h[2 * k] = T[k].real();
     h[2 * k + 1] = T[k].imag();
   }
   HIPCHK(c, hipMemcpyAsync(c->tmp.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
   launch_gemm_nn(A, c->n, na, (const double *)c->tmp.p, nb, C, c->n, c->n, st);
-  HIPCHK(c, hipStreamSynchronize(st));
+  if (A2) launch_gemm_nn(A2, c->n, na, (const double *)c->tmp.p, nb, C2, c->n, c->n, st);
   return SSCG_OK;
 }
 
@@ -1502,8 +1511,7 @@ static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, voi
   CHK(gram(c, c->Qbuf.p, r, c->AQbuf.p, r, At, st));
   std::vector<cd> Wr;
   eig_rowmajor(r, At, lam, Wr);
-  CHK(basis_change(c, c->Qbuf.p, r, Wr, r, Xd, st));
-  CHK(basis_change(c, c->AQbuf.p, r, Wr, r, AXd, st));
+  CHK(basis_change(c, c->Qbuf.p, r, Wr, r, Xd, st, c->AQbuf.p, AXd));
   (void)vec;
   return SSCG_OK;
 }

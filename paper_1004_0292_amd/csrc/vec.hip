@@ -25,6 +25,7 @@
 namespace sscg {
 
 static constexpr int kEpt = 2;  // complex entries per thread in streaming kernels
+static_assert(kBlock >= kMaxWBatch, "the shift update forms one shift's scalars per thread");
 
 template <int NW>
 __device__ __forceinline__ double block_sum_all(double v, double *sh) {
@@ -263,21 +264,27 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
       s_up[jj] = 1;
     }
   } else {
+    // the shift states and seed scalars are loaded before the reduction, so their
+    // latency overlaps that of the partials
+    const int jj0 = threadIdx.x;  // kBlock >= kMaxWBatch: one shift per thread at most
+    ShiftState Hl;
+    if (jj0 < j1 - j0) Hl = J.shift[(size_t)l * J.nshift + j0 + jj0];
+    const double alpha = S.alpha, rho = S.rho, bprev = S.beta_prev, aprev = S.alpha_prev, vnorm = S.vnorm;
+    const int it = S.iters;
     double v = 0.0;
     const double *pr = J.rr_partial + (size_t)l * J.nrr;
     for (int t = threadIdx.x; t < J.nrr; t += kBlock) v += pr[t];
     const double rho_new = block_sum_all<kBlock / 64>(v, red);
-    const double alpha = S.alpha;
-    beta64 = rho_new / S.rho;
-    const double c = alpha * S.beta_prev / S.alpha_prev;
+    beta64 = rho_new / rho;
+    const double c = alpha * bprev / aprev;
     const double sq = sqrt(rho_new);
-    const double thr = J.tol * S.vnorm;
-    const int it = S.iters;
+    const double thr = J.tol * vnorm;
     bad = !isfinite(rho_new) || !isfinite(beta64);
     const bool writer = vb == 0 && !bad;
-    for (int jj = threadIdx.x; jj < j1 - j0; jj += kBlock) {
+    if (jj0 < j1 - j0) {
+      const int jj = jj0;
       ShiftState &H = J.shift[(size_t)l * J.nshift + j0 + jj];
-      const ShiftStep o = shift_step(H, alpha, beta64, c, sq, thr);
+      const ShiftStep o = shift_step(Hl, alpha, beta64, c, sq, thr);
       s_a[jj] = o.a;
       s_b[jj] = o.b;
       s_ip[jj] = o.ipi;
@@ -464,17 +471,18 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_kernel(VecBatch B) {
   const double2 rv = reinterpret_cast<const double2 *>(J.c)[(size_t)l * n + ii];
   ShiftState *sh = J.shift + (size_t)l * N;
   const size_t slot0 = (size_t)l * N;
-  // seed scalars of the iteration (every block, the same partials in the same order)
+  // seed scalars of the iteration (every block, the same partials in the same order);
+  // the seed state is loaded before the reduction so the latencies overlap
+  const double alpha = S.alpha, rho = S.rho, bprev = S.beta_prev, aprev = S.alpha_prev, vnorm = S.vnorm;
+  const int it = S.iters;
   double v = 0.0;
   const double *pr = J.rr_partial + (size_t)l * J.nrr;
   for (int t = threadIdx.x; t < J.nrr; t += kMomBlock) v += pr[t];
   const double rho_new = block_sum_all<kMomBlock / 64>(v, red);
-  const double alpha = S.alpha;
-  const double beta = rho_new / S.rho;
-  const double cc = alpha * S.beta_prev / S.alpha_prev;
+  const double beta = rho_new / rho;
+  const double cc = alpha * bprev / aprev;
   const double sq = sqrt(rho_new);
-  const double thr = J.tol * S.vnorm;
-  const int it = S.iters;
+  const double thr = J.tol * vnorm;
   const bool bad = !isfinite(rho_new) || !isfinite(beta);
   if (vb == 0 && threadIdx.x == 0) {
     S.rho_n = rho_new;
