@@ -3,10 +3,10 @@
 // A context owns one lattice: its packed gauge field (FP64 18-real and, for the
 // mixed mode, FP32 18- or 12-real), and the solver workspaces, grown on demand
 // and reused. The shifted CG (Sec. 2.2) runs as a loop of grouped launches
-// (dslash, seed scalars, seed residual, shift scalars, fused shift update) whose
-// scalar state lives in device memory; the host only polls the per-source "done"
-// words every poll_every iterations, and the iterations in between replay as one
-// HIP graph. Several contexts can be solved together (sscg_batch_solve): each
+// (dslash, seed step length and residual, fused shift update with the shift
+// scalars) whose scalar state lives in device memory; the host only polls the
+// per-source "done" words every poll_every iterations, and the iterations in
+// between replay as one HIP graph. Several contexts can be solved together (sscg_batch_solve): each
 // stage is then one launch whose blocks are split over the problems.
 #include "sscg.h"
 
@@ -578,12 +578,10 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
 }
 
 // Per-stage timing with HIP events on the solver stream: an event is recorded
-// before each stage launch and the intervals are read at the next poll. Timing
-// runs use direct launches (event records inside captured graphs are not read
-// back reliably on this runtime).
-// Inside a captured graph the marks are event-record nodes, so the same
-// events are rewritten by every replay and read after it (graph replay keeps its
-// timing); the marks of direct launches are read and cleared at every poll.
+// before each stage launch (or, sampled, around two of them) and the intervals
+// are read at the next poll. Inside a captured graph the marks are event-record
+// nodes, so the same events are rewritten by every replay and read after it; the
+// marks of direct launches are read and cleared at every poll.
 struct Recorder {
   sscg_ctx *c;
   hipStream_t st;
@@ -657,8 +655,9 @@ struct Recorder {
   }
 };
 
-// The iteration after its dslash: step length, seed residual, shift scalars, shift
-// update. rec marks every stage; smp (when given) brackets the shift update alone.
+// The iteration after its dslash: step length, seed residual, (reliable update,)
+// shift update with the shift scalars. rec marks every stage; smp (when given)
+// brackets the shift update alone.
 static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, bool ru, int lr, const Tune &t,
                                   hipStream_t st, Recorder &rec, Recorder *smp) {
   const int sp = (prec == 1 && seed32) ? 1 : 0;  // seed precision
