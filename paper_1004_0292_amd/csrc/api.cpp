@@ -1379,7 +1379,11 @@ void sscg_default_ss_params(sscg_ss_params *p) {
 
 // C (na x nb, row-major on host, complex) = A^H B over n rows; A, B device column sets
 static int gram(sscg_ctx *c, const void *A, int na, const void *B, int nb, std::vector<cd> &out, hipStream_t st) {
-  const int nchunk = 64;
+  // row chunks: enough blocks to spread over the chip, at least 64 rows each (more
+  // chunks also mean more partials to sum afterwards)
+  const int tiles = gemm_cn_tiles(na, nb);
+  int nchunk = std::max(1, std::min(256, 512 / tiles));
+  nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(nchunk, c->n / 64));
   const size_t nout = (size_t)na * nb;
   CHK(ensure(c, c->small, nchunk * nout * 2 * sizeof(double) + nout * 2 * sizeof(double)));
   double *part = (double *)c->small.p;

@@ -7,63 +7,138 @@
 
 namespace sscg {
 
-constexpr int kT = 16;  // output tile edge for the Gram kernel
+// Both products tile their output in 64 x 64 blocks of 256 threads; a thread owns
+// 4 x 4 outputs (rows/columns t + 16 i), and operands pass through LDS in steps of 16
+// along the summed index, so every LDS read feeds four complex multiply-adds.
+constexpr int kGT = 64;  // output tile edge
+constexpr int kGK = 16;  // summed-index step staged in LDS
 
 // partial[chunk][a][b] = sum over the chunk's rows of conj(A[row][a]) B[row][b]
 __global__ __launch_bounds__(256) void gemm_cn_kernel(const double2 *__restrict__ A, int64_t lda, int na,
                                                       const double2 *__restrict__ B, int64_t ldb, int nb,
                                                       int64_t n, double2 *partial, int nchunk) {
-  __shared__ double2 As[kT][kT + 1];
-  __shared__ double2 Bs[kT][kT + 1];
-  const int tiles_b = (nb + kT - 1) / kT;
+  __shared__ double2 As[kGK][kGT + 1];
+  __shared__ double2 Bs[kGK][kGT + 1];
+  const int tiles_b = (nb + kGT - 1) / kGT;
   const int tile = blockIdx.x, chunk = blockIdx.y;
-  const int a0 = (tile / tiles_b) * kT, b0 = (tile % tiles_b) * kT;
-  const int tx = threadIdx.x & (kT - 1), ty = threadIdx.x / kT;
+  const int a0 = (tile / tiles_b) * kGT, b0 = (tile % tiles_b) * kGT;
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
   const int64_t rows_per = (n + nchunk - 1) / nchunk;
   const int64_t r_begin = (int64_t)chunk * rows_per;
   const int64_t r_end = min(n, r_begin + rows_per);
-  double2 acc = make_double2(0, 0);
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += kT) {
-    // load: thread (ty, tx) fetches row r0 + tx of column a0 + ty (and b0 + ty)
-    const int64_t row = r0 + tx;
-    const bool rv = row < r_end;
-    As[ty][tx] = (rv && a0 + ty < na) ? A[(size_t)(a0 + ty) * lda + row] : make_double2(0, 0);
-    Bs[ty][tx] = (rv && b0 + ty < nb) ? B[(size_t)(b0 + ty) * ldb + row] : make_double2(0, 0);
-    __syncthreads();
+  double2 acc[4][4];
 #pragma unroll
-    for (int k = 0; k < kT; ++k) cfmac(acc, As[ty][k], Bs[tx][k]);
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0, 0);
+  // loader: row (t & 15) of columns (t >> 4) + 16 q: 16 threads read 16 consecutive
+  // rows; the next step's values are loaded into registers while this step computes
+  const int lrow = t & 15, lcol = t >> 4;
+  double2 pa[4], pb[4];
+  auto fetch = [&](int64_t r0) {
+    const int64_t row = r0 + lrow;
+    const bool rv = row < r_end;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int col = lcol + 16 * q;
+      pa[q] = (rv && a0 + col < na) ? A[(size_t)(a0 + col) * lda + row] : make_double2(0, 0);
+      pb[q] = (rv && b0 + col < nb) ? B[(size_t)(b0 + col) * ldb + row] : make_double2(0, 0);
+    }
+  };
+  if (r_begin < r_end) fetch(r_begin);
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[lrow][lcol + 16 * q] = pa[q];
+      Bs[lrow][lcol + 16 * q] = pb[q];
+    }
+    __syncthreads();
+    if (r0 + kGK < r_end) fetch(r0 + kGK);
+#pragma unroll 4
+    for (int k = 0; k < kGK; ++k) {
+      double2 av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[k][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[k][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cfmac(acc[i][j], av[i], bv[j]);
+    }
     __syncthreads();
   }
-  const int a = a0 + ty, b = b0 + tx;
-  if (a < na && b < nb) partial[((size_t)chunk * na + a) * nb + b] = acc;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = a0 + ty + 16 * i, b = b0 + tx + 16 * j;
+      if (a < na && b < nb) partial[((size_t)chunk * na + a) * nb + b] = acc[i][j];
+    }
 }
 
-// C[:, b] = sum_a A[:, a] T[a][b], T row-major (na x nb) in device memory.
-constexpr int kNB = 16;
+// C[:, b] = sum_a A[:, a] T[a][b], T row-major (na x nb) in device memory. Block:
+// 64 rows x 64 columns of C; thread t owns rows (t & 15) + 16 r and columns
+// (t >> 4) + 16 c.
 __global__ __launch_bounds__(256) void gemm_nn_kernel(const double2 *__restrict__ A, int64_t lda, int na,
                                                       const double2 *__restrict__ T, int nb,
                                                       double2 *__restrict__ C, int64_t ldc, int64_t n) {
-  extern __shared__ double2 Ts[];  // [na][kNB]
-  const int b0 = blockIdx.y * kNB;
-  const int nbl = min(kNB, nb - b0);
-  for (int t = threadIdx.x; t < na * kNB; t += 256) {
-    const int a = t / kNB, bb = t - a * kNB;
-    Ts[t] = bb < nbl ? T[(size_t)a * nb + b0 + bb] : make_double2(0, 0);
+  __shared__ double2 As[kGK][kGT + 1];  // [a][row]
+  __shared__ double2 Ts[kGK][kGT + 1];  // [a][column]
+  const int64_t i0 = (int64_t)blockIdx.x * kGT;
+  const int b0 = blockIdx.y * kGT;
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  double2 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = make_double2(0, 0);
+  // loader: 64 consecutive rows (or columns) of 4 values of the summed index; the
+  // next step's values are loaded into registers while this step computes
+  const int lx = t & 63, lk = t >> 6;
+  double2 pa[4], pt[4];
+  auto fetch = [&](int ka) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = ka + lk + 4 * q;
+      const int64_t row = i0 + lx;
+      pa[q] = (a < na && row < n) ? A[(size_t)a * lda + row] : make_double2(0, 0);
+      pt[q] = (a < na && b0 + lx < nb) ? T[(size_t)a * nb + b0 + lx] : make_double2(0, 0);
+    }
+  };
+  fetch(0);
+  for (int ka = 0; ka < na; ka += kGK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[lk + 4 * q][lx] = pa[q];
+      Ts[lk + 4 * q][lx] = pt[q];
+    }
+    __syncthreads();
+    if (ka + kGK < na) fetch(ka + kGK);
+#pragma unroll 4
+    for (int k = 0; k < kGK; ++k) {
+      double2 av[4], tv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[r] = As[k][tx + 16 * r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) tv[c] = Ts[k][ty + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cfma(acc[r][c], av[r], tv[c]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  double2 acc[kNB];
 #pragma unroll
-  for (int bb = 0; bb < kNB; ++bb) acc[bb] = make_double2(0, 0);
-  for (int a = 0; a < na; ++a) {
-    const double2 av = A[(size_t)a * lda + i];
+  for (int c = 0; c < 4; ++c) {
+    const int b = b0 + ty + 16 * c;
+    if (b >= nb) continue;
 #pragma unroll
-    for (int bb = 0; bb < kNB; ++bb) cfma(acc[bb], av, Ts[a * kNB + bb]);
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = i0 + tx + 16 * r;
+      if (row < n) C[(size_t)b * ldc + row] = acc[r][c];
+    }
   }
-#pragma unroll
-  for (int bb = 0; bb < kNB; ++bb)
-    if (bb < nbl) C[(size_t)(b0 + bb) * ldc + i] = acc[bb];
 }
 
 __global__ void colscale_kernel(double2 *A, int64_t lda, const double *scale, int64_t n) {
@@ -105,28 +180,36 @@ __global__ __launch_bounds__(256) void resid_cols_kernel(const double2 *AX, cons
   }
 }
 
-// out[o] = sum_k partial[k][o] for o < nout (partials laid out [nchunk][nout]); doubles
-__global__ void reduce_partials_kernel(const double *partial, int nchunk, int nout, double *out) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= nout) return;
+// out[o] = sum_k partial[k][o] for o < nout (partials laid out [nchunk][nout]); doubles.
+// Block of 256 threads per 64 outputs: wavefront w sums the chunks k = w mod 4 (four
+// independent load streams per output), then the four sums are added in a fixed order.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double *partial, int nchunk, int nout,
+                                                              double *out) {
+  __shared__ double red[4][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int o = blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int k = 0; k < nchunk; ++k) s += partial[(size_t)k * nout + o];
-  out[o] = s;
+  if (o < nout)
+    for (int k = w; k < nchunk; k += 4) s += partial[(size_t)k * nout + o];
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && o < nout) out[o] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 void launch_gemm_cn(const void *A, int64_t lda, int na, const void *B, int64_t ldb, int nb, int64_t n,
                     double *partial, int nchunk, hipStream_t st) {
-  const int tiles = ((na + kT - 1) / kT) * ((nb + kT - 1) / kT);
+  const int tiles = gemm_cn_tiles(na, nb);
   hipLaunchKernelGGL(gemm_cn_kernel, dim3(tiles, nchunk), dim3(256), 0, st, (const double2 *)A, lda, na,
                      (const double2 *)B, ldb, nb, n, (double2 *)partial, nchunk);
 }
 void launch_gemm_nn(const void *A, int64_t lda, int na, const double *T, int nb, void *C, int64_t ldc,
                     int64_t n, hipStream_t st) {
-  const dim3 grid((unsigned)((n + 255) / 256), (nb + kNB - 1) / kNB);
-  const size_t shm = (size_t)na * kNB * sizeof(double2);
-  hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(256), shm, st, (const double2 *)A, lda, na,
-                     (const double2 *)T, nb, (double2 *)C, ldc, n);
+  if (n <= 0 || na <= 0 || nb <= 0) return;
+  const dim3 grid((unsigned)((n + kGT - 1) / kGT), (nb + kGT - 1) / kGT);
+  hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(256), 0, st, (const double2 *)A, lda, na, (const double2 *)T, nb,
+                     (double2 *)C, ldc, n);
 }
+int gemm_cn_tiles(int na, int nb) { return ((na + kGT - 1) / kGT) * ((nb + kGT - 1) / kGT); }
 void launch_colscale(void *A, int64_t lda, int na, const double *scale, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(colscale_kernel, dim3((unsigned)((n + 255) / 256), na), dim3(256), 0, st, (double2 *)A,
                      lda, scale, n);
@@ -137,8 +220,8 @@ void launch_resid_cols(const void *AX, const void *X, int64_t ld, int ncol, cons
                      (const double2 *)X, ld, ncol, lam, n, partial, nchunk);
 }
 void launch_reduce_partials(const double *partial, int nchunk, int nout, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 255) / 256), dim3(256), 0, st, partial, nchunk,
-                     nout, out);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 63) / 64), dim3(256), 0, st, partial, nchunk, nout,
+                     out);
 }
 
 }  // namespace sscg

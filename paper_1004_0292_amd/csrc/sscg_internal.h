@@ -306,6 +306,8 @@ void launch_gemm_cn(const void *A, int64_t lda, int na, const void *B, int64_t l
                     int64_t n, double *partial, int nchunk, hipStream_t st);
 void launch_gemm_nn(const void *A, int64_t lda, int na, const double *T_dev, int nb,
                     void *C, int64_t ldc, int64_t n, hipStream_t st);
+// output tiles (blocks per chunk) of launch_gemm_cn
+int gemm_cn_tiles(int na, int nb);
 void launch_colscale(void *A, int64_t lda, int na, const double *scale_dev, int64_t n, hipStream_t st);
 void launch_resid_cols(const void *AX, const void *X, int64_t ld, int ncol, const double *lam_dev,
                        int64_t n, double *partial, int nchunk, hipStream_t st);
