@@ -314,6 +314,7 @@ static int nblk_site(const sscg_ctx *c, int bs, int ct, int ty, int tz) {
   return (c->dims[1] / ty) * (c->dims[2] / tz) * ((Lt + ct - 1) / ct);
 }
 static int nblk_vec(const sscg_ctx *c) { return (int)((c->n + kBlock * kEptHost - 1) / (kBlock * kEptHost)); }
+constexpr int kMaxRR = 256;  // blocks (and <r, r> partials) per source of the seed passes
 
 // FP64 dslash of nsrc planar vectors: out = A in (mode 0) or sigma in - A in (mode 1)
 static void dslash_with(sscg_ctx *c, const Tune &t, const void *in, void *out, int nsrc, int prec, int mode,
@@ -496,6 +497,7 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
     sscg_ctx *c = P[i].c;
     const int L = P[i].L, N = P[i].N;
     const int nbs = nblk_site(c, t.bs, pl.ct, tys[i], tzs[i]), nbv = nblk_vec(c);
+    const int nbr = std::min(nbv, kMaxRR);
     const int groups = (L + t.nr - 1) / t.nr;
     SeedState *seed = (SeedState *)c->seed.p;
     ShiftState *shift = (ShiftState *)c->shift.p;
@@ -532,18 +534,24 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
       j.a = a; j.b = b; j.c = cc; j.d = d; j.e = nullptr; j.partial = (double *)c->rr_part.p;
       j.seed = seed; j.shift = shift; j.n = c->n; j.nsrc = L; j.nshift = N; j.nblk_vec = nbv;
       j.block_begin = begin; j.nblocks = nblocks; j.wbatch = t.wbatch; j.border = t.border;
-      j.rr_partial = (const double *)c->rr_part.p; j.nrr = nbv; j.tol = o.tol;
+      j.rr_partial = (const double *)c->rr_part.p; j.nrr = nbr; j.tol = o.tol;
     };
-    mk_v(pl.r64.job[i], c->r64.p, c->q64.p, nullptr, nullptr, bv, L * nbv);
-    mk_v(pl.r32.job[i], c->r32.p, c->q32.p, c->xpart32.p, c->p32.p, bv, L * nbv);
+    // the seed passes run at most kMaxRR blocks per source (strided over the
+    // entries), so the <r, r> partials every shift-update block sums stay few
+    auto seed_pass = [&](VecJob &j, void *a, void *b, void *cc, void *d) {
+      mk_v(j, a, b, cc, d, bv, L * nbr);
+      j.nblk_vec = nbr;
+    };
+    seed_pass(pl.r64.job[i], c->r64.p, c->q64.p, nullptr, nullptr);
+    seed_pass(pl.r32.job[i], c->r32.p, c->q32.p, c->xpart32.p, c->p32.p);
     if (pl.fuse_alpha)
       for (VecJob *rj : {&pl.r64.job[i], &pl.r32.job[i]}) {
         rj->npq = (c->V + 63) / 64;
         rj->pq_partial = (const double *)c->pq_part.p;
       }
-    mk_v(pl.fold_seed.job[i], c->xpart64.p, c->xpart32.p, nullptr, nullptr, bv, L * nbv);
-    mk_v(pl.rel.job[i], c->rbase.p, c->q64.p, c->r64.p, c->r32.p, bv, L * nbv);
-    bv += L * nbv;
+    seed_pass(pl.fold_seed.job[i], c->xpart64.p, c->xpart32.p, nullptr, nullptr);
+    seed_pass(pl.rel.job[i], c->rbase.p, c->q64.p, c->r64.p, c->r32.p);
+    bv += L * nbr;
     const int nbatch = (N + t.wbatch - 1) / t.wbatch;
     mk_v(pl.u64.job[i], P[i].y, c->W.p, c->r64.p, c->p64.p, bu, L * nbatch * nbv);
     mk_v(pl.u32.job[i], P[i].y, c->W.p, c->r32.p, c->p32.p, bu, L * nbatch * nbv);

@@ -139,23 +139,27 @@ __global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
   C *xp = J.c ? reinterpret_cast<C *>(J.c) + (size_t)l * J.n : nullptr;
   const C *p = J.d ? reinterpret_cast<const C *>(J.d) + (size_t)l * J.n : nullptr;
   double acc = 0.0;
-  const int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x;
+  // chunks of kBlock kEpt entries, strided by the source's block count (at most
+  // kMaxRR blocks per source, so the consumers of the partials sum few of them)
+  const int64_t stride = (int64_t)J.nblk_vec * kBlock * kEpt;
+  for (int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x; base - threadIdx.x < J.n; base += stride) {
 #pragma unroll
-  for (int e = 0; e < kEpt; ++e) {
-    const int64_t i = base + (int64_t)e * kBlock;
-    if (i < J.n) {
-      C rv = r[i];
-      const C qv = q[i];
-      rv.x -= alpha * qv.x;
-      rv.y -= alpha * qv.y;
-      r[i] = rv;
-      acc += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
-      if (xp) {
-        C xv = xp[i];
-        const C pv = p[i];
-        xv.x += alpha * pv.x;
-        xv.y += alpha * pv.y;
-        xp[i] = xv;
+    for (int e = 0; e < kEpt; ++e) {
+      const int64_t i = base + (int64_t)e * kBlock;
+      if (i < J.n) {
+        C rv = r[i];
+        const C qv = q[i];
+        rv.x -= alpha * qv.x;
+        rv.y -= alpha * qv.y;
+        r[i] = rv;
+        acc += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
+        if (xp) {
+          C xv = xp[i];
+          const C pv = p[i];
+          xv.x += alpha * pv.x;
+          xv.y += alpha * pv.y;
+          xp[i] = xv;
+        }
       }
     }
   }
@@ -583,15 +587,17 @@ __global__ __launch_bounds__(kBlock) void reliable_residual_kernel(VecBatch B) {
   double2 *r64 = reinterpret_cast<double2 *>(J.c) + off;
   float2 *r32 = reinterpret_cast<float2 *>(J.d) + off;
   double acc = 0.0;
-  const int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x;
+  const int64_t stride = (int64_t)J.nblk_vec * kBlock * kEpt;
+  for (int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x; base - threadIdx.x < J.n; base += stride) {
 #pragma unroll
-  for (int e = 0; e < kEpt; ++e) {
-    const int64_t i = base + (int64_t)e * kBlock;
-    if (i < J.n) {
-      const double2 rv = rb[i] - q[i];
-      r64[i] = rv;
-      r32[i] = make_float2((float)rv.x, (float)rv.y);
-      acc += rv.x * rv.x + rv.y * rv.y;
+    for (int e = 0; e < kEpt; ++e) {
+      const int64_t i = base + (int64_t)e * kBlock;
+      if (i < J.n) {
+        const double2 rv = rb[i] - q[i];
+        r64[i] = rv;
+        r32[i] = make_float2((float)rv.x, (float)rv.y);
+        acc += rv.x * rv.x + rv.y * rv.y;
+      }
     }
   }
   const double tot = block_sum_all<kBlock / 64>(acc, red);
@@ -608,17 +614,19 @@ __global__ __launch_bounds__(kBlock) void fold_seed_kernel(VecBatch B) {
   const size_t off = (size_t)l * J.n;
   double2 *x64 = reinterpret_cast<double2 *>(J.a) + off;
   float2 *x32 = reinterpret_cast<float2 *>(J.b) + off;
-  const int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x;
+  const int64_t stride = (int64_t)J.nblk_vec * kBlock * kEpt;
+  for (int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x; base - threadIdx.x < J.n; base += stride) {
 #pragma unroll
-  for (int e = 0; e < kEpt; ++e) {
-    const int64_t i = base + (int64_t)e * kBlock;
-    if (i < J.n) {
-      const float2 xv = x32[i];
-      double2 xm = x64[i];
-      xm.x += (double)xv.x;
-      xm.y += (double)xv.y;
-      x64[i] = xm;
-      x32[i] = make_float2(0.f, 0.f);
+    for (int e = 0; e < kEpt; ++e) {
+      const int64_t i = base + (int64_t)e * kBlock;
+      if (i < J.n) {
+        const float2 xv = x32[i];
+        double2 xm = x64[i];
+        xm.x += (double)xv.x;
+        xm.y += (double)xv.y;
+        x64[i] = xm;
+        x32[i] = make_float2(0.f, 0.f);
+      }
     }
   }
 }
