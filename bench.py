@@ -455,7 +455,7 @@ def main():
         "timing": ("graph replay, no events" if args.no_events else
                    "direct launches, HIP events around every launch" if args.sample_every == 1 else
                    f"graph replay, HIP event-record nodes around the dslash and shift update of every "
-                   f"{args.sample_every}th iteration"),
+                   f"{args.sample_every}th iteration (offset {args.sample_every // 2} in each poll interval)"),
         "value_without_events": round(graph_value, 1) if graph_value else None,
     }
     if not args.no_compare:

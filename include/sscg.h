@@ -255,9 +255,10 @@ int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs);
  *   level 1  every launch of the solve loop is bracketed by events, and the loop runs
  *            its launches directly (no graph replay);
  *   level k > 1  graph replay stays on, and the dslash (stage 0) and the shift update
- *            (stage 4) of every k-th iteration of each poll interval are bracketed by
- *            event-record nodes in the graph; the other stages are not timed. Stage
- *            averages are then over that sample, at a small cost to the loop.
+ *            (stage 4) of the iterations i of each poll interval with i % k == k / 2 are
+ *            bracketed by event-record nodes in the graph; the other stages are not
+ *            timed. Stage averages are then over that sample, at a small cost to the
+ *            loop.
  * A level below 0 is SSCG_EINVAL. When timing is on, sscg_apply_A also adds its dslash
  * time to stage 0 (and blocks until it ends). */
 int sscg_set_profiling(sscg_ctx *ctx, int32_t level);

@@ -699,12 +699,13 @@ static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, boo
 // shift partials into the FP64 solutions in both FP32 modes).
 // Timing marks: with every == 1 each launch is bracketed (the marks chain, one
 // interval per stage); with every == k > 1 only the dslash and the shift update of
-// iterations it % k == 0 are bracketed (start and stop marks).
+// iterations it % k == k / 2 are bracketed (start and stop marks; the first iteration
+// after a poll, whose launches start on an idle device, is not sampled).
 static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru, int lr, const Tune &t,
                              hipStream_t st, Recorder &rec, int it = 0, int every = 1) {
   const int sp = (prec == 1 && seed32) ? 1 : 0;  // seed precision
   if (every > 1) {
-    const bool smp = it % every == 0;
+    const bool smp = it % every == every / 2;
     Recorder off{rec.c, st, false, {}, nullptr};
     if (smp) rec.mark(ST_DSLASH);
     launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, pl.ct, st);
@@ -1028,9 +1029,11 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     cap.on = c0->profiling > 0;
     cap.in_graph = true;
     cap.stages.clear();
-    while (cap.on && cg.ev.size() < (size_t)len * (ST_N + 1) + 1) {  // events exist before capture
+    // events exist before capture; they only time, so they skip the system-scope
+    // release (cache write-back) an event normally carries, which shortens the node
+    while (cap.on && cg.ev.size() < (size_t)len * (ST_N + 1) + 1) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) {
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
         (void)hipGetLastError();
         cap.on = false;
         break;

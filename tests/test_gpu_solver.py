@@ -103,7 +103,7 @@ def test_profiling_levels(sscg, prob):
     launched = calls1[0]            # one dslash per launched iteration
     assert launched >= int(np.max(r_ref.iters)) and calls1[4] == launched
     assert calls1[2] == launched and calls1[3] == 0 and np.all(ms1[[0, 2, 4]] > 0)
-    # every 5th iteration of each 50-iteration poll interval
+    # iterations 2, 7, 12, ... of each 50-iteration poll interval
     assert calls5[0] == calls5[4] == launched // 5 and np.all(calls5[[1, 2, 3, 5]] == 0)
     for s in (0, 4):
         a1, a5 = ms1[s] / calls1[s], ms5[s] / calls5[s]
