@@ -1449,6 +1449,35 @@ static void eig_rowmajor(int n, const std::vector<cd> &A, std::vector<double> &e
     for (int i = 0; i < n; ++i) W[(size_t)i * n + k] = cd(vv[2 * (i + (size_t)n * k)], vv[2 * (i + (size_t)n * k) + 1]);
 }
 
+// Upper Cholesky factor of a Hermitian positive definite row-major n x n matrix,
+// G = R^H R, and its inverse Rinv (row-major, upper triangular). Returns false if a
+// pivot is not positive.
+static bool chol_inverse_upper(int n, const std::vector<cd> &G, std::vector<cd> &Rinv) {
+  std::vector<cd> R((size_t)n * n, cd(0, 0));
+  for (int j = 0; j < n; ++j) {
+    double d = G[(size_t)j * n + j].real();
+    for (int k = 0; k < j; ++k) d -= std::norm(R[(size_t)k * n + j]);
+    if (!(d > 0.0)) return false;
+    const double rjj = std::sqrt(d);
+    R[(size_t)j * n + j] = rjj;
+    for (int i = j + 1; i < n; ++i) {
+      cd v = G[(size_t)j * n + i];
+      for (int k = 0; k < j; ++k) v -= std::conj(R[(size_t)k * n + j]) * R[(size_t)k * n + i];
+      R[(size_t)j * n + i] = v / rjj;
+    }
+  }
+  Rinv.assign((size_t)n * n, cd(0, 0));
+  for (int i = 0; i < n; ++i) {  // column i of R^-1 by back substitution
+    Rinv[(size_t)i * n + i] = 1.0 / R[(size_t)i * n + i];
+    for (int j = i - 1; j >= 0; --j) {
+      cd v = 0;
+      for (int k = j + 1; k <= i; ++k) v += R[(size_t)j * n + k] * Rinv[(size_t)k * n + i];
+      Rinv[(size_t)j * n + i] = -v / R[(size_t)j * n + j];
+    }
+  }
+  return true;
+}
+
 static int apply_A_planar(sscg_ctx *c, const void *X, void *AX, int ncol, hipStream_t st) {
   const size_t vec = c->n * sizeof(double2);
   for (int k = 0; k < ncol; k += 8) {
@@ -1518,12 +1547,18 @@ static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, voi
   CHK(basis_change(c, S, ncol, T1, r, c->AQbuf.p, st));  // Q1 (held in AQbuf for now)
   std::vector<cd> G2;
   CHK(gram(c, c->AQbuf.p, r, c->AQbuf.p, r, G2, st));
-  std::vector<double> ev2;
-  std::vector<cd> W2;
-  eig_rowmajor(r, G2, ev2, W2);
-  std::vector<cd> T2((size_t)r * r);
-  for (int a = 0; a < r; ++a)
-    for (int q = 0; q < r; ++q) T2[(size_t)a * r + q] = W2[(size_t)a * r + q] / std::sqrt(std::max(ev2[q], 1e-300));
+  // second pass: Q1 is orthonormal up to rounding, so its Gram matrix is close to I and
+  // a Cholesky factor G2 = R^H R gives Q = Q1 R^-1 (an eigen-decomposition of G2 is
+  // the fallback if a pivot is not positive)
+  std::vector<cd> T2;
+  if (!chol_inverse_upper(r, G2, T2)) {
+    std::vector<double> ev2;
+    std::vector<cd> W2;
+    eig_rowmajor(r, G2, ev2, W2);
+    T2.assign((size_t)r * r, cd(0, 0));
+    for (int a = 0; a < r; ++a)
+      for (int q = 0; q < r; ++q) T2[(size_t)a * r + q] = W2[(size_t)a * r + q] / std::sqrt(std::max(ev2[q], 1e-300));
+  }
   CHK(basis_change(c, c->AQbuf.p, r, T2, r, c->Qbuf.p, st));  // Q
   CHK(apply_A_planar(c, c->Qbuf.p, c->AQbuf.p, r, st));         // A Q
   std::vector<cd> At;

@@ -109,6 +109,27 @@ __global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
   const int l = lb / J.nblk_vec, vb = lb - l * J.nblk_vec;
   SeedState &S = J.seed[l];
   if (S.done) return;
+  C *r = reinterpret_cast<C *>(J.a) + (size_t)l * J.n;
+  const C *q = reinterpret_cast<const C *>(J.b) + (size_t)l * J.n;
+  C *xp = J.c ? reinterpret_cast<C *>(J.c) + (size_t)l * J.n : nullptr;
+  const C *p = J.d ? reinterpret_cast<const C *>(J.d) + (size_t)l * J.n : nullptr;
+  // chunks of kBlock kEpt entries, strided by the source's block count (at most
+  // kMaxRR blocks per source, so the consumers of the partials sum few of them); the
+  // first chunk is loaded before the step length is formed, so the two latencies overlap
+  const int64_t base0 = (int64_t)vb * kBlock * kEpt + threadIdx.x;
+  C r0[kEpt], q0[kEpt], x0[kEpt], p0[kEpt];
+#pragma unroll
+  for (int e = 0; e < kEpt; ++e) {
+    const int64_t i = base0 + (int64_t)e * kBlock;
+    if (i < J.n) {
+      r0[e] = r[i];
+      q0[e] = q[i];
+      if (xp) {
+        x0[e] = xp[i];
+        p0[e] = p[i];
+      }
+    }
+  }
   double alpha64;
   if (J.npq > 0) {
     // the step length of the alpha kernel, formed by every block from the same
@@ -134,33 +155,29 @@ __global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
     alpha64 = S.alpha;
   }
   const T alpha = (T)alpha64;
-  C *r = reinterpret_cast<C *>(J.a) + (size_t)l * J.n;
-  const C *q = reinterpret_cast<const C *>(J.b) + (size_t)l * J.n;
-  C *xp = J.c ? reinterpret_cast<C *>(J.c) + (size_t)l * J.n : nullptr;
-  const C *p = J.d ? reinterpret_cast<const C *>(J.d) + (size_t)l * J.n : nullptr;
   double acc = 0.0;
-  // chunks of kBlock kEpt entries, strided by the source's block count (at most
-  // kMaxRR blocks per source, so the consumers of the partials sum few of them)
+  auto update = [&](int64_t i, C rv, C qv, C xv, C pv) {
+    rv.x -= alpha * qv.x;
+    rv.y -= alpha * qv.y;
+    r[i] = rv;
+    acc += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
+    if (xp) {
+      xv.x += alpha * pv.x;
+      xv.y += alpha * pv.y;
+      xp[i] = xv;
+    }
+  };
+#pragma unroll
+  for (int e = 0; e < kEpt; ++e) {
+    const int64_t i = base0 + (int64_t)e * kBlock;
+    if (i < J.n) update(i, r0[e], q0[e], x0[e], p0[e]);
+  }
   const int64_t stride = (int64_t)J.nblk_vec * kBlock * kEpt;
-  for (int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x; base - threadIdx.x < J.n; base += stride) {
+  for (int64_t base = base0 + stride; base - threadIdx.x < J.n; base += stride) {
 #pragma unroll
     for (int e = 0; e < kEpt; ++e) {
       const int64_t i = base + (int64_t)e * kBlock;
-      if (i < J.n) {
-        C rv = r[i];
-        const C qv = q[i];
-        rv.x -= alpha * qv.x;
-        rv.y -= alpha * qv.y;
-        r[i] = rv;
-        acc += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
-        if (xp) {
-          C xv = xp[i];
-          const C pv = p[i];
-          xv.x += alpha * pv.x;
-          xv.y += alpha * pv.y;
-          xp[i] = xv;
-        }
-      }
+      if (i < J.n) update(i, r[i], q[i], xp ? xp[i] : C{}, xp ? p[i] : C{});
     }
   }
   const double tot = block_sum_all<kBlock / 64>(acc, red);
