@@ -573,6 +573,7 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
   pl.m64.njobs = pl.m32.njobs = np;
   pl.m64.total_blocks = pl.m32.total_blocks = bm;
   pl.d64.njobs = pl.d32.njobs = pl.dru.njobs = np;
+  pl.d64.commit = pl.d32.commit = 1;  // the iteration's first launch commits the previous one
   pl.d64.total_blocks = pl.d32.total_blocks = bd;
   pl.dru.total_blocks = bdru;
   pl.alpha.njobs = np;

@@ -26,6 +26,15 @@
 
 namespace sscg {
 
+// A solve-loop launch carries one extra block (the last) that commits the staged
+// state of the previous iteration of every job; the other blocks read only the done
+// flags, so at worst they compute a finished source once more, whose result is not
+// used.
+__device__ __forceinline__ void commit_batch(const DslashBatch &B) {
+  for (int k = 0; k < B.njobs; ++k)
+    if (B.job[k].shift) commit_states(B.job[k].seed, B.job[k].shift, B.job[k].nsrc, B.job[k].nshift);
+}
+
 __device__ __forceinline__ int xcd_remap_block(int b, int nb) {
   const int q = nb >> 3, rem = nb & 7;
   const int x = b & 7, local = b >> 3;
@@ -159,7 +168,11 @@ template <typename T, int NR, int LR, int BS>
 __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap) {
   using C = V2<T>;
   int b = blockIdx.x;
-  if (xcd_remap) b = xcd_remap_block(b, gridDim.x);
+  if (B.commit && b == B.total_blocks) {
+    commit_batch(B);
+    return;
+  }
+  if (xcd_remap) b = xcd_remap_block(b, B.total_blocks);
   int begins[kMaxJobs];
 #pragma unroll
   for (int k = 0; k < kMaxJobs; ++k) begins[k] = B.job[k].block_begin;
@@ -180,10 +193,6 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
   }
   const int l0 = group * NR;
   const int nvalid = min(NR, J.nsrc - l0);
-  // the first block of a solve-loop launch commits the previous iteration's staged
-  // state (the other blocks read only the done flags: at worst they compute a
-  // finished source once more, whose result is not used)
-  if (lb == 0 && J.shift) commit_states(J.seed, J.shift, J.nsrc, J.nshift);
   if (J.seed) {
     bool all_done = true;
     for (int r = 0; r < nvalid; ++r) all_done &= (J.seed[l0 + r].done != 0);
@@ -275,7 +284,11 @@ __global__ __launch_bounds__(256) void dslash_split_kernel(DslashBatch B, int xc
   __shared__ C red[4][NR * 12][64];
   __shared__ double dsum[4][NR];
   int b = blockIdx.x;
-  if (xcd_remap) b = xcd_remap_block(b, gridDim.x);
+  if (B.commit && b == B.total_blocks) {
+    commit_batch(B);
+    return;
+  }
+  if (xcd_remap) b = xcd_remap_block(b, B.total_blocks);
   int begins[kMaxJobs];
 #pragma unroll
   for (int k = 0; k < kMaxJobs; ++k) begins[k] = B.job[k].block_begin;
@@ -286,10 +299,6 @@ __global__ __launch_bounds__(256) void dslash_split_kernel(DslashBatch B, int xc
   const int sblk = lb / groups, group = lb - sblk * groups;
   const int l0 = group * NR;
   const int nvalid = min(NR, J.nsrc - l0);
-  // the first block of a solve-loop launch commits the previous iteration's staged
-  // state (the other blocks read only the done flags: at worst they compute a
-  // finished source once more, whose result is not used)
-  if (lb == 0 && J.shift) commit_states(J.seed, J.shift, J.nsrc, J.nshift);
   if (J.seed) {
     bool all_done = true;
     for (int r = 0; r < nvalid; ++r) all_done &= (J.seed[l0 + r].done != 0);
@@ -459,7 +468,11 @@ __global__ __launch_bounds__(MAXBS) void dslash_tile_kernel(DslashBatch B, int x
   extern __shared__ __align__(16) unsigned char dslash_lds[];
   C *lds = reinterpret_cast<C *>(dslash_lds);
   int b = blockIdx.x;
-  if (xcd_remap) b = xcd_remap_block(b, gridDim.x);
+  if (B.commit && b == B.total_blocks) {
+    commit_batch(B);
+    return;
+  }
+  if (xcd_remap) b = xcd_remap_block(b, B.total_blocks);
   int begins[kMaxJobs];
 #pragma unroll
   for (int k = 0; k < kMaxJobs; ++k) begins[k] = B.job[k].block_begin;
@@ -496,10 +509,6 @@ __global__ __launch_bounds__(MAXBS) void dslash_tile_kernel(DslashBatch B, int x
   const int t0 = range * J.ct, t1 = min(t0 + J.ct, Lt);
   const int l0 = group * NR;
   const int nvalid = min(NR, J.nsrc - l0);
-  // the first block of a solve-loop launch commits the previous iteration's staged
-  // state (the other blocks read only the done flags: at worst they compute a
-  // finished source once more, whose result is not used)
-  if (lb == 0 && J.shift) commit_states(J.seed, J.shift, J.nsrc, J.nshift);
   if (J.seed) {
     bool all_done = true;
     for (int r = 0; r < nvalid; ++r) all_done &= (J.seed[l0 + r].done != 0);
@@ -639,7 +648,7 @@ static void launch_tile(const DslashBatch &b, int bs, size_t shm, int xcd, hipSt
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     raised = true;
   }
-  hipLaunchKernelGGL((dslash_tile_kernel<T, NR, LR, MAXBS>), dim3(b.total_blocks), dim3(bs), shm, st, b, xcd);
+  hipLaunchKernelGGL((dslash_tile_kernel<T, NR, LR, MAXBS>), dim3(b.total_blocks + b.commit), dim3(bs), shm, st, b, xcd);
 }
 
 template <typename T, int NR, int LR>
@@ -656,20 +665,20 @@ static void launch_m(const DslashBatch &b, int xcd, hipStream_t st) {
 template <typename T, int NR, int LR>
 static void launch_t(const DslashBatch &b, int bs, int xcd, hipStream_t st) {
   if (bs == 64)
-    hipLaunchKernelGGL((dslash_kernel<T, NR, LR, 64>), dim3(b.total_blocks), dim3(64), 0, st, b, xcd);
+    hipLaunchKernelGGL((dslash_kernel<T, NR, LR, 64>), dim3(b.total_blocks + b.commit), dim3(64), 0, st, b, xcd);
   else if (bs == 128)
-    hipLaunchKernelGGL((dslash_kernel<T, NR, LR, 128>), dim3(b.total_blocks), dim3(128), 0, st, b, xcd);
+    hipLaunchKernelGGL((dslash_kernel<T, NR, LR, 128>), dim3(b.total_blocks + b.commit), dim3(128), 0, st, b, xcd);
   else
-    hipLaunchKernelGGL((dslash_kernel<T, NR, LR, 256>), dim3(b.total_blocks), dim3(256), 0, st, b, xcd);
+    hipLaunchKernelGGL((dslash_kernel<T, NR, LR, 256>), dim3(b.total_blocks + b.commit), dim3(256), 0, st, b, xcd);
 }
 
 template <typename T, int LR>
 static void launch_nr(const DslashBatch &b, int nr, int bs, int xcd, int ct, hipStream_t st) {
   if (ct < 0) {
     if (nr == 1)
-      hipLaunchKernelGGL((dslash_split_kernel<T, 1, LR>), dim3(b.total_blocks), dim3(256), 0, st, b, xcd);
+      hipLaunchKernelGGL((dslash_split_kernel<T, 1, LR>), dim3(b.total_blocks + b.commit), dim3(256), 0, st, b, xcd);
     else
-      hipLaunchKernelGGL((dslash_split_kernel<T, 2, LR>), dim3(b.total_blocks), dim3(256), 0, st, b, xcd);
+      hipLaunchKernelGGL((dslash_split_kernel<T, 2, LR>), dim3(b.total_blocks + b.commit), dim3(256), 0, st, b, xcd);
     return;
   }
   if (ct > 0) {

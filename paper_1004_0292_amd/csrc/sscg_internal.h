@@ -201,7 +201,7 @@ struct DslashJob {
   const void *gauge;     // [4][LR/2][V] of V2<T>
   double *partial;       // [nsrc][ceil(V/64)] partial Re<in, out> per wavefront, or nullptr
   SeedState *seed;       // per-source done flags, or nullptr (always compute)
-  ShiftState *shift;     // solve loop: the first block commits the staged states (or nullptr)
+  ShiftState *shift;     // solve loop: the states the launch's commit block commits (or nullptr)
   int32_t nshift, pad0;
   double kappa, sigma;   // out = sigma in - A in (mode 1) or A in (mode 0)
   int32_t dims[4];
@@ -210,7 +210,9 @@ struct DslashJob {
   int32_t ty, tz;        // tile kernel: tile of Lx x ty x tz sites (one thread per site)
   int32_t order;         // block order: 0 source groups outermost, 1 sites outermost
 };
-struct DslashBatch { DslashJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
+// commit = 1: one block more than total_blocks, which commits the staged states of
+// the jobs with a shift table (solve loop)
+struct DslashBatch { DslashJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; int32_t commit; int32_t pad; };
 
 // Step length kernel (large lattices): one block per (job, source).
 struct ScalarJob {
