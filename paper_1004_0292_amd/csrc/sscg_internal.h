@@ -60,9 +60,9 @@ template <typename C> __host__ __device__ __forceinline__ C cneg(C a) { C c; c.x
 // ---- solver state (device memory) ------------------------------------------
 // The shift update kernel forms the scalars of its iteration itself (every block
 // from the same inputs, so every block gets the same values) and may not change
-// what its other blocks read; it stages the new values ("_n" fields), and the first
-// block of the next iteration's dslash commits them (commit_states below), or a
-// commit launch does before the host reads the state.
+// what its other blocks read; it stages the new values ("_n" fields), and an extra
+// block of the next iteration's dslash launch commits them (commit_states below), or
+// a commit launch does before the host reads the state.
 // Per source: the seed CG scalars of (sigma I - A) x = v.
 struct SeedState {
   double rho;        // <r_k, r_k>
