@@ -311,7 +311,7 @@ def main():
                     help="skip the dslash-only measurement on the 24^3 x 48 lattice")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 vs mixed time-to-solution comparison")
     ap.add_argument("--no-events", action="store_true", help="time without per-launch events")
-    ap.add_argument("--sample-every", type=int, default=10,
+    ap.add_argument("--sample-every", type=int, default=25,
                     help="time the dslash and shift update of every k-th iteration (graph replay kept); "
                          "1 times every launch with direct launches")
     ap.add_argument("--copy-calibration", action="store_true",
