@@ -108,7 +108,10 @@ typedef struct {
   int32_t poll_every;    /* host checks the device "all converged" word this often    */
   double switch_tol;     /* MIXED: FP64 -> FP32 switch when max active ||r_j||/||v||
                             is below this                                              */
-  int32_t use_graph;     /* 1: replay the iterations between polls as a HIP graph     */
+  int32_t use_graph;     /* 1: replay the iterations between polls as a HIP graph;
+                            the graphs stay in the context, and a later solve whose
+                            launches are the same (shapes, buffers, options) replays
+                            them without capturing again                            */
 } sscg_solve_opts;
 
 /* Default options: tol 1e-12, maxiter 100000, FP64, ru 50, poll 50, switch 1e-6, graph 1. */
