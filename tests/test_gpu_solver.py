@@ -89,17 +89,19 @@ def test_profiling_levels(sscg, prob):
     U, A, V, z = prob
     y_ref, r_ref = solve(sscg, U, V, z, poll_every=50, use_graph=1)
     out = {}
-    for level in (1, 5):
+    for level, graph in ((1, 1), (5, 1), (5, 0)):
         c = sscg.Context(CFG1.dims, CFG1.kappa)
         c.set_gauge(U, 18)
         c.set_profiling(level)
         y = to_dev(np.zeros((V.shape[0], len(z), V.shape[1])))
-        r = c.shifted_cg_solve(to_dev(V), z, 0.0, y, sscg.default_opts(poll_every=50, use_graph=1))
+        r = c.shifted_cg_solve(to_dev(V), z, 0.0, y, sscg.default_opts(poll_every=50, use_graph=graph))
         ms, calls = c.stage_times()
         assert np.array_equal(to_host(y), y_ref) and np.array_equal(r.iters, r_ref.iters)
-        out[level] = (np.array(ms), np.array(calls))
+        out[level, graph] = (np.array(ms), np.array(calls))
         c.close()
-    (ms1, calls1), (ms5, calls5) = out[1], out[5]
+    (ms1, calls1), (ms5, calls5) = out[1, 1], out[5, 1]
+    # sampling with direct launches takes the same samples as inside the graphs
+    assert np.array_equal(out[5, 0][1][:6], calls5[:6])
     launched = calls1[0]            # one dslash per launched iteration
     assert launched >= int(np.max(r_ref.iters)) and calls1[4] == launched
     assert calls1[2] == launched and calls1[3] == 0 and np.all(ms1[[0, 2, 4]] > 0)
