@@ -373,6 +373,34 @@ static double time_launches(hipStream_t st, F &&launch, int reps) {
 // (candidates are tried in a fixed order).
 constexpr double kTuneMargin = 0.97;
 
+// Second round of a shape search: the kRefine fastest shapes of the first round are
+// timed again with more launches, twice, and the shortest of those times decides
+// (the first round's short timings only preselect).
+constexpr int kRefine = 4;
+struct Trial {
+  double t;
+  int order;
+  Tune cd;
+};
+template <typename F>
+static Tune refine_shapes(std::vector<Trial> &trials, const Tune &fallback, F &&time_shape) {
+  if (trials.empty()) return fallback;
+  std::sort(trials.begin(), trials.end(),
+            [](const Trial &a, const Trial &b) { return a.t < b.t || (a.t == b.t && a.order < b.order); });
+  if (trials.size() > (size_t)kRefine) trials.resize(kRefine);
+  std::sort(trials.begin(), trials.end(), [](const Trial &a, const Trial &b) { return a.order < b.order; });
+  Tune best = trials[0].cd;
+  double tbest = 1e300;
+  for (const Trial &tr : trials) {
+    const double t = std::min(time_shape(tr.cd), time_shape(tr.cd));
+    if (t < kTuneMargin * tbest || tbest == 1e300) {
+      tbest = t;
+      best = tr.cd;
+    }
+  }
+  return best;
+}
+
 // Dslash launch shape for out = A in on nsrc vectors outside a solve (apply_A, true
 // residuals, Rayleigh-Ritz products): with autotuning on, every shape of the
 // site-parallel and tile kernels is timed once on the caller's buffers (out is
@@ -383,16 +411,15 @@ static Tune apply_tune(sscg_ctx *c, const void *in, void *out, int nsrc, int pre
   const std::string key = "apply|" + std::to_string(prec) + "|" + std::to_string(nsrc);
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) return it->second;
-  Tune best = c->tune, cand = c->tune;
-  double tbest = 1e300;
+  Tune cand = c->tune;
+  std::vector<Trial> trials;
+  auto time_shape = [&](const Tune &cd, int reps) {
+    return time_launches(st, [&] { dslash_with(c, cd, in, out, nsrc, prec, 0, 0.0, nullptr, nullptr, st); }, reps);
+  };
   auto try_shape = [&](const Tune &cd) {
     int ty, tz;
     if (cd.ct > 0 && !tile_shape(c, cd.tbs, cd.nr, prec, ty, tz)) return;
-    const double t = time_launches(st, [&] { dslash_with(c, cd, in, out, nsrc, prec, 0, 0.0, nullptr, nullptr, st); }, 3);
-    if (t < kTuneMargin * tbest) {
-      tbest = t;
-      best = cd;
-    }
+    trials.push_back({time_shape(cd, 3), (int)trials.size(), cd});
   };
   for (int nr : {1, 2, 4}) {
     if (nr > 1 && nr > nsrc) continue;
@@ -416,6 +443,7 @@ static Tune apply_tune(sscg_ctx *c, const void *in, void *out, int nsrc, int pre
         try_shape(cand);
       }
   }
+  const Tune best = refine_shapes(trials, c->tune, [&](const Tune &cd) { return time_shape(cd, 10); });
   if (getenv("SSCG_VERBOSE"))
     fprintf(stderr, "[sscg] tuned %s: nr=%d bs=%d xcd=%d ct=%d tbs=%d\n", key.c_str(), best.nr, best.bs, best.xcd,
             best.ct, best.tbs);
@@ -860,24 +888,21 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
   const int dprec = o.prec == SSCG_MIXED ? 1 : 0;
   if (dprec == 1)
     for (Prob &p : P) launch_cast(p.c->p64.p, 0, p.c->p32.p, 1, (int64_t)p.L * p.c->n, st);
-  double tbest = 1e300;
   Tune cand = best;
+  std::vector<Trial> trials;
+  auto time_shape = [&](const Tune &cd, int reps) {
+    IterPlan pl;
+    build_plan(P, pl, o, cd);
+    return time_it([&] {
+      launch_dslash(dprec ? pl.d32 : pl.d64, dprec, cd.nr, dprec ? lr : 18, cd.bs, cd.xcd, pl.ct, st);
+    }, reps);
+  };
   // site-parallel kernel: sources per thread, sites per block, XCD order
   auto try_shape = [&](const Tune &cd) {
     IterPlan pl;
     build_plan(P, pl, o, cd);
     if (cd.ct != 0 && pl.ct == 0) return;  // no tile of this size on some lattice
-    const double t = time_it([&] {
-      launch_dslash(dprec ? pl.d32 : pl.d64, dprec, cd.nr, dprec ? lr : 18, cd.bs, cd.xcd, pl.ct, st);
-    }, 5);
-    if (t < kTuneMargin * tbest) {
-      tbest = t;
-      best.nr = cd.nr;
-      best.bs = cd.bs;
-      best.xcd = cd.xcd;
-      best.ct = cd.ct;
-      best.tbs = cd.tbs;
-    }
+    trials.push_back({time_shape(cd, 5), (int)trials.size(), cd});
   };
   for (int nr : {1, 2, 4}) {
     if (nr > 1 && nr > maxL) continue;
@@ -903,6 +928,14 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
         try_shape(cand);
       }
   }
+  {
+    const Tune d = refine_shapes(trials, best, [&](const Tune &cd) { return time_shape(cd, 15); });
+    best.nr = d.nr;
+    best.bs = d.bs;
+    best.xcd = d.xcd;
+    best.ct = d.ct;
+    best.tbs = d.tbs;
+  }
   // fused shift update as an identity on the current data (identity jobs: every
   // shift updated with alpha_j = 0, beta_j = 1, 1/pi_j = 0, no state written; not
   // used, and not timed, when the moments are accumulated in the loop: there is no y_j)
@@ -914,8 +947,14 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
     for (SeedState &x : sd) x.pending = 1;
     HIPCHK(p.c, hipMemcpy(p.c->seed.p, sd.data(), sd.size() * sizeof(SeedState), hipMemcpyHostToDevice));
   }
-  tbest = 1e300;
   cand = best;
+  std::vector<Trial> utrials;
+  auto time_update = [&](const Tune &cd, int reps) {
+    IterPlan pl;
+    build_plan(P, pl, o, cd);
+    for (int i = 0; i < pl.u64.njobs; ++i) pl.u64.job[i].identity = 1;
+    return time_it([&] { launch_shift_update(pl.u64, 0, 0, 0, cd.unroll, cd.nt, st); }, reps);
+  };
   for (int w : {2, 4, 8, 16, 32}) {
     if (!tune_update) break;
     if (w > 2 && w / 2 >= maxN) continue;
@@ -927,19 +966,16 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
           cand.unroll = u;
           cand.nt = nt;
           cand.border = bo;
-          IterPlan pl;
-          build_plan(P, pl, o, cand);
-          for (int i = 0; i < pl.u64.njobs; ++i) pl.u64.job[i].identity = 1;
-          const double t = time_it([&] { launch_shift_update(pl.u64, 0, 0, 0, u, nt, st); }, 3);
-          if (t < kTuneMargin * tbest) {
-            tbest = t;
-            best.wbatch = w;
-            best.unroll = u;
-            best.nt = nt;
-            best.border = bo;
-          }
+          utrials.push_back({time_update(cand, 3), (int)utrials.size(), cand});
         }
     }
+  }
+  if (tune_update) {
+    const Tune d = refine_shapes(utrials, best, [&](const Tune &cd) { return time_update(cd, 10); });
+    best.wbatch = d.wbatch;
+    best.unroll = d.unroll;
+    best.nt = d.nt;
+    best.border = d.border;
   }
   if (getenv("SSCG_VERBOSE"))
     fprintf(stderr, "[sscg] tuned %s: nr=%d bs=%d xcd=%d ct=%d tbs=%d wbatch=%d unroll=%d nt=%d border=%d\n",
