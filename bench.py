@@ -311,9 +311,10 @@ def main():
                     help="skip the dslash-only measurement on the 24^3 x 48 lattice")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 vs mixed time-to-solution comparison")
     ap.add_argument("--no-events", action="store_true", help="time without per-launch events")
-    ap.add_argument("--sample-every", type=int, default=25,
-                    help="time the dslash and shift update of every k-th iteration (graph replay kept); "
-                         "1 times every launch with direct launches")
+    ap.add_argument("--sample-every", type=int, default=None,
+                    help="time the dslash and shift update of every k-th iteration (graph replay kept; "
+                         "default 25 for FP64 solves, 10 for the mixed modes); 1 times every launch with "
+                         "direct launches")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy five times (for counter scaling) and exit")
     args = ap.parse_args()
@@ -356,6 +357,10 @@ def main():
                                  spur_tol=1e-6, solve=opts, moments_in_loop=int(args.moments_in_loop),
                                  weighted_tol=int(args.weighted_tol))
     max_eigs = min(w.M * w.L, 32)
+    if args.sample_every is None:
+        # the sample must hit every poll interval at the same rate: FP64 solves poll
+        # every 50 iterations; the FP64 phase of the mixed modes polls every 10
+        args.sample_every = 25 if prec == S.FP64 else 10
     ctx.set_profiling(0 if args.no_events else args.sample_every)
     for _ in range(args.warmup):
         ctx.ss_eigs(params, vd, max_eigs=max_eigs)

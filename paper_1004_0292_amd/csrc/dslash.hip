@@ -462,8 +462,15 @@ __device__ __forceinline__ int tile_nb(int tid, int l, int T, int L, int stride,
 // multiple of 64 (at most 1024); dynamic LDS of nr * 12 * Lx ty tz complex numbers.
 // Partials of Re <psi, out>: one per 64-site wavefront, indexed by (slice, tile,
 // wavefront), V / 64 of them as in the site-parallel kernel.
+// FP32 tiles with one source per thread fit three wavefronts per SIMD in 168
+// registers; the bound keeps the compiler there (a register more would cost a
+// wavefront per SIMD on 256-thread tiles).
+template <typename T, int NR, int MAXBS>
+constexpr int tile_min_blocks() { return (sizeof(T) == 4 && NR == 1 && MAXBS == 256) ? 3 : 1; }
+
 template <typename T, int NR, int LR, int MAXBS>
-__global__ __launch_bounds__(MAXBS) void dslash_tile_kernel(DslashBatch B, int xcd_remap) {
+__global__ __launch_bounds__(MAXBS, (tile_min_blocks<T, NR, MAXBS>())) void dslash_tile_kernel(DslashBatch B,
+                                                                                              int xcd_remap) {
   using C = V2<T>;
   extern __shared__ __align__(16) unsigned char dslash_lds[];
   C *lds = reinterpret_cast<C *>(dslash_lds);
