@@ -8,22 +8,28 @@ Rayleigh-Ritz extraction with acceptance (sscg_ss_eigs). The throughput is
 shift-updates per second: the number of (source, shift) vector updates the
 shifted CG performs, summed over the timed steps, divided by their wall time.
 
-Printed as one JSON line on rank 0. Besides the throughput it carries:
-  roofline      the dominant kernel (by measured time), its algorithmic bytes per
-                launch over its average launch duration from HIP events recorded
-                around every launch inside the timed region, against 8 TB/s;
-                traffic from committed rocprofv3 counter summaries when they match
-                the current kernel source, else null
-  dslash        the same figures for the Wilson dslash
+The default workload is the largest single-GPU one, a 24^3 x 48 lattice with 64
+nodes and 8 sources, timed in FP64 (the paper's arithmetic). Printed as one JSON
+line; besides the throughput it carries:
+  roofline      the dominant kernel (by time per step): algorithmic bytes per launch
+                over its average launch duration from HIP events recorded inside the
+                solve's graphs, against 8 TB/s; traffic from the committed rocprofv3
+                counter summary when it matches the current kernel source, else null
+  dslash        the same figures for the Wilson dslash of the solve
+  stage_ms_per_step  every stage of the solve, from the sampled launch times scaled
+                by the launches of that stage (the split of the paper's Table 2:
+                matrix-vector products against everything else)
+  tts           time to solution of the step in FP64 and the two mixed-precision
+                modes on the same interval, with each mode's largest FP64 true residual
+  tts_window    the same on an interval that holds eigenvalues, with the eigenvalues
+                of each mode, their agreement with FP64 and with the reference spectrum
+  extraction    Rayleigh-Ritz against block Hankel on that window: extraction time,
+                device memory, residuals and eigenvalue error
   dslash_24x48  the dslash alone on the 24^3 x 48 lattice with 8 sources (FP32 with
                 12-real links, FP64 with 18-real links), autotuned launch shape
-  tts           time to solution of the step in FP64 and FP64-seed / FP32-shift
-                precision, with stored solutions and with in-loop moments
-  tts_window    the same comparison on a window of the field's spectrum that holds
-                eigenvalues, with both modes' eigenvalues and residuals
-  cpu_baseline  the FP64 CPU oracle (numpy/scipy) on the host: one source's full
-                shifted CG (all N shifts) on the same workload, bounded in time
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
+  cpu_baseline  the FP64 CPU oracle (numpy/scipy) on the host, on a bounded sample of
+                the same workload, and the solve time extrapolated from it
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--prec P]
 """
 from __future__ import annotations
 
@@ -40,7 +46,8 @@ sys.path.insert(0, str(ROOT))
 
 METRIC = "shift-updates/sec & dslash HBM GB/s (frac of peak), mixed/batched vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
-DEFAULT_CONFIG = "wilson8_fp64"
+MALL_BYTES = 256 << 20          # Infinity Cache of the MI355X
+DEFAULT_CONFIG = "wilson24x48"
 STAGES = ["dslash", "seed_alpha", "seed_r_update", "unused", "shift_update", "reliable_update",
           "solve_loop"]
 KERNEL_SOURCES = {"shift_update": "paper_1004_0292_amd/csrc/vec.hip",
@@ -53,9 +60,9 @@ def source_hash(rel):
     return hashlib.sha256((ROOT / rel).read_bytes()).hexdigest()[:16]
 
 
-def pmc_traffic(kernel, workload):
+def pmc_traffic(kernel, workload, prec):
     """HBM bytes per launch from the committed counter summary, if it still matches."""
-    f = ROOT / "profiles" / f"{kernel}_{workload}_pmc.txt"
+    f = ROOT / "profiles" / f"{kernel}_{workload}_{prec}_pmc.txt"
     if not f.exists():
         return None
     d = json.loads(f.read_text())
@@ -74,21 +81,32 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(w, budget_s=20.0):
-    """Oracle shifted CG (all N shifts) on the workload's sources, one after another,
-    stopped after budget_s seconds of wall time."""
+def cpu_baseline(w, gpu_iters, budget_s=20.0, max_shifts=16):
+    """The FP64 oracle's shifted CG on the host, on a bounded sample of the workload:
+    source 0 with every (N / max_shifts)-th node, iterated until budget_s seconds or 25
+    iterations. Reports the oracle's shift-updates per second on that sample, and the
+    solve of the whole workload extrapolated from it (oracle matrix-vector product
+    time plus per-shift vector time, times the GPU's seed iterations)."""
     import numpy as np
     from oracle import quadrature as quad
     from oracle import solvers, wilson
-    import synth
 
     t_setup = time.perf_counter()
     U = w.gauge()
     A = wilson.hermitian_wilson(U, w.dims, w.kappa)
-    V = w.sources().reshape(w.L, -1)
-    z, zeta = quad.line_nodes(w.N, w.gamma, w.rho, w.beta)
+    del U
+    v = w.sources()[0].reshape(-1)
+    z, _ = quad.line_nodes(w.N, w.gamma, w.rho, w.beta)
+    stride = max(1, w.N // max_shifts)
+    zs = z[::stride]
     setup = time.perf_counter() - t_setup
+    # the oracle's matrix-vector product alone
+    t0 = time.perf_counter()
+    for _ in range(3):
+        _ = A @ v
+    t_mv = (time.perf_counter() - t0) / 3
     updates = [0]
+    iters = [0]
     t0 = time.perf_counter()
     c0 = time.process_time()
 
@@ -97,93 +115,140 @@ def cpu_baseline(w, budget_s=20.0):
 
     def rec(k, st):
         updates[0] += st["updated"]
-        if time.perf_counter() - t0 > budget_s:
+        iters[0] += 1
+        if time.perf_counter() - t0 > budget_s or iters[0] >= 25:
             raise Stop()
 
-    done = 0
     try:
-        for l in range(w.L):
-            solvers.shifted_cg(lambda x: A @ x, V[l], z, w.gamma, w.tol, record=rec)
-            done += 1
+        solvers.shifted_cg(lambda x: A @ x, v, zs, w.gamma, w.tol, record=rec)
     except Stop:
         pass
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
-    return {"value": updates[0] / wall, "unit": "shift-updates/s", "cores": max(1, round(cpu / wall)),
+    t_it = wall / max(iters[0], 1)
+    per_shift = max(t_it - t_mv, 0.0) / len(zs)
+    t_it_full = t_mv + per_shift * w.N
+    return {"value": round(updates[0] / wall, 2), "unit": "shift-updates/s", "cores": max(1, round(cpu / wall)),
             "kind": "oracle",
-            "sample": (f"FP64 shifted CG for all {w.N} shifts on the explicit sparse A (scipy CSR), sources "
-                       f"solved one after another: {done} of {w.L} to convergence"
-                       f"{'' if done == w.L else ', the next stopped at the time limit'}; "
+            "sample": (f"FP64 oracle shifted CG (scipy CSR matrix, numpy vectors) on source 0 of {w.L} with "
+                       f"{len(zs)} of the {w.N} nodes (every {stride}th), {iters[0]} iterations, "
                        f"{updates[0]} shift-updates in {wall:.1f} s; cores = process CPU time / wall time; "
                        f"matrix assembly ({setup:.1f} s) excluded"),
+            "oracle_matvec_s": round(t_mv, 4),
+            "oracle_iteration_s_all_nodes": round(t_it_full, 3),
+            "extrapolated_solve_s": round(t_it_full * gpu_iters, 1),
+            "extrapolation": (f"oracle iteration with all {w.N} nodes (matrix-vector product + {w.N} x the "
+                              f"measured per-node vector time) times the {gpu_iters} seed iterations the GPU "
+                              f"ran over all sources in one step: extrapolated, not run"),
             "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
 
 
-def tts_compare(S, ctx, params, vd, max_eigs, steps):
-    """Time to solution of the whole step in FP64 and in the FP64-seed / FP32-shift mode,
-    each with stored solutions and with the moments summed inside the solve, on the
-    same inputs (graph replay, no per-launch events)."""
-    import copy
+PRECS = {"fp64": 0, "mixed": 1, "mixed_shifts": 2}
+
+
+def solve_steps(S, ctx, params, vd, max_eigs, steps, warmup=1):
+    """Run ss_eigs warmup + steps times; per-step wall time and the last result."""
     import torch
-    out = {}
-    ctx.set_profiling(False)
-    for name, prec, in_loop in (("fp64", S.FP64, 0), ("mixed_shifts", S.MIXED_SHIFTS, 0),
-                                ("fp64_inloop", S.FP64, 1), ("mixed_shifts_inloop", S.MIXED_SHIFTS, 1)):
+    for _ in range(warmup):
+        ctx.ss_eigs(params, vd, max_eigs=max_eigs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = ctx.ss_eigs(params, vd, max_eigs=max_eigs)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, r
+
+
+def mode_summary(r, ms, nsrc):
+    i = r.info
+    return {"ms_per_step": round(ms, 2), "status": int(r.status), "seed_iters_per_source": i.seed_iters / nsrc,
+            "switch_iter": int(i.switch_iter), "max_true_res": float(i.max_true_res),
+            "shift_updates": int(i.shift_updates), "shift_updates_fp32": int(i.shift_updates_fp32),
+            "eigenpairs_found": int(r.n_found), "eigs": r.lam.round(13).tolist(),
+            "max_res": float(r.res.max()) if len(r.res) else None,
+            "t_solve_s": round(i.t_solve, 4), "t_extract_s": round(i.t_extract, 4)}
+
+
+def tts_compare(S, ctx, params, vd, max_eigs, steps, base_ms, base_res):
+    """Time to solution of the whole step in the two mixed-precision modes on the same
+    inputs and interval as the FP64 steps (graph replay, sampled events off)."""
+    import copy
+    ctx.set_profiling(0)
+    out = {"fp64": dict(base_res)}
+    for name in ("mixed_shifts", "mixed"):
         p = copy.copy(params)
         p.solve = copy.copy(params.solve)
-        p.solve.prec = prec
-        p.moments_in_loop = in_loop
-        ctx.ss_eigs(p, vd, max_eigs=max_eigs)          # tune for this mode
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            r = ctx.ss_eigs(p, vd, max_eigs=max_eigs)
-        torch.cuda.synchronize()
-        out[name + "_ms_per_step"] = round((time.perf_counter() - t0) / steps * 1e3, 3)
-        out[name + "_eigs"] = r.lam.round(12).tolist()
-        out[name + "_max_res"] = float(r.res.max()) if len(r.res) else None
-    out["speedup_mixed_vs_fp64"] = round(out["fp64_ms_per_step"] / out["mixed_shifts_ms_per_step"], 3)
-    out["speedup_mixed_inloop_vs_fp64"] = round(out["fp64_ms_per_step"] / out["mixed_shifts_inloop_ms_per_step"], 3)
+        p.solve.prec = PRECS[name]
+        dt, r = solve_steps(S, ctx, p, vd, max_eigs, steps)
+        out[name] = mode_summary(r, dt * 1e3, vd.shape[0])
+        out[name]["speedup_vs_fp64"] = round(base_ms / (dt * 1e3), 3)
     return out
 
 
-# Eigenvalue windows that do contain eigenvalues of a workload's field (from its
-# reference spectrum), for the time-to-solution comparison at equal accuracy.
-WINDOWS = {"wilson8_fp64": dict(lo=0.3700, hi=0.3735, beta=0.5, N=32, M=8)}
+# Intervals of a workload's field that hold eigenvalues (from its reference
+# spectrum), for the time-to-solution comparison at equal accuracy: the interval
+# [lo, hi], the line offset beta, N nodes, M moments and L sources.
+WINDOWS = {"wilson8_fp64": dict(lo=0.3700, hi=0.3735, beta=0.5, N=32, M=8, L=4),
+           "wilson16x32_mixed": None,
+           "wilson24x48": None}
 
 
-def tts_window(S, ctx, w, vd, steps):
-    """Time to solution and accuracy of FP64 against the FP32-shift mode on a window
-    with eigenvalues: per-step time, the eigenvalues and residuals of each mode, and
-    the largest relative eigenvalue difference between the two."""
+def reference_spectrum(name):
+    """Reference eigenvalues of a workload's field (written by the oracle scripts under
+    tests/golden), or None."""
+    g = ROOT / "tests" / "golden"
+    if name == "wilson8_fp64":
+        f = g / "wilson8.json"
+        return json.loads(f.read_text())["lowest_eigs"]["lam"] if f.exists() else None
+    f = g / f"spectrum_{name}.json"
+    return json.loads(f.read_text())["lam"] if f.exists() else None
+
+
+def tts_window(S, ctx, w, vd_all, steps):
+    """FP64 against both mixed modes on a window that holds eigenvalues: per-step time,
+    eigenvalues and residuals, the largest relative eigenvalue difference from FP64 and
+    from the reference spectrum; and Rayleigh-Ritz against block Hankel (extraction
+    time, device memory, accuracy) on the FP64 solve of that window."""
     import numpy as np
-    import torch
     win = WINDOWS.get(w.name)
-    if win is None:
-        return None
+    if not win:
+        return None, None
+    ref = reference_spectrum(w.name)
     gamma, rho = 0.5 * (win["lo"] + win["hi"]), 0.5 * (win["hi"] - win["lo"])
-    out = {"window": [win["lo"], win["hi"]], "beta": win["beta"], "N": win["N"], "M": win["M"]}
-    ctx.set_profiling(False)
+    vd = vd_all[:win["L"]].contiguous()
+    out = {"window": [win["lo"], win["hi"]], "beta": win["beta"], "N": win["N"], "M": win["M"], "L": win["L"]}
+    truth = None
+    if ref is not None:
+        lam_ref = np.array(ref)
+        truth = np.sort(lam_ref[(lam_ref >= win["lo"]) & (lam_ref <= win["hi"])])
+        out["reference_eigs"] = truth.round(13).tolist()
+    ctx.set_profiling(0)
     lams = {}
-    for name, prec in (("fp64", S.FP64), ("mixed_shifts", S.MIXED_SHIFTS)):
-        opts = S.default_opts(tol=w.tol, prec=prec, ru_interval=w.ru_interval, switch_tol=w.switch_tol)
+    ext = {}
+    for name in ("fp64", "mixed_shifts", "mixed", "fp64_hankel"):
+        opts = S.default_opts(tol=w.tol, prec=PRECS[name.replace("_hankel", "")], ru_interval=w.ru_interval,
+                              switch_tol=w.switch_tol)
         p = S.default_ss_params(gamma=gamma, rho=rho, beta=win["beta"], N=win["N"], M=win["M"], rank_tol=1e-7,
-                                spur_tol=1e-6, solve=opts)
-        ctx.ss_eigs(p, vd, max_eigs=32)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            r = ctx.ss_eigs(p, vd, max_eigs=32)
-        torch.cuda.synchronize()
-        out[name + "_ms_per_step"] = round((time.perf_counter() - t0) / steps * 1e3, 3)
-        out[name + "_eigs"] = r.lam.round(13).tolist()
-        out[name + "_max_res"] = float(r.res.max()) if len(r.res) else None
+                                spur_tol=1e-6, solve=opts, method=S.HANKEL if name.endswith("hankel") else S.RR)
+        dt, r = solve_steps(S, ctx, p, vd, 32, steps)
+        s = mode_summary(r, dt * 1e3, win["L"])
+        if truth is not None and len(r.lam) == len(truth) and len(truth):
+            s["max_rel_err_vs_reference"] = float(np.max(np.abs(r.lam - truth) / np.abs(truth)))
         lams[name] = r.lam
-    a, b = lams["fp64"], lams["mixed_shifts"]
-    out["eigs_found"] = [len(a), len(b)]
-    out["max_rel_eig_diff"] = float(np.max(np.abs(a - b) / np.abs(a))) if len(a) == len(b) and len(a) else None
-    out["speedup_mixed_vs_fp64"] = round(out["fp64_ms_per_step"] / out["mixed_shifts_ms_per_step"], 3)
-    return out
+        if name in ("fp64", "fp64_hankel"):
+            ext["rr" if name == "fp64" else "hankel"] = {
+                "t_extract_ms": round(r.info.t_extract * 1e3, 2), "extract_bytes": int(r.info.extract_bytes),
+                "rank": int(r.info.rank), "eigenpairs_found": int(r.n_found),
+                "max_res": s["max_res"], "max_rel_err_vs_reference": s.get("max_rel_err_vs_reference")}
+            continue
+        out[name] = s
+    a = lams["fp64"]
+    for name in ("mixed_shifts", "mixed"):
+        b = lams[name]
+        out[name]["max_rel_eig_diff_vs_fp64"] = (float(np.max(np.abs(a - b) / np.abs(a)))
+                                                 if len(a) == len(b) and len(a) else None)
+        out[name]["speedup_vs_fp64"] = round(out["fp64"]["ms_per_step"] / out[name]["ms_per_step"], 3)
+    return out, ext
 
 
 def bench_batch(args):
@@ -249,7 +314,7 @@ def dslash_large(S, reps=10):
     against its compulsory HBM bytes (spinors in and out once, links once)."""
     import torch
     import synth
-    w = synth.CONFIGS["wilson24x48_mixed12"]
+    w = synth.CONFIGS["wilson24x48"]
     U = w.gauge()
     x = torch.from_numpy(w.sources()).to("cuda:0")
     y = torch.empty_like(x)
@@ -258,7 +323,7 @@ def dslash_large(S, reps=10):
         c = S.Context(w.dims, w.kappa)
         c.set_gauge(U, lr)
         c.apply_A(x, y, prec)            # chooses the launch shape
-        c.set_profiling(True)
+        c.set_profiling(1)
         for _ in range(reps):
             c.apply_A(x, y, prec)
         ms, calls = c.stage_times()
@@ -267,7 +332,7 @@ def dslash_large(S, reps=10):
         ach = nbytes / avg_s / 1e9
         out[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": pmc_traffic("dslash_" + name, w.name), "avg_launch_us": round(avg_s * 1e6, 2),
+                     "traffic": pmc_traffic("dslash_" + name, w.name, "apply"), "avg_launch_us": round(avg_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": nbytes, "launches": int(calls[0])}
         c.close()
     del x, y
@@ -294,27 +359,50 @@ def copy_bandwidth(nbytes=2 << 30, reps=5):
     return round(gbs, 1)
 
 
+def kernel_bytes(w, prec, tot, link_launches, moments_in_loop):
+    """Algorithmic (compulsory) HBM bytes of the shift update and the dslash over the
+    timed steps. Shift update: read and write x_j and p_j per active (shift, source,
+    entry) (64 B FP64, 32 B FP32), the seed r read once and the seed p read and written
+    once per (source, entry, iteration) (48 B FP64, 24 B FP32 for the FP32 seed of the
+    "mixed" mode). Dslash: the spinor in and out per (source, site) and the four
+    forward links per site once per launch."""
+    n = w.n
+    seed32 = prec == PRECS["mixed"]
+    su64 = tot["shift_updates"] - tot["shift_updates_fp32"]
+    su32 = tot["shift_updates_fp32"]
+    it64 = tot["seed_iters"] - tot["seed_iters_fp32"]
+    it32 = tot["seed_iters_fp32"]
+    shift = (su64 * 64 + it64 * 48) * n + (su32 * 32 + it32 * (24 if seed32 else 48)) * n
+    if moments_in_loop:
+        # p_j read and written per active (shift, source, entry); per (source, entry,
+        # iteration) the seed r read, the seed p read and written, the M moments read
+        # and written
+        shift = (su64 * 32 + su32 * 16 + (it64 + it32) * (48 + 32 * w.M)) * n
+    dslash = (it64 * 48 * 8 + it32 * 48 * (4 if seed32 else 8)) * w.V
+    dslash += (link_launches[0] * 18 * 8 + link_launches[1] * (w.link_reals * 4 if seed32 else 18 * 8)) * 4 * w.V
+    return shift, dslash
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tts-steps", type=int, default=2, help="steps per mode of the time-to-solution comparisons")
     ap.add_argument("--config", default=DEFAULT_CONFIG)
     ap.add_argument("--method", default="rr", choices=["rr", "hankel"])
-    ap.add_argument("--prec", default=None, choices=["fp64", "mixed", "mixed_shifts"],
-                    help="override the workload's precision mode")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed", "mixed_shifts", "workload"],
+                    help="precision of the timed steps (default FP64; 'workload' = the workload's own mode)")
     ap.add_argument("--moments-in-loop", action="store_true",
                     help="accumulate the moments inside the solve (no stored solutions)")
     ap.add_argument("--weighted-tol", action="store_true", help="moment-weighted per-shift stopping")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dslash-large", action="store_true",
                     help="skip the dslash-only measurement on the 24^3 x 48 lattice")
-    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 vs mixed time-to-solution comparison")
-    ap.add_argument("--no-events", action="store_true", help="time without per-launch events")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 vs mixed time-to-solution comparisons")
     ap.add_argument("--sample-every", type=int, default=None,
-                    help="time the dslash and shift update of every k-th iteration (graph replay kept; "
-                         "default 25 for FP64 solves, 10 for the mixed modes); 1 times every launch with "
-                         "direct launches")
+                    help="time every stage of every k-th iteration (graph replay kept; default 25 for FP64 "
+                         "solves, 10 for the mixed modes); 1 times every launch with direct launches")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy five times (for counter scaling) and exit")
     args = ap.parse_args()
@@ -342,15 +430,14 @@ def main():
         bench_batch(args)
         return
     w = synth.CONFIGS[args.config]
-    mode = args.prec or w.prec
-    prec = {"fp64": S.FP64, "mixed": S.MIXED, "mixed_shifts": S.MIXED_SHIFTS}[mode]
-    seed32 = prec == S.MIXED
+    mode = w.prec if args.prec == "workload" else args.prec
+    prec = PRECS[mode]
+    print(f"[bench] {w.name} {w.dims} N={w.N} L={w.L} M={w.M} prec={mode}", file=sys.stderr, flush=True)
     U = w.gauge()
-    V = w.sources()
     ctx = S.Context(w.dims, w.kappa, device=0)
     ctx.set_gauge(U, w.link_reals)
-    vd = torch.from_numpy(V).to("cuda:0")
-    del V
+    del U
+    vd = torch.from_numpy(w.sources()).to("cuda:0")
     opts = S.default_opts(tol=w.tol, prec=prec, ru_interval=w.ru_interval, switch_tol=w.switch_tol)
     params = S.default_ss_params(gamma=w.gamma, rho=w.rho, beta=w.beta, N=w.N, M=w.M,
                                  method=S.RR if args.method == "rr" else S.HANKEL, rank_tol=1e-7,
@@ -361,76 +448,65 @@ def main():
         # the sample must hit every poll interval at the same rate: FP64 solves poll
         # every 50 iterations; the FP64 phase of the mixed modes polls every 10
         args.sample_every = 25 if prec == S.FP64 else 10
-    ctx.set_profiling(0 if args.no_events else args.sample_every)
+    ctx.set_profiling(args.sample_every)
     for _ in range(args.warmup):
         ctx.ss_eigs(params, vd, max_eigs=max_eigs)
     torch.cuda.synchronize()
+    print("[bench] warm-up done", file=sys.stderr, flush=True)
     stage_ms = np.zeros(8)
     stage_calls = np.zeros(8, dtype=np.int64)
+    stage_est = np.zeros(8)          # sampled average times launches, summed over steps
     tot = dict(shift_updates=0, shift_updates_fp32=0, seed_iters=0, seed_iters_fp32=0, matvecs=0,
                t_solve=0.0, t_moments=0.0, t_extract=0.0)
     link_launches = [0, 0]   # dslash launches doing work in the FP64 and FP32 phases
+    launched_tot = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out = ctx.ss_eigs(params, vd, max_eigs=max_eigs)
         ms, calls = ctx.stage_times()
+        launched = ctx.stage_launches()
         stage_ms += ms
         stage_calls += calls
+        for k in range(6):
+            if calls[k] > 0:
+                stage_est[k] += ms[k] / calls[k] * launched[k]
+        launched_tot += int(launched[6])
         for k in tot:
             tot[k] += getattr(out.info, k)
         sw = out.info.switch_iter if out.info.switch_iter >= 0 else out.info.iters
         link_launches[0] += min(out.info.iters, sw)
         link_launches[1] += max(0, out.info.iters - sw)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    n = w.n
+    elapsed = time.perf_counter() - t0
+    print("[bench] timed steps done", file=sys.stderr, flush=True)
     value = tot["shift_updates"] / elapsed
-    graph_value = None
-    if not args.no_events:
-        # the same steps again without events (shows what the timing costs)
-        ctx.set_profiling(False)
-        su = 0
-        torch.cuda.synchronize()
-        g0 = time.perf_counter()
-        for _ in range(args.steps):
-            su += ctx.ss_eigs(params, vd, max_eigs=max_eigs).info.shift_updates
-        torch.cuda.synchronize()
-        graph_value = su / (time.perf_counter() - g0)
+    step_ms = elapsed / args.steps * 1e3
 
-    # algorithmic bytes (compulsory traffic) per kernel over the timed steps
-    su64 = tot["shift_updates"] - tot["shift_updates_fp32"]
-    su32 = tot["shift_updates_fp32"]
-    it64 = tot["seed_iters"] - tot["seed_iters_fp32"]
-    it32 = tot["seed_iters_fp32"]
-    # shift update: read and write x_j and p_j per active (shift, source, entry); seed r
-    # read once and seed p read and written once per (source, entry, iteration)
-    # (the seed vectors are FP32 in the FP32 phase only in the "mixed" mode)
-    shift_bytes = (su64 * 64 + it64 * 48) * n + (su32 * 32 + it32 * (24 if seed32 else 48)) * n
-    if args.moments_in_loop:
-        # p_j read and written per active (shift, source, entry); per (source, entry,
-        # iteration) the seed r read, the seed p read and written, and the M moments read
-        # and written
-        shift_bytes = (su64 * 32 + su32 * 16 + (it64 + it32) * (48 + 32 * w.M)) * n
-    # dslash: spinor in and out per (source, site) and the four forward links per site
-    dslash_bytes = (it64 * 48 * 8 + it32 * 48 * (4 if seed32 else 8)) * w.V
-    dslash_bytes += (link_launches[0] * 18 * 8 +
-                     link_launches[1] * (w.link_reals * 4 if seed32 else 18 * 8)) * 4 * w.V
+    shift_bytes, dslash_bytes = kernel_bytes(w, prec, tot, link_launches, args.moments_in_loop)
+    # working set of the solve: the FP64 shift slots and solutions (or moments) of every
+    # (source, node), the seed vectors and the links; above the 256 MB Infinity Cache
+    # the streams come from HBM, below it they can stay in the cache
+    ws_bytes = w.L * w.N * w.n * 16 * (1 if args.moments_in_loop else 2) + 4 * w.L * w.n * 16 + w.V * 4 * 144
+    resident = "hbm" if ws_bytes > MALL_BYTES else "mall"
     rep = {}
-    launched = int(stage_calls[6])   # iterations launched (one dslash and one shift update each)
     for name, idx, b in (("shift_update", 4, shift_bytes), ("dslash", 0, dslash_bytes)):
         calls = int(stage_calls[idx])  # launches timed (every k-th when sampling)
-        if calls == 0 or stage_ms[idx] <= 0 or launched == 0:
+        if calls == 0 or stage_ms[idx] <= 0 or launched_tot == 0:
             rep[name] = None
             continue
         avg_s = stage_ms[idx] / 1e3 / calls
-        per_launch = b / launched
+        per_launch = b / launched_tot
         ach = per_launch / avg_s / 1e9
         rep[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(name, w.name),
-                     "kernel": name, "launches": launched, "launches_timed": calls, "avg_launch_us": round(avg_s * 1e6, 2),
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": pmc_traffic(name, w.name, mode), "kernel": name,
+                     "working_set_resident_in": resident,
+                     "launches": launched_tot, "launches_timed": calls, "avg_launch_us": round(avg_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": round(per_launch)}
-    dominant = "shift_update" if stage_ms[4] >= stage_ms[0] else "dslash"
+    per_step = stage_est / args.steps
+    dominant = "shift_update" if per_step[4] >= per_step[0] else "dslash"
+    stage_split = {STAGES[i]: round(float(per_step[i]), 3) for i in range(6) if i != 3}
+    matvec_ms = float(per_step[0])
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -438,7 +514,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "ms_per_step": round(step_ms, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -447,34 +523,46 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.dims), "kappa": w.kappa, "eps": w.eps, "seed": w.seed,
                    "interval": [w.gamma - w.rho, w.gamma + w.rho], "beta": w.beta, "N": w.N, "L": w.L,
-                   "M": w.M, "tol": w.tol, "prec": mode, "link_reals": w.link_reals,
+                   "M": w.M, "tol": w.tol, "prec": mode,
+                   "link_reals": w.link_reals if prec == S.MIXED else 18,
                    "method": args.method, "moments_in_loop": bool(args.moments_in_loop),
                    "weighted_tol": bool(args.weighted_tol), "parallelism": "single GPU"},
         "roofline": rep[dominant],
         "dslash": rep["dslash"],
         "site_shift_updates_per_s": round(value * w.V, 1),
-        "seed_iters_per_step": tot["seed_iters"] / args.steps / w.L,
+        "seed_iters_per_source": tot["seed_iters"] / args.steps / w.L,
         "eigenpairs_found": int(out.n_found),
-        "stage_ms_per_step": {STAGES[i]: round(stage_ms[i] / args.steps, 3) for i in range(7) if i != 3},
+        "stage_ms_per_step": stage_split,
+        "table2_split": {"total_ms_per_step": round(step_ms, 2), "matvec_ms_per_step": round(matvec_ms, 2),
+                         "matvec_fraction": round(matvec_ms / step_ms, 4),
+                         "note": ("the paper's Table 2 reports matrix-vector time against total time; here "
+                                  "the seed dslash (the only product with A in the solve) against the step")},
         "phase_ms_per_step": {k: round(tot[k] * 1e3 / args.steps, 3) for k in ("t_solve", "t_moments", "t_extract")},
-        "timing": ("graph replay, no events" if args.no_events else
-                   "direct launches, HIP events around every launch" if args.sample_every == 1 else
-                   f"graph replay, HIP event-record nodes around the dslash and shift update of every "
-                   f"{args.sample_every}th iteration (offset {args.sample_every // 2} in each poll interval)"),
-        "value_without_events": round(graph_value, 1) if graph_value else None,
+        "timing": ("direct launches, HIP events around every launch" if args.sample_every == 1 else
+                   f"graph replay, HIP event-record nodes around every stage of every {args.sample_every}th "
+                   f"iteration (offset {args.sample_every // 2} in each poll interval) and around every "
+                   f"reliable update; stage times per step = sampled average x launches of the stage"),
     }
+    base_res = mode_summary(out, step_ms, w.L)
     if not args.no_compare:
-        line["tts"] = tts_compare(S, ctx, params, vd, max_eigs, args.steps)
-        tw = tts_window(S, ctx, w, vd, args.steps)
+        print("[bench] mixed-precision comparison", file=sys.stderr, flush=True)
+        line["tts"] = tts_compare(S, ctx, params, vd, max_eigs, args.tts_steps, step_ms, base_res)
+        print("[bench] eigen window", file=sys.stderr, flush=True)
+        tw, ext = tts_window(S, ctx, w, vd, 1)
         if tw is not None:
             line["tts_window"] = tw
+            line["extraction"] = ext
+    ctx.close()
+    del vd
+    torch.cuda.empty_cache()
     line["copy_bw_GBs"] = copy_bandwidth()
     if not args.no_dslash_large:
+        print("[bench] dslash alone on 24^3 x 48", file=sys.stderr, flush=True)
         line["dslash_24x48"] = dslash_large(S)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w)
+        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, tot["seed_iters"] // args.steps)
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

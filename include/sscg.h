@@ -61,7 +61,9 @@ enum {
   SSCG_EDEVICE = -3,     /* a HIP call failed                                    */
   SSCG_ENOTCONV = -4,    /* maxiter reached before every shift converged         */
   SSCG_EBREAKDOWN = -5,  /* <p, (sigma I - A) p> = 0 or a non-finite CG scalar   */
-  SSCG_ESTATE = -6       /* call out of order (e.g. no gauge field set)          */
+  SSCG_ESTATE = -6,      /* call out of order (e.g. no gauge field set)          */
+  SSCG_EINACCURATE = -7  /* a mixed-precision solve converged, but some shift's
+                            FP64 true residual exceeds true_factor * tol          */
 };
 
 enum { SSCG_FP64 = 0,    /* every vector, product and scalar in FP64                 */
@@ -112,9 +114,19 @@ typedef struct {
                             the graphs stay in the context, and a later solve whose
                             launches are the same (shapes, buffers, options) replays
                             them without capturing again                            */
+  int32_t pad;
+  double true_factor;    /* MIXED and MIXED_SHIFTS: after the solve every shift's
+                            FP64 true residual ||v - (z_j I - A) y_j|| / ||v|| is
+                            recomputed (FP32 updates can leave it above the implicit
+                            residual that froze the shift); if one exceeds
+                            true_factor * tol (times the shift's own tolerance
+                            multiplier, see weighted_tol) the solve returns
+                            SSCG_EINACCURATE with every output written. 0: the
+                            residuals are still computed and reported, no status   */
 } sscg_solve_opts;
 
-/* Default options: tol 1e-12, maxiter 100000, FP64, ru 50, poll 50, switch 1e-6, graph 1. */
+/* Default options: tol 1e-12, maxiter 100000, FP64, ru 50, poll 50, switch 1e-6, graph 1,
+ * true_factor 100. */
 void sscg_default_opts(sscg_solve_opts *o);
 
 /* Shifted CG (Sec. 2.2, eqs. 4-5): solves (z_j I - A) y_{l,j} = v_l for every
@@ -131,8 +143,10 @@ void sscg_default_opts(sscg_solve_opts *o);
  *              ||v_l - (z_j I - A) y_{l,j}|| / ||v_l|| recomputed in FP64
  *   iters      host int32 [nsrc] (output, may be NULL): seed iterations per source
  * Returns SSCG_ENOTCONV if some shift did not converge within maxiter (outputs are
- * still written), SSCG_EBREAKDOWN on a CG breakdown, SSCG_EINVAL for a zero or
- * non-finite source. Blocking. */
+ * still written), SSCG_EINACCURATE if a mixed-precision solve left some true
+ * residual above true_factor * tol (outputs written; true_res, when given, names the
+ * shifts), SSCG_EBREAKDOWN on a CG breakdown, SSCG_EINVAL for a zero or non-finite
+ * source. Blocking. */
 int sscg_shifted_cg_solve(sscg_ctx *ctx, const void *v, int32_t nsrc,
                           const double *z, int32_t nshift, double sigma_seed,
                           const sscg_solve_opts *opts, void *y, int32_t *conv_iter,
@@ -192,6 +206,12 @@ typedef struct {
   int64_t seed_iters_fp32;  /* of seed_iters, those made in the FP32 phase           */
   int32_t switch_iter;      /* iteration at which the FP32 phase began, -1 if never  */
   int32_t pad;
+  double max_true_res;      /* largest FP64 true residual ||v - (z_j I - A) y_j||/||v||
+                               over every node and source, recomputed after a
+                               mixed-precision solve with stored solutions; -1 when
+                               not computed (FP64 solves, moments in the loop)       */
+  int64_t extract_bytes;    /* device memory the extraction stage works in beyond the
+                               solve's: moment vectors, bases, products and vectors  */
 } sscg_ss_info;
 
 void sscg_default_ss_params(sscg_ss_params *p);
@@ -211,7 +231,8 @@ void sscg_default_ss_params(sscg_ss_params *p);
  *   n_found host int32 (output): pairs accepted; if more than max_eigs qualify,
  *           the max_eigs nearest gamma are returned and n_found is the full count
  *   info    host (output, may be NULL)
- * Blocking. */
+ * Returns SSCG_OK, or SSCG_ENOTCONV / SSCG_EINACCURATE from the solve stage with the
+ * extraction still done and every output written. Blocking. */
 int sscg_ss_eigs(sscg_ctx *ctx, const sscg_ss_params *p, const void *v, int32_t nsrc,
                  int32_t max_eigs, double *lambda, void *X, double *res,
                  int32_t *n_found, sscg_ss_info *info);
@@ -239,13 +260,17 @@ int sscg_batch_solve(sscg_ctx *const *ctxs, int32_t nprob, const void *const *v,
                      void *const *y, int32_t *const *conv_iter, double *const *true_res,
                      int32_t *const *iters);
 
-/* Eigen-decomposition of a small Hermitian matrix (host, FP64, cyclic Jacobi), the
- * dense step of the Rayleigh-Ritz and Hankel extraction (Sec. 2.1).
+/* Eigen-decomposition of a small Hermitian matrix (host, FP64: Householder reduction
+ * to a real symmetric tridiagonal matrix, then implicit symmetric QR steps with
+ * Wilkinson shifts), the dense step of the Rayleigh-Ritz and Hankel extraction
+ * (Sec. 2.1).
  *   A      host complex128 n x n, column-major (element (i, j) at 2 (i + n j)); read only
  *   evals  host double [n] (output, ascending)
  *   evecs  host complex128 n x n column-major (output, column k = unit eigenvector k),
  *          or NULL
- * Only the Hermitian part of A is used. Needs no device. */
+ * Only the Hermitian part of A is used. Needs no device. Returns SSCG_ENOTCONV if the
+ * QR iteration does not converge within 30 n + 30 steps (outputs undefined); the
+ * extraction in sscg_ss_eigs returns the same status in that case. */
 int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs);
 
 /* Per-stage timing of the last solve on this context, from HIP events on the
@@ -257,15 +282,19 @@ int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs);
  *   level 0  off (the default);
  *   level 1  every launch of the solve loop is bracketed by events, and the loop runs
  *            its launches directly (no graph replay);
- *   level k > 1  graph replay stays on, and the dslash (stage 0) and the shift update
- *            (stage 4) of the iterations i of each poll interval with i % k == k / 2 are
- *            bracketed by event-record nodes in the graph; the other stages are not
- *            timed. Stage averages are then over that sample, at a small cost to the
- *            loop.
+ *   level k > 1  graph replay stays on, and every stage of the iterations i of each
+ *            poll interval with i % k == k / 2 is bracketed by event-record nodes in the
+ *            graph, as is every reliable update (stage 5, on the last iteration of an
+ *            FP32 chunk). Stage averages are then over that sample, at a small cost
+ *            to the loop; sscg_stage_launches gives the launches to scale them by.
  * A level below 0 is SSCG_EINVAL. When timing is on, sscg_apply_A also adds its dslash
  * time to stage 0 (and blocks until it ends). */
 int sscg_set_profiling(sscg_ctx *ctx, int32_t level);
 int sscg_stage_times(const sscg_ctx *ctx, double ms[8], int64_t calls[8]);
+/* Launches of each stage (indices as above) in the last solve on this context,
+ * counted whether or not they were timed; stage 6 holds the iterations launched.
+ * A stage's time in the solve is ms[k] / calls[k] * launched[k]. */
+int sscg_stage_launches(const sscg_ctx *ctx, int64_t launched[8]);
 
 #ifdef __cplusplus
 }

@@ -21,12 +21,12 @@ import numpy as np
 _PKG = Path(__file__).resolve().parent
 LIB_PATH = Path(os.environ.get("SSCG_LIB", _PKG / "libsscg.so"))
 
-OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, ESTATE = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, ESTATE, EINACCURATE = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED, MIXED_SHIFTS = 0, 1, 2
 PATH_LINES, PATH_CIRCLE = 0, 1
 RR, HANKEL = 0, 1
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOTCONV: "ENOTCONV",
-           EBREAKDOWN: "EBREAKDOWN", ESTATE: "ESTATE"}
+           EBREAKDOWN: "EBREAKDOWN", ESTATE: "ESTATE", EINACCURATE: "EINACCURATE"}
 
 
 class SSCGError(RuntimeError):
@@ -38,7 +38,7 @@ class SSCGError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("prec", C.c_int32),
                 ("ru_interval", C.c_int32), ("poll_every", C.c_int32), ("switch_tol", C.c_double),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("pad", C.c_int32), ("true_factor", C.c_double)]
 
 
 class SSParams(C.Structure):
@@ -54,13 +54,15 @@ class SSInfo(C.Structure):
                 ("solve_status", C.c_int32), ("t_solve", C.c_double), ("t_moments", C.c_double),
                 ("t_extract", C.c_double), ("shift_updates", C.c_int64), ("matvecs", C.c_int64),
                 ("shift_updates_fp32", C.c_int64), ("seed_iters", C.c_int64), ("seed_iters_fp32", C.c_int64),
-                ("switch_iter", C.c_int32), ("pad", C.c_int32)]
+                ("switch_iter", C.c_int32), ("pad", C.c_int32), ("max_true_res", C.c_double),
+                ("extract_bytes", C.c_int64)]
 
 
 EXPORTS = ["sscg_create", "sscg_destroy", "sscg_last_error", "sscg_global_error", "sscg_set_gauge",
            "sscg_apply_A", "sscg_default_opts", "sscg_shifted_cg_solve", "sscg_ss_moments",
            "sscg_default_ss_params", "sscg_ss_eigs", "sscg_quad_lines", "sscg_quad_circle",
-           "sscg_batch_solve", "sscg_herm_eig", "sscg_set_profiling", "sscg_stage_times"]
+           "sscg_batch_solve", "sscg_herm_eig", "sscg_set_profiling", "sscg_stage_times",
+           "sscg_stage_launches"]
 
 _lib = None
 
@@ -99,6 +101,7 @@ def lib() -> C.CDLL:
     L.sscg_herm_eig.argtypes = [i32, pd, pd, pd]
     L.sscg_set_profiling.argtypes = [vp, i32]
     L.sscg_stage_times.argtypes = [vp, pd, C.POINTER(C.c_int64)]
+    L.sscg_stage_launches.argtypes = [vp, C.POINTER(C.c_int64)]
     _lib = L
     return L
 
@@ -299,6 +302,12 @@ class Context:
         calls = np.zeros(8, dtype=np.int64)
         lib().sscg_stage_times(self._h, _pd(ms), calls.ctypes.data_as(C.POINTER(C.c_int64)))
         return ms, calls
+
+    def stage_launches(self):
+        """Launches of each stage in the last solve (timed or not); index 6 = iterations."""
+        n = np.zeros(8, dtype=np.int64)
+        lib().sscg_stage_launches(self._h, n.ctypes.data_as(C.POINTER(C.c_int64)))
+        return n
 
 
 def batch_solve(ctxs, vs, zs, sigmas, ys, opts: SolveOpts | None = None, true_res=True):

@@ -69,13 +69,14 @@ struct sscg_ctx {
   std::map<std::string, Tune> tuned;
   // solver workspaces
   DevBuf v64, r64, p64, q64, W, r32, p32, q32, rbase, xpart64, xpart32, tmp, pq_part, rr_part, seed,
-      shift, zdev, small, cmom, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out;
+      shift, zdev, small, cmom, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out, trpart;
   SeedState *seed_host = nullptr;
   int seed_host_cap = 0;
   // profiling
   int profiling = 0;  // 0 off, 1 every launch, k > 1 every k-th iteration in graphs
   double stage_ms[ST_N] = {};
   int64_t stage_calls[ST_N] = {};
+  int64_t stage_launched[ST_N] = {};  // launches of each stage in the last solve
   std::vector<hipEvent_t> events;
   std::vector<double> hstage;  // host staging of small matrices sent to the device
   // solve-loop graphs kept across solves (FP64 and FP32 phase), with the bytes of
@@ -204,7 +205,7 @@ void sscg_destroy(sscg_ctx *c) {
   DevBuf *bufs[] = {&c->g64, &c->g32, &c->v64, &c->r64, &c->p64, &c->q64, &c->W, &c->r32, &c->p32,
                     &c->q32, &c->rbase, &c->xpart64, &c->xpart32, &c->tmp, &c->pq_part, &c->rr_part,
                     &c->seed, &c->shift, &c->zdev, &c->small, &c->cmom, &c->Ybuf, &c->Sbuf, &c->Qbuf, &c->AQbuf,
-                    &c->Xbuf, &c->AXbuf, &c->Accbuf, &c->apply_in, &c->apply_out};
+                    &c->Xbuf, &c->AXbuf, &c->Accbuf, &c->apply_in, &c->apply_out, &c->trpart};
   for (DevBuf *b : bufs) release(*b);
   if (c->seed_host) hipHostFree(c->seed_host);
   for (hipEvent_t e : c->events) hipEventDestroy(e);
@@ -226,6 +227,8 @@ void sscg_default_opts(sscg_solve_opts *o) {
   o->poll_every = 50;
   o->switch_tol = 1e-6;
   o->use_graph = 1;
+  o->pad = 0;
+  o->true_factor = 100.0;
 }
 
 int sscg_set_gauge(sscg_ctx *c, const double *U, int32_t link_reals) {
@@ -272,6 +275,11 @@ int sscg_stage_times(const sscg_ctx *c, double ms[8], int64_t calls[8]) {
     ms[i] = c->stage_ms[i];
     calls[i] = c->stage_calls[i];
   }
+  return SSCG_OK;
+}
+int sscg_stage_launches(const sscg_ctx *c, int64_t launched[8]) {
+  if (!c || !launched) return SSCG_EINVAL;
+  for (int i = 0; i < ST_N; ++i) launched[i] = c->stage_launched[i];
   return SSCG_OK;
 }
 
@@ -347,25 +355,41 @@ static void dslash_with(sscg_ctx *c, const Tune &t, const void *in, void *out, i
   launch_dslash(b, prec, t.nr, prec == 0 ? 18 : c->link_reals, t.bs, t.xcd, ct, st);
 }
 
-// Mean duration (ms) of reps launches after one warm-up launch, from HIP events.
+// A launch shape whose launch the runtime rejected (kTuneFailed) never wins a search.
+constexpr double kTuneFailed = 1e300;
+
+// Mean duration (ms) of reps launches after one warm-up launch, from HIP events on
+// events e0, e1; kTuneFailed if any launch was rejected (the error is cleared).
+template <typename F>
+static double time_with_events(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F &&launch, int reps) {
+  (void)hipGetLastError();
+  launch();
+  if (hipGetLastError() != hipSuccess) return kTuneFailed;
+  hipEventRecord(e0, st);
+  for (int r = 0; r < reps; ++r) launch();
+  const hipError_t le = hipGetLastError();
+  hipEventRecord(e1, st);
+  hipEventSynchronize(e1);
+  if (le != hipSuccess) return kTuneFailed;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+    (void)hipGetLastError();
+    return kTuneFailed;
+  }
+  return ms / reps;
+}
 template <typename F>
 static double time_launches(hipStream_t st, F &&launch, int reps) {
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return 1e300;
+  if (hipEventCreate(&e0) != hipSuccess) return kTuneFailed;
   if (hipEventCreate(&e1) != hipSuccess) {
     hipEventDestroy(e0);
-    return 1e300;
+    return kTuneFailed;
   }
-  launch();
-  hipEventRecord(e0, st);
-  for (int r = 0; r < reps; ++r) launch();
-  hipEventRecord(e1, st);
-  hipEventSynchronize(e1);
-  float ms = 0.f;
-  hipEventElapsedTime(&ms, e0, e1);
+  const double t = time_with_events(st, e0, e1, launch, reps);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  return ms / reps;
+  return t;
 }
 
 // A launch shape replaces the best one found so far only when it is at least 3 %
@@ -384,6 +408,8 @@ struct Trial {
 };
 template <typename F>
 static Tune refine_shapes(std::vector<Trial> &trials, const Tune &fallback, F &&time_shape) {
+  trials.erase(std::remove_if(trials.begin(), trials.end(), [](const Trial &t) { return t.t >= kTuneFailed; }),
+               trials.end());
   if (trials.empty()) return fallback;
   std::sort(trials.begin(), trials.end(),
             [](const Trial &a, const Trial &b) { return a.t < b.t || (a.t == b.t && a.order < b.order); });
@@ -393,6 +419,7 @@ static Tune refine_shapes(std::vector<Trial> &trials, const Tune &fallback, F &&
   double tbest = 1e300;
   for (const Trial &tr : trials) {
     const double t = std::min(time_shape(tr.cd), time_shape(tr.cd));
+    if (t >= kTuneFailed) continue;
     if (t < kTuneMargin * tbest || tbest == 1e300) {
       tbest = t;
       best = tr.cd;
@@ -486,6 +513,7 @@ struct Prob {
   int32_t *iters = nullptr;
   int status = SSCG_OK;
   int switch_iter = -1;   // iteration at which the FP32 phase began (output)
+  double max_true_res = -1.0;  // largest FP64 true residual if computed (output), else -1
   // moments accumulated inside the solve (y == nullptr then): S device FP64
   // planar [nmom][L][n] (zeroed by the caller), coefficients device [nmom][N]
   void *mom = nullptr;
@@ -693,10 +721,10 @@ struct Recorder {
 };
 
 // The iteration after its dslash: step length, seed residual, (reliable update,)
-// shift update with the shift scalars. rec marks every stage; smp (when given)
-// brackets the shift update alone.
+// shift update with the shift scalars. rec marks every stage; ru_rec (when given)
+// brackets the reliable update alone.
 static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, bool ru, int lr, const Tune &t,
-                                  hipStream_t st, Recorder &rec, Recorder *smp) {
+                                  hipStream_t st, Recorder &rec, Recorder *ru_rec) {
   const int sp = (prec == 1 && seed32) ? 1 : 0;  // seed precision
   if (!pl.fuse_alpha) {
     rec.mark(ST_ALPHA);
@@ -707,19 +735,19 @@ static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, boo
   launch_seed_r_update(sp == 0 ? pl.r64 : pl.r32, sp, st);
   if (ru_now) {
     rec.mark(ST_RU);
+    if (ru_rec) ru_rec->mark(ST_RU);
     launch_fold_seed(pl.fold_seed, st);
     launch_dslash(pl.dru, 0, t.nr, 18, t.bs, t.xcd, pl.ct, st);
     launch_reliable_residual(pl.rel, st);
+    if (ru_rec) ru_rec->mark(-1);
   }
   rec.mark(ST_SHIFT);
-  if (smp) smp->mark(ST_SHIFT);
   if (pl.nmom_max > 0) {  // FP64 seed in both phases (checked by run_solve)
     launch_shift_moments(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, st);
   } else {
     const VecBatch &u = prec == 0 ? pl.u64 : (sp == 1 ? pl.u32 : pl.u32s);
     launch_shift_update(u, prec, sp, prec == 1 && ru, t.unroll, t.nt, st);
   }
-  if (smp) smp->mark(-1);
 }
 
 // One iteration. prec: 0 FP64 phase, 1 FP32 phase; seed32: the FP32 phase also runs
@@ -727,20 +755,21 @@ static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, boo
 // iteration of an FP32 chunk (seed reliable update if seed32, fold of the FP32
 // shift partials into the FP64 solutions in both FP32 modes).
 // Timing marks: with every == 1 each launch is bracketed (the marks chain, one
-// interval per stage); with every == k > 1 only the dslash and the shift update of
-// iterations it % k == k / 2 are bracketed (start and stop marks; the first iteration
-// after a poll, whose launches start on an idle device, is not sampled).
+// interval per stage); with every == k > 1 every stage of the iterations
+// it % k == k / 2 is bracketed (a chain of marks closed by a stop mark; the first
+// iteration after a poll, whose launches start on an idle device, is not sampled),
+// and so is every reliable update (it falls on the last iteration of a chunk).
 static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru, int lr, const Tune &t,
                              hipStream_t st, Recorder &rec, int it = 0, int every = 1) {
   const int sp = (prec == 1 && seed32) ? 1 : 0;  // seed precision
   if (every > 1) {
     const bool smp = it % every == every / 2;
     Recorder off{rec.c, st, false, {}, nullptr};
-    if (smp) rec.mark(ST_DSLASH);
+    Recorder &r = smp ? rec : off;
+    r.mark(ST_DSLASH);
     launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, pl.ct, st);
-    if (smp) rec.mark(-1);
-    // the rest of the iteration untimed up to the shift update
-    launch_iteration_tail(pl, prec, seed32, ru, lr, t, st, off, smp ? &rec : nullptr);
+    launch_iteration_tail(pl, prec, seed32, ru, lr, t, st, r, smp ? nullptr : &rec);
+    r.mark(-1);
     return;
   }
   rec.mark(ST_DSLASH);
@@ -867,16 +896,7 @@ static int autotune(std::vector<Prob> &P, const sscg_solve_opts &o, int lr, hipS
   hipEvent_t e0, e1;
   HIPCHK(c0, hipEventCreate(&e0));
   HIPCHK(c0, hipEventCreate(&e1));
-  auto time_it = [&](auto &&launch, int reps) -> double {
-    launch();  // warm
-    hipEventRecord(e0, st);
-    for (int r = 0; r < reps; ++r) launch();
-    hipEventRecord(e1, st);
-    hipEventSynchronize(e1);
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    return ms / reps;
-  };
+  auto time_it = [&](auto &&launch, int reps) -> double { return time_with_events(st, e0, e1, launch, reps); };
   int maxL = 1, maxN = 1;
   for (Prob &p : P) {
     maxL = std::max(maxL, p.L);
@@ -1030,7 +1050,17 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   for (int i = 0; i < ST_N; ++i) {
     c0->stage_ms[i] = 0.0;
     c0->stage_calls[i] = 0;
+    c0->stage_launched[i] = 0;
   }
+  // launches of each stage in a chunk of len iterations of phase prec
+  auto count_chunk = [&](int prec, int len, bool full) {
+    int64_t *n = c0->stage_launched;
+    n[ST_DSLASH] += len;
+    n[ST_RUPD] += len;
+    n[ST_SHIFT] += len;
+    if (!pl.fuse_alpha) n[ST_ALPHA] += len;
+    if (prec == 1 && o.prec == SSCG_MIXED && full) n[ST_RU] += 1;
+  };
   Recorder rec{c0, st, c0->profiling > 0, {}, nullptr};
   // profiling level 1 times every launch and runs them directly (an event-record node
   // in a graph costs more than the launch gap it would hide); a level k > 1 samples
@@ -1120,6 +1150,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       for (int kk = 0; kk < chunk; ++kk)
         launch_iteration(pl, prec, seed32, prec == 1 && (kk == chunk - 1) && full, lr, tn, st, rec, kk, every);
     }
+    count_chunk(prec, chunk, full);
     k += chunk;
     // poll: commit the last iteration's staged state, then read the seed states
     if (!(use_graph && full)) rec.mark(-1);
@@ -1171,6 +1202,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   auto t1 = std::chrono::steady_clock::now();
   c0->stage_ms[ST_LOOP] = std::chrono::duration<double, std::milli>(t1 - t0).count();
   c0->stage_calls[ST_LOOP] = k;
+  c0->stage_launched[ST_LOOP] = k;
   // results
   int worst = SSCG_OK;
   for (Prob &p : P) {
@@ -1189,26 +1221,53 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       for (int j = 0; j < N; ++j)
         if (p.conv_iter) p.conv_iter[(size_t)l * N + j] = sh[(size_t)l * N + j].conv_iter;
     }
-    p.status = st_p;
-    if (st_p == SSCG_EBREAKDOWN) worst = SSCG_EBREAKDOWN;
-    else if (st_p == SSCG_ENOTCONV && worst == SSCG_OK) worst = SSCG_ENOTCONV;
-    // FP64 true residuals ||v - (z_j - A) y_j|| / ||v||
-    if (p.true_res && p.y) {
+    // FP64 true residuals ||v - (z_j - A) y_j|| / ||v||: when the caller asks for them,
+    // and always after a mixed-precision solve, whose FP32 updates can leave a shift's
+    // true residual above the implicit one that froze it; such a solve returns
+    // SSCG_EINACCURATE when one exceeds true_factor * tol (times the shift's own
+    // tolerance multiplier)
+    p.max_true_res = -1.0;
+    const bool mixed = o.prec != SSCG_FP64;
+    if (p.y && (p.true_res || mixed)) {
       const size_t n = c->n, vec64 = n * sizeof(double2);
       const int nb = 64;
+      std::vector<double> local;
+      double *tr = p.true_res;
+      if (!tr) {
+        local.resize((size_t)L * N);
+        tr = local.data();
+      }
+      // A y_j for L shifts at a time into q64 (one dslash launch), then the residual
+      // partials of those shifts; one read-back of all partials at the end
+      CHK(ensure(c, c->trpart, (size_t)L * N * nb * sizeof(double)));
+      double *part = (double *)c->trpart.p;
       for (int l = 0; l < L; ++l) {
         for (int j0 = 0; j0 < N; j0 += L) {
           const int cnt = std::min(L, N - j0);
           const char *yj = (const char *)p.y + ((size_t)l * N + j0) * vec64;
           dslash_with(c, apply_tune(c, yj, c->q64.p, cnt, 0, st), yj, c->q64.p, cnt, 0, 0, 0.0, nullptr, nullptr, st);
           launch_true_residual((const char *)c->v64.p + l * vec64, yj, c->q64.p, (const double *)c->zdev.p + 2 * j0,
-                               (int64_t)n, cnt, (double *)c->rr_part.p, nb, st);
-          std::vector<double> r2;
-          CHK(host_sum_partials(c, (double *)c->rr_part.p, cnt, nb, r2, st));
-          for (int t = 0; t < cnt; ++t) p.true_res[(size_t)l * N + j0 + t] = std::sqrt(r2[t]) / seeds[l].vnorm;
+                               (int64_t)n, cnt, part + ((size_t)l * N + j0) * nb, nb, st);
         }
       }
+      std::vector<double> r2;
+      CHK(host_sum_partials(c, part, L * N, nb, r2, st));
+      for (int l = 0; l < L; ++l)
+        for (int j = 0; j < N; ++j) tr[(size_t)l * N + j] = std::sqrt(r2[(size_t)l * N + j]) / seeds[l].vnorm;
+      bool inaccurate = false;
+      for (int l = 0; l < L; ++l)
+        for (int j = 0; j < N; ++j) {
+          const double t = tr[(size_t)l * N + j];
+          p.max_true_res = std::max(p.max_true_res, t);
+          const double scale = p.tscale.empty() ? 1.0 : p.tscale[j];
+          if (!(t <= o.true_factor * o.tol * scale)) inaccurate = true;
+        }
+      if (mixed && o.true_factor > 0 && inaccurate && st_p == SSCG_OK) st_p = SSCG_EINACCURATE;
     }
+    p.status = st_p;
+    if (st_p == SSCG_EBREAKDOWN) worst = SSCG_EBREAKDOWN;
+    else if (st_p == SSCG_ENOTCONV && worst != SSCG_EBREAKDOWN) worst = SSCG_ENOTCONV;
+    else if (st_p == SSCG_EINACCURATE && worst == SSCG_OK) worst = SSCG_EINACCURATE;
     if (!p.keep_planar && p.y) {
       const size_t n = c->n, vec64 = n * sizeof(double2);
       for (size_t kk = 0; kk < (size_t)L * N; ++kk) {
@@ -1287,7 +1346,7 @@ int sscg_quad_circle(int32_t N, double gamma, double rho, double *z, double *zet
 
 int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs) {
   if (n <= 0 || !A || !evals) return fail(nullptr, SSCG_EINVAL, "bad argument");
-  herm_eig(n, A, evals, evecs);
+  if (!herm_eig(n, A, evals, evecs)) return fail(nullptr, SSCG_ENOTCONV, "QR iteration did not converge");
   return SSCG_OK;
 }
 
@@ -1359,6 +1418,7 @@ int sscg_shifted_cg_solve(sscg_ctx *c, const void *v, int32_t nsrc, const double
   int rc = run_solve(P, *opts);
   if (rc == SSCG_ENOTCONV) c->err = "maxiter reached before every shift converged";
   if (rc == SSCG_EBREAKDOWN) c->err = "CG breakdown: <p, (sigma I - A) p> vanished or a scalar is not finite";
+  if (rc == SSCG_EINACCURATE) c->err = "a shift's FP64 true residual exceeds true_factor * tol after the mixed solve";
   return rc;
 }
 
@@ -1472,7 +1532,7 @@ static int basis_change(sscg_ctx *c, const void *A, int na, const std::vector<cd
 // Hermitian eigen-decomposition of a row-major n x n complex matrix (uses the
 // column-major routine on the transpose; for a Hermitian matrix the transpose is
 // the conjugate, whose eigenvectors are the conjugates).
-static void eig_rowmajor(int n, const std::vector<cd> &A, std::vector<double> &ev, std::vector<cd> &W) {
+static bool eig_rowmajor(int n, const std::vector<cd> &A, std::vector<double> &ev, std::vector<cd> &W) {
   std::vector<double> a(2 * (size_t)n * n), vv(2 * (size_t)n * n);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {  // column-major element (i, j) = A[i][j]
@@ -1480,11 +1540,16 @@ static void eig_rowmajor(int n, const std::vector<cd> &A, std::vector<double> &e
       a[2 * (i + (size_t)n * j) + 1] = A[(size_t)i * n + j].imag();
     }
   ev.resize(n);
-  herm_eig(n, a.data(), ev.data(), vv.data());
+  const bool ok = herm_eig(n, a.data(), ev.data(), vv.data());
   W.resize((size_t)n * n);  // row-major: W[i][k] = component i of eigenvector k
   for (int k = 0; k < n; ++k)
     for (int i = 0; i < n; ++i) W[(size_t)i * n + k] = cd(vv[2 * (i + (size_t)n * k)], vv[2 * (i + (size_t)n * k) + 1]);
+  return ok;
 }
+#define EIGCHK(ctx, call) \
+  do { \
+    if (!(call)) return fail(ctx, SSCG_ENOTCONV, "dense Hermitian eigensolver did not converge"); \
+  } while (0)
 
 // Upper Cholesky factor of a Hermitian positive definite row-major n x n matrix,
 // G = R^H R, and its inverse Rinv (row-major, upper triangular). Returns false if a
@@ -1568,7 +1633,7 @@ static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, voi
     for (int b = 0; b < ncol; ++b) Gs[(size_t)a * ncol + b] = dsc[a] * G[(size_t)a * ncol + b] * dsc[b];
   std::vector<double> ev;
   std::vector<cd> W;
-  eig_rowmajor(ncol, Gs, ev, W);
+  EIGCHK(c, eig_rowmajor(ncol, Gs, ev, W));
   const double emax = ev.back();
   std::vector<int> keep;
   for (int k = ncol - 1; k >= 0; --k)
@@ -1591,7 +1656,7 @@ static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, voi
   if (!chol_inverse_upper(r, G2, T2)) {
     std::vector<double> ev2;
     std::vector<cd> W2;
-    eig_rowmajor(r, G2, ev2, W2);
+    EIGCHK(c, eig_rowmajor(r, G2, ev2, W2));
     T2.assign((size_t)r * r, cd(0, 0));
     for (int a = 0; a < r; ++a)
       for (int q = 0; q < r; ++q) T2[(size_t)a * r + q] = W2[(size_t)a * r + q] / std::sqrt(std::max(ev2[q], 1e-300));
@@ -1601,7 +1666,7 @@ static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, voi
   std::vector<cd> At;
   CHK(gram(c, c->Qbuf.p, r, c->AQbuf.p, r, At, st));
   std::vector<cd> Wr;
-  eig_rowmajor(r, At, lam, Wr);
+  EIGCHK(c, eig_rowmajor(r, At, lam, Wr));
   CHK(basis_change(c, c->Qbuf.p, r, Wr, r, Xd, st, c->AQbuf.p, AXd));
   (void)vec;
   return SSCG_OK;
@@ -1643,7 +1708,7 @@ static int extract_hankel(sscg_ctx *c, const std::vector<cd> &mu, int L, int M, 
         }
   std::vector<double> ev;
   std::vector<cd> W;
-  eig_rowmajor(m, H, ev, W);
+  EIGCHK(c, eig_rowmajor(m, H, ev, W));
   const double emax = ev.back();
   std::vector<int> keep;
   for (int k = m - 1; k >= 0; --k)
@@ -1667,7 +1732,7 @@ static int extract_hankel(sscg_ctx *c, const std::vector<cd> &mu, int L, int M, 
     }
   std::vector<double> eta;
   std::vector<cd> T;
-  eig_rowmajor(r, red, eta, T);
+  EIGCHK(c, eig_rowmajor(r, red, eta, T));
   lam.resize(r);
   for (int q = 0; q < r; ++q) lam[q] = gamma + rho * eta[q];
   std::vector<cd> Tc((size_t)m * r, cd(0, 0));
@@ -1804,7 +1869,7 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   PP[0].conv_iter = conv.data();
   auto t0 = std::chrono::steady_clock::now();
   int rc = run_solve(PP, p->solve);
-  if (rc != SSCG_OK && rc != SSCG_ENOTCONV) return rc;
+  if (rc != SSCG_OK && rc != SSCG_ENOTCONV && rc != SSCG_EINACCURATE) return rc;
   auto t1 = std::chrono::steady_clock::now();
   double t_mom = 0.0;
   if (!in_loop) CHK(ensure(c, c->Sbuf, (size_t)ncol * vec));
@@ -1832,6 +1897,7 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   };
   std::vector<Acc> acc;
   int total_found = 0, rank_max = 0, ncand = 0;
+  int64_t ext_bytes = 0;
   if (X && max_eigs > 0) CHK(ensure(c, c->Accbuf, (size_t)max_eigs * vec));
   for (int q = 0; q < P; ++q) {
     const void *Sq = c->Sbuf.p;
@@ -1867,6 +1933,11 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
     }
     rank_max = std::max(rank_max, r);
     ncand += r;
+    // device memory of this pair's extraction: the moment vectors S (n x M L); for
+    // Rayleigh-Ritz the basis Q and A Q (r vectors each); for both, the vectors X and
+    // A X of the r candidates (the buffers are reused from pair to pair)
+    ext_bytes = std::max(ext_bytes, (int64_t)((size_t)ncol + (p->method == SSCG_RR ? 2 * (size_t)r : 0) +
+                                              2 * (size_t)r) * (int64_t)vec);
     if (r == 0) continue;
     std::vector<double> rs, xn;
     CHK(col_residuals(c, AXd, Xd, r, lam, rs, xn, st));
@@ -1959,6 +2030,8 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
     info->seed_iters = mv;
     info->seed_iters_fp32 = it32;
     info->switch_iter = ks;
+    info->max_true_res = PP[0].max_true_res;
+    info->extract_bytes = ext_bytes + (X && max_eigs > 0 ? (int64_t)max_eigs * (int64_t)vec : 0);
   }
-  return rc == SSCG_ENOTCONV ? SSCG_ENOTCONV : SSCG_OK;
+  return rc == SSCG_ENOTCONV || rc == SSCG_EINACCURATE ? rc : SSCG_OK;
 }

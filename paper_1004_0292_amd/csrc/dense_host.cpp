@@ -2,15 +2,23 @@
 // projected matrices of the Rayleigh-Ritz and Hankel extraction (Sec. 2.1);
 // sizes are at most M*L (a few hundred).
 //
-// Method: Householder reduction to a real symmetric tridiagonal matrix followed
-// by the implicit QL iteration with shifts (the tql2 scheme of Bowdler, Martin,
-// Reinsch and Wilkinson, 1968), then back-transformation of the eigenvectors.
+// Method: Householder reduction to a real symmetric tridiagonal matrix, the
+// implicit symmetric QR iteration with Wilkinson shifts on it, then
+// back-transformation of the eigenvectors.
 //   1. For k = 0 .. n-3 a reflector H_k = I - beta v v^H maps column k below the
 //      diagonal onto alpha e_1 and is applied to the trailing block as a
 //      Hermitian rank-2 update; A = Q T Q^H with Q = H_0 ... H_{n-3}.
 //   2. The complex sub-diagonal of T is made real by a diagonal unitary D:
 //      T = D T_r D^H with T_r real symmetric tridiagonal.
-//   3. QL with implicit shifts diagonalises T_r = Z diag(lambda) Z^T.
+//   3. Implicit QR steps diagonalise T_r = Z diag(lambda) Z^T. Each step works on
+//      the trailing unreduced block [lo, hi] (off-diagonal entries below
+//      eps (|a_k| + |a_{k+1}|) count as zero): the shift mu is the eigenvalue of
+//      the block's last 2x2 corner nearer to a_hi; a rotation in the plane
+//      (lo, lo+1) taken from the first column (a_lo - mu, b_lo) of T - mu I
+//      starts the step, and rotations in the planes (k, k+1) then move the
+//      off-tridiagonal entry it creates down the block until it leaves at the
+//      bottom. T stays symmetric tridiagonal, the step equals one shifted QR
+//      step on the block, and b_{hi-1} falls off quickly (cubically near the end).
 //   4. Eigenvectors of A are the columns of Q D Z.
 //
 // Matrices are column-major, complex as interleaved doubles: element (i, j) is
@@ -38,9 +46,9 @@ inline double hyp(double a, double b) {
 
 // Built twice, for AVX2 with FMA and for plain x86-64; the loader picks the first at
 // run time where the processor has it.
-__attribute__((target_clones("arch=x86-64-v3", "default"))) void herm_eig(int n, const double *Ain, double *evals,
+__attribute__((target_clones("arch=x86-64-v3", "default"))) bool herm_eig(int n, const double *Ain, double *evals,
                                                                           double *evecs) {
-  if (n <= 0) return;
+  if (n <= 0) return true;
   const size_t nn = (size_t)n * n;
   std::vector<double> Ar(nn), Ai(nn);  // column-major, split real / imaginary parts
   // Hermitian part of the input
@@ -123,53 +131,65 @@ __attribute__((target_clones("arch=x86-64-v3", "default"))) void herm_eig(int n,
     } else { dr[k + 1] = dr[k]; di[k + 1] = di[k]; }
   }
   e[n - 1] = 0.0;
-  // 3. implicit QL on (d, e); Z accumulates the rotations (column-major n x n)
+  // 3. implicit symmetric QR on (d, e): d the diagonal, e[k] the entry (k, k+1);
+  // Z accumulates the rotations (column-major n x n)
   std::vector<double> Z(nn, 0.0);
   for (int i = 0; i < n; ++i) Z[id(i, i)] = 1.0;
   const double eps = std::numeric_limits<double>::epsilon();
-  for (int l = 0; l < n; ++l) {
-    int iter = 0;
-    for (;;) {
-      int m = l;
-      for (; m < n - 1; ++m) {
-        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-        if (std::fabs(e[m]) <= eps * dd) break;
+  auto negligible = [&](int k) { return std::fabs(e[k]) <= eps * (std::fabs(d[k]) + std::fabs(d[k + 1])); };
+  // rotation G = [[c, s], [-s, c]] in the plane (k, k+1): T <- G T G^T, Z <- Z G^T
+  auto rotate_z = [&](int k, double c, double s) {
+    double *zk = &Z[id(0, k)], *zk1 = &Z[id(0, k + 1)];
+    for (int q = 0; q < n; ++q) {
+      const double u = zk[q], v = zk1[q];
+      zk[q] = c * u + s * v;
+      zk1[q] = c * v - s * u;
+    }
+  };
+  bool converged = true;
+  long steps = 0;
+  const long max_steps = 30L * n + 30;
+  int hi = n - 1;
+  while (hi > 0) {
+    if (negligible(hi - 1)) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && !negligible(lo - 1)) --lo;
+    if (lo > 0) e[lo - 1] = 0.0;
+    if (++steps > max_steps) {
+      converged = false;
+      break;
+    }
+    // Wilkinson shift: eigenvalue of [[d_{hi-1}, e_{hi-1}], [e_{hi-1}, d_hi]] nearer d_hi
+    const double half = 0.5 * (d[hi - 1] - d[hi]), bb = e[hi - 1];
+    const double den = half + (half >= 0.0 ? hyp(half, bb) : -hyp(half, bb));
+    const double mu = d[hi] - bb * (bb / den);
+    double x = d[lo] - mu, z = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = hyp(x, z);
+      const double c = r > 0.0 ? x / r : 1.0, s = r > 0.0 ? z / r : 0.0;
+      if (k > lo) e[k - 1] = r;  // the entry (k-1, k+1) is rotated away
+      const double ak = d[k], ak1 = d[k + 1], bk = e[k];
+      const double cc = c * c, ss = s * s, cs = c * s;
+      d[k] = cc * ak + 2.0 * cs * bk + ss * ak1;
+      d[k + 1] = ss * ak - 2.0 * cs * bk + cc * ak1;
+      e[k] = cs * (ak1 - ak) + (cc - ss) * bk;
+      if (k + 1 < hi) {  // the rotation creates the entry (k, k+2) = s e_{k+1}
+        z = s * e[k + 1];
+        e[k + 1] *= c;
+        x = e[k];
       }
-      if (m == l) break;
-      if (++iter > 60) break;  // does not happen for Hermitian input; guards the loop
-      // shift from the leading 2x2 block of the unreduced part
-      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = hyp(g, 1.0);
-      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
-      double s = 1.0, c = 1.0, pp = 0.0;
-      bool deflated = false;
-      for (int i = m - 1; i >= l; --i) {
-        const double f = s * e[i], bb = c * e[i];
-        r = hyp(f, g);
-        e[i + 1] = r;
-        if (r == 0.0) { d[i + 1] -= pp; e[m] = 0.0; deflated = true; break; }
-        s = f / r; c = g / r;
-        g = d[i + 1] - pp;
-        r = (d[i] - g) * s + 2.0 * c * bb;
-        pp = s * r;
-        d[i + 1] = g + pp;
-        g = c * r - bb;
-        double *zi = &Z[id(0, i)], *zi1 = &Z[id(0, i + 1)];
-        for (int q = 0; q < n; ++q) {
-          const double t = zi1[q];
-          zi1[q] = s * zi[q] + c * t;
-          zi[q] = c * zi[q] - s * t;
-        }
-      }
-      if (deflated) continue;
-      d[l] -= pp; e[l] = g; e[m] = 0.0;
+      rotate_z(k, c, s);
     }
   }
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::sort(order.begin(), order.end(), [&](int x, int y) { return d[x] < d[y]; });
   for (int k = 0; k < n; ++k) evals[k] = d[order[k]];
-  if (!evecs) return;
+  if (!evecs) return converged;
   // 4. eigenvectors X = Q D Z (columns in ascending eigenvalue order), held
   // row-major (X[i][c] at i n + c) so the reflector sums run over contiguous columns
   std::vector<double> Xr(nn), Xi(nn), tr(n), ti(n);
@@ -208,5 +228,6 @@ __attribute__((target_clones("arch=x86-64-v3", "default"))) void herm_eig(int n,
       evecs[2 * id(i, c)] = Xr[(size_t)i * n + c];
       evecs[2 * id(i, c) + 1] = Xi[(size_t)i * n + c];
     }
+  return converged;
 }
 }  // namespace sscg

@@ -22,6 +22,8 @@
 // (shifted by the hop); neighbour reuse is left to L2. Blocks are renumbered so
 // that consecutive site tiles land on the same XCD (the hardware deals blocks
 // round-robin over the 8 XCDs, each with its own L2).
+#include <algorithm>
+
 #include "sscg_internal.h"
 
 namespace sscg {
@@ -649,10 +651,18 @@ __global__ __launch_bounds__(MAXBS, (tile_min_blocks<T, NR, MAXBS>())) void dsla
 
 template <typename T, int NR, int LR, int MAXBS>
 static void launch_tile(const DslashBatch &b, int bs, size_t shm, int xcd, hipStream_t st) {
-  static bool raised = false;  // allow more than the default dynamic LDS once per kernel
-  if (shm > 65536 && !raised) {
+  // dynamic LDS above the default needs the kernel attribute; it is raised once per
+  // instantiation to the most this instantiation can ask for (NR sources of MAXBS
+  // sites), so every tile size it launches is covered (the device limit is checked
+  // by the caller's tile choice)
+  static bool raised = false;
+  constexpr size_t kMaxShm = (size_t)NR * 12 * MAXBS * sizeof(V2<T>);
+  if (kMaxShm > 65536 && !raised) {
+    int dev = 0, lim = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lim = 65536;
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&dslash_tile_kernel<T, NR, LR, MAXBS>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::min(kMaxShm, (size_t)lim));
     raised = true;
   }
   hipLaunchKernelGGL((dslash_tile_kernel<T, NR, LR, MAXBS>), dim3(b.total_blocks + b.commit), dim3(bs), shm, st, b, xcd);

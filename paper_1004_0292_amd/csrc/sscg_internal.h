@@ -316,8 +316,9 @@ void launch_resid_cols(const void *AX, const void *X, int64_t ld, int ncol, cons
 void launch_reduce_partials(const double *partial, int nchunk, int nout, double *out, hipStream_t st);
 
 // dense_host.cpp: Hermitian eigen-decomposition (Householder tridiagonalisation and
-// implicit QL), column-major complex matrices as interleaved doubles. Eigenvalues
-// ascending.
-void herm_eig(int n, const double *A, double *evals, double *evecs);
+// implicit symmetric QR with Wilkinson shifts), column-major complex matrices as
+// interleaved doubles. Eigenvalues ascending. Returns false if the QR iteration did
+// not converge within its step limit (outputs then undefined).
+bool herm_eig(int n, const double *A, double *evals, double *evecs);
 
 }  // namespace sscg

@@ -148,7 +148,7 @@ CONFIGS = {
                          0.0, 0.08, 0.25, 32, 4, 16, prec="mixed"),
     "batch_16": Workload("batch_16", (16, 16, 16, 16), 0.13, 0.5, 5,
                          0.0, 0.05, 0.25, 48, 4, 24, prec="mixed"),
-    "wilson24x48_mixed12": Workload("wilson24x48_mixed12", (24, 24, 24, 48), 0.135, 0.7, 6,
+    "wilson24x48": Workload("wilson24x48", (24, 24, 24, 48), 0.135, 0.7, 6,
                                     0.0, 0.05, 0.4, 64, 8, 24, prec="mixed", link_reals=12),
 }
 BATCH = ("batch_8", "batch_12", "batch_16")

@@ -135,3 +135,30 @@ def test_struct_layouts_match_header(sscg, tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+@pytest.mark.parametrize("n", [1, 2, 256])
+def test_herm_eig_sizes(sscg, n):
+    """Smallest sizes and the largest projected matrix the extraction forms (M L <= 256),
+    with a graded spectrum spanning ten orders of magnitude."""
+    rng = np.random.default_rng(100 + n)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    lam = np.sort(np.geomspace(1e-10, 1.0, n) * np.where(np.arange(n) % 2, -1.0, 1.0))
+    A = (Q * lam) @ Q.conj().T
+    ev, V = sscg.herm_eig(A)
+    assert np.abs(ev - lam).max() < 1e-13
+    assert np.abs(A @ V - V * ev).max() < 1e-13
+    assert np.abs(V.conj().T @ V - np.eye(n)).max() < 1e-12
+
+
+def test_herm_eig_already_split(sscg):
+    """A tridiagonal input whose off-diagonal entries are below the deflation threshold
+    in some places (the iteration splits it into independent blocks)."""
+    n = 40
+    d = np.linspace(-1.0, 1.0, n)
+    e = np.full(n - 1, 0.3)
+    e[::7] = 1e-18
+    A = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    ev, V = sscg.herm_eig(A.astype(complex))
+    assert np.abs(ev - np.linalg.eigvalsh(A)).max() < 1e-14
+    assert np.abs(A @ V - V * ev).max() < 1e-14

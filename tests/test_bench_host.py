@@ -24,12 +24,12 @@ def test_committed_counter_summaries_are_well_formed():
     assert files
     for f in files:
         d = json.loads(f.read_text())
-        for key in ("workload", "kernel", "source", "source_sha256_16", "hbm_bytes_per_launch", "calibration",
-                    "command_fetch", "command_write"):
+        for key in ("workload", "prec", "kernel", "source", "source_sha256_16", "hbm_bytes_per_launch",
+                    "calibration", "command_fetch", "command_write"):
             assert key in d, (f.name, key)
         cal = d["calibration"]
         rd = d["fetch_kib_per_dispatch"] * 1024 * cal["fetch_scale"]
         wr = d["write_kib_per_dispatch"] * 1024 * cal["write_scale"]
         assert abs(d["hbm_bytes_per_launch"] - (rd + wr)) <= 2
         assert (ROOT / d["source"]).exists()
-        assert f.name == f"{d['kernel']}_{d['workload']}_pmc.txt"
+        assert f.name == f"{d['kernel']}_{d['workload']}_{d['prec']}_pmc.txt"

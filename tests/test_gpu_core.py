@@ -19,7 +19,7 @@ import pytest
 import synth
 from oracle import quadrature as quad
 from oracle import solvers, ss, wilson
-from tests.helpers import case, rel, to_dev, to_host
+from tests.helpers import case, to_dev, to_host, vec_err
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +53,7 @@ def test_apply_A_fp64(sscg, dims, nsrc):
     c.apply_A(xd, yd)
     y = to_host(yd).reshape(nsrc, -1)
     ref = np.array([A @ xv for xv in x.reshape(nsrc, -1)])
-    assert rel(y, ref) < 1e-14
+    assert vec_err(y, ref) < 1e-14
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 2, 5), (8, 8, 8, 8), (3, 5, 7, 2)])
@@ -84,11 +84,11 @@ def test_apply_A_tile_kernel(sscg, monkeypatch, dims, ct, nr, tbs):
             c.apply_A(to_dev(x), yd, prec=prec)
             out[k, prec, lr] = to_host(yd).reshape(nsrc, -1)
             c.close()
-    assert rel(out["march", sscg.FP64, 18], ref) < 1e-14
-    assert rel(out["march", sscg.FP64, 18], out["plain", sscg.FP64, 18]) < 1e-15
+    assert vec_err(out["march", sscg.FP64, 18], ref) < 1e-14
+    assert vec_err(out["march", sscg.FP64, 18], out["plain", sscg.FP64, 18]) < 1e-15
     for lr in (18, 12):
-        assert rel(out["march", sscg.MIXED, lr], out["plain", sscg.MIXED, lr]) < 1e-6
-        assert rel(out["march", sscg.MIXED, lr], ref) < 2e-6
+        assert vec_err(out["march", sscg.MIXED, lr], out["plain", sscg.MIXED, lr]) < 1e-6
+        assert vec_err(out["march", sscg.MIXED, lr], ref) < 2e-6
 
 
 @pytest.mark.parametrize("link_reals", [18, 12])
@@ -101,7 +101,7 @@ def test_apply_A_fp32(sscg, cfg1, link_reals):
     c.apply_A(to_dev(x), yd, prec=sscg.MIXED)
     y = to_host(yd).reshape(2, -1)
     ref = np.array([A @ xv for xv in x.reshape(2, -1)])
-    assert rel(y, ref) < 2e-6
+    assert vec_err(y, ref) < 2e-6
 
 
 def test_shifted_cg_fixed_iteration(sscg, cfg1):
@@ -122,7 +122,7 @@ def test_shifted_cg_fixed_iteration(sscg, cfg1):
     r = c.shifted_cg_solve(to_dev(v), z, CFG1.gamma, y, sscg.default_opts(maxiter=20, poll_every=7))
     assert r.status == sscg.ENOTCONV
     assert r.iters[0] == 20
-    assert rel(to_host(y).reshape(CFG1.N, -1), snap["X"]) < 1e-10
+    assert vec_err(to_host(y).reshape(CFG1.N, -1), snap["X"]) < 1e-10
 
 
 def test_shifted_cg_converged(sscg, cfg1):
@@ -136,11 +136,37 @@ def test_shifted_cg_converged(sscg, cfg1):
     r = c.shifted_cg_solve(to_dev(v), z, CFG1.gamma, y)
     assert r.status == sscg.OK
     Y = to_host(y).reshape(CFG1.N, -1)
-    assert rel(Y, ref.Y) < 1e-9
+    assert vec_err(Y, ref.Y) < 1e-9
     assert np.all(np.abs(r.conv_iter[0] - ref.conv_iter) <= 2)
     assert r.true_res.max() < 5e-12
     tr = solvers.true_residuals(lambda x: A @ x, v[0], z, Y)
     assert tr.max() < 5e-12
+
+
+@pytest.mark.parametrize("L", [1, 2, 7])
+def test_free_field_block_ss(sscg, L):
+    """Block SS with L sources (Sec. 2.1, block form) on the free field, whose spectrum
+    is known in closed form: at 4^4 and kappa = 0.12 the eigenvalues nearest 0 are
+    +-0.04, each six-fold, and the next |lambda| is 0.369. The interval [-0.03, 0.03]
+    holds no eigenvalue, so nothing may be reported there; [-0.05, 0.05] gives +-0.04
+    with multiplicity min(L, 6) (the moments of L sources span at most L vectors of an
+    eigenspace), with orthonormal eigenvectors."""
+    case(f"free-field block SS L={L}")
+    dims, kappa = (4, 4, 4, 4), 0.12
+    spec = wilson.free_field_spectrum(dims, kappa)
+    assert np.sum(np.abs(spec) <= 0.05) == 12 and np.sum(np.abs(spec) <= 0.03) == 0
+    U = synth.unit_gauge(dims)
+    c = make_ctx(sscg, dims, kappa, U)
+    vd = to_dev(synth.sources(256, L, 3).reshape(L, -1))
+    out = c.ss_eigs(sscg.default_ss_params(gamma=0.0, rho=0.03, beta=0.25, N=16, M=8), vd, max_eigs=32)
+    assert out.n_found == 0
+    out = c.ss_eigs(sscg.default_ss_params(gamma=0.0, rho=0.05, beta=0.25, N=16, M=8), vd, max_eigs=32)
+    m = min(L, 6)
+    assert out.n_found == 2 * m
+    assert np.abs(np.sort(out.lam) - np.array([-0.04] * m + [0.04] * m)).max() < 1e-12
+    assert out.res.max() < 1e-8
+    X = to_host(out.X).reshape(2 * m, -1)
+    assert np.abs(X.conj() @ X.T - np.eye(2 * m)).max() < 1e-8
 
 
 def test_moments(sscg, cfg1):
@@ -154,7 +180,7 @@ def test_moments(sscg, cfg1):
     c = sscg.Context(CFG1.dims, CFG1.kappa)
     s = to_dev(np.zeros((L, M, CFG1.n)))
     c.ss_moments(to_dev(Y), N, quad.moment_coefficients(zeta, w, M), s)
-    assert rel(to_host(s), ref) < 1e-14
+    assert vec_err(to_host(s), ref) < 1e-14
 
 
 def test_ss_eigs_many_columns(sscg, cfg1):

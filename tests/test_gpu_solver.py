@@ -24,7 +24,7 @@ import pytest
 import synth
 from oracle import quadrature as quad
 from oracle import solvers, wilson
-from tests.helpers import case, rel, to_dev, to_host
+from tests.helpers import case, to_dev, to_host, vec_err
 
 pytestmark = pytest.mark.gpu
 
@@ -83,8 +83,9 @@ def test_graphs_kept_across_solves(sscg, prob, monkeypatch):
 
 def test_profiling_levels(sscg, prob):
     """Level 1 times every launch (direct launches); level 5 keeps graph replay and
-    times the dslash and shift update of every 5th iteration. Neither changes the
-    results (bitwise), and the sampled launch averages agree with the full ones."""
+    times every stage of every 5th iteration. Neither changes the results (bitwise),
+    the sampled launch averages agree with the full ones, and the launch counts the
+    context reports scale the sample to the whole solve."""
     case("profiling levels")
     U, A, V, z = prob
     y_ref, r_ref = solve(sscg, U, V, z, poll_every=50, use_graph=1)
@@ -96,8 +97,10 @@ def test_profiling_levels(sscg, prob):
         y = to_dev(np.zeros((V.shape[0], len(z), V.shape[1])))
         r = c.shifted_cg_solve(to_dev(V), z, 0.0, y, sscg.default_opts(poll_every=50, use_graph=graph))
         ms, calls = c.stage_times()
+        launches = c.stage_launches()
         assert np.array_equal(to_host(y), y_ref) and np.array_equal(r.iters, r_ref.iters)
         out[level, graph] = (np.array(ms), np.array(calls))
+        out["launches", level, graph] = launches
         c.close()
     (ms1, calls1), (ms5, calls5) = out[1, 1], out[5, 1]
     # sampling with direct launches takes the same samples as inside the graphs
@@ -105,9 +108,14 @@ def test_profiling_levels(sscg, prob):
     launched = calls1[0]            # one dslash per launched iteration
     assert launched >= int(np.max(r_ref.iters)) and calls1[4] == launched
     assert calls1[2] == launched and calls1[3] == 0 and np.all(ms1[[0, 2, 4]] > 0)
-    # iterations 2, 7, 12, ... of each 50-iteration poll interval
-    assert calls5[0] == calls5[4] == launched // 5 and np.all(calls5[[1, 2, 3, 5]] == 0)
-    for s in (0, 4):
+    # every stage of iterations 2, 7, 12, ... of each 50-iteration poll interval (the
+    # step length is fused into the residual update on this lattice: no alpha stage)
+    assert calls5[0] == calls5[2] == calls5[4] == launched // 5 and np.all(calls5[[1, 3, 5]] == 0)
+    # launch counts: one dslash, residual update and shift update per launched iteration
+    for key in (("launches", 1, 1), ("launches", 5, 1), ("launches", 5, 0)):
+        n = out[key]
+        assert n[0] == n[2] == n[4] == n[6] == launched and n[1] == n[3] == n[5] == 0
+    for s in (0, 2, 4):
         a1, a5 = ms1[s] / calls1[s], ms5[s] / calls5[s]
         assert 0.3 < a5 / a1 < 3.0, (s, a1, a5)
     with pytest.raises(sscg.SSCGError):
@@ -153,7 +161,7 @@ def test_launch_shapes_agree(sscg, prob, monkeypatch, env):
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     y, r = solve(sscg, U, V, z)
-    assert rel(y, y_ref) < 1e-11
+    assert vec_err(y, y_ref) < 1e-11
     assert np.all(np.abs(r.conv_iter - r_ref.conv_iter) <= 2)
 
 
@@ -164,7 +172,7 @@ def test_several_sources_and_seed_shift(sscg, prob):
     assert r.status == sscg.OK
     for l in range(3):
         ref = solvers.shifted_cg(lambda x: A @ x, V[l], z, 0.07, 1e-12)
-        assert rel(y[l], ref.Y) < 1e-9
+        assert vec_err(y[l], ref.Y) < 1e-9
         assert np.all(np.abs(r.conv_iter[l] - ref.conv_iter) <= 2)
         assert r.iters[l] == pytest.approx(ref.iters, abs=2)
     assert r.true_res.max() < 5e-12
@@ -182,7 +190,7 @@ def test_mixed_precision_accuracy(sscg, prob, mode, link_reals):
     for l in range(3):
         tr = solvers.true_residuals(lambda x: A @ x, V[l], z, y[l])
         assert tr.max() < 1e-10
-    assert rel(y, y64) < 1e-9
+    assert vec_err(y, y64) < 1e-9
 
 
 def test_mixed_shifts_matches_fp32_emulation(sscg, prob):
@@ -201,7 +209,7 @@ def test_mixed_shifts_matches_fp32_emulation(sscg, prob):
         for Y in (y[l], emu.Y):
             err = np.linalg.norm(Y - exact, axis=1) / np.linalg.norm(exact, axis=1)
             assert err.max() < 1e-10
-        assert rel(y[l], emu.Y) < 1e-10
+        assert vec_err(y[l], emu.Y) < 1e-10
 
 
 @pytest.mark.parametrize("mode", ["mixed", "mixed_shifts"])
@@ -212,8 +220,13 @@ def test_mixed_precision_with_early_switch(sscg, prob, mode):
     U, A, V, z = prob
     prec = sscg.MIXED if mode == "mixed" else sscg.MIXED_SHIFTS
     y, r = solve(sscg, U, V, z, prec=prec, ru_interval=10, switch_tol=1.0)
-    assert r.status == sscg.OK
     assert r.true_res.max() < 1e-4
+    # the FP64 check after the solve names the inaccuracy: true residuals above
+    # true_factor * tol (default 100 * 1e-12) give SSCG_EINACCURATE, not OK
+    assert r.status == (sscg.OK if r.true_res.max() <= 100 * 1e-12 else sscg.EINACCURATE)
+    for l in range(V.shape[0]):
+        tr = solvers.true_residuals(lambda x: A @ x, V[l], z, y[l])
+        assert np.abs(tr - r.true_res[l]).max() <= 1e-3 * tr.max()
 
 
 def test_batch_equals_single(sscg):
@@ -235,7 +248,7 @@ def test_batch_equals_single(sscg):
     res = sscg.batch_solve(ctxs, vs, zs, [0.0] * 3, ys)
     for (ys_single, r_single), y, r in zip(singles, ys, res):
         assert r.status == sscg.OK
-        assert rel(to_host(y), ys_single) < 1e-11
+        assert vec_err(to_host(y), ys_single) < 1e-11
         assert np.all(np.abs(r.iters - r_single.iters) <= 2)
         assert np.all(np.abs(r.conv_iter - r_single.conv_iter) <= 2)
         # FP64 rounding gap between the recursive and the true residual is about
@@ -294,3 +307,39 @@ def test_shift_on_eigenvalue_only_that_shift_fails(sscg):
     assert r.status == sscg.ENOTCONV
     assert r.conv_iter[0, 0] == -1 and r.conv_iter[0, 1] > 0 and r.conv_iter[0, 2] > 0
     assert r.true_res[0, 1] < 5e-12 and r.true_res[0, 2] < 5e-12
+
+
+@pytest.mark.parametrize("mode", ["mixed", "mixed_shifts"])
+def test_mixed_accuracy_check_status(sscg, prob, mode):
+    """After a mixed-precision solve every shift's FP64 true residual is recomputed even
+    when the caller does not ask for it: a bound below what the solve reached
+    (true_factor 0.01, i.e. 1e-14) turns OK into SSCG_EINACCURATE, true_factor 0 only
+    reports; the residuals it reports agree with the oracle's."""
+    case(f"{mode} accuracy check status")
+    U, A, V, z = prob
+    prec = sscg.MIXED if mode == "mixed" else sscg.MIXED_SHIFTS
+    y, r = solve(sscg, U, V, z, prec=prec, ru_interval=20, switch_tol=1e-6, true_factor=0.01)
+    assert r.status == sscg.EINACCURATE
+    for l in range(V.shape[0]):
+        tr = solvers.true_residuals(lambda x: A @ x, V[l], z, y[l])
+        assert np.abs(tr - r.true_res[l]).max() <= 1e-3 * tr.max()
+    y2, r2 = solve(sscg, U, V, z, prec=prec, ru_interval=20, switch_tol=1e-6, true_factor=0.0)
+    assert r2.status == sscg.OK
+    assert vec_err(y2, y) < 1e-11   # separate contexts may tune other launch shapes
+
+
+def test_ss_eigs_reports_mixed_true_residual(sscg, prob):
+    """ss_eigs states the error of a mixed solve (largest FP64 true residual over all
+    nodes and sources) and reports -1 for an FP64 solve, where it is not recomputed."""
+    case("ss_eigs max_true_res")
+    U, A, V, z = prob
+    c = sscg.Context(CFG1.dims, CFG1.kappa)
+    c.set_gauge(U)
+    vd = to_dev(V)
+    out64 = c.ss_eigs(sscg.default_ss_params(gamma=0.0, rho=0.2, beta=0.25, N=16, M=8), vd, max_eigs=8)
+    assert out64.info.max_true_res == -1.0
+    p = sscg.default_ss_params(gamma=0.0, rho=0.2, beta=0.25, N=16, M=8,
+                               solve=sscg.default_opts(prec=sscg.MIXED_SHIFTS, ru_interval=20))
+    out = c.ss_eigs(p, vd, max_eigs=8)
+    assert out.status == sscg.OK
+    assert 0.0 < out.info.max_true_res < 1e-10

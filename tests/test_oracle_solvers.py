@@ -8,6 +8,8 @@
 * One shift equal to the seed reduces to textbook CG (scipy's cg, positive definite seed).
 * The implicit residual sqrt(rho)/|pi_j| equals the true shifted residual (collinearity).
 * Conjugate nodes have conjugate scalars, hence identical convergence iterations.
+* The independent per-shift route (CG on the normal equations of each z_j I - A)
+  reaches the spectral solution of every shift.
 * Failure paths: zero source, maxiter, breakdown on B v = 0, a shift on an eigenvalue.
 """
 import numpy as np
@@ -22,10 +24,8 @@ CFG1 = synth.CONFIGS["wilson4_fp64"]
 
 
 @pytest.fixture(scope="module")
-def cfg1_spec():
-    U = CFG1.gauge()
-    A = wilson.hermitian_wilson(U, CFG1.dims, CFG1.kappa)
-    lam, W = np.linalg.eigh(A.toarray())
+def cfg1_spec(cfg1_dense):
+    U, A, lam, W = cfg1_dense
     return A, lam, W
 
 
@@ -43,6 +43,32 @@ def test_converged_matches_spectral_solution(cfg1_spec):
     Y = spectral_solve(lam, W, z, v)
     assert np.linalg.norm(r.Y - Y) / np.linalg.norm(Y) < 1e-10
     assert solvers.true_residuals(lambda x: A @ x, v, z, r.Y).max() < 2e-12
+
+
+def test_normal_cg_matches_spectral_solution(cfg1_spec):
+    """normal_cg, which shares nothing with the shifted recurrences, reaches the dense
+    spectral solution of every node (per-shift bar: its condition number times the
+    1e-13 residual it stops at is below 1e-11)."""
+    A, lam, W = cfg1_spec
+    v = CFG1.sources().reshape(-1)
+    z, _ = quad.line_nodes(CFG1.N, CFG1.gamma, CFG1.rho, CFG1.beta)
+    Y = solvers.normal_cg(lambda X: (A @ X.T).T, z, np.tile(v, (z.size, 1)), tol=1e-13)
+    Yref = spectral_solve(lam, W, z, v)
+    for j in range(z.size):
+        assert np.abs(Y[j] - Yref[j]).max() <= 1e-10 * np.abs(Yref[j]).max()
+    assert solvers.true_residuals(lambda x: A @ x, v, z, Y).max() < 1e-13
+
+
+def test_normal_cg_pin_catches_a_conjugated_node(cfg1_spec):
+    """Planted mistake: solving with conj(z_j) in place of z_j (a conjugation slip in
+    B_j or B_j^H) gives another vector, which the pin above would reject."""
+    A, lam, W = cfg1_spec
+    v = CFG1.sources().reshape(-1)
+    z, _ = quad.line_nodes(CFG1.N, CFG1.gamma, CFG1.rho, CFG1.beta)
+    zc = np.conj(z)
+    Y = solvers.normal_cg(lambda X: (A @ X.T).T, zc, np.tile(v, (z.size, 1)), tol=1e-13, maxiter=400)
+    Yref = spectral_solve(lam, W, z, v)
+    assert max(np.abs(Y[j] - Yref[j]).max() / np.abs(Yref[j]).max() for j in range(z.size)) > 1e-3
 
 
 def lanczos_basis(A, v, k):
@@ -216,3 +242,21 @@ def test_fp32_shift_emulation(cfg1_spec):
     r0 = solvers.shifted_cg(Amul, v, z, CFG1.gamma, 1e-12, fp32_switch=10.0, maxiter=2000)
     err0 = np.linalg.norm(r0.Y - exact, axis=1) / np.linalg.norm(exact, axis=1)
     assert err0.max() > 1e-8
+
+
+def test_golden_wilson8_certified_by_normal_equations():
+    """The stored 8^4 shifted-CG solutions (tests/golden/wilson8.json) agree with the
+    independent normal-equation route on every (source, shift), and that route met
+    its residual bound: the golden values do not rest on the shifted recurrences alone."""
+    import json
+    from pathlib import Path
+    g = json.loads((Path(__file__).resolve().parent / "golden" / "wilson8.json").read_text())
+    assert len(g["sources"]) == 4
+    for s in g["sources"]:
+        assert s["status"] == "ok"
+        assert s["true_res_max"] < 5e-12
+        assert s["normal_cg_true_res_max"] < 1e-13
+        assert s["normal_cg_max_rel_diff"] < 1e-9
+        yn = np.array(s["yn_sample_re"]) + 1j * np.array(s["yn_sample_im"])
+        ys = np.array(s["y_sample_re"]) + 1j * np.array(s["y_sample_im"])
+        assert np.abs(ys - yn).max() <= 1e-9 * np.abs(yn).max()

@@ -21,10 +21,8 @@ CFG1 = synth.CONFIGS["wilson4_fp64"]
 
 
 @pytest.fixture(scope="module")
-def spec():
-    U = CFG1.gauge()
-    A = wilson.hermitian_wilson(U, CFG1.dims, CFG1.kappa)
-    lam, W = np.linalg.eigh(A.toarray())
+def spec(cfg1_dense):
+    U, A, lam, W = cfg1_dense
     return A, lam, W
 
 

@@ -91,7 +91,7 @@ def test_gauge_covariance():
 
 
 def test_norm_bounds():
-    dims, kappa = (4, 4, 4, 4), 0.11
+    dims, kappa = (3, 3, 3, 4), 0.11
     A = wilson.hermitian_wilson(synth.gauge_field(dims, 0.9, 4), dims, kappa)
     ev = np.linalg.eigvalsh(A.toarray())
     assert np.abs(ev).max() <= 1 + 8 * kappa
@@ -101,7 +101,8 @@ def test_norm_bounds():
 # ---- planted mistakes -------------------------------------------------------
 
 def pins_pass(monkeypatch_build):
-    dims, kappa = (4, 4, 4, 4), 0.12
+    # every extent >= 3, so forward and backward neighbours differ in each direction
+    dims, kappa = (3, 3, 3, 4), 0.12
     A = monkeypatch_build(synth.gauge_field(dims, 0.4, 0), dims, kappa)
     herm = abs(A - A.getH()).max() < 1e-14
     A1 = monkeypatch_build(synth.unit_gauge(dims), dims, kappa)
