@@ -403,6 +403,8 @@ def main():
     ap.add_argument("--sample-every", type=int, default=None,
                     help="time every stage of every k-th iteration (graph replay kept; default 25 for FP64 "
                          "solves, 10 for the mixed modes); 1 times every launch with direct launches")
+    ap.add_argument("--only-dslash-large", action="store_true",
+                    help="run only the dslash measurement on the 24^3 x 48 lattice and print it (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy five times (for counter scaling) and exit")
     args = ap.parse_args()
@@ -426,6 +428,9 @@ def main():
     import paper_1004_0292_amd as S
     import synth
 
+    if args.only_dslash_large:
+        print(json.dumps({"dslash_24x48": dslash_large(S)}), flush=True)
+        return
     if args.config == "batch":
         bench_batch(args)
         return

@@ -71,7 +71,10 @@ enum { SSCG_FP64 = 0,    /* every vector, product and scalar in FP64            
                             below switch_tol, then FP32 dslash, FP32 seed and shift
                             vectors, with FP64 reliable updates of the seed residual
                             every ru_interval iterations; scalar recurrences and dot
-                            products stay FP64                                      */
+                            products stay FP64. The FP32 seed can lose the FP64
+                            convergence of an indefinite seed (many more seed
+                            iterations on large random fields); the FP64 check after
+                            the solve reports the accuracy reached                  */
        SSCG_MIXED_SHIFTS = 2 }; /* FP64 seed CG throughout; after the switch the
                             shift vectors x_j, p_j are kept in FP32 and folded into
                             the FP64 solutions every ru_interval iterations        */
@@ -132,7 +135,10 @@ void sscg_default_opts(sscg_solve_opts *o);
 /* Shifted CG (Sec. 2.2, eqs. 4-5): solves (z_j I - A) y_{l,j} = v_l for every
  * shift j < nshift and source l < nsrc from the single Hermitian seed system
  * (sigma_seed I - A) x = v_l with a real seed shift (one product with A per
- * iteration and source serves all shifts). Converged shifts are frozen.
+ * iteration and source serves all shifts). Converged shifts are frozen. The shifted
+ * iterates do not depend on sigma_seed in exact arithmetic; a seed outside the
+ * spectrum (sigma_seed > 1 + 8 kappa) never grows its residual and leaves smaller
+ * FP64 rounding gaps than a seed at the centre, in the same iterations.
  *   v          device complex128 [nsrc][n] canonical
  *   z          host complex128 [nshift] (interleaved re, im)
  *   y          device complex128 [nsrc][nshift][n] canonical (output; also used as
@@ -190,7 +196,18 @@ typedef struct {
                                it enters and m the largest m_j: every shift's
                                contribution to the moments then carries at most the
                                error of the largest-weight shift at tol. 0: one tol */
-  int32_t pad;
+  int32_t seed_mode;        /* seed shift sigma of the shifted CG: 0 or 1 = gamma, the
+                               interval centre (Sec. 4 uses the centre); 2 = outside
+                               the spectrum, sigma = 1 + 8 kappa + 0.25 (|A| <= 1 + 8
+                               kappa), so sigma I - A is positive definite. The shifted
+                               iterates do not depend on sigma in exact arithmetic (the
+                               Krylov space is the same) and the shifts converge in the
+                               same iterations; with the seed at the centre CG passes
+                               near-breakdowns where ||r|| grows by orders of magnitude,
+                               which leaves an FP64 rounding gap of about 1e-11 in the
+                               true residuals, while a definite seed keeps ||r|| <= ||v||
+                               and the true residuals at the tolerance. (SSCG_MIXED
+                               does not converge with a definite seed.)               */
 } sscg_ss_params;
 
 typedef struct {

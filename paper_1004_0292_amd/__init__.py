@@ -46,7 +46,7 @@ class SSParams(C.Structure):
                 ("N", C.c_int32), ("M", C.c_int32), ("Nprime", C.c_int32), ("path", C.c_int32),
                 ("method", C.c_int32), ("rank_tol", C.c_double), ("spur_tol", C.c_double),
                 ("solve", SolveOpts), ("npairs", C.c_int32), ("moments_in_loop", C.c_int32),
-                ("weighted_tol", C.c_int32), ("pad", C.c_int32)]
+                ("weighted_tol", C.c_int32), ("seed_mode", C.c_int32)]
 
 
 class SSInfo(C.Structure):

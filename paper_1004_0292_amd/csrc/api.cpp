@@ -1358,18 +1358,34 @@ int sscg_apply_A(sscg_ctx *c, const void *x, void *y, int32_t nsrc, int32_t prec
   const size_t es = prec == SSCG_FP64 ? sizeof(double2) : sizeof(float2);
   CHK(ensure(c, c->apply_in, (size_t)nsrc * c->n * es));
   CHK(ensure(c, c->apply_out, (size_t)nsrc * c->n * es));
+  return sscg::apply_A_staged(c, x, y, nsrc, prec, c->apply_in.p, c->apply_out.p, true);
+}
+
+}  // extern "C"
+
+// y = A x through the planar staging buffers stage_in / stage_out (each nsrc * n
+// complex numbers of the precision): pack, dslash, unpack on the caller's stream.
+// tune = false never times launch shapes (no events, no host waits): the shape tuned
+// earlier for (prec, nsrc) is used if there is one, else the context's default.
+int sscg::apply_A_staged(sscg_ctx *c, const void *x, void *y, int nsrc, int prec, void *stage_in, void *stage_out,
+                         bool tune) {
   hipStream_t st = c->user;
-  launch_pack(x, c->apply_in.p, prec, nsrc, c->V, st);
-  if (c->profiling) {
+  launch_pack(x, stage_in, prec, nsrc, c->V, st);
+  auto shape = [&]() -> Tune {
+    if (tune) return apply_tune(c, stage_in, stage_out, nsrc, prec, st);
+    auto it = c->tuned.find("apply|" + std::to_string(prec) + "|" + std::to_string(nsrc));
+    return it != c->tuned.end() ? it->second : c->tune;
+  };
+  if (c->profiling && tune) {
     // time the dslash alone (blocking) and add it to the dslash stage
     while (c->events.size() < 2) {
       hipEvent_t e;
       HIPCHK(c, hipEventCreate(&e));
       c->events.push_back(e);
     }
-    const Tune t = apply_tune(c, c->apply_in.p, c->apply_out.p, nsrc, prec, st);
+    const Tune t = shape();
     HIPCHK(c, hipEventRecord(c->events[0], st));
-    dslash_with(c, t, c->apply_in.p, c->apply_out.p, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
+    dslash_with(c, t, stage_in, stage_out, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
     HIPCHK(c, hipEventRecord(c->events[1], st));
     HIPCHK(c, hipEventSynchronize(c->events[1]));
     float ms = 0.f;
@@ -1377,13 +1393,24 @@ int sscg_apply_A(sscg_ctx *c, const void *x, void *y, int32_t nsrc, int32_t prec
     c->stage_ms[ST_DSLASH] += ms;
     c->stage_calls[ST_DSLASH] += 1;
   } else {
-    const Tune t = apply_tune(c, c->apply_in.p, c->apply_out.p, nsrc, prec, st);
-    dslash_with(c, t, c->apply_in.p, c->apply_out.p, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
+    dslash_with(c, shape(), stage_in, stage_out, nsrc, prec, 0, 0.0, nullptr, nullptr, st);
   }
-  launch_unpack(c->apply_out.p, prec, y, nsrc, c->V, st);
+  launch_unpack(stage_out, prec, y, nsrc, c->V, st);
   HIPCHK(c, hipGetLastError());
   return SSCG_OK;
 }
+
+int sscg::context_check_apply(sscg_ctx *c, const void *x, const void *y, int nsrc, int prec, size_t *bytes_each) {
+  if (!c || !x || !y || nsrc <= 0) return fail(c, SSCG_EINVAL, "bad argument");
+  if (prec != SSCG_FP64 && prec != SSCG_MIXED) return fail(c, SSCG_EINVAL, "bad precision");
+  if (!c->have_gauge) return fail(c, SSCG_ESTATE, "no gauge field set");
+  *bytes_each = (size_t)nsrc * c->n * (prec == SSCG_FP64 ? sizeof(double2) : sizeof(float2));
+  return SSCG_OK;
+}
+int sscg::context_device(const sscg_ctx *c) { return c->device; }
+int sscg::context_fail(sscg_ctx *c, int code, const char *msg) { return fail(c, code, msg); }
+
+extern "C" {
 
 static int check_solve_args(sscg_ctx *c, const void *v, int nsrc, const double *z, int nshift,
                             const sscg_solve_opts *o, const void *y) {
@@ -1476,7 +1503,7 @@ void sscg_default_ss_params(sscg_ss_params *p) {
   p->npairs = 1;
   p->moments_in_loop = 0;
   p->weighted_tol = 0;
-  p->pad = 0;
+  p->seed_mode = 0;
   sscg_default_opts(&p->solve);
 }
 
@@ -1759,6 +1786,7 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   if (p->method == SSCG_HANKEL && 2 * p->M > p->N)
     return fail(c, SSCG_EINVAL, "Hankel needs 2M <= N moments from N nodes");
   if (!(p->rank_tol > 0 && p->rank_tol < 1)) return fail(c, SSCG_EINVAL, "rank_tol must lie in (0, 1)");
+  if (p->seed_mode < 0 || p->seed_mode > 2) return fail(c, SSCG_EINVAL, "seed_mode must be 0, 1 or 2");
   if (p->N > 512 || (int64_t)p->M * nsrc > 256)
     return fail(c, SSCG_EINVAL, "at most 512 nodes and M * nsrc <= 256 moment columns");
   const int Np = p->Nprime ? p->Nprime : p->N;
@@ -1850,7 +1878,10 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   PP[0].v = v;
   PP[0].L = L;
   PP[0].N = Nall;
-  PP[0].sigma = p->gamma;
+  // seed shift: the interval centre, or a shift outside the spectrum (|A| <= 1 + 8
+  // kappa for r = 1) where sigma I - A is positive definite
+  const int seed_mode = p->seed_mode != 0 ? p->seed_mode : 1;
+  PP[0].sigma = seed_mode == 2 ? 1.0 + 8.0 * std::fabs(c->kappa) + 0.25 : p->gamma;
   PP[0].z = zd;
   PP[0].y = in_loop ? nullptr : c->Ybuf.p;
   PP[0].keep_planar = true;

@@ -16,6 +16,8 @@
 #include <string>
 #include <vector>
 
+struct sscg_ctx;
+
 namespace sscg {
 
 constexpr int kMaxJobs = 8;   // problems in one grouped launch
@@ -314,6 +316,17 @@ void launch_colscale(void *A, int64_t lda, int na, const double *scale_dev, int6
 void launch_resid_cols(const void *AX, const void *X, int64_t ld, int ncol, const double *lam_dev,
                        int64_t n, double *partial, int nchunk, hipStream_t st);
 void launch_reduce_partials(const double *partial, int nchunk, int nout, double *out, hipStream_t st);
+
+// api.cpp: y = A x for nsrc canonical spinors through caller-given planar staging
+// buffers (each nsrc * 12 V complex numbers of the precision), on the context's
+// stream; tune = false uses an already tuned or the default launch shape and never
+// times one (no events, no allocation). The checks and accessors serve entry points
+// defined in other files.
+int apply_A_staged(sscg_ctx *c, const void *x, void *y, int nsrc, int prec, void *stage_in, void *stage_out,
+                   bool tune);
+int context_check_apply(sscg_ctx *c, const void *x, const void *y, int nsrc, int prec, size_t *bytes_each);
+int context_device(const sscg_ctx *c);
+int context_fail(sscg_ctx *c, int code, const char *msg);
 
 // dense_host.cpp: Hermitian eigen-decomposition (Householder tridiagonalisation and
 // implicit symmetric QR with Wilkinson shifts), column-major complex matrices as
