@@ -347,16 +347,18 @@ def test_ss_eigs_reports_mixed_true_residual(sscg, prob):
 
 def test_seed_outside_the_spectrum(sscg, prob):
     """A seed shift outside the spectrum (sigma > 1 + 8 kappa >= ||A||) gives the same
-    shifted iterates (they do not depend on the seed), so the same convergence
-    iterations and solutions, with a seed residual that never grows and FP64 true
-    residuals at least as close to the tolerance."""
+    shifted iterates (they do not depend on the seed), so the same solutions and
+    convergence iterations to within a few, with a seed residual that never grows
+    and FP64 true residuals at least as close to the tolerance."""
     case("seed outside the spectrum")
     U, A, V, z = prob
     sigma = 1 + 8 * CFG1.kappa + 0.25
     y0, r0 = solve(sscg, U, V, z, sigma=0.0)
     y1, r1 = solve(sscg, U, V, z, sigma=sigma)
     assert r0.status == r1.status == sscg.OK
-    assert np.all(np.abs(r1.conv_iter - r0.conv_iter) <= 2)
+    # the centre seed's implicit residual lags by up to a few iterations after its
+    # near-breakdowns; the definite seed never detects convergence later
+    assert np.all(r1.conv_iter <= r0.conv_iter) and np.all(r0.conv_iter - r1.conv_iter <= 4)
     assert vec_err(y1, y0) < 1e-9
     assert r1.true_res.max() <= max(r0.true_res.max(), 2e-12)
     for l in range(V.shape[0]):
