@@ -105,6 +105,18 @@ int sscg_set_gauge(sscg_ctx *ctx, const double *U, int32_t link_reals);
  * applies A in FP32 and widens the result. Stream-ordered. */
 int sscg_apply_A(sscg_ctx *ctx, const void *x, void *y, int32_t nsrc, int32_t prec);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): sscg_apply_A with the same
+ * arguments, layout and result, but no device allocation and no launch-shape timing.
+ * The planar staging of x and y lives in one library-wide device array of 32 MiB per
+ * device (held until the process ends): nsrc * 12 V may be at most 1048576 (FP64) or
+ * 2097152 (FP32), else SSCG_EINVAL. It uses the launch shape sscg_apply_A tuned for
+ * (prec, nsrc) on this context if there is one, else the default shape (results then
+ * agree with sscg_apply_A to rounding). Every call on a device shares that device's
+ * array: calls that overlap in time on one device (other streams, other contexts,
+ * other host threads) race and must be ordered by the caller. Stream-ordered. */
+int sscg_apply_A_noalloc(sscg_ctx *ctx, const void *x, void *y, int32_t nsrc, int32_t prec);
+
 typedef struct {
   double tol;            /* per-shift stop: ||r_j|| <= tol ||v|| (Sec. 4 criterion)   */
   int32_t maxiter;       /* seed iterations at most                                    */

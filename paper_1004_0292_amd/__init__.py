@@ -59,7 +59,7 @@ class SSInfo(C.Structure):
 
 
 EXPORTS = ["sscg_create", "sscg_destroy", "sscg_last_error", "sscg_global_error", "sscg_set_gauge",
-           "sscg_apply_A", "sscg_default_opts", "sscg_shifted_cg_solve", "sscg_ss_moments",
+           "sscg_apply_A", "sscg_apply_A_noalloc", "sscg_default_opts", "sscg_shifted_cg_solve", "sscg_ss_moments",
            "sscg_default_ss_params", "sscg_ss_eigs", "sscg_quad_lines", "sscg_quad_circle",
            "sscg_batch_solve", "sscg_herm_eig", "sscg_set_profiling", "sscg_stage_times",
            "sscg_stage_launches"]
@@ -86,6 +86,7 @@ def lib() -> C.CDLL:
     L.sscg_global_error.restype = C.c_char_p
     L.sscg_set_gauge.argtypes = [vp, pd, i32]
     L.sscg_apply_A.argtypes = [vp, vp, vp, i32, i32]
+    L.sscg_apply_A_noalloc.argtypes = [vp, vp, vp, i32, i32]
     L.sscg_default_opts.argtypes = [C.POINTER(SolveOpts)]
     L.sscg_default_opts.restype = None
     L.sscg_shifted_cg_solve.argtypes = [vp, vp, i32, pd, i32, dbl, C.POINTER(SolveOpts), vp, pi, pd, pi]
@@ -239,6 +240,15 @@ class Context:
         if x.numel() != nsrc * self.n or y.numel() != x.numel():
             raise ValueError("x and y must hold nsrc * 12V entries")
         rc = lib().sscg_apply_A(self._h, _check_dev(x, "x"), _check_dev(y, "y"), nsrc, prec)
+        if rc != OK:
+            self._raise(rc)
+
+    def apply_A_noalloc(self, x, y, prec=FP64):
+        """y = A x with no device allocation (the library's static staging array)."""
+        nsrc = x.numel() // self.n
+        if x.numel() != nsrc * self.n or y.numel() != x.numel():
+            raise ValueError("x and y must hold nsrc * 12V entries")
+        rc = lib().sscg_apply_A_noalloc(self._h, _check_dev(x, "x"), _check_dev(y, "y"), nsrc, prec)
         if rc != OK:
             self._raise(rc)
 
