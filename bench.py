@@ -465,6 +465,7 @@ def main():
                t_solve=0.0, t_moments=0.0, t_extract=0.0)
     link_launches = [0, 0]   # dslash launches doing work in the FP64 and FP32 phases
     launched_tot = 0
+    work_launches = 0        # launches with a source still iterating (the others exit at once)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out = ctx.ss_eigs(params, vd, max_eigs=max_eigs)
@@ -476,6 +477,7 @@ def main():
             if calls[k] > 0:
                 stage_est[k] += ms[k] / calls[k] * launched[k]
         launched_tot += int(launched[6])
+        work_launches += int(out.info.iters)
         for k in tot:
             tot[k] += getattr(out.info, k)
         sw = out.info.switch_iter if out.info.switch_iter >= 0 else out.info.iters
@@ -496,17 +498,21 @@ def main():
     rep = {}
     for name, idx, b in (("shift_update", 4, shift_bytes), ("dslash", 0, dslash_bytes)):
         calls = int(stage_calls[idx])  # launches timed (every k-th when sampling)
-        if calls == 0 or stage_ms[idx] <= 0 or launched_tot == 0:
+        if calls == 0 or stage_ms[idx] <= 0 or work_launches == 0:
             rep[name] = None
             continue
         avg_s = stage_ms[idx] / 1e3 / calls
-        per_launch = b / launched_tot
+        # the sampled iterations lie inside the run of every source, so their launches
+        # do work: the bytes are averaged over the launches that do work (iterations
+        # launched after the last source finished exit at once)
+        per_launch = b / work_launches
         ach = per_launch / avg_s / 1e9
         rep[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": pmc_traffic(name, w.name, mode), "kernel": name,
                      "working_set_resident_in": resident,
-                     "launches": launched_tot, "launches_timed": calls, "avg_launch_us": round(avg_s * 1e6, 2),
+                     "launches": launched_tot, "launches_doing_work": work_launches, "launches_timed": calls,
+                     "avg_launch_us": round(avg_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": round(per_launch)}
     per_step = stage_est / args.steps
     dominant = "shift_update" if per_step[4] >= per_step[0] else "dslash"
