@@ -32,6 +32,8 @@
 #include <numeric>
 #include <vector>
 
+#include "host_math.h"
+
 namespace sscg {
 
 namespace {
@@ -45,9 +47,14 @@ inline double hyp(double a, double b) {
 }  // namespace
 
 // Built twice, for AVX2 with FMA and for plain x86-64; the loader picks the first at
-// run time where the processor has it.
-__attribute__((target_clones("arch=x86-64-v3", "default"))) bool herm_eig(int n, const double *Ain, double *evals,
-                                                                          double *evecs) {
+// run time where the processor has it (one plain build when SSCG_NO_TARGET_CLONES is
+// defined, as in the sanitizer build of the host code).
+#ifdef SSCG_NO_TARGET_CLONES
+#define SSCG_HOST_CLONES
+#else
+#define SSCG_HOST_CLONES __attribute__((target_clones("arch=x86-64-v3", "default")))
+#endif
+SSCG_HOST_CLONES bool herm_eig(int n, const double *Ain, double *evals, double *evecs) {
   if (n <= 0) return true;
   const size_t nn = (size_t)n * n;
   std::vector<double> Ar(nn), Ai(nn);  // column-major, split real / imaginary parts

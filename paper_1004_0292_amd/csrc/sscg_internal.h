@@ -331,7 +331,7 @@ int context_fail(sscg_ctx *c, int code, const char *msg);
 // dense_host.cpp: Hermitian eigen-decomposition (Householder tridiagonalisation and
 // implicit symmetric QR with Wilkinson shifts), column-major complex matrices as
 // interleaved doubles. Eigenvalues ascending. Returns false if the QR iteration did
-// not converge within its step limit (outputs then undefined).
-bool herm_eig(int n, const double *A, double *evals, double *evecs);
+// not converge within its step limit (outputs then undefined). Declared in
+// host_math.h.
 
 }  // namespace sscg
