@@ -189,7 +189,7 @@ def tts_compare(S, ctx, params, vd, max_eigs, steps, base_ms, base_res):
 # spectrum), for the time-to-solution comparison at equal accuracy: the interval
 # [lo, hi], the line offset beta, N nodes, M moments and L sources.
 WINDOWS = {"wilson8_fp64": dict(lo=0.3700, hi=0.3735, beta=0.5, N=32, M=8, L=4),
-           "wilson16x32_mixed": None,
+           "wilson16x32_mixed": dict(lo=0.3652, hi=0.36637, beta=0.5, N=32, M=8, L=4),
            "wilson24x48": None}
 
 

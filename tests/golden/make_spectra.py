@@ -4,7 +4,7 @@ Calls only the CPU oracle and the seeded input generators; run from the
 repository root:
 
     python tests/golden/make_spectra.py wilson16x32_mixed 24
-    python tests/golden/make_spectra.py wilson24x48 16
+    python tests/golden/make_spectra.py wilson24x48 6 1e-8
 
 Output: tests/golden/spectrum_<workload>.json with the k eigenvalues of A of
 smallest magnitude (ascending), the residual ||A x - lambda x|| of each unit
@@ -43,4 +43,4 @@ def main(name: str, k: int, tol: float = 1e-10):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], int(sys.argv[2]))
+    main(sys.argv[1], int(sys.argv[2]), float(sys.argv[3]) if len(sys.argv) > 3 else 1e-10)

@@ -157,6 +157,47 @@ def test_wilson16x32_mixed_all_sources(sscg):
     c.close()
 
 
+@pytest.mark.parametrize("mode,method", [("fp64", "rr"), ("mixed_shifts", "rr"), ("fp64", "hankel")])
+def test_wilson16x32_window_eigenpairs(sscg, mode, method):
+    """A window of the 16^3 x 32 field that holds eigenvalues, [0.3652, 0.36637] (the
+    reference spectrum, tests/golden/spectrum_wilson16x32_mixed.json, written by the
+    oracle, covers every |lambda| <= 0.36686, so it is complete there): both
+    eigenvalues found, each within 1e-10 max(|lambda|, 0.1 rho) of the reference, with
+    residuals ||A x - lambda x|| below 1e-8 (the accuracy targets of the paper's
+    Table 1 residuals), in FP64 and with FP32 shift vectors, by Rayleigh-Ritz and by
+    block Hankel; sampled rows of A x - lambda x from the oracle's row-wise matrix
+    bound the reported residual."""
+    w = synth.CONFIGS["wilson16x32_mixed"]
+    case(f"16^3x32 eigen window {mode} {method}")
+    ref = json.loads((GOLD.parent / "spectrum_wilson16x32_mixed.json").read_text())
+    lam_ref = np.array(ref["lam"])
+    lo, hi = 0.3652, 0.36637
+    assert np.max(np.abs(lam_ref)) > hi
+    truth = np.sort(lam_ref[(lam_ref >= lo) & (lam_ref <= hi)])
+    assert len(truth) == 2
+    U = w.gauge()
+    c = sscg.Context(w.dims, w.kappa)
+    c.set_gauge(U, w.link_reals)
+    prec = sscg.FP64 if mode == "fp64" else sscg.MIXED_SHIFTS
+    gamma, rho = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    p = sscg.default_ss_params(gamma=gamma, rho=rho, beta=0.5, N=32, M=8,
+                               method=sscg.RR if method == "rr" else sscg.HANKEL,
+                               solve=sscg.default_opts(prec=prec, ru_interval=w.ru_interval, switch_tol=w.switch_tol))
+    V = w.sources().reshape(w.L, -1)[:4]
+    out = c.ss_eigs(p, to_dev(V), max_eigs=16)
+    assert out.status == sscg.OK
+    assert out.n_found == len(truth)
+    assert np.all(np.abs(out.lam - truth) <= 1e-10 * np.maximum(np.abs(truth), 0.1 * rho))
+    assert out.res.max() < 1e-8
+    X = to_host(out.X)
+    sites = np.random.default_rng(11).choice(w.V, 16, replace=False)
+    for k in range(len(out.lam)):
+        rows = wilson.apply_rows(U, w.dims, w.kappa, X[k], sites)
+        r = rows - out.lam[k] * X[k].reshape(-1, 12)[sites]
+        assert np.abs(r).max() <= out.res[k] + 1e-13
+    c.close()
+
+
 def test_batched_workload_equals_single_runs(sscg):
     names = synth.BATCH
     case("batched 8^4 / 12^4 / 16^4 mixed")
