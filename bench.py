@@ -51,6 +51,7 @@ DEFAULT_CONFIG = "wilson24x48"
 STAGES = ["dslash", "seed_alpha", "seed_r_update", "unused", "shift_update", "reliable_update",
           "solve_loop"]
 KERNEL_SOURCES = {"shift_update": "paper_1004_0292_amd/csrc/vec.hip",
+                  "shift_moments": "paper_1004_0292_amd/csrc/vec.hip",
                   "dslash": "paper_1004_0292_amd/csrc/dslash.hip",
                   "dslash_fp32_links12": "paper_1004_0292_amd/csrc/dslash.hip",
                   "dslash_fp64_links18": "paper_1004_0292_amd/csrc/dslash.hip"}
@@ -169,19 +170,30 @@ def mode_summary(r, ms, nsrc):
             "t_solve_s": round(i.t_solve, 4), "t_extract_s": round(i.t_extract, 4)}
 
 
-def tts_compare(S, ctx, params, vd, max_eigs, steps, base_ms, base_res):
-    """Time to solution of the whole step in the two mixed-precision modes on the same
-    inputs and interval as the FP64 steps (graph replay, sampled events off)."""
+def tts_compare(S, ctx, params, vd, max_eigs, steps, base_ms, base_res, with_mixed_seed, deadline):
+    """Time to solution of the whole step on the same inputs and interval as the timed
+    steps, in the other precision modes and moment forms (graph replay, sampled events
+    off): FP64 with stored solutions, FP32 shift vectors with moments in the loop and
+    with stored solutions, and (when asked for) the FP32-seed mode."""
     import copy
     ctx.set_profiling(0)
-    out = {"fp64": dict(base_res)}
-    for name in ("mixed_shifts", "mixed"):
+    out = {"timed_steps": dict(base_res)}
+    modes = [("fp64_stored", S.FP64, 0), ("mixed_shifts", S.MIXED_SHIFTS, params.moments_in_loop),
+             ("mixed_shifts_stored", S.MIXED_SHIFTS, 0)]
+    if with_mixed_seed:
+        modes.append(("mixed_seed32", S.MIXED, 0))
+    for name, prec, in_loop in modes:
+        if time.perf_counter() > deadline:
+            out[name] = "skipped: time budget of the benchmark"
+            continue
         p = copy.copy(params)
         p.solve = copy.copy(params.solve)
-        p.solve.prec = PRECS[name]
+        p.solve.prec = prec
+        p.moments_in_loop = in_loop
         dt, r = solve_steps(S, ctx, p, vd, max_eigs, steps)
         out[name] = mode_summary(r, dt * 1e3, vd.shape[0])
-        out[name]["speedup_vs_fp64"] = round(base_ms / (dt * 1e3), 3)
+        out[name]["moments_in_loop"] = bool(in_loop)
+        out[name]["speedup_vs_timed_steps"] = round(base_ms / (dt * 1e3), 3)
     return out
 
 
@@ -189,7 +201,7 @@ def tts_compare(S, ctx, params, vd, max_eigs, steps, base_ms, base_res):
 # spectrum), for the time-to-solution comparison at equal accuracy: the interval
 # [lo, hi], the line offset beta, N nodes, M moments and L sources.
 WINDOWS = {"wilson8_fp64": dict(lo=0.3700, hi=0.3735, beta=0.5, N=32, M=8, L=4),
-           "wilson16x32_mixed": dict(lo=0.3652, hi=0.36637, beta=0.5, N=32, M=8, L=4),
+           "wilson16x32_mixed": dict(lo=0.3650, hi=0.3661, beta=0.5, N=32, M=8, L=4),
            "wilson24x48": None}
 
 
@@ -376,7 +388,8 @@ def kernel_bytes(w, prec, tot, link_launches, moments_in_loop):
     if moments_in_loop:
         # p_j read and written per active (shift, source, entry); per (source, entry,
         # iteration) the seed r read, the seed p read and written, the M moments read
-        # and written
+        # and written (the stage also holds the table launch that forms the shift
+        # scalars, a few hundred bytes per shift, not counted)
         shift = (su64 * 32 + su32 * 16 + (it64 + it32) * (48 + 32 * w.M)) * n
     dslash = (it64 * 48 * 8 + it32 * 48 * (4 if seed32 else 8)) * w.V
     dslash += (link_launches[0] * 18 * 8 + link_launches[1] * (w.link_reals * 4 if seed32 else 18 * 8)) * 4 * w.V
@@ -393,8 +406,14 @@ def main():
     ap.add_argument("--method", default="rr", choices=["rr", "hankel"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed", "mixed_shifts", "workload"],
                     help="precision of the timed steps (default FP64; 'workload' = the workload's own mode)")
-    ap.add_argument("--moments-in-loop", action="store_true",
-                    help="accumulate the moments inside the solve (no stored solutions)")
+    ap.add_argument("--stored", action="store_true",
+                    help="store the shifted solutions and form the moments after the solve (default: the moments "
+                         "are accumulated inside the solve when the extraction allows it, Rayleigh-Ritz with "
+                         "at most 32 moments)")
+    ap.add_argument("--with-mixed-seed", action="store_true",
+                    help="also time the FP32-seed mode (SSCG_MIXED) in the comparison")
+    ap.add_argument("--budget", type=float, default=420.0,
+                    help="seconds after which the optional comparisons are skipped")
     ap.add_argument("--weighted-tol", action="store_true", help="moment-weighted per-shift stopping")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dslash-large", action="store_true",
@@ -434,8 +453,10 @@ def main():
     if args.config == "batch":
         bench_batch(args)
         return
+    t_start = time.perf_counter()
     w = synth.CONFIGS[args.config]
     mode = w.prec if args.prec == "workload" else args.prec
+    args.moments_in_loop = (not args.stored and args.method == "rr" and w.M <= 32 and mode != "mixed")
     prec = PRECS[mode]
     print(f"[bench] {w.name} {w.dims} N={w.N} L={w.L} M={w.M} prec={mode}", file=sys.stderr, flush=True)
     U = w.gauge()
@@ -496,7 +517,8 @@ def main():
     ws_bytes = w.L * w.N * w.n * 16 * (1 if args.moments_in_loop else 2) + 4 * w.L * w.n * 16 + w.V * 4 * 144
     resident = "hbm" if ws_bytes > MALL_BYTES else "mall"
     rep = {}
-    for name, idx, b in (("shift_update", 4, shift_bytes), ("dslash", 0, dslash_bytes)):
+    upd_name = "shift_moments" if args.moments_in_loop else "shift_update"
+    for name, idx, b in ((upd_name, 4, shift_bytes), ("dslash", 0, dslash_bytes)):
         calls = int(stage_calls[idx])  # launches timed (every k-th when sampling)
         if calls == 0 or stage_ms[idx] <= 0 or work_launches == 0:
             rep[name] = None
@@ -515,7 +537,7 @@ def main():
                      "avg_launch_us": round(avg_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": round(per_launch)}
     per_step = stage_est / args.steps
-    dominant = "shift_update" if per_step[4] >= per_step[0] else "dslash"
+    dominant = upd_name if per_step[4] >= per_step[0] else "dslash"
     stage_split = {STAGES[i]: round(float(per_step[i]), 3) for i in range(6) if i != 3}
     matvec_ms = float(per_step[0])
     line = {
@@ -557,9 +579,11 @@ def main():
     base_res = mode_summary(out, step_ms, w.L)
     if not args.no_compare:
         print("[bench] mixed-precision comparison", file=sys.stderr, flush=True)
-        line["tts"] = tts_compare(S, ctx, params, vd, max_eigs, args.tts_steps, step_ms, base_res)
+        line["tts"] = tts_compare(S, ctx, params, vd, max_eigs, args.tts_steps, step_ms, base_res,
+                                  args.with_mixed_seed, t_start + args.budget)
         print("[bench] eigen window", file=sys.stderr, flush=True)
-        tw, ext = tts_window(S, ctx, w, vd, 1)
+        tw, ext = (tts_window(S, ctx, w, vd, 1) if time.perf_counter() < t_start + args.budget
+                   else ({"skipped": "time budget of the benchmark"}, None))
         if tw is not None:
             line["tts_window"] = tw
             line["extraction"] = ext
@@ -573,6 +597,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, tot["seed_iters"] // args.steps)
+    line["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(line), flush=True)
 
 

@@ -42,6 +42,8 @@
  *            SSCG_XCD, SSCG_CT, SSCG_TBS, SSCG_WBATCH, SSCG_UNROLL, SSCG_NT set,
  *            fixes the shapes (read at sscg_create); with fixed shapes a solve is
  *            bitwise reproducible (the reductions do not depend on the schedule).
+ *            SSCG_MOMUB (1, 2 or 4; default 2) sets how many shifts' loads the
+ *            in-loop moment update issues together.
  */
 #ifndef SSCG_H
 #define SSCG_H
@@ -197,7 +199,9 @@ typedef struct {
                                each shift's step alpha_j p_j is added to every
                                s_k = sum_j w_j zeta_j^k y_j as it is made, so the
                                solutions y_j are never stored (one fewer vector
-                               read and write per shift and iteration). Rayleigh-
+                               read and write per shift and iteration; the shift
+                               scalars and coefficients of an iteration are formed
+                               once into a small device table). Rayleigh-
                                Ritz sums M moments per pair, Hankel 2M (its block
                                moments V^H s_k run to k = 2M - 1); needs npairs
                                times that <= 32 and a solve precision of SSCG_FP64

@@ -70,7 +70,7 @@ struct sscg_ctx {
   std::map<std::string, Tune> tuned;
   // solver workspaces
   DevBuf v64, r64, p64, q64, W, r32, p32, q32, rbase, xpart64, xpart32, tmp, pq_part, rr_part, seed,
-      shift, zdev, small, cmom, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out, trpart;
+      shift, zdev, small, cmom, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out, trpart, momtab;
   SeedState *seed_host = nullptr;
   int seed_host_cap = 0;
   // profiling
@@ -206,7 +206,7 @@ void sscg_destroy(sscg_ctx *c) {
   DevBuf *bufs[] = {&c->g64, &c->g32, &c->v64, &c->r64, &c->p64, &c->q64, &c->W, &c->r32, &c->p32,
                     &c->q32, &c->rbase, &c->xpart64, &c->xpart32, &c->tmp, &c->pq_part, &c->rr_part,
                     &c->seed, &c->shift, &c->zdev, &c->small, &c->cmom, &c->Ybuf, &c->Sbuf, &c->Qbuf, &c->AQbuf,
-                    &c->Xbuf, &c->AXbuf, &c->Accbuf, &c->apply_in, &c->apply_out, &c->trpart};
+                    &c->Xbuf, &c->AXbuf, &c->Accbuf, &c->apply_in, &c->apply_out, &c->trpart, &c->momtab};
   for (DevBuf *b : bufs) release(*b);
   if (c->seed_host) hipHostFree(c->seed_host);
   for (hipEvent_t e : c->events) hipEventDestroy(e);
@@ -528,7 +528,9 @@ struct IterPlan {
   ScalarBatch alpha;
   VecBatch r64, r32, u64, u32, u32s, fold_seed, rel;
   VecBatch m64, m32;  // shift update with in-loop moments (FP64 / FP32 shift vectors)
+  VecBatch mt;        // its table kernel (per (source, shift) scalars of the iteration)
   int nmom_max;       // 0: the solutions are stored
+  int mom_ub;         // shifts per load batch of the in-loop moment update
   int ct;             // dslash kernel: t-slices per block (0: site-parallel)
   bool fuse_alpha;    // the residual update forms the seed step length itself
 };
@@ -536,7 +538,8 @@ constexpr int kFuseAlphaMax = 1024;  // <p, Bp> partials per source up to which 
 
 static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts &o, const Tune &t) {
   memset(&pl, 0, sizeof(pl));
-  int bd = 0, bdru = 0, bs = 0, bv = 0, bu = 0, bm = 0;
+  int bd = 0, bdru = 0, bs = 0, bv = 0, bu = 0, bm = 0, bmt = 0;
+  pl.mom_ub = env_int("SSCG_MOMUB", 2);
   const int np = (int)P.size();
   // the tile kernel needs a tile of t.tbs sites on every lattice of the batch, with
   // LDS for FP64 spinors (the FP64 phase and the reliable updates use it too)
@@ -619,16 +622,25 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
       for (VecBatch *mb : {&pl.m64, &pl.m32}) {
         VecJob &j = mb->job[i];
         mk_v(j, P[i].mom, c->W.p, c->r64.p, c->p64.p, bm, L * nbm);
+        j.e = c->momtab.p;
         j.mcoef = (const double2 *)P[i].mom_coef;
         j.nmom = P[i].nmom;
         j.nblk_mom = nbm;
       }
       bm += L * nbm;
+      const int nch = (N + kBlock - 1) / kBlock;
+      VecJob &jt = pl.mt.job[i];
+      mk_v(jt, P[i].mom, c->W.p, c->r64.p, c->p64.p, bmt, L * nch);
+      jt.e = c->momtab.p;
+      jt.mcoef = (const double2 *)P[i].mom_coef;
+      jt.nmom = P[i].nmom;
+      bmt += L * nch;
       pl.nmom_max = std::max(pl.nmom_max, P[i].nmom);
     }
   }
-  pl.m64.njobs = pl.m32.njobs = np;
+  pl.m64.njobs = pl.m32.njobs = pl.mt.njobs = np;
   pl.m64.total_blocks = pl.m32.total_blocks = bm;
+  pl.mt.total_blocks = bmt;
   pl.d64.njobs = pl.d32.njobs = pl.dru.njobs = np;
   pl.d64.commit = pl.d32.commit = 1;  // the iteration's first launch commits the previous one
   pl.d64.total_blocks = pl.d32.total_blocks = bd;
@@ -744,7 +756,8 @@ static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, boo
   }
   rec.mark(ST_SHIFT);
   if (pl.nmom_max > 0) {  // FP64 seed in both phases (checked by run_solve)
-    launch_shift_moments(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, st);
+    launch_shift_table(pl.mt, st);
+    launch_shift_moments_tab(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, pl.mom_ub, st);
   } else {
     const VecBatch &u = prec == 0 ? pl.u64 : (sp == 1 ? pl.u32 : pl.u32s);
     launch_shift_update(u, prec, sp, prec == 1 && ru, t.unroll, t.nt, st);
@@ -793,6 +806,7 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
   CHK(ensure(c, c->seed, L * sizeof(SeedState)));
   CHK(ensure(c, c->shift, L * N * sizeof(ShiftState)));
   CHK(ensure(c, c->zdev, N * 2 * sizeof(double)));
+  if (p.nmom > 0) CHK(ensure(c, c->momtab, shift_table_bytes((int)L, (int)N)));
   if (o.prec == SSCG_MIXED) {  // FP32 seed vectors and reliable-update storage
     CHK(ensure(c, c->r32, L * vec32));
     CHK(ensure(c, c->p32, L * vec32));

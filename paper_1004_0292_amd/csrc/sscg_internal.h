@@ -97,6 +97,16 @@ struct ShiftState {
   int32_t pad;
 };
 
+// Scalars of one (source, shift) pair for the iteration, formed once per iteration by
+// the table kernel of the in-loop moment update: alpha_{j,k}, beta_{j,k}, 1/pi_{j,k+1}
+// and whether the shift is updated. The moment coefficients g_{kj} = c_{kj} alpha_{j,k}
+// follow the table in the same buffer, kMomRows per shift (zero beyond the moments
+// summed). Every block of the update reads them at wavefront-uniform addresses.
+struct ShiftTab {
+  double2 a, b, ipi;
+  int32_t upd, pad;
+};
+
 // Scalars of one shift in iteration k (Sec. 2.2): from alpha_k, beta_k,
 // c = alpha_k beta_{k-1} / alpha_{k-1}, sqrt(rho_{k+1}) and the committed pi values,
 //   pi_{j,k+1} = (1 + c + alpha_k s_j) pi_{j,k} - c pi_{j,k-1},
@@ -285,7 +295,17 @@ void launch_reliable_residual(const VecBatch &b, hipStream_t st);
 // job: a = moments S (column k L + l of n entries), b = shift slots (p_j),
 // c = seed r, d = seed p (FP64); mcoef [nmom][nshift].
 constexpr int kMomBlock = 256;   // entries (threads) per block of the in-loop moment kernel
-void launch_shift_moments(const VecBatch &b, int prec, int nmom_max, hipStream_t st);
+// In-loop moments in two launches: the table kernel (one thread per (source, shift),
+// job e = table buffer of nsrc * nshift ShiftTab records followed by nsrc * nshift *
+// kMomRows coefficients) stages the iteration's scalars; the update kernel (one entry
+// per thread) reads them with uniform loads. Blocks per source of the table kernel:
+// ceil(nshift / kBlock); of the update: nblk_mom.
+void launch_shift_table(const VecBatch &b, hipStream_t st);
+// ub: shifts whose loads are issued together (1, 2, 4)
+void launch_shift_moments_tab(const VecBatch &b, int prec, int nmom_max, int ub, hipStream_t st);
+inline size_t shift_table_bytes(int nsrc, int nshift) {
+  return (size_t)nsrc * nshift * (sizeof(ShiftTab) + (size_t)kMomRows * sizeof(double2));
+}
 void launch_fold_seed(const VecBatch &b, hipStream_t st);
 void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st);
 void launch_init_shifts(void *y, void *W, const void *v, int64_t n, int nsrc, int nshift, hipStream_t st);

@@ -20,6 +20,8 @@
 //                 scalars are staged for the commit.
 // Every reduction writes one partial per block and the consumer sums them in a
 // fixed order, so results do not depend on scheduling.
+#include <cstddef>
+
 #include "sscg_internal.h"
 
 namespace sscg {
@@ -447,17 +449,8 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
   }
 }
 
-// Fused shift update with in-loop moment sums (eq. 2 accumulated as the solve runs):
-// for every shift updated in this iteration, the step alpha_j p_j that would be added
-// to x_j is instead added to every moment, s_{k,l} += c[k][j] alpha_j p_j, and p_j is
-// advanced as usual. One thread owns one entry of one source and loops over all
-// shifts, so each moment entry has a single writer; the shift vectors x_j are never
-// stored. Shift vectors are FP64 (T = double) or FP32 (after the FP32 switch); the
-// seed and the moments stay FP64. Per chunk of shifts the block forms the shifts'
-// scalars (shift_step) and g[k][j] = c[k][j] alpha_j in LDS (the first block of the
-// source stages the new scalars for the commit), and the loads of several shifts
-// are issued together.
-// shift slots: an FP64 p_j fills its slot of n double2, an FP32 one the first half
+// Shift vectors of the in-loop moment update: an FP64 p_j fills its slot of n
+// double2, an FP32 one the first half.
 template <typename T>
 __device__ __forceinline__ double2 ld_shift(const void *base, size_t slot, int64_t n, int64_t i) {
   if constexpr (sizeof(T) == 8) return reinterpret_cast<const double2 *>(base)[slot * n + i];
@@ -470,107 +463,153 @@ __device__ __forceinline__ void st_shift(void *base, size_t slot, int64_t n, int
   else reinterpret_cast<float2 *>(reinterpret_cast<double2 *>(base) + slot * n)[i] = make_float2((float)v.x, (float)v.y);
 }
 
-template <typename T, int MM>
-__global__ __launch_bounds__(kMomBlock) void shift_moments_kernel(VecBatch B) {
-  constexpr int JC = 32;  // shifts staged in LDS at once
-  constexpr int UB = 8;   // shifts whose loads are issued together
-  __shared__ double2 gs[MM][JC];       // g[k][j] of the chunk (zero rows from M on)
-  __shared__ double2 as[JC], bs[JC], ips[JC];  // alpha_j, beta_j and 1/pi_j of the chunk
-  __shared__ int ups[JC];              // shift updated this iteration
-  __shared__ double red[kMomBlock / 64];
+// Moment sums accumulated inside the solve (eq. 2 summed as the solve runs): for every
+// shift updated in an iteration, the step alpha_j p_j that would be added to x_j is
+// added to every moment instead, s_{k,l} += c[k][j] alpha_j p_j, and p_j advances as
+// usual; the solutions x_j are never stored. Two launches per iteration. The table
+// kernel forms, once per iteration and
+// (source, shift), the scalars of shift_step from the seed scalars and the new
+// <r, r> (summed from the residual update's partials by every block in the same
+// order), writes a_j, b_j, 1/pi_j, the update flag and g_kj = c_kj a_j for k < kMomRows
+// (zero beyond the moments summed) to the table, and stages the shift state for the
+// commit (one writer per shift; the first block of a source stages the seed scalars).
+__global__ __launch_bounds__(kBlock) void shift_table_kernel(VecBatch B) {
+  __shared__ double red[kBlock / 64];
   const int b = blockIdx.x;
   const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
   const int lb = b - J.block_begin;
-  const int l = lb / J.nblk_mom, vb = lb - l * J.nblk_mom;
+  const int nch = (J.nshift + kBlock - 1) / kBlock;
+  const int l = lb / nch, ch = lb - l * nch;
   SeedState &S = J.seed[l];
   if (S.done || !S.pending) return;  // uniform over the block
-  const int64_t n = J.n;
-  const int M = J.nmom, N = J.nshift;
-  const int64_t i = (int64_t)vb * kMomBlock + threadIdx.x;
-  const bool valid = i < n;
-  const int64_t ii = valid ? i : 0;  // invalid lanes read entry 0 and store nothing
-  const double2 rv = reinterpret_cast<const double2 *>(J.c)[(size_t)l * n + ii];
-  ShiftState *sh = J.shift + (size_t)l * N;
-  const size_t slot0 = (size_t)l * N;
-  // seed scalars of the iteration (every block, the same partials in the same order);
-  // the seed state is loaded before the reduction so the latencies overlap
+  const int N = J.nshift;
+  const int j = ch * kBlock + threadIdx.x;
+  ShiftState Hl;
+  if (j < N) Hl = J.shift[(size_t)l * N + j];
   const double alpha = S.alpha, rho = S.rho, bprev = S.beta_prev, aprev = S.alpha_prev, vnorm = S.vnorm;
   const int it = S.iters;
   double v = 0.0;
   const double *pr = J.rr_partial + (size_t)l * J.nrr;
-  for (int t = threadIdx.x; t < J.nrr; t += kMomBlock) v += pr[t];
-  const double rho_new = block_sum_all<kMomBlock / 64>(v, red);
+  for (int t = threadIdx.x; t < J.nrr; t += kBlock) v += pr[t];
+  const double rho_new = block_sum_all<kBlock / 64>(v, red);
   const double beta = rho_new / rho;
   const double cc = alpha * bprev / aprev;
   const double sq = sqrt(rho_new);
   const double thr = J.tol * vnorm;
   const bool bad = !isfinite(rho_new) || !isfinite(beta);
-  if (vb == 0 && threadIdx.x == 0) {
+  if (ch == 0 && threadIdx.x == 0) {
     S.rho_n = rho_new;
     S.beta_n = beta;
     S.brk_n = bad ? 1 : 0;
     S.staged = 1;
   }
-  if (bad) return;  // uniform: the commit ends this source's run
+  if (j >= N) return;
+  ShiftTab *tab = reinterpret_cast<ShiftTab *>(J.e) + (size_t)l * N;
+  double2 *g = reinterpret_cast<double2 *>(reinterpret_cast<ShiftTab *>(J.e) + (size_t)J.nsrc * N) +
+               ((size_t)l * N + j) * kMomRows;
+  ShiftStep o;
+  if (bad) {
+    o.a = o.b = o.ipi = o.pn = make_double2(0.0, 0.0);
+    o.upd = o.frz = 0;
+  } else {
+    o = shift_step(Hl, alpha, beta, cc, sq, thr);
+  }
+  ShiftTab t;
+  t.a = o.a;
+  t.b = o.b;
+  t.ipi = o.ipi;
+  t.upd = o.upd;
+  t.pad = 0;
+  tab[j] = t;
+#pragma unroll 4
+  for (int k = 0; k < kMomRows; ++k)
+    g[k] = (o.upd && k < J.nmom) ? cmul(J.mcoef[(size_t)k * N + j], o.a) : make_double2(0.0, 0.0);
+  if (o.upd) {
+    ShiftState &H = J.shift[(size_t)l * N + j];
+    H.pi_n = o.pn;
+    H.res_n = o.res;
+    H.frz_n = o.frz;
+    if (o.frz) H.conv_iter = it + 1;
+  }
+}
+
+// The update of the table form: one thread per entry of one source loops over the
+// shifts (UB at a time, their loads issued together), adds g_kj p_j to each of its MM
+// moment sums (rows beyond the moments summed have g = 0) and advances p_j <- r / pi_j
+// + b_j p_j for every shift the table marks as updated. The table and coefficients
+// sit at addresses that are the same for the whole wavefront; the seed direction is
+// advanced with the staged beta_k. job: a = moments, b = shift slots, c = seed r,
+// d = seed p (FP64), e = the table.
+template <typename T, int MM, int UB>
+__global__ __launch_bounds__(kMomBlock) void shift_moments_tab_kernel(VecBatch B) {
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int lb = b - J.block_begin;
+  const int l = lb / J.nblk_mom, vb = lb - l * J.nblk_mom;
+  const SeedState &S = J.seed[l];
+  if (S.done || !S.pending || S.brk_n) return;  // uniform over the block
+  const int64_t n = J.n;
+  const int N = J.nshift;
+  const int64_t i = (int64_t)vb * kMomBlock + threadIdx.x;
+  const bool valid = i < n;
+  const int64_t ii = valid ? i : 0;  // invalid lanes read entry 0 and store nothing
+  const double2 rv = reinterpret_cast<const double2 *>(J.c)[(size_t)l * n + ii];
+  // the table is read-only for this kernel: read through the constant address space,
+  // where the wavefront-uniform addresses become scalar loads into SGPRs (record t
+  // holds a, b, ipi at doubles kRecD t .. kRecD t + 5 and the flag at int kRecI t + kUpdI)
+  typedef __attribute__((address_space(4))) const double CDbl;
+  typedef __attribute__((address_space(4))) const int32_t CInt;
+  constexpr int kRecD = sizeof(ShiftTab) / sizeof(double), kRecI = sizeof(ShiftTab) / sizeof(int32_t);
+  constexpr int kUpdI = offsetof(ShiftTab, upd) / sizeof(int32_t);
+  CDbl *tabd = reinterpret_cast<CDbl *>(reinterpret_cast<uintptr_t>(J.e)) + (size_t)l * N * kRecD;
+  CInt *tabi = reinterpret_cast<CInt *>(reinterpret_cast<uintptr_t>(J.e)) + (size_t)l * N * kRecI;
+  CDbl *gtab = reinterpret_cast<CDbl *>(reinterpret_cast<uintptr_t>(reinterpret_cast<const ShiftTab *>(J.e) +
+                                                                  (size_t)J.nsrc * N)) +
+               (size_t)l * N * kMomRows * 2;
+  const size_t slot0 = (size_t)l * N;
   double2 acc[MM];
 #pragma unroll
-  for (int k = 0; k < MM; ++k) acc[k] = make_double2(0, 0);
-  for (int j0 = 0; j0 < N; j0 += JC) {
-    const int jn = min(JC, N - j0);
-    __syncthreads();
-    for (int jj = threadIdx.x; jj < JC; jj += kMomBlock) {
-      ShiftStep o;
-      if (jj < jn) {
-        ShiftState &H = sh[j0 + jj];
-        o = shift_step(H, alpha, beta, cc, sq, thr);
-        if (vb == 0 && o.upd) {
-          H.pi_n = o.pn;
-          H.res_n = o.res;
-          H.frz_n = o.frz;
-          if (o.frz) H.conv_iter = it + 1;
-        }
-      } else {
-        o.a = o.b = o.ipi = make_double2(0, 0);
-        o.upd = 0;
-      }
-      ups[jj] = o.upd;
-      as[jj] = o.a;
-      bs[jj] = o.b;
-      ips[jj] = o.ipi;
+  for (int k = 0; k < MM; ++k) acc[k] = make_double2(0.0, 0.0);
+  for (int j0 = 0; j0 < N; j0 += UB) {
+    double2 pv[UB];
+    bool up[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int j = j0 + u;
+      up[u] = j < N && tabi[(size_t)j * kRecI + kUpdI] != 0;
+      pv[u] = up[u] ? ld_shift<T>(J.b, slot0 + j, n, ii) : make_double2(0.0, 0.0);
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < MM * JC; t += kMomBlock) {
-      const int k = t / JC, jj = t - k * JC;
-      gs[k][jj] = (k < M && jj < jn && ups[jj]) ? cmul(J.mcoef[(size_t)k * N + j0 + jj], as[jj]) : make_double2(0, 0);
-    }
-    __syncthreads();
-    for (int u0 = 0; u0 < JC; u0 += UB) {
-      double2 pv[UB];
-      bool up[UB];
 #pragma unroll
-      for (int uu = 0; uu < UB; ++uu) {
-        const int jj = u0 + uu;
-        up[uu] = ups[jj] != 0;
-        if (up[uu]) pv[uu] = ld_shift<T>(J.b, slot0 + j0 + jj, n, ii);
+    for (int u = 0; u < UB; ++u) {
+      if (!up[u]) continue;  // uniform
+      const int j = j0 + u;
+      CDbl *gj = gtab + (size_t)j * kMomRows * 2;
+      // eight moments at a time, so that one chunk's coefficients (32 SGPRs) are live
+      // at once; the empty asm keeps the next chunk's loads after this chunk's FMAs
+#pragma unroll
+      for (int k0 = 0; k0 < MM; k0 += 8) {
+        double gx[8], gy[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          gx[q] = gj[2 * (k0 + q)];
+          gy[q] = gj[2 * (k0 + q) + 1];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cfma(acc[k0 + q], make_double2(gx[q], gy[q]), pv[u]);
+        asm volatile("" ::: "memory");
       }
-#pragma unroll
-      for (int uu = 0; uu < UB; ++uu) {
-        const int jj = u0 + uu;
-        // (rows k >= M of g are zero: no branch per moment)
-        if (up[uu]) {
-#pragma unroll
-          for (int k = 0; k < MM; ++k) cfma(acc[k], gs[k][jj], pv[uu]);
-        }
-        if (up[uu] && valid) {
-          double2 pn = cmul(ips[jj], rv);
-          cfma(pn, bs[jj], pv[uu]);
-          st_shift<T>(J.b, slot0 + j0 + jj, n, i, pn);
-        }
+      if (valid) {
+        CDbl *t = tabd + (size_t)j * kRecD;
+        const double2 bj = make_double2(t[2], t[3]), ip = make_double2(t[4], t[5]);
+        double2 pn = cmul(ip, rv);
+        cfma(pn, bj, pv[u]);
+        st_shift<T>(J.b, slot0 + j, n, i, pn);
       }
     }
   }
   if (!valid) return;
   double2 *Sm = reinterpret_cast<double2 *>(J.a);
+  const int M = J.nmom;
 #pragma unroll
   for (int k = 0; k < MM; ++k) {
     if (k < M) {
@@ -581,7 +620,7 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_kernel(VecBatch B) {
       *sp = o;
     }
   }
-  // seed direction p <- r + beta p
+  const double beta = S.beta_n;
   double2 *p = reinterpret_cast<double2 *>(J.d) + (size_t)l * n;
   double2 pv = p[i];
   pv.x = rv.x + beta * pv.x;
@@ -824,18 +863,28 @@ void launch_shift_update(const VecBatch &b, int prec, int seed_prec, int fold, i
     else launch_su_u<float, float, false>(b, unroll, nt, st);
   }
 }
-template <typename T>
-static void launch_sm(const VecBatch &b, int mm, hipStream_t st) {
-  const dim3 g(b.total_blocks), t(kMomBlock);
-  if (mm <= 8) hipLaunchKernelGGL((shift_moments_kernel<T, 8>), g, t, 0, st, b);
-  else if (mm <= 16) hipLaunchKernelGGL((shift_moments_kernel<T, 16>), g, t, 0, st, b);
-  else if (mm <= 24) hipLaunchKernelGGL((shift_moments_kernel<T, 24>), g, t, 0, st, b);
-  else hipLaunchKernelGGL((shift_moments_kernel<T, 32>), g, t, 0, st, b);
-}
-void launch_shift_moments(const VecBatch &b, int prec, int nmom_max, hipStream_t st) {
+void launch_shift_table(const VecBatch &b, hipStream_t st) {
   if (b.total_blocks <= 0) return;
-  if (prec == 0) launch_sm<double>(b, nmom_max, st);
-  else launch_sm<float>(b, nmom_max, st);
+  hipLaunchKernelGGL(shift_table_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+}
+template <typename T, int MM>
+static void launch_smt_ub(const VecBatch &b, int ub, hipStream_t st) {
+  const dim3 g(b.total_blocks), t(kMomBlock);
+  if (ub >= 4) hipLaunchKernelGGL((shift_moments_tab_kernel<T, MM, 4>), g, t, 0, st, b);
+  else if (ub == 2) hipLaunchKernelGGL((shift_moments_tab_kernel<T, MM, 2>), g, t, 0, st, b);
+  else hipLaunchKernelGGL((shift_moments_tab_kernel<T, MM, 1>), g, t, 0, st, b);
+}
+template <typename T>
+static void launch_smt(const VecBatch &b, int mm, int ub, hipStream_t st) {
+  if (mm <= 8) launch_smt_ub<T, 8>(b, ub, st);
+  else if (mm <= 16) launch_smt_ub<T, 16>(b, ub, st);
+  else if (mm <= 24) launch_smt_ub<T, 24>(b, ub, st);
+  else launch_smt_ub<T, 32>(b, ub, st);
+}
+void launch_shift_moments_tab(const VecBatch &b, int prec, int nmom_max, int ub, hipStream_t st) {
+  if (b.total_blocks <= 0) return;
+  if (prec == 0) launch_smt<double>(b, nmom_max, ub, st);
+  else launch_smt<float>(b, nmom_max, ub, st);
 }
 void launch_reliable_residual(const VecBatch &b, hipStream_t st) {
   hipLaunchKernelGGL(reliable_residual_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
