@@ -451,16 +451,17 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
 
 // Shift vectors of the in-loop moment update: an FP64 p_j fills its slot of n
 // double2, an FP32 one the first half.
-template <typename T>
+template <typename T, bool NT = false>
 __device__ __forceinline__ double2 ld_shift(const void *base, size_t slot, int64_t n, int64_t i) {
-  if constexpr (sizeof(T) == 8) return reinterpret_cast<const double2 *>(base)[slot * n + i];
-  const float2 f = reinterpret_cast<const float2 *>(reinterpret_cast<const double2 *>(base) + slot * n)[i];
+  if constexpr (sizeof(T) == 8) return ldc<NT>(reinterpret_cast<const double2 *>(base) + slot * n + i);
+  const float2 f = ldc<NT>(reinterpret_cast<const float2 *>(reinterpret_cast<const double2 *>(base) + slot * n) + i);
   return make_double2(f.x, f.y);
 }
-template <typename T>
+template <typename T, bool NT = false>
 __device__ __forceinline__ void st_shift(void *base, size_t slot, int64_t n, int64_t i, double2 v) {
-  if constexpr (sizeof(T) == 8) reinterpret_cast<double2 *>(base)[slot * n + i] = v;
-  else reinterpret_cast<float2 *>(reinterpret_cast<double2 *>(base) + slot * n)[i] = make_float2((float)v.x, (float)v.y);
+  if constexpr (sizeof(T) == 8) stc<NT>(reinterpret_cast<double2 *>(base) + slot * n + i, v);
+  else stc<NT>(reinterpret_cast<float2 *>(reinterpret_cast<double2 *>(base) + slot * n) + i,
+               make_float2((float)v.x, (float)v.y));
 }
 
 // Moment sums accumulated inside the solve (eq. 2 summed as the solve runs): for every
@@ -542,6 +543,7 @@ __global__ __launch_bounds__(kBlock) void shift_table_kernel(VecBatch B) {
 // d = seed p (FP64), e = the table.
 template <typename T, int MM, int UB>
 __global__ __launch_bounds__(kMomBlock) void shift_moments_tab_kernel(VecBatch B) {
+  constexpr bool NT = true;  // the shift vectors and moments are streamed (non-temporal access)
   const int b = blockIdx.x;
   const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
   const int lb = b - J.block_begin;
@@ -577,15 +579,14 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_tab_kernel(VecBatch B
     for (int u = 0; u < UB; ++u) {
       const int j = j0 + u;
       up[u] = j < N && tabi[(size_t)j * kRecI + kUpdI] != 0;
-      pv[u] = up[u] ? ld_shift<T>(J.b, slot0 + j, n, ii) : make_double2(0.0, 0.0);
+      pv[u] = up[u] ? ld_shift<T, NT>(J.b, slot0 + j, n, ii) : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
       if (!up[u]) continue;  // uniform
       const int j = j0 + u;
       CDbl *gj = gtab + (size_t)j * kMomRows * 2;
-      // eight moments at a time, so that one chunk's coefficients (32 SGPRs) are live
-      // at once; the empty asm keeps the next chunk's loads after this chunk's FMAs
+      // eight moments at a time: one chunk's coefficients take 32 SGPRs
 #pragma unroll
       for (int k0 = 0; k0 < MM; k0 += 8) {
         double gx[8], gy[8];
@@ -596,14 +597,13 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_tab_kernel(VecBatch B
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) cfma(acc[k0 + q], make_double2(gx[q], gy[q]), pv[u]);
-        asm volatile("" ::: "memory");
       }
       if (valid) {
         CDbl *t = tabd + (size_t)j * kRecD;
         const double2 bj = make_double2(t[2], t[3]), ip = make_double2(t[4], t[5]);
         double2 pn = cmul(ip, rv);
         cfma(pn, bj, pv[u]);
-        st_shift<T>(J.b, slot0 + j, n, i, pn);
+        st_shift<T, NT>(J.b, slot0 + j, n, i, pn);
       }
     }
   }
@@ -614,10 +614,10 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_tab_kernel(VecBatch B
   for (int k = 0; k < MM; ++k) {
     if (k < M) {
       double2 *sp = Sm + ((size_t)k * J.nsrc + l) * n + i;
-      double2 o = *sp;
+      double2 o = ldc<NT>(sp);
       o.x += acc[k].x;
       o.y += acc[k].y;
-      *sp = o;
+      stc<NT>(sp, o);
     }
   }
   const double beta = S.beta_n;
