@@ -42,8 +42,10 @@
  *            SSCG_XCD, SSCG_CT, SSCG_TBS, SSCG_WBATCH, SSCG_UNROLL, SSCG_NT set,
  *            fixes the shapes (read at sscg_create); with fixed shapes a solve is
  *            bitwise reproducible (the reductions do not depend on the schedule).
- *            SSCG_MOMUB (1, 2 or 4; default 2) sets how many shifts' loads the
- *            in-loop moment update issues together.
+ *            SSCG_MOMUB (1, 2 or 4; default 1) sets how many shifts' loads the
+ *            in-loop moment update issues together, and SSCG_MOMPF (default 1)
+ *            whether it issues the next group's loads before the current group's
+ *            stores (read at the start of each solve; same results either way).
  */
 #ifndef SSCG_H
 #define SSCG_H

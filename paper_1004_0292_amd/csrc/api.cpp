@@ -531,6 +531,7 @@ struct IterPlan {
   VecBatch mt;        // its table kernel (per (source, shift) scalars of the iteration)
   int nmom_max;       // 0: the solutions are stored
   int mom_ub;         // shifts per load batch of the in-loop moment update
+  int mom_pf;         // in-loop moment update: next batch's loads issued before this batch's stores
   int ct;             // dslash kernel: t-slices per block (0: site-parallel)
   bool fuse_alpha;    // the residual update forms the seed step length itself
 };
@@ -539,7 +540,10 @@ constexpr int kFuseAlphaMax = 1024;  // <p, Bp> partials per source up to which 
 static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts &o, const Tune &t) {
   memset(&pl, 0, sizeof(pl));
   int bd = 0, bdru = 0, bs = 0, bv = 0, bu = 0, bm = 0, bmt = 0;
-  pl.mom_ub = env_int("SSCG_MOMUB", 2);
+  // one shift per group, the next shift's loads ahead of this shift's stores: the
+  // fastest form at 24^3 x 48 in FP64 and with FP32 directions
+  pl.mom_ub = env_int("SSCG_MOMUB", 1);
+  pl.mom_pf = env_int("SSCG_MOMPF", 1);
   const int np = (int)P.size();
   // the tile kernel needs a tile of t.tbs sites on every lattice of the batch, with
   // LDS for FP64 spinors (the FP64 phase and the reliable updates use it too)
@@ -757,7 +761,7 @@ static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, boo
   rec.mark(ST_SHIFT);
   if (pl.nmom_max > 0) {  // FP64 seed in both phases (checked by run_solve)
     launch_shift_table(pl.mt, st);
-    launch_shift_moments_tab(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, pl.mom_ub, st);
+    launch_shift_moments_tab(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, pl.mom_ub, pl.mom_pf, st);
   } else {
     const VecBatch &u = prec == 0 ? pl.u64 : (sp == 1 ? pl.u32 : pl.u32s);
     launch_shift_update(u, prec, sp, prec == 1 && ru, t.unroll, t.nt, st);
@@ -799,7 +803,10 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
   CHK(ensure(c, c->r64, L * vec64));
   CHK(ensure(c, c->p64, L * vec64));
   CHK(ensure(c, c->q64, L * vec64));
-  CHK(ensure(c, c->W, L * N * vec64));
+  // shift directions: one vector per (source, shift), chunk-blocked and padded to a
+  // multiple of 64 entries in the in-loop moment form
+  const size_t npad = (n + 63) / 64 * 64;
+  CHK(ensure(c, c->W, L * N * (p.nmom > 0 ? npad : n) * sizeof(double2)));
   CHK(ensure(c, c->tmp, vec64));
   CHK(ensure(c, c->pq_part, L * (size_t)((c->V + 63) / 64) * sizeof(double)));
   CHK(ensure(c, c->rr_part, std::max<size_t>(L * nblk_vec(c), L * 64) * sizeof(double)));
@@ -827,7 +834,10 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
   launch_pack(p.v, c->v64.p, 0, (int)L, c->V, st);
   HIPCHK(c, hipMemcpyAsync(c->r64.p, c->v64.p, L * vec64, hipMemcpyDeviceToDevice, st));
   HIPCHK(c, hipMemcpyAsync(c->p64.p, c->v64.p, L * vec64, hipMemcpyDeviceToDevice, st));
-  launch_init_shifts(p.y, c->W.p, c->v64.p, (int64_t)n, (int)L, (int)N, st);
+  if (p.nmom > 0)
+    launch_init_shifts_blocked(c->W.p, c->v64.p, (int64_t)n, (int)L, (int)N, st);
+  else
+    launch_init_shifts(p.y, c->W.p, c->v64.p, (int64_t)n, (int)L, (int)N, st);
   // ||v||
   const int nb = 64;
   launch_norm2_partial(c->v64.p, c->n, (int)L, (double *)c->rr_part.p, nb, st);
@@ -876,6 +886,10 @@ static int switch_to_fp32(Prob &p, bool seed32, hipStream_t st) {
     HIPCHK(c, hipMemcpyAsync(c->rbase.p, c->r64.p, L * vec64, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemsetAsync(c->xpart64.p, 0, L * vec64, st));
     HIPCHK(c, hipMemsetAsync(c->xpart32.p, 0, L * n * sizeof(float2), st));
+  }
+  if (p.nmom > 0) {  // in-loop moment form: chunk-blocked directions, converted in place
+    launch_blocked_to_fp32(c->W.p, (int64_t)n, (int)L, (int)N, st);
+    return SSCG_OK;
   }
   for (size_t k = 0; k < L * N; ++k) {
     char *slot = (char *)c->W.p + k * vec64;

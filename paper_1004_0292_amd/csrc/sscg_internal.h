@@ -59,6 +59,55 @@ template <typename C> __host__ __device__ __forceinline__ C ci(C a) { C c; c.x =
 template <typename C> __host__ __device__ __forceinline__ C cmi(C a) { C c; c.x = a.y; c.y = -a.x; return c; }
 template <typename C> __host__ __device__ __forceinline__ C cneg(C a) { C c; c.x = -a.x; c.y = -a.y; return c; }
 
+// ---- raw buffer access ------------------------------------------------------
+// Loads and stores through a buffer resource: base address and size in bytes in
+// scalar registers, a 32-bit per-lane byte offset and a scalar byte offset. A lane
+// whose offset lies at or past the size reads zero and writes nothing, with no memory
+// access. AUX = 2 marks the access non-temporal.
+
+// A value the same on every lane (a scalar offset, a resource word); readfirstlane
+// states it, so the compiler keeps it in scalar registers also where it meets per-lane
+// branches (a resource the compiler takes for per-lane is used lane group by lane group).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int nbytes) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  void *q = reinterpret_cast<void *>(((unsigned long long)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, uni(nbytes), 0x00020000);
+}
+
+template <typename T, int AUX = 0> struct BufIO;
+template <int AUX> struct BufIO<double, AUX> {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ double2 ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    const v2 v = __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, uni(soff), AUX));
+    return make_double2(v.x, v.y);
+  }
+  static __device__ __forceinline__ void st(double2 x, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    v2 v;
+    v.x = x.x;
+    v.y = x.y;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, voff, uni(soff), AUX);
+  }
+};
+template <int AUX> struct BufIO<float, AUX> {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ float2 ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    const v2 v = __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, uni(soff), AUX));
+    return make_float2(v.x, v.y);
+  }
+  static __device__ __forceinline__ void st(float2 x, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    v2 v;
+    v.x = x.x;
+    v.y = x.y;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, uni(soff), AUX);
+  }
+};
+
 // ---- solver state (device memory) ------------------------------------------
 // The shift update kernel forms the scalars of its iteration itself (every block
 // from the same inputs, so every block gets the same values) and may not change
@@ -302,13 +351,19 @@ constexpr int kMomBlock = 256;   // entries (threads) per block of the in-loop m
 // ceil(nshift / kBlock); of the update: nblk_mom.
 void launch_shift_table(const VecBatch &b, hipStream_t st);
 // ub: shifts whose loads are issued together (1, 2, 4)
-void launch_shift_moments_tab(const VecBatch &b, int prec, int nmom_max, int ub, hipStream_t st);
+void launch_shift_moments_tab(const VecBatch &b, int prec, int nmom_max, int ub, int pf, hipStream_t st);
 inline size_t shift_table_bytes(int nsrc, int nshift) {
   return (size_t)nsrc * nshift * (sizeof(ShiftTab) + (size_t)kMomRows * sizeof(double2));
 }
 void launch_fold_seed(const VecBatch &b, hipStream_t st);
 void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st);
 void launch_init_shifts(void *y, void *W, const void *v, int64_t n, int nsrc, int nshift, hipStream_t st);
+// in-loop moment form: p_j = v in the chunk-blocked layout of the shift directions
+// (entry 64 c + q of shift j of source l at double2 ((l ceil(n/64) + c) N + j) 64 + q),
+// and the in-place FP32 switch of that layout (each 64-entry run's float2 in its
+// first half)
+void launch_init_shifts_blocked(void *W, const void *v, int64_t n, int nsrc, int nshift, hipStream_t st);
+void launch_blocked_to_fp32(void *W, int64_t n, int nsrc, int nshift, hipStream_t st);
 void launch_moments_strided(const void *y, int nsrc, int nshift, const double *c_dev, int nmom, void *s,
                             int64_t n, int64_t sl, int64_t sk, hipStream_t st);
 // y: [nsrc] blocks of y_stride_l vectors, the first nshift of each used

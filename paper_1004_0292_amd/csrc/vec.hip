@@ -449,21 +449,6 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
   }
 }
 
-// Shift vectors of the in-loop moment update: an FP64 p_j fills its slot of n
-// double2, an FP32 one the first half.
-template <typename T, bool NT = false>
-__device__ __forceinline__ double2 ld_shift(const void *base, size_t slot, int64_t n, int64_t i) {
-  if constexpr (sizeof(T) == 8) return ldc<NT>(reinterpret_cast<const double2 *>(base) + slot * n + i);
-  const float2 f = ldc<NT>(reinterpret_cast<const float2 *>(reinterpret_cast<const double2 *>(base) + slot * n) + i);
-  return make_double2(f.x, f.y);
-}
-template <typename T, bool NT = false>
-__device__ __forceinline__ void st_shift(void *base, size_t slot, int64_t n, int64_t i, double2 v) {
-  if constexpr (sizeof(T) == 8) stc<NT>(reinterpret_cast<double2 *>(base) + slot * n + i, v);
-  else stc<NT>(reinterpret_cast<float2 *>(reinterpret_cast<double2 *>(base) + slot * n) + i,
-               make_float2((float)v.x, (float)v.y));
-}
-
 // Moment sums accumulated inside the solve (eq. 2 summed as the solve runs): for every
 // shift updated in an iteration, the step alpha_j p_j that would be added to x_j is
 // added to every moment instead, s_{k,l} += c[k][j] alpha_j p_j, and p_j advances as
@@ -534,16 +519,37 @@ __global__ __launch_bounds__(kBlock) void shift_table_kernel(VecBatch B) {
   }
 }
 
+// Shift directions of the in-loop moment form, chunk-blocked: entry i = 64 c + q of
+// shift j of source l is double2 number ((l nch + c) N + j) 64 + q of the slot
+// buffer (nch = ceil(n / 64), entries past n are padding). A wavefront that owns one
+// chunk of 64 entries then walks one contiguous run of N kilobytes over its shifts,
+// instead of N runs a whole vector apart (about 10 % more of the HBM peak for the
+// streaming pattern of this update). In the FP32 phase a chunk holds its 64 float2 in
+// its first half (the chunk stride stays 1 KB), so the switch converts each chunk in
+// place.
+__device__ __forceinline__ size_t blk_chunk(int l, int64_t c, int j, int64_t nch, int N) {
+  return (((size_t)l * nch + c) * N + j) * 64;  // double2 index of chunk (l, c, j)
+}
+
 // The update of the table form: one thread per entry of one source loops over the
-// shifts (UB at a time, their loads issued together), adds g_kj p_j to each of its MM
-// moment sums (rows beyond the moments summed have g = 0) and advances p_j <- r / pi_j
-// + b_j p_j for every shift the table marks as updated. The table and coefficients
-// sit at addresses that are the same for the whole wavefront; the seed direction is
-// advanced with the staged beta_k. job: a = moments, b = shift slots, c = seed r,
-// d = seed p (FP64), e = the table.
-template <typename T, int MM, int UB>
+// shifts (UB at a time), adds g_kj p_j to each of its MM moment sums (rows beyond the
+// moments summed have g = 0) and advances p_j <- r / pi_j + b_j p_j for every shift
+// the table marks as updated. The table and coefficients sit at addresses that are
+// the same for the whole wavefront; the seed direction is advanced with the staged
+// beta_k. job: a = moments, b = shift directions (chunk-blocked), c = seed r, d = seed
+// p (FP64), e = the table.
+// Memory: each (chunk, shift) run of 64 entries is read and written through a buffer
+// resource of its own, of size zero for a shift not updated; lanes past the end get
+// an offset past the size. Every load and store is therefore issued on every path (a
+// masked lane or shift moves no data), so the number of memory operations in flight
+// is known and the compiler waits for exactly the loads it needs. Vector loads and
+// stores share one completion counter that counts down in issue order, so a load
+// issued after a store is only seen complete once the store is: the moments (and the
+// seed direction) are read at the start and written only at the end, and with PF = 1
+// the loads of the next group of UB shifts are issued before the stores of the
+// current group.
+template <typename T, int MM, int UB, int PF>
 __global__ __launch_bounds__(kMomBlock) void shift_moments_tab_kernel(VecBatch B) {
-  constexpr bool NT = true;  // the shift vectors and moments are streamed (non-temporal access)
   const int b = blockIdx.x;
   const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
   const int lb = b - J.block_begin;
@@ -551,10 +557,13 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_tab_kernel(VecBatch B
   const SeedState &S = J.seed[l];
   if (S.done || !S.pending || S.brk_n) return;  // uniform over the block
   const int64_t n = J.n;
+  const int64_t nch = (n + 63) / 64;
   const int N = J.nshift;
   const int64_t i = (int64_t)vb * kMomBlock + threadIdx.x;
   const bool valid = i < n;
   const int64_t ii = valid ? i : 0;  // invalid lanes read entry 0 and store nothing
+  const int64_t c = i >> 6;          // the wavefront's chunk (the same on all its lanes)
+  const int q = (int)(i & 63);
   const double2 rv = reinterpret_cast<const double2 *>(J.c)[(size_t)l * n + ii];
   // the table is read-only for this kernel: read through the constant address space,
   // where the wavefront-uniform addresses become scalar loads into SGPRs (record t
@@ -568,64 +577,108 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_tab_kernel(VecBatch B
   CDbl *gtab = reinterpret_cast<CDbl *>(reinterpret_cast<uintptr_t>(reinterpret_cast<const ShiftTab *>(J.e) +
                                                                   (size_t)J.nsrc * N)) +
                (size_t)l * N * kMomRows * 2;
-  const size_t slot0 = (size_t)l * N;
+  // moment k of this source through a resource of its own (size zero for k >= M)
+  const double2 *Sm = reinterpret_cast<const double2 *>(J.a);
+  const int M = J.nmom;
+  const int voff16 = valid ? (int)(i * 16) : 0x7fffffff;
+  auto mom_rsrc = [&](int k) { return make_rsrc(Sm + ((size_t)k * J.nsrc + l) * n, k < M ? (int)(n * 16) : 0); };
   double2 acc[MM];
 #pragma unroll
-  for (int k = 0; k < MM; ++k) acc[k] = make_double2(0.0, 0.0);
+  for (int k = 0; k < MM; ++k) acc[k] = BufIO<double, 2>::ld(mom_rsrc(k), voff16, 0);
+  double2 *p = reinterpret_cast<double2 *>(J.d) + (size_t)l * n;
+  const double2 pold = p[ii];
+  // shift j's run of this chunk (64 entries of V2<T>, 1 KB apart from the next shift's)
+  constexpr int kW = sizeof(V2<T>);
+  const int voff = valid ? q * kW : 0x7fffffff;
+  const double2 *W = reinterpret_cast<const double2 *>(J.b);
+  auto run_rsrc = [&](int j, bool upd) { return make_rsrc(W + blk_chunk(l, c, j, nch, N), upd ? 64 * kW : 0); };
+  auto fetch = [&](int j0, double2 (&v)[UB], bool (&f)[UB]) {
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int j = j0 + u;
+      f[u] = j < N && tabi[(size_t)j * kRecI + kUpdI] != 0;
+      const V2<T> x = BufIO<T, 2>::ld(run_rsrc(j, f[u]), voff, 0);
+      v[u] = make_double2(x.x, x.y);
+    }
+  };
+  double2 nv[UB];
+  bool nup[UB];
+  if constexpr (PF) fetch(0, nv, nup);
   for (int j0 = 0; j0 < N; j0 += UB) {
     double2 pv[UB];
     bool up[UB];
+    if constexpr (PF) {
 #pragma unroll
-    for (int u = 0; u < UB; ++u) {
-      const int j = j0 + u;
-      up[u] = j < N && tabi[(size_t)j * kRecI + kUpdI] != 0;
-      pv[u] = up[u] ? ld_shift<T, NT>(J.b, slot0 + j, n, ii) : make_double2(0.0, 0.0);
+      for (int u = 0; u < UB; ++u) {
+        pv[u] = nv[u];
+        up[u] = nup[u];
+      }
+      if (j0 + UB < N) fetch(j0 + UB, nv, nup);
+    } else {
+      fetch(j0, pv, up);
     }
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
-      if (!up[u]) continue;  // uniform
       const int j = j0 + u;
-      CDbl *gj = gtab + (size_t)j * kMomRows * 2;
-      // eight moments at a time: one chunk's coefficients take 32 SGPRs
+      if (up[u]) {  // uniform
+        CDbl *gj = gtab + (size_t)j * kMomRows * 2;
+        // eight moments at a time: one chunk's coefficients take 32 SGPRs
 #pragma unroll
-      for (int k0 = 0; k0 < MM; k0 += 8) {
-        double gx[8], gy[8];
+        for (int k0 = 0; k0 < MM; k0 += 8) {
+          double gx[8], gy[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          gx[q] = gj[2 * (k0 + q)];
-          gy[q] = gj[2 * (k0 + q) + 1];
+          for (int e = 0; e < 8; ++e) {
+            gx[e] = gj[2 * (k0 + e)];
+            gy[e] = gj[2 * (k0 + e) + 1];
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e) cfma(acc[k0 + e], make_double2(gx[e], gy[e]), pv[u]);
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) cfma(acc[k0 + q], make_double2(gx[q], gy[q]), pv[u]);
       }
-      if (valid) {
-        CDbl *t = tabd + (size_t)j * kRecD;
-        const double2 bj = make_double2(t[2], t[3]), ip = make_double2(t[4], t[5]);
-        double2 pn = cmul(ip, rv);
-        cfma(pn, bj, pv[u]);
-        st_shift<T, NT>(J.b, slot0 + j, n, i, pn);
-      }
+      // issued for every shift of the group: the resource of a shift not updated (or
+      // past the last) has size zero, and the store moves nothing
+      CDbl *t = tabd + (size_t)min(j, N - 1) * kRecD;
+      const double2 bj = make_double2(t[2], t[3]), ip = make_double2(t[4], t[5]);
+      double2 pn = cmul(ip, rv);
+      cfma(pn, bj, pv[u]);
+      V2<T> x;
+      x.x = pn.x;
+      x.y = pn.y;
+      BufIO<T, 2>::st(x, run_rsrc(j, up[u]), voff, 0);
     }
   }
+#pragma unroll
+  for (int k = 0; k < MM; ++k) BufIO<double, 2>::st(acc[k], mom_rsrc(k), voff16, 0);
   if (!valid) return;
-  double2 *Sm = reinterpret_cast<double2 *>(J.a);
-  const int M = J.nmom;
-#pragma unroll
-  for (int k = 0; k < MM; ++k) {
-    if (k < M) {
-      double2 *sp = Sm + ((size_t)k * J.nsrc + l) * n + i;
-      double2 o = ldc<NT>(sp);
-      o.x += acc[k].x;
-      o.y += acc[k].y;
-      stc<NT>(sp, o);
-    }
-  }
   const double beta = S.beta_n;
-  double2 *p = reinterpret_cast<double2 *>(J.d) + (size_t)l * n;
-  double2 pv = p[i];
-  pv.x = rv.x + beta * pv.x;
-  pv.y = rv.y + beta * pv.y;
+  double2 pv;
+  pv.x = rv.x + beta * pold.x;
+  pv.y = rv.y + beta * pold.y;
   p[i] = pv;
+}
+
+// Start of an in-loop solve: p_j = v_l in the chunk-blocked layout (padding zero).
+// Grid: (ceil(nch 64 / kBlock), nsrc * nshift).
+__global__ void init_shifts_blocked_kernel(double2 *W, const double2 *v, int64_t n, int nshift) {
+  const int slot = blockIdx.y;
+  const int l = slot / nshift, j = slot - l * nshift;
+  const int64_t nch = (n + 63) / 64;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nch * 64) return;
+  W[blk_chunk(l, i >> 6, j, nch, nshift) + (i & 63)] = i < n ? v[(size_t)l * n + i] : make_double2(0.0, 0.0);
+}
+
+// FP32 switch of the chunk-blocked directions, in place: one wavefront per (source,
+// chunk, shift) run reads its 64 double2 and writes them back as 64 float2 into the
+// run's first half (the store depends on the loaded values, so the whole run is read
+// before any of it is written). nruns = nsrc * nch * nshift.
+__global__ void blocked_to_fp32_kernel(double2 *W, int64_t nruns) {
+  const int64_t run = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (run >= nruns) return;
+  const int q = threadIdx.x & 63;
+  double2 *base = W + (size_t)run * 64;
+  const double2 x = base[q];
+  reinterpret_cast<float2 *>(base)[q] = make_float2((float)x.x, (float)x.y);
 }
 
 // Reliable update: r64 = r_base - B x_part (q = B x_part already computed in FP64),
@@ -868,23 +921,28 @@ void launch_shift_table(const VecBatch &b, hipStream_t st) {
   hipLaunchKernelGGL(shift_table_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
 }
 template <typename T, int MM>
-static void launch_smt_ub(const VecBatch &b, int ub, hipStream_t st) {
+static void launch_smt_ub(const VecBatch &b, int ub, int pf, hipStream_t st) {
   const dim3 g(b.total_blocks), t(kMomBlock);
-  if (ub >= 4) hipLaunchKernelGGL((shift_moments_tab_kernel<T, MM, 4>), g, t, 0, st, b);
-  else if (ub == 2) hipLaunchKernelGGL((shift_moments_tab_kernel<T, MM, 2>), g, t, 0, st, b);
-  else hipLaunchKernelGGL((shift_moments_tab_kernel<T, MM, 1>), g, t, 0, st, b);
+  if (pf) {
+    if (ub >= 2) hipLaunchKernelGGL((shift_moments_tab_kernel<T, MM, 2, 1>), g, t, 0, st, b);
+    else hipLaunchKernelGGL((shift_moments_tab_kernel<T, MM, 1, 1>), g, t, 0, st, b);
+    return;
+  }
+  if (ub >= 4) hipLaunchKernelGGL((shift_moments_tab_kernel<T, MM, 4, 0>), g, t, 0, st, b);
+  else if (ub == 2) hipLaunchKernelGGL((shift_moments_tab_kernel<T, MM, 2, 0>), g, t, 0, st, b);
+  else hipLaunchKernelGGL((shift_moments_tab_kernel<T, MM, 1, 0>), g, t, 0, st, b);
 }
 template <typename T>
-static void launch_smt(const VecBatch &b, int mm, int ub, hipStream_t st) {
-  if (mm <= 8) launch_smt_ub<T, 8>(b, ub, st);
-  else if (mm <= 16) launch_smt_ub<T, 16>(b, ub, st);
-  else if (mm <= 24) launch_smt_ub<T, 24>(b, ub, st);
-  else launch_smt_ub<T, 32>(b, ub, st);
+static void launch_smt(const VecBatch &b, int mm, int ub, int pf, hipStream_t st) {
+  if (mm <= 8) launch_smt_ub<T, 8>(b, ub, pf, st);
+  else if (mm <= 16) launch_smt_ub<T, 16>(b, ub, pf, st);
+  else if (mm <= 24) launch_smt_ub<T, 24>(b, ub, pf, st);
+  else launch_smt_ub<T, 32>(b, ub, pf, st);
 }
-void launch_shift_moments_tab(const VecBatch &b, int prec, int nmom_max, int ub, hipStream_t st) {
+void launch_shift_moments_tab(const VecBatch &b, int prec, int nmom_max, int ub, int pf, hipStream_t st) {
   if (b.total_blocks <= 0) return;
-  if (prec == 0) launch_smt<double>(b, nmom_max, ub, st);
-  else launch_smt<float>(b, nmom_max, ub, st);
+  if (prec == 0) launch_smt<double>(b, nmom_max, ub, pf, st);
+  else launch_smt<float>(b, nmom_max, ub, pf, st);
 }
 void launch_reliable_residual(const VecBatch &b, hipStream_t st) {
   hipLaunchKernelGGL(reliable_residual_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
@@ -897,6 +955,17 @@ void launch_to_fp32(const void *src64, void *dst32, void *zero32, int64_t n, hip
   if (n <= 0) return;
   hipLaunchKernelGGL(to_fp32_kernel, dim3(nblocks1d(n)), dim3(kBlock), 0, st,
                      (const double2 *)src64, (float2 *)dst32, (float2 *)zero32, n);
+}
+void launch_init_shifts_blocked(void *W, const void *v, int64_t n, int nsrc, int nshift, hipStream_t st) {
+  const int64_t npad = (n + 63) / 64 * 64;
+  hipLaunchKernelGGL(init_shifts_blocked_kernel, dim3(nblocks1d(npad), nsrc * nshift), dim3(kBlock), 0, st,
+                     (double2 *)W, (const double2 *)v, n, nshift);
+}
+void launch_blocked_to_fp32(void *W, int64_t n, int nsrc, int nshift, hipStream_t st) {
+  const int64_t nruns = (int64_t)nsrc * ((n + 63) / 64) * nshift;
+  const int64_t per = kBlock / 64;
+  hipLaunchKernelGGL(blocked_to_fp32_kernel, dim3((unsigned)((nruns + per - 1) / per)), dim3(kBlock), 0, st,
+                     (double2 *)W, nruns);
 }
 void launch_init_shifts(void *y, void *W, const void *v, int64_t n, int nsrc, int nshift, hipStream_t st) {
   if (n <= 0 || nsrc * nshift <= 0) return;

@@ -108,12 +108,18 @@ def test_rr_more_accurate_than_hankel(sscg, f4):
             assert np.abs(lam - l).min() <= r_ + 1e-13
 
 
-@pytest.mark.parametrize("prec,P", [("fp64", 1), ("mixed_shifts", 1), ("fp64", 3)])
-def test_moments_in_loop(sscg, f4, prec, P):
+@pytest.mark.parametrize("prec,P,pf,ub", [("fp64", 1, 0, 2), ("mixed_shifts", 1, 0, 2), ("fp64", 3, 0, 2),
+                                         ("fp64", 1, 1, 1), ("fp64", 1, 1, 2), ("mixed_shifts", 1, 1, 2),
+                                         ("fp64", 3, 1, 1), ("fp64", 1, 0, 4)])
+def test_moments_in_loop(sscg, f4, monkeypatch, prec, P, pf, ub):
     """Moments summed inside the solve (no stored y_j) equal the stored-solution path
     and the oracle: same count, eigenvalues within 1e-10 relative, residuals below 1e-8
-    (or twice the oracle's where N = 16, M = 8 leave the oracle itself above it)."""
-    case(f"in-loop moments {prec} P={P}")
+    (or twice the oracle's where N = 16, M = 8 leave the oracle itself above it). The
+    update kernel runs with ub shifts per load group, with (pf = 1) or without the next
+    group's loads issued ahead of the current group's stores."""
+    case(f"in-loop moments {prec} P={P} pf={pf} ub={ub}")
+    monkeypatch.setenv("SSCG_MOMPF", str(pf))
+    monkeypatch.setenv("SSCG_MOMUB", str(ub))
     U, A, lam, c = f4
     V = synth.sources(CFG1.V, 2, 8).reshape(2, -1)
     pr = {"fp64": sscg.FP64, "mixed_shifts": sscg.MIXED_SHIFTS}[prec]
@@ -138,6 +144,35 @@ def test_moments_in_loop(sscg, f4, prec, P):
     for k in range(fused.n_found):
         ov = abs(np.vdot(Xf[k].ravel(), Xs[k].ravel()))
         assert ov > 1 - 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_shifts"])
+def test_moments_in_loop_ragged_chunks(sscg, prec):
+    """In-loop moments on a lattice whose vector length n = 12 V = 1620 is not a
+    multiple of 64: the shift directions are stored in 64-entry chunks with a padded
+    last chunk. Eigenpairs equal the stored-solution path and the dense spectrum."""
+    case(f"in-loop moments ragged chunks {prec}")
+    dims, kappa = (3, 3, 3, 5), 0.12
+    U = synth.gauge_field(dims, 0.3, 11)
+    A = wilson.hermitian_wilson(U, dims, kappa)
+    lam = np.linalg.eigvalsh(A.toarray())
+    V = synth.sources(int(np.prod(dims)), 2, 12).reshape(2, -1)
+    # a window around the smallest positive eigenvalue holding a few eigenvalues
+    pos = np.sort(lam[lam > 0])
+    gamma, rho = float(0.5 * (pos[0] + pos[3])), float(0.5 * (pos[3] - pos[0]) + 0.25 * (pos[4] - pos[3]))
+    inside = lam[(lam > gamma - rho) & (lam < gamma + rho)]
+    c = sscg.Context(dims, kappa)
+    c.set_gauge(U)
+    pr = {"fp64": sscg.FP64, "mixed_shifts": sscg.MIXED_SHIFTS}[prec]
+    opts = sscg.default_opts(prec=pr, switch_tol=1e-6, ru_interval=20)
+    kw = dict(gamma=gamma, rho=rho, beta=0.25, N=16, M=8, rank_tol=1e-7)
+    stored = c.ss_eigs(sscg.default_ss_params(solve=opts, **kw), to_dev(V), max_eigs=16)
+    fused = c.ss_eigs(sscg.default_ss_params(solve=opts, moments_in_loop=1, **kw), to_dev(V), max_eigs=16)
+    c.close()
+    assert fused.n_found == stored.n_found == len(inside) > 0
+    assert np.all(np.abs(fused.lam - stored.lam) <= 1e-11 * np.abs(stored.lam))
+    assert np.all(np.abs(np.sort(fused.lam) - np.sort(inside)) <= 1e-10 * np.abs(np.sort(inside)))
+    assert np.all(fused.res < 1e-8)
 
 
 def test_moments_in_loop_rejects(sscg, f4):
