@@ -1507,33 +1507,42 @@ void sscg_default_ss_params(sscg_ss_params *p) {
 // ---------------------------------------------------------------------------
 // extraction (Sec. 2.1): Rayleigh-Ritz or block Hankel, then acceptance (Sec. 3)
 
-// C (na x nb, row-major on host, complex) = A^H B over n rows; A, B device column sets
-static int gram(sscg_ctx *c, const void *A, int na, const void *B, int nb, std::vector<cd> &out, hipStream_t st) {
+// C (na x nb, row-major on host, complex) = A^H B over n rows; A, B device column sets.
+// herm: the product is Hermitian (A^H A, or Q^H (A Q) with A Hermitian; na = nb): the
+// device computes the tiles on and above the diagonal, and the entries below the
+// diagonal are the conjugates of those above.
+static int gram(sscg_ctx *c, const void *A, int na, const void *B, int nb, std::vector<cd> &out, hipStream_t st,
+                bool herm = false) {
+  if (herm && na != nb) return fail(c, SSCG_EINVAL, "internal: Hermitian product of unequal sizes");
   // row chunks: enough blocks to spread over the chip, at least 64 rows each (more
   // chunks also mean more partials to sum afterwards)
-  const int tiles = gemm_cn_tiles(na, nb);
+  const int tiles = gemm_cn_tiles(na, nb, herm ? 1 : 0);
   int nchunk = std::max(1, std::min(256, 512 / tiles));
   nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(nchunk, c->n / 64));
   const size_t nout = (size_t)na * nb;
   CHK(ensure(c, c->small, nchunk * nout * 2 * sizeof(double) + nout * 2 * sizeof(double)));
   double *part = (double *)c->small.p;
   double *red = part + nchunk * nout * 2;
-  launch_gemm_cn(A, c->n, na, B, c->n, nb, c->n, part, nchunk, st);
+  launch_gemm_cn(A, c->n, na, B, c->n, nb, c->n, part, nchunk, herm ? 1 : 0, st);
   launch_reduce_partials(part, nchunk, (int)(2 * nout), red, st);
   std::vector<double> h(2 * nout);
   HIPCHK(c, hipMemcpyAsync(h.data(), red, 2 * nout * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(c, hipStreamSynchronize(st));
   out.resize(nout);
   for (size_t k = 0; k < nout; ++k) out[k] = cd(h[2 * k], h[2 * k + 1]);
+  if (herm)
+    for (int a = 1; a < na; ++a)
+      for (int b = 0; b < a; ++b) out[(size_t)a * nb + b] = std::conj(out[(size_t)b * nb + a]);
   return SSCG_OK;
 }
 
-// C = A T (and C2 = A2 T when A2 is given) with T (na x nb) row-major host complex.
-// Stream-ordered: T goes through the context's host staging vector, which the next
-// call only rewrites after a synchronisation (every caller reads a Gram matrix or
-// residuals back between two calls).
+// C = A T (and C2 = A2 T when A2 is given) with T (na x nb) row-major host complex;
+// upper: T is upper triangular (the products skip its zero part). Stream-ordered: T
+// goes through the context's host staging vector, which the next call only rewrites
+// after a synchronisation (every caller reads a Gram matrix or residuals back between
+// two calls).
 static int basis_change(sscg_ctx *c, const void *A, int na, const std::vector<cd> &T, int nb, void *C,
-                        hipStream_t st, const void *A2 = nullptr, void *C2 = nullptr) {
+                        hipStream_t st, const void *A2 = nullptr, void *C2 = nullptr, bool upper = false) {
   const size_t need = (size_t)na * nb * sizeof(double2);
   if (c->tmp.bytes < need) {  // a kernel still reading the old buffer finishes first
     HIPCHK(c, hipStreamSynchronize(st));
@@ -1546,8 +1555,8 @@ static int basis_change(sscg_ctx *c, const void *A, int na, const std::vector<cd
     h[2 * k + 1] = T[k].imag();
   }
   HIPCHK(c, hipMemcpyAsync(c->tmp.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  launch_gemm_nn(A, c->n, na, (const double *)c->tmp.p, nb, C, c->n, c->n, st);
-  if (A2) launch_gemm_nn(A2, c->n, na, (const double *)c->tmp.p, nb, C2, c->n, c->n, st);
+  launch_gemm_nn(A, c->n, na, (const double *)c->tmp.p, nb, C, c->n, c->n, upper ? 1 : 0, st);
+  if (A2) launch_gemm_nn(A2, c->n, na, (const double *)c->tmp.p, nb, C2, c->n, c->n, upper ? 1 : 0, st);
   return SSCG_OK;
 }
 
@@ -1618,7 +1627,7 @@ static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, voi
                       std::vector<double> &lam, int &r, hipStream_t st) {
   const size_t vec = c->n * sizeof(double2);
   std::vector<cd> G;
-  CHK(gram(c, S, ncol, S, ncol, G, st));
+  CHK(gram(c, S, ncol, S, ncol, G, st, true));
   std::vector<double> dsc(ncol);
   for (int a = 0; a < ncol; ++a) dsc[a] = G[(size_t)a * ncol + a].real() > 0 ? 1.0 / std::sqrt(G[(size_t)a * ncol + a].real()) : 0.0;
   std::vector<cd> Gs((size_t)ncol * ncol);
@@ -1641,12 +1650,13 @@ static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, voi
   CHK(ensure(c, c->AQbuf, (size_t)r * vec));
   CHK(basis_change(c, S, ncol, T1, r, c->AQbuf.p, st));  // Q1 (held in AQbuf for now)
   std::vector<cd> G2;
-  CHK(gram(c, c->AQbuf.p, r, c->AQbuf.p, r, G2, st));
+  CHK(gram(c, c->AQbuf.p, r, c->AQbuf.p, r, G2, st, true));
   // second pass: Q1 is orthonormal up to rounding, so its Gram matrix is close to I and
   // a Cholesky factor G2 = R^H R gives Q = Q1 R^-1 (an eigen-decomposition of G2 is
   // the fallback if a pivot is not positive)
   std::vector<cd> T2;
-  if (!chol_inverse_upper(r, G2, T2)) {
+  const bool chol = chol_inverse_upper(r, G2, T2);  // T2 = R^-1, upper triangular
+  if (!chol) {
     std::vector<double> ev2;
     std::vector<cd> W2;
     EIGCHK(c, eig_rowmajor(r, G2, ev2, W2));
@@ -1654,10 +1664,10 @@ static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, voi
     for (int a = 0; a < r; ++a)
       for (int q = 0; q < r; ++q) T2[(size_t)a * r + q] = W2[(size_t)a * r + q] / std::sqrt(std::max(ev2[q], 1e-300));
   }
-  CHK(basis_change(c, c->AQbuf.p, r, T2, r, c->Qbuf.p, st));  // Q
+  CHK(basis_change(c, c->AQbuf.p, r, T2, r, c->Qbuf.p, st, nullptr, nullptr, chol));  // Q
   CHK(apply_A_planar(c, c->Qbuf.p, c->AQbuf.p, r, st));         // A Q
   std::vector<cd> At;
-  CHK(gram(c, c->Qbuf.p, r, c->AQbuf.p, r, At, st));
+  CHK(gram(c, c->Qbuf.p, r, c->AQbuf.p, r, At, st, true));  // Hermitian since A is
   std::vector<cd> Wr;
   EIGCHK(c, eig_rowmajor(r, At, lam, Wr));
   CHK(basis_change(c, c->Qbuf.p, r, Wr, r, Xd, st, c->AQbuf.p, AXd));

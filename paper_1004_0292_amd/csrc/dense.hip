@@ -13,15 +13,27 @@ namespace sscg {
 constexpr int kGT = 64;  // output tile edge
 constexpr int kGK = 16;  // summed-index step staged in LDS
 
-// partial[chunk][a][b] = sum over the chunk's rows of conj(A[row][a]) B[row][b]
+// partial[chunk][a][b] = sum over the chunk's rows of conj(A[row][a]) B[row][b].
+// herm = 1 (a Hermitian product, na = nb): only the tiles on and above the diagonal
+// (the caller mirrors the rest); the blocks enumerate them row by row.
 __global__ __launch_bounds__(256) void gemm_cn_kernel(const double2 *__restrict__ A, int64_t lda, int na,
                                                       const double2 *__restrict__ B, int64_t ldb, int nb,
-                                                      int64_t n, double2 *partial, int nchunk) {
+                                                      int64_t n, double2 *partial, int nchunk, int herm) {
   __shared__ double2 As[kGK][kGT + 1];
   __shared__ double2 Bs[kGK][kGT + 1];
   const int tiles_b = (nb + kGT - 1) / kGT;
   const int tile = blockIdx.x, chunk = blockIdx.y;
-  const int a0 = (tile / tiles_b) * kGT, b0 = (tile % tiles_b) * kGT;
+  int ta = tile / tiles_b, tb = tile % tiles_b;
+  if (herm) {
+    ta = 0;
+    tb = tile;
+    while (tb >= tiles_b - ta) {  // row ta holds tiles ta .. tiles_b - 1
+      tb -= tiles_b - ta;
+      ++ta;
+    }
+    tb += ta;
+  }
+  const int a0 = ta * kGT, b0 = tb * kGT;
   const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
   const int64_t rows_per = (n + nchunk - 1) / nchunk;
   const int64_t r_begin = (int64_t)chunk * rows_per;
@@ -79,10 +91,12 @@ __global__ __launch_bounds__(256) void gemm_cn_kernel(const double2 *__restrict_
 
 // C[:, b] = sum_a A[:, a] T[a][b], T row-major (na x nb) in device memory. Block:
 // 64 rows x 64 columns of C; thread t owns rows (t & 15) + 16 r and columns
-// (t >> 4) + 16 c.
+// (t >> 4) + 16 c. upper = 1: T is upper triangular (T[a][b] = 0 for a > b), and the
+// sum for a column tile stops at its last column (the skipped terms are zero).
 __global__ __launch_bounds__(256) void gemm_nn_kernel(const double2 *__restrict__ A, int64_t lda, int na,
                                                       const double2 *__restrict__ T, int nb,
-                                                      double2 *__restrict__ C, int64_t ldc, int64_t n) {
+                                                      double2 *__restrict__ C, int64_t ldc, int64_t n,
+                                                      int upper) {
   __shared__ double2 As[kGK][kGT + 1];  // [a][row]
   __shared__ double2 Ts[kGK][kGT + 1];  // [a][column]
   const int64_t i0 = (int64_t)blockIdx.x * kGT;
@@ -106,15 +120,16 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const double2 *__restrict_
       pt[q] = (a < na && b0 + lx < nb) ? T[(size_t)a * nb + b0 + lx] : make_double2(0, 0);
     }
   };
+  const int kend = upper ? min(na, b0 + kGT) : na;
   fetch(0);
-  for (int ka = 0; ka < na; ka += kGK) {
+  for (int ka = 0; ka < kend; ka += kGK) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       As[lk + 4 * q][lx] = pa[q];
       Ts[lk + 4 * q][lx] = pt[q];
     }
     __syncthreads();
-    if (ka + kGK < na) fetch(ka + kGK);
+    if (ka + kGK < kend) fetch(ka + kGK);
 #pragma unroll 4
     for (int k = 0; k < kGK; ++k) {
       double2 av[4], tv[4];
@@ -197,19 +212,22 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *part
 }
 
 void launch_gemm_cn(const void *A, int64_t lda, int na, const void *B, int64_t ldb, int nb, int64_t n,
-                    double *partial, int nchunk, hipStream_t st) {
-  const int tiles = gemm_cn_tiles(na, nb);
+                    double *partial, int nchunk, int herm, hipStream_t st) {
+  const int tiles = gemm_cn_tiles(na, nb, herm);
   hipLaunchKernelGGL(gemm_cn_kernel, dim3(tiles, nchunk), dim3(256), 0, st, (const double2 *)A, lda, na,
-                     (const double2 *)B, ldb, nb, n, (double2 *)partial, nchunk);
+                     (const double2 *)B, ldb, nb, n, (double2 *)partial, nchunk, herm);
 }
 void launch_gemm_nn(const void *A, int64_t lda, int na, const double *T, int nb, void *C, int64_t ldc,
-                    int64_t n, hipStream_t st) {
+                    int64_t n, int upper, hipStream_t st) {
   if (n <= 0 || na <= 0 || nb <= 0) return;
   const dim3 grid((unsigned)((n + kGT - 1) / kGT), (nb + kGT - 1) / kGT);
   hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(256), 0, st, (const double2 *)A, lda, na, (const double2 *)T, nb,
-                     (double2 *)C, ldc, n);
+                     (double2 *)C, ldc, n, upper);
 }
-int gemm_cn_tiles(int na, int nb) { return ((na + kGT - 1) / kGT) * ((nb + kGT - 1) / kGT); }
+int gemm_cn_tiles(int na, int nb, int herm) {
+  const int ta = (na + kGT - 1) / kGT, tb = (nb + kGT - 1) / kGT;
+  return herm ? ta * (ta + 1) / 2 : ta * tb;
+}
 void launch_colscale(void *A, int64_t lda, int na, const double *scale, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(colscale_kernel, dim3((unsigned)((n + 255) / 256), na), dim3(256), 0, st, (double2 *)A,
                      lda, scale, n);

@@ -380,13 +380,15 @@ void launch_moments(const void *y, int nsrc, int nshift, const double *c_dev, in
                     void *s, int64_t n, hipStream_t st);
 void launch_vdot_block(const void *V, int nv, const void *Y, int ny, int64_t n, double *partial,
                        int nblk, hipStream_t st);
-// dense.hip: tall-skinny products (FP64 complex)
+// dense.hip: tall-skinny products (FP64 complex). gemm_cn with herm = 1 (Hermitian
+// product, na = nb) computes the 64 x 64 output tiles on and above the diagonal only
+// (the entries below are not written); gemm_nn with upper = 1 takes T upper triangular.
 void launch_gemm_cn(const void *A, int64_t lda, int na, const void *B, int64_t ldb, int nb,
-                    int64_t n, double *partial, int nchunk, hipStream_t st);
+                    int64_t n, double *partial, int nchunk, int herm, hipStream_t st);
 void launch_gemm_nn(const void *A, int64_t lda, int na, const double *T_dev, int nb,
-                    void *C, int64_t ldc, int64_t n, hipStream_t st);
+                    void *C, int64_t ldc, int64_t n, int upper, hipStream_t st);
 // output tiles (blocks per chunk) of launch_gemm_cn
-int gemm_cn_tiles(int na, int nb);
+int gemm_cn_tiles(int na, int nb, int herm);
 void launch_colscale(void *A, int64_t lda, int na, const double *scale_dev, int64_t n, hipStream_t st);
 void launch_resid_cols(const void *AX, const void *X, int64_t ld, int ncol, const double *lam_dev,
                        int64_t n, double *partial, int nchunk, hipStream_t st);
