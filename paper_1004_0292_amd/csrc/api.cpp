@@ -1517,7 +1517,8 @@ static int gram(sscg_ctx *c, const void *A, int na, const void *B, int nb, std::
   // row chunks: enough blocks to spread over the chip, at least 64 rows each (more
   // chunks also mean more partials to sum afterwards)
   const int tiles = gemm_cn_tiles(na, nb, herm ? 1 : 0);
-  int nchunk = std::max(1, std::min(256, 512 / tiles));
+  // three 256-thread blocks fit per CU: about three per CU in all
+  int nchunk = std::max(1, std::min(256, 768 / tiles));
   nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(nchunk, c->n / 64));
   const size_t nout = (size_t)na * nb;
   CHK(ensure(c, c->small, nchunk * nout * 2 * sizeof(double) + nout * 2 * sizeof(double)));
@@ -1623,8 +1624,12 @@ static int col_residuals(sscg_ctx *c, const void *AX, const void *X, int ncol, c
 // unit-norm columns (the second restores the orthogonality the first loses),
 // keeping directions whose singular value exceeds rank_tol times the largest; then
 // A~ = Q^H (A Q), its eigenpairs, X = Q W and A X = (A Q) W in Xd / AXd.
+// Only the Ritz values that the caller's filter `want` keeps get their vectors: X
+// and A X hold them in order, and `sel` lists their indices into lam (the acceptance
+// rectangle discards the others, so their vectors are never needed).
+template <typename Want>
 static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, void *Xd, void *AXd,
-                      std::vector<double> &lam, int &r, hipStream_t st) {
+                      std::vector<double> &lam, int &r, std::vector<int> &sel, Want &&want, hipStream_t st) {
   const size_t vec = c->n * sizeof(double2);
   std::vector<cd> G;
   CHK(gram(c, S, ncol, S, ncol, G, st, true));
@@ -1670,7 +1675,15 @@ static int extract_rr(sscg_ctx *c, const void *S, int ncol, double rank_tol, voi
   CHK(gram(c, c->Qbuf.p, r, c->AQbuf.p, r, At, st, true));  // Hermitian since A is
   std::vector<cd> Wr;
   EIGCHK(c, eig_rowmajor(r, At, lam, Wr));
-  CHK(basis_change(c, c->Qbuf.p, r, Wr, r, Xd, st, c->AQbuf.p, AXd));
+  sel.clear();
+  for (int k = 0; k < r; ++k)
+    if (want(lam[k])) sel.push_back(k);
+  const int m = (int)sel.size();
+  if (m == 0) return SSCG_OK;
+  std::vector<cd> Wsel((size_t)r * m);
+  for (int a = 0; a < r; ++a)
+    for (int i = 0; i < m; ++i) Wsel[(size_t)a * m + i] = Wr[(size_t)a * r + sel[i]];
+  CHK(basis_change(c, c->Qbuf.p, r, Wsel, m, Xd, st, c->AQbuf.p, AXd));
   (void)vec;
   return SSCG_OK;
 }
@@ -1919,35 +1932,6 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
       HIPCHK(c, hipStreamSynchronize(st));
       t_mom += std::chrono::duration<double>(std::chrono::steady_clock::now() - tm0).count();
     }
-    std::vector<double> lam;
-    int r = 0;
-    if (p->method == SSCG_RR) {
-      CHK(extract_rr(c, Sq, ncol, p->rank_tol, Xd, AXd, lam, r, st));
-    } else {
-      std::vector<cd> mu;
-      if (in_loop) {
-        // mu_k = V^H s_k from the 2M moment vectors summed in the loop
-        std::vector<cd> Gs;
-        CHK(gram(c, c->v64.p, L, Sq, K * L, Gs, st));  // [a][k L + l]
-        mu.assign((size_t)K * L * L, cd(0, 0));
-        for (int k = 0; k < K; ++k)
-          for (int a = 0; a < L; ++a)
-            for (int l = 0; l < L; ++l) mu[((size_t)k * L + a) * L + l] = Gs[(size_t)a * K * L + (size_t)k * L + l];
-      } else {
-        mu = block_moments_from_solutions(Gv, L, Nall, offsets[q], N, M, zeta, w);
-      }
-      CHK(extract_hankel(c, mu, L, M, centres[q], p->rho, p->rank_tol, Sq, Xd, AXd, lam, r, st));
-    }
-    rank_max = std::max(rank_max, r);
-    ncand += r;
-    // device memory of this pair's extraction: the moment vectors S (n x M L); for
-    // Rayleigh-Ritz the basis Q and A Q (r vectors each); for both, the vectors X and
-    // A X of the r candidates (the buffers are reused from pair to pair)
-    ext_bytes = std::max(ext_bytes, (int64_t)((size_t)ncol + (p->method == SSCG_RR ? 2 * (size_t)r : 0) +
-                                              2 * (size_t)r) * (int64_t)vec);
-    if (r == 0) continue;
-    std::vector<double> rs, xn;
-    CHK(col_residuals(c, AXd, Xd, r, lam, rs, xn, st));
     // acceptance (Sec. 3): the rectangle of the N' nodes nearest this pair's centre;
     // half-open on the right except for the last pair, so a shared edge counts once
     double lo, hi;
@@ -1968,27 +1952,63 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
       lo = centres[q] - p->rho;
       hi = centres[q] + p->rho;
     }
-    for (int k = 0; k < r; ++k) {
-      const bool inside = lam[k] >= lo && (q < P - 1 ? lam[k] < hi : lam[k] <= hi);
-      if (!inside || !(rs[k] <= p->spur_tol)) continue;
+    auto inside = [&](double x) { return x >= lo && (q < P - 1 ? x < hi : x <= hi); };
+    std::vector<double> lam;
+    std::vector<int> sel;  // candidates whose vectors are in Xd / AXd, in order
+    int r = 0;
+    if (p->method == SSCG_RR) {
+      CHK(extract_rr(c, Sq, ncol, p->rank_tol, Xd, AXd, lam, r, sel, inside, st));
+    } else {
+      std::vector<cd> mu;
+      if (in_loop) {
+        // mu_k = V^H s_k from the 2M moment vectors summed in the loop
+        std::vector<cd> Gs;
+        CHK(gram(c, c->v64.p, L, Sq, K * L, Gs, st));  // [a][k L + l]
+        mu.assign((size_t)K * L * L, cd(0, 0));
+        for (int k = 0; k < K; ++k)
+          for (int a = 0; a < L; ++a)
+            for (int l = 0; l < L; ++l) mu[((size_t)k * L + a) * L + l] = Gs[(size_t)a * K * L + (size_t)k * L + l];
+      } else {
+        mu = block_moments_from_solutions(Gv, L, Nall, offsets[q], N, M, zeta, w);
+      }
+      CHK(extract_hankel(c, mu, L, M, centres[q], p->rho, p->rank_tol, Sq, Xd, AXd, lam, r, st));
+      sel.resize(r);
+      for (int k = 0; k < r; ++k) sel[k] = k;
+    }
+    rank_max = std::max(rank_max, r);
+    ncand += r;
+    // device memory of this pair's extraction: the moment vectors S (n x M L); for
+    // Rayleigh-Ritz the basis Q and A Q (r vectors each); the vectors X and A X of the
+    // candidates (the r Hankel ones, the Ritz ones inside the rectangle; the buffers
+    // are reused from pair to pair)
+    const int nsel = (int)sel.size();
+    ext_bytes = std::max(ext_bytes, (int64_t)((size_t)ncol + (p->method == SSCG_RR ? 2 * (size_t)r : 0) +
+                                              2 * (size_t)nsel) * (int64_t)vec);
+    if (nsel == 0) continue;
+    std::vector<double> lsel(nsel), rs, xn;
+    for (int i = 0; i < nsel; ++i) lsel[i] = lam[sel[i]];
+    CHK(col_residuals(c, AXd, Xd, nsel, lsel, rs, xn, st));
+    for (int i = 0; i < nsel; ++i) {
+      const int k = sel[i];
+      if (!inside(lam[k]) || !(rs[i] <= p->spur_tol)) continue;
       ++total_found;
       if (max_eigs == 0) continue;
       const double dist = std::fabs(lam[k] - p->gamma);
       int slot = -1;
       if ((int)acc.size() < max_eigs) {
         slot = (int)acc.size();
-        acc.push_back({lam[k], rs[k], dist, slot});
+        acc.push_back({lam[k], rs[i], dist, slot});
       } else {
         auto worst = std::max_element(acc.begin(), acc.end(), [](const Acc &a, const Acc &b) { return a.dist < b.dist; });
         if (worst->dist <= dist) continue;
         slot = worst->slot;
-        *worst = {lam[k], rs[k], dist, slot};
+        *worst = {lam[k], rs[i], dist, slot};
       }
       if (X) {
         // unit-normalised copy of the candidate's vector into its slot
-        std::vector<double> one(1, xn[k] > 0 ? 1.0 / xn[k] : 1.0);
+        std::vector<double> one(1, xn[i] > 0 ? 1.0 / xn[i] : 1.0);
         char *dst = (char *)c->Accbuf.p + (size_t)slot * vec;
-        HIPCHK(c, hipMemcpyAsync(dst, (const char *)Xd + (size_t)k * vec, vec, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(dst, (const char *)Xd + (size_t)i * vec, vec, hipMemcpyDeviceToDevice, st));
         CHK(ensure(c, c->small, sizeof(double)));
         HIPCHK(c, hipMemcpyAsync(c->small.p, one.data(), sizeof(double), hipMemcpyHostToDevice, st));
         launch_colscale(dst, (int64_t)n, 1, (const double *)c->small.p, (int64_t)n, st);

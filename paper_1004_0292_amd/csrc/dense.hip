@@ -16,7 +16,9 @@ constexpr int kGK = 16;  // summed-index step staged in LDS
 // partial[chunk][a][b] = sum over the chunk's rows of conj(A[row][a]) B[row][b].
 // herm = 1 (a Hermitian product, na = nb): only the tiles on and above the diagonal
 // (the caller mirrors the rest); the blocks enumerate them row by row.
-__global__ __launch_bounds__(256) void gemm_cn_kernel(const double2 *__restrict__ A, int64_t lda, int na,
+// Held to 168 registers (three wavefronts per SIMD; the two registers it gives up are
+// spilled outside the summation loop).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void gemm_cn_kernel(const double2 *__restrict__ A, int64_t lda, int na,
                                                       const double2 *__restrict__ B, int64_t ldb, int nb,
                                                       int64_t n, double2 *partial, int nchunk, int herm) {
   __shared__ double2 As[kGK][kGT + 1];
