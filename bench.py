@@ -202,7 +202,10 @@ def tts_compare(S, ctx, params, vd, max_eigs, steps, base_ms, base_res, with_mix
 # [lo, hi], the line offset beta, N nodes, M moments and L sources.
 WINDOWS = {"wilson8_fp64": dict(lo=0.3700, hi=0.3735, beta=0.5, N=32, M=8, L=4),
            "wilson16x32_mixed": dict(lo=0.3650, hi=0.3661, beta=0.5, N=32, M=8, L=4),
-           "wilson24x48": None}
+           # one eigenvalue (0.3454946), certified by the oracle's matrix in the tests;
+           # SSCG_MIXED is left out at this size (its FP32 seed does not converge here)
+           "wilson24x48": dict(lo=0.3450, hi=0.3457, beta=0.5, N=32, M=8, L=2,
+                               modes=("fp64", "mixed_shifts", "fp64_hankel"))}
 
 
 def reference_spectrum(name):
@@ -237,7 +240,7 @@ def tts_window(S, ctx, w, vd_all, steps):
     ctx.set_profiling(0)
     lams = {}
     ext = {}
-    for name in ("fp64", "mixed_shifts", "mixed", "fp64_hankel"):
+    for name in win.get("modes", ("fp64", "mixed_shifts", "mixed", "fp64_hankel")):
         opts = S.default_opts(tol=w.tol, prec=PRECS[name.replace("_hankel", "")], ru_interval=w.ru_interval,
                               switch_tol=w.switch_tol)
         p = S.default_ss_params(gamma=gamma, rho=rho, beta=win["beta"], N=win["N"], M=win["M"], rank_tol=1e-7,
@@ -257,6 +260,8 @@ def tts_window(S, ctx, w, vd_all, steps):
         out[name] = s
     a = lams["fp64"]
     for name in ("mixed_shifts", "mixed"):
+        if name not in lams:
+            continue
         b = lams[name]
         out[name]["max_rel_eig_diff_vs_fp64"] = (float(np.max(np.abs(a - b) / np.abs(a)))
                                                  if len(a) == len(b) and len(a) else None)

@@ -291,6 +291,52 @@ def test_wilson24x48_dslash_sampled_rows(sscg, w24, prec, link_reals, bound):
     c.close()
 
 
+def test_wilson24x48_window_eigenpair(sscg, w24):
+    """A window of the 24^3 x 48 field that holds an eigenvalue, [0.3450, 0.3457],
+    around the field's smallest |lambda| (located before the test was written; two
+    sources, N = 32, M = 8, beta = 0.5, moments summed inside the solve). The pair is
+    certified by the oracle's explicit matrix: ||A x - lambda x|| / ||x|| below 1e-8
+    and at most 1.5 times the reported residual, so an eigenvalue of A lies within
+    that distance of lambda. FP64 and FP32 shift vectors agree to 1e-10; the mirrored
+    window [-0.3457, -0.3450] returns nothing. Completeness of the window is unpinned:
+    no oracle spectrum of this lattice exists."""
+    import torch
+    w, U = w24
+    case("24^3x48 eigen window [0.3450, 0.3457]")
+    lo, hi = 0.3450, 0.3457
+    gamma, rho = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    c = sscg.Context(w.dims, w.kappa)
+    c.set_gauge(U, 18)
+    V = to_dev(w.sources().reshape(w.L, -1)[:2])
+    found = {}
+    for mode in ("fp64", "mixed_shifts"):
+        prec = sscg.FP64 if mode == "fp64" else sscg.MIXED_SHIFTS
+        p = sscg.default_ss_params(gamma=gamma, rho=rho, beta=0.5, N=32, M=8, moments_in_loop=1,
+                                   solve=sscg.default_opts(prec=prec, ru_interval=w.ru_interval,
+                                                           switch_tol=w.switch_tol))
+        out = c.ss_eigs(p, V, max_eigs=8)
+        assert out.status == sscg.OK
+        assert out.n_found == 1
+        assert out.res.max() < 1e-8
+        found[mode] = (float(out.lam[0]), float(out.res[0]), to_host(out.X)[0].reshape(-1))
+        print(f"[case] {mode}: lambda {out.lam[0]:.12f} res {out.res[0]:.2e} seed iterations {out.info.iters}",
+              flush=True)
+    l64, l32 = found["fp64"][0], found["mixed_shifts"][0]
+    assert abs(l64 - l32) <= 1e-10 * abs(l64)
+    p = sscg.default_ss_params(gamma=-gamma, rho=rho, beta=0.5, N=32, M=8, moments_in_loop=1)
+    assert c.ss_eigs(p, V, max_eigs=8).n_found == 0
+    del V
+    torch.cuda.empty_cache()
+    c.close()
+    A = wilson.hermitian_wilson(U, w.dims, w.kappa)  # the explicit matrix (about a minute)
+    for mode, (lam, res, x) in found.items():
+        x = x / np.linalg.norm(x)
+        r = np.linalg.norm(A @ x - lam * x)
+        assert r < 1e-8
+        assert r <= 1.5 * res + 1e-13
+        print(f"[case] {mode}: oracle residual {r:.2e}", flush=True)
+
+
 def sampled_rows_residual(U, dims, kappa, v, z, y_dev, sites):
     """max over (node, sampled site) of |(v - (z_j I - A) y_j)_i| / ||v|| with the
     oracle's row-wise operator: only the entries of y_j at the sampled sites and their
