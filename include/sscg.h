@@ -206,9 +206,11 @@ typedef struct {
                                once into a small device table). Rayleigh-
                                Ritz sums M moments per pair, Hankel 2M (its block
                                moments V^H s_k run to k = 2M - 1); needs npairs
-                               times that <= 32 and a solve precision of SSCG_FP64
-                               or SSCG_MIXED_SHIFTS, else SSCG_EINVAL. 0: solutions
-                               stored, moments after the solve.                     */
+                               times that <= 32, a solve precision of SSCG_FP64
+                               or SSCG_MIXED_SHIFTS and 12 V < 2^27 (vectors under
+                               2 GiB), else SSCG_EINVAL. The shift directions are
+                               stored in 64-entry chunks per (source, shift). 0:
+                               solutions stored, moments after the solve.           */
   int32_t weighted_tol;     /* 1: shift j stops at tol * m / m_j, where m_j is the
                                largest |w_j zeta_j^k| over the moments (and pairs)
                                it enters and m the largest m_j: every shift's

@@ -1820,6 +1820,9 @@ extern "C" int sscg_ss_eigs(sscg_ctx *c, const sscg_ss_params *p, const void *v,
   const int K = (in_loop && p->method == SSCG_HANKEL) ? 2 * M : M;
   if (in_loop && (P * K > 32 || p->solve.prec == SSCG_MIXED))
     return fail(c, SSCG_EINVAL, "in-loop moments need npairs * M (2M for Hankel) <= 32 and an FP64 seed");
+  // the in-loop update addresses a moment vector with 32-bit byte offsets
+  if (in_loop && (int64_t)c->n * 16 >= ((int64_t)1 << 31))
+    return fail(c, SSCG_EINVAL, "in-loop moments need 12 V < 134217728 (vectors under 2 GiB)");
   const int ncol = M * L;
   // moment coefficients c[k][j] = w_j zeta_j^k of one pair (eq. 2), k < K
   std::vector<double> cf(2 * (size_t)K * N);
