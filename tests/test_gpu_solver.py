@@ -270,6 +270,30 @@ def test_zero_and_nan_sources_rejected(sscg, prob):
         assert e.value.code == sscg.EINVAL
 
 
+def test_empty_inputs_rejected(sscg, prob):
+    """Empty inputs are argument errors at every entry point (no source, no shift, no
+    moment), and an ss_eigs call that asks for no eigenpairs only counts them."""
+    import torch
+    case("empty inputs")
+    U, A, V, z = prob
+    c = sscg.Context(CFG1.dims, CFG1.kappa)
+    c.set_gauge(U)
+    empty = torch.zeros(0, dtype=torch.complex128, device="cuda:0")
+    for call in (lambda: c.apply_A(empty, empty),
+                 lambda: c.shifted_cg_solve(empty, z, 0.0, empty),
+                 lambda: c.shifted_cg_solve(to_dev(V[:1]), np.zeros(0, complex), 0.0, empty),
+                 lambda: c.ss_moments(to_dev(np.zeros((1, len(z), CFG1.n))), len(z), np.zeros((0, len(z))),
+                                      to_dev(np.zeros((1, CFG1.n))))):
+        with pytest.raises(sscg.SSCGError) as e:
+            call()
+        assert e.value.code == sscg.EINVAL
+    p = sscg.default_ss_params(gamma=0.225, rho=0.03, beta=0.25, N=16, M=8, rank_tol=1e-7)
+    full = c.ss_eigs(p, to_dev(V[:2]), max_eigs=16)
+    count = c.ss_eigs(p, to_dev(V[:2]), max_eigs=0)
+    assert full.n_found > 0 and count.n_found == full.n_found
+    c.close()
+
+
 def test_no_gauge_is_a_state_error(sscg, prob):
     case("no gauge")
     U, A, V, z = prob
