@@ -202,8 +202,8 @@ def tts_compare(S, ctx, params, vd, max_eigs, steps, base_ms, base_res, with_mix
 # [lo, hi], the line offset beta, N nodes, M moments and L sources.
 WINDOWS = {"wilson8_fp64": dict(lo=0.3700, hi=0.3735, beta=0.5, N=32, M=8, L=4),
            "wilson16x32_mixed": dict(lo=0.3650, hi=0.3661, beta=0.5, N=32, M=8, L=4),
-           # one eigenvalue (0.3454946), certified by the oracle's matrix in the tests;
-           # SSCG_MIXED is left out at this size (its FP32 seed does not converge here)
+           # one eigenvalue (0.3454946 in the oracle's reference spectrum); SSCG_MIXED
+           # is left out at this size (its FP32 seed does not converge here)
            "wilson24x48": dict(lo=0.3450, hi=0.3457, beta=0.5, N=32, M=8, L=2,
                                modes=("fp64", "mixed_shifts", "fp64_hankel"))}
 

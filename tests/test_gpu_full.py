@@ -293,17 +293,22 @@ def test_wilson24x48_dslash_sampled_rows(sscg, w24, prec, link_reals, bound):
 
 def test_wilson24x48_window_eigenpair(sscg, w24):
     """A window of the 24^3 x 48 field that holds an eigenvalue, [0.3450, 0.3457],
-    around the field's smallest |lambda| (located before the test was written; two
-    sources, N = 32, M = 8, beta = 0.5, moments summed inside the solve). The pair is
-    certified by the oracle's explicit matrix: ||A x - lambda x|| / ||x|| below 1e-8
-    and at most 1.5 times the reported residual, so an eigenvalue of A lies within
-    that distance of lambda. FP64 and FP32 shift vectors agree to 1e-10; the mirrored
-    window [-0.3457, -0.3450] returns nothing. Completeness of the window is unpinned:
-    no oracle spectrum of this lattice exists."""
+    around the field's smallest |lambda| (two sources, N = 32, M = 8, beta = 0.5,
+    moments summed inside the solve). The reference spectrum
+    (tests/golden/spectrum_wilson24x48.json, the six smallest |lambda| from the
+    oracle's Lanczos on A^2) holds every |lambda| below its fifth value, 0.34621, so
+    it is complete inside this window and its mirror: one eigenvalue, 0.3454945964,
+    and none in [-0.3457, -0.3450]. The pair matches it to 1e-10 in FP64 and with FP32
+    shift vectors, and is certified by the oracle's explicit matrix: ||A x - lambda x||
+    / ||x|| below 1e-8 and at most 1.5 times the reported residual."""
     import torch
     w, U = w24
     case("24^3x48 eigen window [0.3450, 0.3457]")
     lo, hi = 0.3450, 0.3457
+    ref = np.array(json.loads((GOLD.parent / "spectrum_wilson24x48.json").read_text())["lam"])
+    assert np.sort(np.abs(ref))[4] > hi
+    truth = ref[(ref >= lo) & (ref <= hi)]
+    assert len(truth) == 1 and not np.any((ref >= -hi) & (ref <= -lo))
     gamma, rho = 0.5 * (lo + hi), 0.5 * (hi - lo)
     c = sscg.Context(w.dims, w.kappa)
     c.set_gauge(U, 18)
@@ -323,6 +328,7 @@ def test_wilson24x48_window_eigenpair(sscg, w24):
               flush=True)
     l64, l32 = found["fp64"][0], found["mixed_shifts"][0]
     assert abs(l64 - l32) <= 1e-10 * abs(l64)
+    assert abs(l64 - truth[0]) <= 1e-10 * abs(truth[0])
     p = sscg.default_ss_params(gamma=-gamma, rho=rho, beta=0.5, N=32, M=8, moments_in_loop=1)
     assert c.ss_eigs(p, V, max_eigs=8).n_found == 0
     del V
