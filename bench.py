@@ -9,8 +9,9 @@ shift-updates per second: the number of (source, shift) vector updates the
 shifted CG performs, summed over the timed steps, divided by their wall time.
 
 The default workload is the largest single-GPU one, a 24^3 x 48 lattice with 64
-nodes and 8 sources, timed in FP64 (the paper's arithmetic). Printed as one JSON
-line; besides the throughput it carries:
+nodes, 8 sources and 24 moments, timed in FP64 (the paper's arithmetic) with the
+moments summed inside the solve (each shift's step added to the moments as it is
+made). Printed as one JSON line; besides the throughput it carries:
   roofline      the dominant kernel (by time per step): algorithmic bytes per launch
                 over its average launch duration from HIP events recorded inside the
                 solve's graphs, against 8 TB/s; traffic from the committed rocprofv3
@@ -19,8 +20,10 @@ line; besides the throughput it carries:
   stage_ms_per_step  every stage of the solve, from the sampled launch times scaled
                 by the launches of that stage (the split of the paper's Table 2:
                 matrix-vector products against everything else)
-  tts           time to solution of the step in FP64 and the two mixed-precision
-                modes on the same interval, with each mode's largest FP64 true residual
+  tts           time to solution of the same step in its other forms: FP64 with the
+                solutions stored, FP32 shift directions with the moments inside or the
+                solutions stored (and SSCG_MIXED with --with-mixed-seed), with each
+                mode's largest FP64 true residual where solutions are stored
   tts_window    the same on an interval that holds eigenvalues, with the eigenvalues
                 of each mode, their agreement with FP64 and with the reference spectrum
   extraction    Rayleigh-Ritz against block Hankel on that window: extraction time,
