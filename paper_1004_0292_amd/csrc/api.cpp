@@ -46,7 +46,7 @@ struct Tune {
   int border = 0;   // shift-update block order (1: the shift batches of an entry chunk adjacent)
 };
 
-enum Stage { ST_DSLASH = 0, ST_ALPHA, ST_RUPD, ST_SCAL, ST_SHIFT, ST_RU, ST_LOOP, ST_N = 8 };
+enum Stage { ST_DSLASH = 0, ST_ALPHA, ST_RUPD, ST_SCAL, ST_SHIFT, ST_RU, ST_LOOP, ST_PASS, ST_N = 8 };
 
 struct sscg_ctx {
   int device = 0;
@@ -70,7 +70,7 @@ struct sscg_ctx {
   std::map<std::string, Tune> tuned;
   // solver workspaces
   DevBuf v64, r64, p64, q64, W, r32, p32, q32, rbase, xpart64, xpart32, tmp, pq_part, rr_part, seed,
-      shift, zdev, small, cmom, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out, trpart, momtab;
+      shift, zdev, small, cmom, Ybuf, Sbuf, Qbuf, AQbuf, Xbuf, AXbuf, Accbuf, apply_in, apply_out, trpart, momtab, ring;
   SeedState *seed_host = nullptr;
   int seed_host_cap = 0;
   // profiling
@@ -206,7 +206,7 @@ void sscg_destroy(sscg_ctx *c) {
   DevBuf *bufs[] = {&c->g64, &c->g32, &c->v64, &c->r64, &c->p64, &c->q64, &c->W, &c->r32, &c->p32,
                     &c->q32, &c->rbase, &c->xpart64, &c->xpart32, &c->tmp, &c->pq_part, &c->rr_part,
                     &c->seed, &c->shift, &c->zdev, &c->small, &c->cmom, &c->Ybuf, &c->Sbuf, &c->Qbuf, &c->AQbuf,
-                    &c->Xbuf, &c->AXbuf, &c->Accbuf, &c->apply_in, &c->apply_out, &c->trpart, &c->momtab};
+                    &c->Xbuf, &c->AXbuf, &c->Accbuf, &c->apply_in, &c->apply_out, &c->trpart, &c->momtab, &c->ring};
   for (DevBuf *b : bufs) release(*b);
   if (c->seed_host) hipHostFree(c->seed_host);
   for (hipEvent_t e : c->events) hipEventDestroy(e);
@@ -520,6 +520,7 @@ struct Prob {
   void *mom = nullptr;
   const void *mom_coef = nullptr;
   int nmom = 0;
+  int blk = 0;  // block length of the in-loop update's block form (0: per iteration)
   std::vector<double> tscale;  // per-shift tolerance multipliers (empty: all 1)
 };
 
@@ -529,6 +530,8 @@ struct IterPlan {
   VecBatch r64, r32, u64, u32, u32s, fold_seed, rel;
   VecBatch m64, m32;  // shift update with in-loop moments (FP64 / FP32 shift vectors)
   VecBatch mt;        // its table kernel (per (source, shift) scalars of the iteration)
+  VecBatch sp, bc;    // block form: seed direction update, composition of a block
+  int blk;            // block form: block length (0: the per-iteration form)
   int nmom_max;       // 0: the solutions are stored
   int mom_ub;         // shifts per load batch of the in-loop moment update
   int mom_pf;         // in-loop moment update: next batch's loads issued before this batch's stores
@@ -539,12 +542,13 @@ constexpr int kFuseAlphaMax = 1024;  // <p, Bp> partials per source up to which 
 
 static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts &o, const Tune &t) {
   memset(&pl, 0, sizeof(pl));
-  int bd = 0, bdru = 0, bs = 0, bv = 0, bu = 0, bm = 0, bmt = 0;
+  int bd = 0, bdru = 0, bs = 0, bv = 0, bu = 0, bm = 0, bmt = 0, bbc = 0;
   // one shift per group, the next shift's loads ahead of this shift's stores: the
   // fastest form at 24^3 x 48 in FP64 and with FP32 directions
   pl.mom_ub = env_int("SSCG_MOMUB", 1);
   pl.mom_pf = env_int("SSCG_MOMPF", 1);
   const int np = (int)P.size();
+  pl.blk = P[0].blk;  // one form per batch (run_solve sets it for every problem)
   // the tile kernel needs a tile of t.tbs sites on every lattice of the batch, with
   // LDS for FP64 spinors (the FP64 phase and the reliable updates use it too)
   pl.ct = t.ct;
@@ -606,7 +610,12 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
       mk_v(j, a, b, cc, d, bv, L * nbr);
       j.nblk_vec = nbr;
     };
-    seed_pass(pl.r64.job[i], c->r64.p, c->q64.p, nullptr, nullptr);
+    seed_pass(pl.r64.job[i], pl.blk > 0 ? c->ring.p : c->r64.p, c->q64.p, nullptr, nullptr);
+    if (pl.blk > 0) {
+      pl.r64.job[i].ring = pl.blk;
+      seed_pass(pl.sp.job[i], c->ring.p, nullptr, nullptr, c->p64.p);
+      pl.sp.job[i].ring = pl.blk;
+    }
     seed_pass(pl.r32.job[i], c->r32.p, c->q32.p, c->xpart32.p, c->p32.p);
     if (pl.fuse_alpha)
       for (VecJob *rj : {&pl.r64.job[i], &pl.r32.job[i]}) {
@@ -625,8 +634,9 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
       const int nbm = (int)((c->n + kMomBlock - 1) / kMomBlock);
       for (VecBatch *mb : {&pl.m64, &pl.m32}) {
         VecJob &j = mb->job[i];
-        mk_v(j, P[i].mom, c->W.p, c->r64.p, c->p64.p, bm, L * nbm);
+        mk_v(j, P[i].mom, c->W.p, pl.blk > 0 ? c->ring.p : c->r64.p, c->p64.p, bm, L * nbm);
         j.e = c->momtab.p;
+        j.ring = pl.blk;
         j.mcoef = (const double2 *)P[i].mom_coef;
         j.nmom = P[i].nmom;
         j.nblk_mom = nbm;
@@ -638,13 +648,25 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
       jt.e = c->momtab.p;
       jt.mcoef = (const double2 *)P[i].mom_coef;
       jt.nmom = P[i].nmom;
+      jt.ring = pl.blk;
       bmt += L * nch;
+      if (pl.blk > 0) {  // composition: one block per source
+        VecJob &jc = pl.bc.job[i];
+        mk_v(jc, P[i].mom, c->W.p, c->ring.p, c->p64.p, bbc, L);
+        jc.e = c->momtab.p;
+        jc.mcoef = (const double2 *)P[i].mom_coef;
+        jc.nmom = P[i].nmom;
+        jc.ring = pl.blk;
+        bbc += L;
+      }
       pl.nmom_max = std::max(pl.nmom_max, P[i].nmom);
     }
   }
   pl.m64.njobs = pl.m32.njobs = pl.mt.njobs = np;
   pl.m64.total_blocks = pl.m32.total_blocks = bm;
   pl.mt.total_blocks = bmt;
+  pl.bc.njobs = pl.blk > 0 ? np : 0;
+  pl.bc.total_blocks = bbc;
   pl.d64.njobs = pl.d32.njobs = pl.dru.njobs = np;
   pl.d64.commit = pl.d32.commit = 1;  // the iteration's first launch commits the previous one
   pl.d64.total_blocks = pl.d32.total_blocks = bd;
@@ -655,6 +677,8 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
     vb->njobs = np;
     vb->total_blocks = bv;
   }
+  pl.sp.njobs = pl.blk > 0 ? np : 0;
+  pl.sp.total_blocks = pl.blk > 0 ? bv : 0;
   pl.u64.njobs = pl.u32.njobs = pl.u32s.njobs = np;
   pl.u64.total_blocks = pl.u32.total_blocks = pl.u32s.total_blocks = bu;
 }
@@ -741,7 +765,7 @@ struct Recorder {
 // shift update with the shift scalars. rec marks every stage; ru_rec (when given)
 // brackets the reliable update alone.
 static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, bool ru, int lr, const Tune &t,
-                                  hipStream_t st, Recorder &rec, Recorder *ru_rec) {
+                                  hipStream_t st, Recorder &rec, Recorder *ru_rec, int slot) {
   const int sp = (prec == 1 && seed32) ? 1 : 0;  // seed precision
   if (!pl.fuse_alpha) {
     rec.mark(ST_ALPHA);
@@ -749,7 +773,7 @@ static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, boo
   }
   rec.mark(ST_RUPD);
   const bool ru_now = sp == 1 && ru;
-  launch_seed_r_update(sp == 0 ? pl.r64 : pl.r32, sp, st);
+  launch_seed_r_update(sp == 0 ? pl.r64 : pl.r32, sp, st, slot);
   if (ru_now) {
     rec.mark(ST_RU);
     if (ru_rec) ru_rec->mark(ST_RU);
@@ -759,7 +783,15 @@ static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, boo
     if (ru_rec) ru_rec->mark(-1);
   }
   rec.mark(ST_SHIFT);
-  if (pl.nmom_max > 0) {  // FP64 seed in both phases (checked by run_solve)
+  if (pl.nmom_max > 0 && pl.blk > 0) {  // block form: the sweep after a block's last iteration
+    launch_shift_table(pl.mt, st, slot);
+    launch_seed_p_update(pl.sp, slot, st);
+    if (slot == pl.blk - 1) {
+      rec.mark(ST_PASS);
+      launch_blk_compose(pl.bc, pl.blk, st);
+      launch_blk_pass(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, pl.blk, st);
+    }
+  } else if (pl.nmom_max > 0) {  // FP64 seed in both phases (checked by run_solve)
     launch_shift_table(pl.mt, st);
     launch_shift_moments_tab(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, pl.mom_ub, pl.mom_pf, st);
   } else {
@@ -780,19 +812,25 @@ static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, boo
 static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru, int lr, const Tune &t,
                              hipStream_t st, Recorder &rec, int it = 0, int every = 1) {
   const int sp = (prec == 1 && seed32) ? 1 : 0;  // seed precision
+  // block form: chunks start at multiples of the block length, so the iteration's
+  // place in its block is its place in the chunk modulo the block length
+  const int slot = pl.blk > 0 ? it % pl.blk : 0;
   if (every > 1) {
-    const bool smp = it % every == every / 2;
+    // block form: the sampled iterations are last iterations of a block (about one in
+    // every), so the block sweep is timed with the rest
+    const int q = pl.blk > 0 ? std::max(1, every / pl.blk) : 1;
+    const bool smp = pl.blk > 0 ? (slot == pl.blk - 1 && (it / pl.blk) % q == q / 2) : it % every == every / 2;
     Recorder off{rec.c, st, false, {}, nullptr};
     Recorder &r = smp ? rec : off;
     r.mark(ST_DSLASH);
     launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, pl.ct, st);
-    launch_iteration_tail(pl, prec, seed32, ru, lr, t, st, r, smp ? nullptr : &rec);
+    launch_iteration_tail(pl, prec, seed32, ru, lr, t, st, r, smp ? nullptr : &rec, slot);
     r.mark(-1);
     return;
   }
   rec.mark(ST_DSLASH);
   launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, pl.ct, st);
-  launch_iteration_tail(pl, prec, seed32, ru, lr, t, st, rec, nullptr);
+  launch_iteration_tail(pl, prec, seed32, ru, lr, t, st, rec, nullptr, slot);
 }
 
 static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
@@ -813,7 +851,10 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
   CHK(ensure(c, c->seed, L * sizeof(SeedState)));
   CHK(ensure(c, c->shift, L * N * sizeof(ShiftState)));
   CHK(ensure(c, c->zdev, N * 2 * sizeof(double)));
-  if (p.nmom > 0) CHK(ensure(c, c->momtab, shift_table_bytes((int)L, (int)N)));
+  if (p.nmom > 0)
+    CHK(ensure(c, c->momtab,
+               p.blk > 0 ? blk_layout((int)L, (int)N, p.blk).total : shift_table_bytes((int)L, (int)N)));
+  if (p.blk > 0) CHK(ensure(c, c->ring, (size_t)p.blk * L * vec64));
   if (o.prec == SSCG_MIXED) {  // FP32 seed vectors and reliable-update storage
     CHK(ensure(c, c->r32, L * vec32));
     CHK(ensure(c, c->p32, L * vec32));
@@ -834,6 +875,14 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
   launch_pack(p.v, c->v64.p, 0, (int)L, c->V, st);
   HIPCHK(c, hipMemcpyAsync(c->r64.p, c->v64.p, L * vec64, hipMemcpyDeviceToDevice, st));
   HIPCHK(c, hipMemcpyAsync(c->p64.p, c->v64.p, L * vec64, hipMemcpyDeviceToDevice, st));
+  if (p.blk > 0) {
+    // block form: r_0 = v in the ring's last slot, the other slots zero (a block cut
+    // short reads slots it never wrote, with zero coefficients); history: identity
+    HIPCHK(c, hipMemsetAsync(c->ring.p, 0, (size_t)(p.blk - 1) * L * vec64, st));
+    HIPCHK(c, hipMemcpyAsync((char *)c->ring.p + (size_t)(p.blk - 1) * L * vec64, c->v64.p, L * vec64,
+                             hipMemcpyDeviceToDevice, st));
+    launch_blk_init(c->momtab.p, (int)L, (int)N, p.blk, st);
+  }
   if (p.nmom > 0)
     launch_init_shifts_blocked(c->W.p, c->v64.p, (int64_t)n, (int)L, (int)N, st);
   else
@@ -1048,6 +1097,10 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   if (o.ru_interval < 1) o.ru_interval = 50;
   sscg_ctx *c0 = P[0].c;
   hipStream_t st = c0->work;
+  // block form of the in-loop moment update: block length 4, 8 or 16 (0: per iteration)
+  const int blk = env_int("SSCG_BLOCK", 0);
+  if (blk != 0 && blk != 4 && blk != 8 && blk != 16) return fail(c0, SSCG_EINVAL, "SSCG_BLOCK must be 0, 4, 8 or 16");
+  for (Prob &p : P) p.blk = p.nmom > 0 ? blk : 0;
   for (Prob &p : P) {
     if (!p.c->have_gauge) return fail(p.c, SSCG_ESTATE, "no gauge field set");
     if (p.c->device != c0->device) return fail(c0, SSCG_EINVAL, "all problems must share one device");
@@ -1089,6 +1142,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     n[ST_SHIFT] += len;
     if (!pl.fuse_alpha) n[ST_ALPHA] += len;
     if (prec == 1 && o.prec == SSCG_MIXED && full) n[ST_RU] += 1;
+    if (pl.blk > 0) n[ST_PASS] += len / pl.blk;
   };
   Recorder rec{c0, st, c0->profiling > 0, {}, nullptr};
   // profiling level 1 times every launch and runs them directly (an event-record node
@@ -1160,8 +1214,9 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   while (k < o.maxiter) {
     // the FP64 phase of a mixed solve polls at least every 10 iterations so the
     // switch to FP32 is not delayed by a long poll interval
-    const int period = prec == 1 ? o.ru_interval
-                                 : (o.prec != SSCG_FP64 ? std::min(o.poll_every, 10) : o.poll_every);
+    int period = prec == 1 ? o.ru_interval
+                           : (o.prec != SSCG_FP64 ? std::min(o.poll_every, 10) : o.poll_every);
+    if (pl.blk > 0) period = (period + pl.blk - 1) / pl.blk * pl.blk;  // polls at block ends
     const int chunk = std::min(period, o.maxiter - k);
     const bool full = chunk == period;
     if (use_graph && full) {
@@ -1221,6 +1276,13 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     }
   }
   if (rc != SSCG_OK) return rc;
+  if (pl.blk > 0) {
+    // block form: a block cut short by the iteration limit is swept now (after a
+    // complete block the history is the identity and the sweep returns at once)
+    launch_blk_compose(pl.bc, pl.blk, st);
+    launch_blk_pass(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, pl.blk, st);
+    if (k % pl.blk != 0) c0->stage_launched[ST_PASS] += 1;
+  }
   launch_commit(pl.d64, st);  // (every chunk ends with a commit; kept for a loop left early)
   if (prec == 1) {
     // fold every shift's FP32 partial into its FP64 solution

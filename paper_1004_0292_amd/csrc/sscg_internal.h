@@ -308,6 +308,12 @@ struct VecJob {
   const double2 *mcoef;
   double tol;
   int32_t nrr, identity;
+  // block form of the in-loop moment update: block length (0: the per-iteration form).
+  // The seed residuals of a block live in a ring of `ring` slots of nsrc vectors each
+  // (slot s of source l at complex offset (s nsrc + l) n of the ring buffer); within a
+  // block, iteration s writes r_{s+1} to slot s, and r_0 of a block is the previous
+  // block's last residual, in slot ring - 1.
+  int32_t ring, pad_ring;
 };
 struct VecBatch { VecJob job[kMaxJobs]; int32_t njobs; int32_t total_blocks; };
 
@@ -334,7 +340,7 @@ void launch_dslash(const DslashBatch &b, int prec /*0 fp64, 1 fp32*/, int nr, in
 void launch_seed_alpha(const ScalarBatch &b, hipStream_t st);
 // commit of the staged states of every job with a shift table (one block per job)
 void launch_commit(const DslashBatch &b, hipStream_t st);
-void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st);
+void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st, int slot = 0);
 // prec: shift vectors (0 FP64, 1 FP32); seed_prec: seed r and p (0 FP64, 1 FP32);
 // unroll: shifts whose loads are issued together (1, 2, 4); nt: non-temporal access
 void launch_shift_update(const VecBatch &b, int prec, int seed_prec, int fold, int unroll, int nt,
@@ -349,12 +355,60 @@ constexpr int kMomBlock = 256;   // entries (threads) per block of the in-loop m
 // kMomRows coefficients) stages the iteration's scalars; the update kernel (one entry
 // per thread) reads them with uniform loads. Blocks per source of the table kernel:
 // ceil(nshift / kBlock); of the update: nblk_mom.
-void launch_shift_table(const VecBatch &b, hipStream_t st);
+void launch_shift_table(const VecBatch &b, hipStream_t st, int slot = 0);
 // ub: shifts whose loads are issued together (1, 2, 4)
 void launch_shift_moments_tab(const VecBatch &b, int prec, int nmom_max, int ub, int pf, hipStream_t st);
 inline size_t shift_table_bytes(int nsrc, int nshift) {
   return (size_t)nsrc * nshift * (sizeof(ShiftTab) + (size_t)kMomRows * sizeof(double2));
 }
+// Block form (VecJob::ring = B > 0, B in {4, 8, 16}): the table kernel writes the
+// iteration's record of every (source, shift) into slot s of a history of B records
+// (not-updated records: alpha 0, beta 1, 1/pi 0); after the B-th iteration (and once
+// after the loop) the compose kernel folds the history into one linear map per shift
+// (BlkShift plus B coefficients D) and the moment coefficients G (rows of the g area)
+// and H, and resets the history; the pass kernel applies them in one sweep over the
+// entries. Regions of the table buffer, byte offsets:
+//   hist  ShiftTab [nsrc][nshift][B]      records of the block
+//   g     double2 [nsrc][nshift][kMomRows] G_kj (zero beyond the moments summed)
+//   comp  BlkShift [nsrc][nshift]          C_j and the flags
+//   d     double2 [nsrc][nshift][B]        D_j(B, m), m = 1..B
+//   h     double2 [nsrc][kMomRows][B]      H_km, m = 1..B (the last is zero)
+//   e     double2 [nsrc][nshift][B]        per-shift terms of H (work area)
+//   any   int32 [nsrc]                     0: no shift of the source moved in the block
+constexpr int kMaxBlk = 16;
+struct BlkShift {
+  double2 c;       // C_j(B)
+  int32_t any;     // updated in at least one iteration of the block (p_j(0) is read)
+  int32_t st;      // still active at the end of the block (p_j(B) is written)
+  int32_t pad[2];
+};
+struct BlkLayout {
+  size_t hist, g, comp, d, h, e, any, total;
+};
+__host__ __device__ inline BlkLayout blk_layout(int nsrc, int nshift, int B) {
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t sn = (size_t)nsrc * nshift;
+  BlkLayout o;
+  o.hist = 0;
+  o.g = up(o.hist + sn * B * sizeof(ShiftTab));
+  o.comp = up(o.g + sn * kMomRows * sizeof(double2));
+  o.d = up(o.comp + sn * sizeof(BlkShift));
+  o.h = up(o.d + sn * B * sizeof(double2));
+  o.e = up(o.h + (size_t)nsrc * kMomRows * B * sizeof(double2));
+  o.any = up(o.e + sn * B * sizeof(double2));
+  o.total = up(o.any + (size_t)nsrc * sizeof(int32_t));
+  return o;
+}
+// history records set to the identity (start of a solve)
+void launch_blk_init(void *tab, int nsrc, int nshift, int B, hipStream_t st);
+// p <- r_{s+1} + beta_k p (the seed direction, every iteration of the block form);
+// job a = residual ring, d = seed p; one source per nblk_vec blocks like the seed passes
+void launch_seed_p_update(const VecBatch &b, int slot, hipStream_t st);
+// compose: one block per source (total_blocks = sources of all jobs); job e = table
+void launch_blk_compose(const VecBatch &b, int B, hipStream_t st);
+// pass: the in-loop moment kernel's grid; job a = moments, b = shift directions
+// (chunk-blocked), c = residual ring, e = table
+void launch_blk_pass(const VecBatch &b, int prec, int nmom_max, int B, hipStream_t st);
 void launch_fold_seed(const VecBatch &b, hipStream_t st);
 void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st);
 void launch_init_shifts(void *y, void *W, const void *v, int64_t n, int nsrc, int nshift, hipStream_t st);

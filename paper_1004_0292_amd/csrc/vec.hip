@@ -100,9 +100,11 @@ __global__ __launch_bounds__(kBlock) void commit_kernel(DslashBatch B) {
 
 // ---------------------------------------------------------------------------
 // r <- r - alpha q (and x_part += alpha p in the FP32 phase); partial <r, r>.
-// job: a = r, b = q, c = x_part (or null), d = p.
+// job: a = r, b = q, c = x_part (or null), d = p. With a residual ring (block form of
+// the in-loop update) the new r goes to ring slot `slot` and the old one is read from
+// the slot before it (cyclically), instead of updating r in place.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
+__global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B, int slot) {
   using C = V2<T>;
   __shared__ double red[kBlock / 64];
   const int b = blockIdx.x;
@@ -112,6 +114,12 @@ __global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
   SeedState &S = J.seed[l];
   if (S.done) return;
   C *r = reinterpret_cast<C *>(J.a) + (size_t)l * J.n;
+  const C *rin = r;
+  if (J.ring > 0) {
+    const int sin = slot == 0 ? J.ring - 1 : slot - 1;
+    rin = reinterpret_cast<const C *>(J.a) + ((size_t)sin * J.nsrc + l) * J.n;
+    r = reinterpret_cast<C *>(J.a) + ((size_t)slot * J.nsrc + l) * J.n;
+  }
   const C *q = reinterpret_cast<const C *>(J.b) + (size_t)l * J.n;
   C *xp = J.c ? reinterpret_cast<C *>(J.c) + (size_t)l * J.n : nullptr;
   const C *p = J.d ? reinterpret_cast<const C *>(J.d) + (size_t)l * J.n : nullptr;
@@ -124,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
   for (int e = 0; e < kEpt; ++e) {
     const int64_t i = base0 + (int64_t)e * kBlock;
     if (i < J.n) {
-      r0[e] = r[i];
+      r0[e] = rin[i];
       q0[e] = q[i];
       if (xp) {
         x0[e] = xp[i];
@@ -179,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B) {
 #pragma unroll
     for (int e = 0; e < kEpt; ++e) {
       const int64_t i = base + (int64_t)e * kBlock;
-      if (i < J.n) update(i, r[i], q[i], xp ? xp[i] : C{}, xp ? p[i] : C{});
+      if (i < J.n) update(i, rin[i], q[i], xp ? xp[i] : C{}, xp ? p[i] : C{});
     }
   }
   const double tot = block_sum_all<kBlock / 64>(acc, red);
@@ -459,7 +467,11 @@ __global__ __launch_bounds__(kBlock) void shift_update_kernel(VecBatch B) {
 // order), writes a_j, b_j, 1/pi_j, the update flag and g_kj = c_kj a_j for k < kMomRows
 // (zero beyond the moments summed) to the table, and stages the shift state for the
 // commit (one writer per shift; the first block of a source stages the seed scalars).
-__global__ __launch_bounds__(kBlock) void shift_table_kernel(VecBatch B) {
+// In the block form (J.ring = B > 0) the record goes to slot `slot` of the source's
+// history of B records instead (a shift not updated gets the identity record alpha 0,
+// beta 1, 1/pi 0; the flag word after upd holds the freeze), and no coefficients
+// are written: the compose kernel forms them for the whole block.
+__global__ __launch_bounds__(kBlock) void shift_table_kernel(VecBatch B, int slot) {
   __shared__ double red[kBlock / 64];
   const int b = blockIdx.x;
   const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
@@ -506,10 +518,18 @@ __global__ __launch_bounds__(kBlock) void shift_table_kernel(VecBatch B) {
   t.ipi = o.ipi;
   t.upd = o.upd;
   t.pad = 0;
-  tab[j] = t;
+  if (J.ring > 0) {
+    if (!o.upd) t.b = make_double2(1.0, 0.0);
+    t.pad = o.upd && o.frz;
+    const BlkLayout lay = blk_layout(J.nsrc, N, J.ring);
+    ShiftTab *hist = reinterpret_cast<ShiftTab *>(reinterpret_cast<char *>(J.e) + lay.hist);
+    hist[((size_t)l * N + j) * J.ring + slot] = t;
+  } else {
+    tab[j] = t;
 #pragma unroll 4
-  for (int k = 0; k < kMomRows; ++k)
-    g[k] = (o.upd && k < J.nmom) ? cmul(J.mcoef[(size_t)k * N + j], o.a) : make_double2(0.0, 0.0);
+    for (int k = 0; k < kMomRows; ++k)
+      g[k] = (o.upd && k < J.nmom) ? cmul(J.mcoef[(size_t)k * N + j], o.a) : make_double2(0.0, 0.0);
+  }
   if (o.upd) {
     ShiftState &H = J.shift[(size_t)l * N + j];
     H.pi_n = o.pn;
@@ -655,6 +675,240 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_tab_kernel(VecBatch B
   pv.x = rv.x + beta * pold.x;
   pv.y = rv.y + beta * pold.y;
   p[i] = pv;
+}
+
+// ---- block form of the in-loop moment update ----------------------------------
+// Over a block of B iterations the seed residuals r(1..B) (r(m) = r_{k0+m}) are kept,
+// and every shift direction obeys p_j(s+1) = r(s+1) / pi_j(s) + beta_j(s) p_j(s)
+// (Sec. 2.2, with pi_j(s) = pi_{j,k0+s+1}), so
+//   p_j(s) = C_j(s) p_j(0) + sum_{m=1..s} D_j(s, m) r(m),
+//   C_j(0) = 1, C_j(s+1) = beta_j(s) C_j(s),
+//   D_j(s+1, m) = beta_j(s) D_j(s, m) (m <= s), D_j(s+1, s+1) = 1 / pi_j(s).
+// The block's moment increments sum_s c_kj alpha_j(s) p_j(s) (eq. 2 summed as the
+// solve runs) are then
+//   sum_j G_kj p_j(0) + sum_m H_km r(m),
+//   G_kj = c_kj A_j,  A_j = sum_s alpha_j(s) C_j(s),
+//   H_km = sum_j c_kj E_j(m),  E_j(m) = sum_{s >= m} alpha_j(s) D_j(s, m),
+// and p_j(B) follows from the same C and D: one sweep over the entries reads every
+// p_j once and writes it once per block instead of once per iteration. A shift not
+// updated in an iteration has the identity record (alpha 0, beta 1, 1/pi 0), which
+// leaves C, D and the sums unchanged; a source that finished inside the block has
+// identity records for the iterations it did not run.
+
+// History records set to the identity. nrec = nsrc * nshift * B.
+__global__ void blk_init_kernel(ShiftTab *hist, int64_t nrec) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrec) return;
+  ShiftTab r;
+  r.a = r.ipi = make_double2(0.0, 0.0);
+  r.b = make_double2(1.0, 0.0);
+  r.upd = r.pad = 0;
+  hist[t] = r;
+}
+
+// p <- r(s+1) + beta_k p with the beta_k the table kernel staged (the seed direction
+// the next dslash reads). job: a = residual ring, d = seed p.
+__global__ __launch_bounds__(kBlock) void seed_p_update_kernel(VecBatch B, int slot) {
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int lb = b - J.block_begin;
+  const int l = lb / J.nblk_vec, vb = lb - l * J.nblk_vec;
+  const SeedState &S = J.seed[l];
+  if (S.done || !S.pending || S.brk_n) return;  // uniform over the block
+  const double beta = S.beta_n;
+  const double2 *r = reinterpret_cast<const double2 *>(J.a) + ((size_t)slot * J.nsrc + l) * J.n;
+  double2 *p = reinterpret_cast<double2 *>(J.d) + (size_t)l * J.n;
+  const int64_t stride = (int64_t)J.nblk_vec * kBlock * kEpt;
+  for (int64_t base = (int64_t)vb * kBlock * kEpt + threadIdx.x; base - threadIdx.x < J.n; base += stride) {
+    double2 rv[kEpt], pv[kEpt];
+#pragma unroll
+    for (int e = 0; e < kEpt; ++e) {
+      const int64_t i = base + (int64_t)e * kBlock;
+      if (i < J.n) {
+        rv[e] = r[i];
+        pv[e] = p[i];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kEpt; ++e) {
+      const int64_t i = base + (int64_t)e * kBlock;
+      if (i < J.n) p[i] = make_double2(rv[e].x + beta * pv[e].x, rv[e].y + beta * pv[e].y);
+    }
+  }
+}
+
+// Composition of a block's records, one block of threads per source: a thread per
+// shift runs the recurrences of C_j, D_j, A_j and E_j over the B records (and resets
+// them), writes C_j, the flags, D_j and G_kj, and leaves E_j in the work area; after a
+// barrier the threads form H_km = sum_j c_kj E_j(m). job: e = table.
+template <int BB>
+__global__ __launch_bounds__(kBlock) void blk_compose_kernel(VecBatch B) {
+  __shared__ int any_sh;
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int l = b - J.block_begin;
+  const int N = J.nshift;
+  const BlkLayout lay = blk_layout(J.nsrc, N, BB);
+  char *tb = reinterpret_cast<char *>(J.e);
+  ShiftTab *hist = reinterpret_cast<ShiftTab *>(tb + lay.hist) + (size_t)l * N * BB;
+  double2 *g = reinterpret_cast<double2 *>(tb + lay.g) + (size_t)l * N * kMomRows;
+  BlkShift *cs = reinterpret_cast<BlkShift *>(tb + lay.comp) + (size_t)l * N;
+  double2 *D = reinterpret_cast<double2 *>(tb + lay.d) + (size_t)l * N * BB;
+  double2 *H = reinterpret_cast<double2 *>(tb + lay.h) + (size_t)l * kMomRows * BB;
+  double2 *E = reinterpret_cast<double2 *>(tb + lay.e) + (size_t)l * N * BB;
+  int32_t *anyf = reinterpret_cast<int32_t *>(tb + lay.any);
+  if (threadIdx.x == 0) any_sh = 0;
+  __syncthreads();
+  const double2 zero = make_double2(0.0, 0.0);
+  int any_t = 0;
+  for (int j = threadIdx.x; j < N; j += kBlock) {
+    double2 C = make_double2(1.0, 0.0), A = zero, d[BB], e[BB];  // d[m-1] = D_j(s, m), e[m-1] = E_j(m)
+#pragma unroll
+    for (int m = 0; m < BB; ++m) d[m] = e[m] = zero;
+    int any = 0, frz = 0;
+    ShiftTab *h = hist + (size_t)j * BB;
+#pragma unroll
+    for (int s = 0; s < BB; ++s) {
+      const ShiftTab t = h[s];
+      cfma(A, t.a, C);
+#pragma unroll
+      for (int m = 0; m < s; ++m) cfma(e[m], t.a, d[m]);
+      C = cmul(t.b, C);
+#pragma unroll
+      for (int m = 0; m < s; ++m) d[m] = cmul(t.b, d[m]);
+      d[s] = t.ipi;
+      any |= t.upd;
+      frz |= t.pad;
+    }
+    ShiftTab idr;
+    idr.a = idr.ipi = zero;
+    idr.b = make_double2(1.0, 0.0);
+    idr.upd = idr.pad = 0;
+#pragma unroll
+    for (int s = 0; s < BB; ++s) h[s] = idr;
+    BlkShift o;
+    o.c = C;
+    o.any = any;
+    o.st = any && !frz;
+    o.pad[0] = o.pad[1] = 0;
+    cs[j] = o;
+#pragma unroll
+    for (int m = 0; m < BB; ++m) {
+      D[(size_t)j * BB + m] = d[m];
+      E[(size_t)j * BB + m] = e[m];
+    }
+    for (int k = 0; k < kMomRows; ++k)
+      g[(size_t)j * kMomRows + k] = (any && k < J.nmom) ? cmul(J.mcoef[(size_t)k * N + j], A) : zero;
+    any_t |= any;
+  }
+  if (any_t) any_sh = 1;
+  __syncthreads();  // (also orders this block's E writes before the reads below)
+  for (int t = threadIdx.x; t < kMomRows * BB; t += kBlock) {
+    const int k = t / BB, m = t - k * BB;
+    double2 acc = zero;
+    if (k < J.nmom)
+      for (int j = 0; j < N; ++j) cfma(acc, J.mcoef[(size_t)k * N + j], E[(size_t)j * BB + m]);
+    H[t] = acc;
+  }
+  if (threadIdx.x == 0) anyf[l] = any_sh;
+}
+
+// The block's sweep, one thread per entry of one source (the in-loop kernel's grid
+// and chunk-blocked direction layout): loads the BB residuals r(m) of the block and
+// the MM moment sums, then for every shift reads p_j(0), adds G_kj p_j(0) to the sums
+// and writes p_j(B) = C_j p_j(0) + sum_m D_j(B, m) r(m) (only for shifts still active);
+// finally adds sum_m H_km r(m). The coefficients are read at wavefront-uniform
+// addresses through the constant address space (scalar loads), and the memory
+// operations follow the in-loop kernel's order: moments and residuals first, the next
+// shift's load before this shift's store, the moments written last.
+// job: a = moments, b = shift directions, c = residual ring, e = table.
+template <typename T, int MM, int BB>
+__global__ __launch_bounds__(kMomBlock) void blk_pass_kernel(VecBatch B) {
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int lb = b - J.block_begin;
+  const int l = lb / J.nblk_mom, vb = lb - l * J.nblk_mom;
+  const int N = J.nshift;
+  const BlkLayout lay = blk_layout(J.nsrc, N, BB);
+  typedef __attribute__((address_space(4))) const double CDbl;
+  typedef __attribute__((address_space(4))) const int32_t CInt;
+  const uintptr_t tb = reinterpret_cast<uintptr_t>(J.e);
+  CInt *anyf = reinterpret_cast<CInt *>(tb + lay.any);
+  if (anyf[l] == 0) return;  // uniform over the block
+  constexpr int kCsD = sizeof(BlkShift) / sizeof(double), kCsI = sizeof(BlkShift) / sizeof(int32_t);
+  constexpr int kAnyI = offsetof(BlkShift, any) / sizeof(int32_t), kStI = offsetof(BlkShift, st) / sizeof(int32_t);
+  CDbl *csd = reinterpret_cast<CDbl *>(tb + lay.comp) + (size_t)l * N * kCsD;
+  CInt *csi = reinterpret_cast<CInt *>(tb + lay.comp) + (size_t)l * N * kCsI;
+  CDbl *Dt = reinterpret_cast<CDbl *>(tb + lay.d) + (size_t)l * N * BB * 2;
+  CDbl *gtab = reinterpret_cast<CDbl *>(tb + lay.g) + (size_t)l * N * kMomRows * 2;
+  CDbl *Ht = reinterpret_cast<CDbl *>(tb + lay.h) + (size_t)l * kMomRows * BB * 2;
+  const int64_t n = J.n;
+  const int64_t nch = (n + 63) / 64;
+  const int64_t i = (int64_t)vb * kMomBlock + threadIdx.x;
+  const bool valid = i < n;
+  const int64_t ii = valid ? i : 0;  // invalid lanes read entry 0 and store nothing
+  const int64_t c = i >> 6;
+  const int q = (int)(i & 63);
+  const double2 *Sm = reinterpret_cast<const double2 *>(J.a);
+  const int M = J.nmom;
+  const int voff16 = valid ? (int)(i * 16) : 0x7fffffff;
+  auto mom_rsrc = [&](int k) { return make_rsrc(Sm + ((size_t)k * J.nsrc + l) * n, k < M ? (int)(n * 16) : 0); };
+  double2 acc[MM];
+#pragma unroll
+  for (int k = 0; k < MM; ++k) acc[k] = BufIO<double, 2>::ld(mom_rsrc(k), voff16, 0);
+  const double2 *ring = reinterpret_cast<const double2 *>(J.c);
+  double2 rv[BB];
+#pragma unroll
+  for (int m = 0; m < BB; ++m) rv[m] = ring[((size_t)m * J.nsrc + l) * n + ii];
+  constexpr int kW = sizeof(V2<T>);
+  const int voff = valid ? q * kW : 0x7fffffff;
+  const double2 *W = reinterpret_cast<const double2 *>(J.b);
+  auto run_rsrc = [&](int j, bool on) { return make_rsrc(W + blk_chunk(l, c, j, nch, N), on ? 64 * kW : 0); };
+  auto fetch = [&](int j, double2 &v, bool &f) {
+    f = j < N && csi[(size_t)j * kCsI + kAnyI] != 0;
+    const V2<T> x = BufIO<T, 2>::ld(run_rsrc(j, f), voff, 0);
+    v = make_double2(x.x, x.y);
+  };
+  double2 nv;
+  bool nup;
+  fetch(0, nv, nup);
+  for (int j = 0; j < N; ++j) {
+    const double2 pv = nv;
+    const bool up = nup;
+    if (j + 1 < N) fetch(j + 1, nv, nup);
+    if (up) {  // uniform
+      CDbl *gj = gtab + (size_t)j * kMomRows * 2;
+#pragma unroll
+      for (int k0 = 0; k0 < MM; k0 += 8) {
+        double gx[8], gy[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          gx[e] = gj[2 * (k0 + e)];
+          gy[e] = gj[2 * (k0 + e) + 1];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cfma(acc[k0 + e], make_double2(gx[e], gy[e]), pv);
+      }
+    }
+    const bool stj = up && csi[(size_t)j * kCsI + kStI] != 0;
+    CDbl *cj = csd + (size_t)j * kCsD;
+    CDbl *dj = Dt + (size_t)j * BB * 2;
+    double2 pn = cmul(make_double2(cj[0], cj[1]), pv);
+#pragma unroll
+    for (int m = 0; m < BB; ++m) cfma(pn, make_double2(dj[2 * m], dj[2 * m + 1]), rv[m]);
+    V2<T> x;
+    x.x = pn.x;
+    x.y = pn.y;
+    BufIO<T, 2>::st(x, run_rsrc(j, stj), voff, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < MM; ++k) {
+    CDbl *hk = Ht + (size_t)k * BB * 2;
+#pragma unroll
+    for (int m = 0; m < BB; ++m) cfma(acc[k], make_double2(hk[2 * m], hk[2 * m + 1]), rv[m]);
+  }
+#pragma unroll
+  for (int k = 0; k < MM; ++k) BufIO<double, 2>::st(acc[k], mom_rsrc(k), voff16, 0);
 }
 
 // Start of an in-loop solve: p_j = v_l in the chunk-blocked layout (padding zero).
@@ -890,9 +1144,9 @@ void launch_commit(const DslashBatch &b, hipStream_t st) {
   if (b.njobs <= 0) return;
   hipLaunchKernelGGL(commit_kernel, dim3(b.njobs), dim3(kBlock), 0, st, b);
 }
-void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st) {
-  if (prec == 0) hipLaunchKernelGGL(seed_r_update_kernel<double>, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
-  else hipLaunchKernelGGL(seed_r_update_kernel<float>, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+void launch_seed_r_update(const VecBatch &b, int prec, hipStream_t st, int slot) {
+  if (prec == 0) hipLaunchKernelGGL(seed_r_update_kernel<double>, dim3(b.total_blocks), dim3(kBlock), 0, st, b, slot);
+  else hipLaunchKernelGGL(seed_r_update_kernel<float>, dim3(b.total_blocks), dim3(kBlock), 0, st, b, slot);
 }
 template <typename T, typename TR, bool FOLD, int U>
 static void launch_su_nt(const VecBatch &b, int nt, hipStream_t st) {
@@ -916,9 +1170,9 @@ void launch_shift_update(const VecBatch &b, int prec, int seed_prec, int fold, i
     else launch_su_u<float, float, false>(b, unroll, nt, st);
   }
 }
-void launch_shift_table(const VecBatch &b, hipStream_t st) {
+void launch_shift_table(const VecBatch &b, hipStream_t st, int slot) {
   if (b.total_blocks <= 0) return;
-  hipLaunchKernelGGL(shift_table_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b);
+  hipLaunchKernelGGL(shift_table_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b, slot);
 }
 template <typename T, int MM>
 static void launch_smt_ub(const VecBatch &b, int ub, int pf, hipStream_t st) {
@@ -955,6 +1209,43 @@ void launch_to_fp32(const void *src64, void *dst32, void *zero32, int64_t n, hip
   if (n <= 0) return;
   hipLaunchKernelGGL(to_fp32_kernel, dim3(nblocks1d(n)), dim3(kBlock), 0, st,
                      (const double2 *)src64, (float2 *)dst32, (float2 *)zero32, n);
+}
+void launch_blk_init(void *tab, int nsrc, int nshift, int B, hipStream_t st) {
+  const int64_t nrec = (int64_t)nsrc * nshift * B;
+  if (nrec <= 0) return;
+  hipLaunchKernelGGL(blk_init_kernel, dim3(nblocks1d(nrec)), dim3(kBlock), 0, st,
+                     reinterpret_cast<ShiftTab *>(reinterpret_cast<char *>(tab) + blk_layout(nsrc, nshift, B).hist),
+                     nrec);
+}
+void launch_seed_p_update(const VecBatch &b, int slot, hipStream_t st) {
+  if (b.total_blocks <= 0) return;
+  hipLaunchKernelGGL(seed_p_update_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b, slot);
+}
+void launch_blk_compose(const VecBatch &b, int B, hipStream_t st) {
+  if (b.total_blocks <= 0) return;
+  const dim3 g(b.total_blocks), t(kBlock);
+  if (B == 4) hipLaunchKernelGGL(blk_compose_kernel<4>, g, t, 0, st, b);
+  else if (B == 8) hipLaunchKernelGGL(blk_compose_kernel<8>, g, t, 0, st, b);
+  else hipLaunchKernelGGL(blk_compose_kernel<16>, g, t, 0, st, b);
+}
+template <typename T, int MM>
+static void launch_bp_b(const VecBatch &b, int B, hipStream_t st) {
+  const dim3 g(b.total_blocks), t(kMomBlock);
+  if (B == 4) hipLaunchKernelGGL((blk_pass_kernel<T, MM, 4>), g, t, 0, st, b);
+  else if (B == 8) hipLaunchKernelGGL((blk_pass_kernel<T, MM, 8>), g, t, 0, st, b);
+  else hipLaunchKernelGGL((blk_pass_kernel<T, MM, 16>), g, t, 0, st, b);
+}
+template <typename T>
+static void launch_bp(const VecBatch &b, int mm, int B, hipStream_t st) {
+  if (mm <= 8) launch_bp_b<T, 8>(b, B, st);
+  else if (mm <= 16) launch_bp_b<T, 16>(b, B, st);
+  else if (mm <= 24) launch_bp_b<T, 24>(b, B, st);
+  else launch_bp_b<T, 32>(b, B, st);
+}
+void launch_blk_pass(const VecBatch &b, int prec, int nmom_max, int B, hipStream_t st) {
+  if (b.total_blocks <= 0) return;
+  if (prec == 0) launch_bp<double>(b, nmom_max, B, st);
+  else launch_bp<float>(b, nmom_max, B, st);
 }
 void launch_init_shifts_blocked(void *W, const void *v, int64_t n, int nsrc, int nshift, hipStream_t st) {
   const int64_t npad = (n + 63) / 64 * 64;

@@ -120,6 +120,47 @@ def test_moments_in_loop(sscg, f4, monkeypatch, prec, P, pf, ub):
     case(f"in-loop moments {prec} P={P} pf={pf} ub={ub}")
     monkeypatch.setenv("SSCG_MOMPF", str(pf))
     monkeypatch.setenv("SSCG_MOMUB", str(ub))
+    _in_loop_vs_stored(sscg, f4, prec, P)
+
+
+@pytest.mark.parametrize("prec,P,blk", [("fp64", 1, 4), ("fp64", 1, 8), ("fp64", 1, 16), ("mixed_shifts", 1, 8),
+                                        ("fp64", 3, 8), ("mixed_shifts", 3, 16)])
+def test_moments_in_loop_block(sscg, f4, monkeypatch, prec, P, blk):
+    """Block form of the in-loop update (the recurrences of blk iterations composed
+    into one linear map per shift and applied in one sweep over the directions, the
+    seed residuals of the block kept in a ring): the same bar as the per-iteration
+    form against the stored-solution path and the oracle."""
+    case(f"in-loop moments block {blk} {prec} P={P}")
+    monkeypatch.setenv("SSCG_BLOCK", str(blk))
+    _in_loop_vs_stored(sscg, f4, prec, P)
+
+
+@pytest.mark.parametrize("blk", [8, 16])
+def test_moments_in_loop_block_cut_short(sscg, f4, monkeypatch, blk):
+    """A solve stopped by the iteration limit (37, inside a block) in the block form:
+    the sweep after the loop applies the partial block, so the moments, and the
+    eigenvalues extracted from them, equal the per-iteration form's."""
+    case(f"in-loop moments block {blk} cut short")
+    U, A, lam, c = f4
+    V = to_dev(synth.sources(CFG1.V, 2, 8).reshape(2, -1))
+    # every Ritz value inside the rectangle is reported (no residual filter): the
+    # truncated moments leave residuals far above any acceptance bar
+    kw = dict(gamma=0.225, rho=0.03, beta=0.25, N=16, M=8, rank_tol=1e-7, moments_in_loop=1, spur_tol=1e30)
+    opts = sscg.default_opts(maxiter=37)
+    keep = (sscg.EINVAL, sscg.ENOMEM, sscg.EDEVICE, sscg.ESTATE, sscg.EBREAKDOWN)
+    monkeypatch.setenv("SSCG_BLOCK", "0")
+    a = c.ss_eigs(sscg.default_ss_params(solve=opts, **kw), V, max_eigs=32, raise_on=keep)
+    monkeypatch.setenv("SSCG_BLOCK", str(blk))
+    b = c.ss_eigs(sscg.default_ss_params(solve=opts, **kw), V, max_eigs=32, raise_on=keep)
+    assert a.info.solve_status == b.info.solve_status == sscg.ENOTCONV
+    assert a.info.iters == b.info.iters == 37
+    assert a.info.shift_updates == b.info.shift_updates
+    assert a.info.rank == b.info.rank and a.n_found == b.n_found > 0
+    assert np.all(np.abs(b.lam - a.lam) <= 1e-9 * np.abs(a.lam))
+    assert np.all(np.abs(b.res - a.res) <= 1e-6 * a.res)
+
+
+def _in_loop_vs_stored(sscg, f4, prec, P):
     U, A, lam, c = f4
     V = synth.sources(CFG1.V, 2, 8).reshape(2, -1)
     pr = {"fp64": sscg.FP64, "mixed_shifts": sscg.MIXED_SHIFTS}[prec]
@@ -146,12 +187,14 @@ def test_moments_in_loop(sscg, f4, monkeypatch, prec, P, pf, ub):
         assert ov > 1 - 1e-9
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed_shifts"])
-def test_moments_in_loop_ragged_chunks(sscg, prec):
+@pytest.mark.parametrize("prec,blk", [("fp64", 0), ("mixed_shifts", 0), ("fp64", 8), ("mixed_shifts", 4)])
+def test_moments_in_loop_ragged_chunks(sscg, monkeypatch, prec, blk):
     """In-loop moments on a lattice whose vector length n = 12 V = 1620 is not a
     multiple of 64: the shift directions are stored in 64-entry chunks with a padded
-    last chunk. Eigenpairs equal the stored-solution path and the dense spectrum."""
-    case(f"in-loop moments ragged chunks {prec}")
+    last chunk. Eigenpairs equal the stored-solution path and the dense spectrum
+    (per-iteration form, blk = 0, and block form)."""
+    case(f"in-loop moments ragged chunks {prec} block {blk}")
+    monkeypatch.setenv("SSCG_BLOCK", str(blk))
     dims, kappa = (3, 3, 3, 5), 0.12
     U = synth.gauge_field(dims, 0.3, 11)
     A = wilson.hermitian_wilson(U, dims, kappa)
@@ -187,11 +230,14 @@ def test_moments_in_loop_rejects(sscg, f4):
         assert e.value.code == sscg.EINVAL
 
 
-@pytest.mark.parametrize("in_loop", [0, 1])
-def test_weighted_tolerance(sscg, f4, in_loop):
+@pytest.mark.parametrize("in_loop,blk", [(0, 0), (1, 0), (1, 8)])
+def test_weighted_tolerance(sscg, f4, monkeypatch, in_loop, blk):
     """Moment-weighted stopping on the GPU equals the oracle's: the same shift-update
-    count (each node's convergence iteration within 2), eigenvalues within 1e-10."""
-    case(f"weighted tolerance in_loop={in_loop}")
+    count (each node's convergence iteration within 2), eigenvalues within 1e-10
+    (stored solutions, in-loop moments, and their block form, where the shifts freeze
+    at different iterations inside a block)."""
+    case(f"weighted tolerance in_loop={in_loop} block {blk}")
+    monkeypatch.setenv("SSCG_BLOCK", str(blk))
     U, A, lam, c = f4
     V = synth.sources(CFG1.V, 2, 9).reshape(2, -1)
     kw = dict(gamma=0.225, rho=0.03, beta=0.25, N=16, M=8, rank_tol=1e-7)
@@ -208,10 +254,13 @@ def test_weighted_tolerance(sscg, f4, in_loop):
     assert np.all(out.res <= np.maximum(1e-8, 2 * ref["res"]))
 
 
-def test_hankel_with_moments_in_loop(sscg, f4):
+@pytest.mark.parametrize("blk", [0, 16])
+def test_hankel_with_moments_in_loop(sscg, f4, monkeypatch, blk):
     """Hankel extraction from 2M moments summed inside the solve (block moments
-    V^H s_k formed from them) equals the stored-solution Hankel and the oracle's."""
-    case("Hankel with in-loop moments")
+    V^H s_k formed from them) equals the stored-solution Hankel and the oracle's
+    (per-iteration form, blk = 0, and block form)."""
+    case(f"Hankel with in-loop moments block {blk}")
+    monkeypatch.setenv("SSCG_BLOCK", str(blk))
     U, A, lam, c = f4
     V = synth.sources(CFG1.V, 2, 7).reshape(2, -1)
     kw = dict(gamma=0.225, rho=0.03, beta=0.25, N=16, M=8, rank_tol=1e-7, method=sscg.HANKEL)
