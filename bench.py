@@ -52,9 +52,12 @@ HBM_PEAK_GBS = 8000.0
 MALL_BYTES = 256 << 20          # Infinity Cache of the MI355X
 DEFAULT_CONFIG = "wilson24x48"
 STAGES = ["dslash", "seed_alpha", "seed_r_update", "unused", "shift_update", "reliable_update",
-          "solve_loop"]
+          "solve_loop", "block_sweep"]
+TIMED_STAGES = (0, 1, 2, 4, 5, 7)
+BLOCK_DEFAULT = 16    # block length of the in-loop moment update (SSCG_BLOCK, unless set)
 KERNEL_SOURCES = {"shift_update": "paper_1004_0292_amd/csrc/vec.hip",
                   "shift_moments": "paper_1004_0292_amd/csrc/vec.hip",
+                  "block_sweep": "paper_1004_0292_amd/csrc/vec.hip",
                   "dslash": "paper_1004_0292_amd/csrc/dslash.hip",
                   "dslash_fp32_links12": "paper_1004_0292_amd/csrc/dslash.hip",
                   "dslash_fp64_links18": "paper_1004_0292_amd/csrc/dslash.hip"}
@@ -380,7 +383,7 @@ def copy_bandwidth(nbytes=2 << 30, reps=5):
     return round(gbs, 1)
 
 
-def kernel_bytes(w, prec, tot, link_launches, moments_in_loop):
+def kernel_bytes(w, prec, tot, link_launches, moments_in_loop, blk=0):
     """Algorithmic (compulsory) HBM bytes of the shift update and the dslash over the
     timed steps. Shift update: read and write x_j and p_j per active (shift, source,
     entry) (64 B FP64, 32 B FP32), the seed r read once and the seed p read and written
@@ -394,7 +397,12 @@ def kernel_bytes(w, prec, tot, link_launches, moments_in_loop):
     it64 = tot["seed_iters"] - tot["seed_iters_fp32"]
     it32 = tot["seed_iters_fp32"]
     shift = (su64 * 64 + it64 * 48) * n + (su32 * 32 + it32 * (24 if seed32 else 48)) * n
-    if moments_in_loop:
+    if moments_in_loop and blk:
+        # block form: the shift stage is the table launch (a few hundred bytes per
+        # shift, not counted) and the seed direction update (r read, p read and
+        # written per (source, entry, iteration)); the sweep is counted per pass
+        shift = (it64 + it32) * 48 * n
+    elif moments_in_loop:
         # p_j read and written per active (shift, source, entry); per (source, entry,
         # iteration) the seed r read, the seed p read and written, the M moments read
         # and written (the stage also holds the table launch that forms the shift
@@ -466,6 +474,9 @@ def main():
     w = synth.CONFIGS[args.config]
     mode = w.prec if args.prec == "workload" else args.prec
     args.moments_in_loop = (not args.stored and args.method == "rr" and w.M <= 32 and mode != "mixed")
+    # the block length is set here for the library too (it reads SSCG_BLOCK at each solve)
+    os.environ.setdefault("SSCG_BLOCK", str(BLOCK_DEFAULT))
+    blk = int(os.environ["SSCG_BLOCK"]) if args.moments_in_loop else 0
     prec = PRECS[mode]
     print(f"[bench] {w.name} {w.dims} N={w.N} L={w.L} M={w.M} prec={mode}", file=sys.stderr, flush=True)
     U = w.gauge()
@@ -490,6 +501,8 @@ def main():
     print("[bench] warm-up done", file=sys.stderr, flush=True)
     stage_ms = np.zeros(8)
     stage_calls = np.zeros(8, dtype=np.int64)
+    stage_launched = np.zeros(8, dtype=np.int64)
+    sweep_bytes = 0          # algorithmic bytes of the block sweeps (library count)
     stage_est = np.zeros(8)          # sampled average times launches, summed over steps
     tot = dict(shift_updates=0, shift_updates_fp32=0, seed_iters=0, seed_iters_fp32=0, matvecs=0,
                t_solve=0.0, t_moments=0.0, t_extract=0.0)
@@ -503,7 +516,9 @@ def main():
         launched = ctx.stage_launches()
         stage_ms += ms
         stage_calls += calls
-        for k in range(6):
+        stage_launched += launched
+        sweep_bytes += ctx.sweep_bytes()
+        for k in TIMED_STAGES:
             if calls[k] > 0:
                 stage_est[k] += ms[k] / calls[k] * launched[k]
         launched_tot += int(launched[6])
@@ -519,14 +534,14 @@ def main():
     value = tot["shift_updates"] / elapsed
     step_ms = elapsed / args.steps * 1e3
 
-    shift_bytes, dslash_bytes = kernel_bytes(w, prec, tot, link_launches, args.moments_in_loop)
+    shift_bytes, dslash_bytes = kernel_bytes(w, prec, tot, link_launches, args.moments_in_loop, blk)
     # working set of the solve: the FP64 shift slots and solutions (or moments) of every
     # (source, node), the seed vectors and the links; above the 256 MB Infinity Cache
     # the streams come from HBM, below it they can stay in the cache
     ws_bytes = w.L * w.N * w.n * 16 * (1 if args.moments_in_loop else 2) + 4 * w.L * w.n * 16 + w.V * 4 * 144
     resident = "hbm" if ws_bytes > MALL_BYTES else "mall"
     rep = {}
-    upd_name = "shift_moments" if args.moments_in_loop else "shift_update"
+    upd_name = ("seed_p_update" if blk else "shift_moments") if args.moments_in_loop else "shift_update"
     for name, idx, b in ((upd_name, 4, shift_bytes), ("dslash", 0, dslash_bytes)):
         calls = int(stage_calls[idx])  # launches timed (every k-th when sampling)
         if calls == 0 or stage_ms[idx] <= 0 or work_launches == 0:
@@ -545,9 +560,30 @@ def main():
                      "launches": launched_tot, "launches_doing_work": work_launches, "launches_timed": calls,
                      "avg_launch_us": round(avg_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": round(per_launch)}
+    if blk:
+        # the sweep: the library counts the algorithmic bytes of every sweep of the
+        # solve (the directions actually read and written, the residuals and moment
+        # sums); divided by the sweeps' time estimated from the sampled ones (every
+        # sweep is timed when the sampling period is at most the block length)
+        calls = int(stage_calls[7])
+        if calls > 0 and stage_ms[7] > 0 and stage_launched[7] > 0:
+            avg_s = stage_ms[7] / 1e3 / calls
+            per_pass = sweep_bytes / stage_launched[7]
+            ach = sweep_bytes / (stage_est[7] / 1e3) / 1e9
+            rep["block_sweep"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(ach / HBM_PEAK_GBS, 4),
+                                  "traffic": pmc_traffic("block_sweep", w.name, mode), "kernel": "block_sweep",
+                                  "kernels": ["blk_compose_kernel", "blk_moments_kernel", "blk_dirs_kernel"],
+                                  "block": blk, "working_set_resident_in": resident,
+                                  "launches": int(stage_launched[7]), "launches_timed": calls,
+                                  "avg_launch_us": round(avg_s * 1e6, 2),
+                                  "algorithmic_bytes_per_launch": round(per_pass)}
+        else:
+            rep["block_sweep"] = None
     per_step = stage_est / args.steps
-    dominant = upd_name if per_step[4] >= per_step[0] else "dslash"
-    stage_split = {STAGES[i]: round(float(per_step[i]), 3) for i in range(6) if i != 3}
+    cands = ([("block_sweep", 7)] if blk else []) + [(upd_name, 4), ("dslash", 0)]
+    dominant = max(cands, key=lambda kv: per_step[kv[1]])[0]
+    stage_split = {STAGES[i]: round(float(per_step[i]), 3) for i in TIMED_STAGES if i != 3}
     matvec_ms = float(per_step[0])
     line = {
         "metric": METRIC,
@@ -567,7 +603,7 @@ def main():
                    "interval": [w.gamma - w.rho, w.gamma + w.rho], "beta": w.beta, "N": w.N, "L": w.L,
                    "M": w.M, "tol": w.tol, "prec": mode,
                    "link_reals": w.link_reals if prec == S.MIXED else 18,
-                   "method": args.method, "moments_in_loop": bool(args.moments_in_loop),
+                   "method": args.method, "moments_in_loop": bool(args.moments_in_loop), "block": blk,
                    "weighted_tol": bool(args.weighted_tol), "parallelism": "single GPU"},
         "roofline": rep[dominant],
         "dslash": rep["dslash"],
@@ -581,6 +617,9 @@ def main():
                                   "the seed dslash (the only product with A in the solve) against the step")},
         "phase_ms_per_step": {k: round(tot[k] * 1e3 / args.steps, 3) for k in ("t_solve", "t_moments", "t_extract")},
         "timing": ("direct launches, HIP events around every launch" if args.sample_every == 1 else
+                   (f"graph replay, HIP event-record nodes around every stage of the last iteration of about "
+                    f"one block in every {args.sample_every} iterations (its launches include the block "
+                    f"sweep); stage times per step = sampled average x launches of the stage") if blk else
                    f"graph replay, HIP event-record nodes around every stage of every {args.sample_every}th "
                    f"iteration (offset {args.sample_every // 2} in each poll interval) and around every "
                    f"reliable update; stage times per step = sampled average x launches of the stage"),

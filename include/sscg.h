@@ -42,10 +42,13 @@
  *            SSCG_XCD, SSCG_CT, SSCG_TBS, SSCG_WBATCH, SSCG_UNROLL, SSCG_NT set,
  *            fixes the shapes (read at sscg_create); with fixed shapes a solve is
  *            bitwise reproducible (the reductions do not depend on the schedule).
- *            SSCG_MOMUB (1, 2 or 4; default 1) sets how many shifts' loads the
- *            in-loop moment update issues together, and SSCG_MOMPF (default 1)
- *            whether it issues the next group's loads before the current group's
- *            stores (read at the start of each solve; same results either way).
+ *            SSCG_BLOCK (0, 4, 8, 16 or 32; default 16) sets the block length B
+ *            of the in-loop moment update (see moments_in_loop; 0 selects the
+ *            per-iteration form); SSCG_MOMUB (1, 2 or 4; default 1) sets how many
+ *            shifts' loads the per-iteration form issues together, and SSCG_MOMPF
+ *            (default 1) whether it issues the next group's loads before the
+ *            current group's stores (all read at the start of each solve; the
+ *            results agree to rounding across them).
  */
 #ifndef SSCG_H
 #define SSCG_H
@@ -209,8 +212,18 @@ typedef struct {
                                times that <= 32, a solve precision of SSCG_FP64
                                or SSCG_MIXED_SHIFTS and 12 V < 2^27 (vectors under
                                2 GiB), else SSCG_EINVAL. The shift directions are
-                               stored in 64-entry chunks per (source, shift). 0:
-                               solutions stored, moments after the solve.           */
+                               stored in 64-entry chunks per (source, shift).
+                               Block form (the default, block length B = 16): the
+                               recurrences of B iterations are composed into one
+                               linear map per shift, p_j(B) = C_j p_j(0) +
+                               sum_m D_jm r(m) with the seed residuals r(m) of the
+                               block (kept in a ring of B vectors per source), and
+                               the moments gain sum_j G_kj p_j(0) + sum_m H_km r(m),
+                               so the directions are read and written once per B
+                               iterations; a block cut short by the iteration limit
+                               is applied after the loop. The poll interval is
+                               rounded up to a multiple of B. 0: solutions stored,
+                               moments after the solve.                             */
   int32_t weighted_tol;     /* 1: shift j stops at tol * m / m_j, where m_j is the
                                largest |w_j zeta_j^k| over the moments (and pairs)
                                it enters and m the largest m_j: every shift's
@@ -313,8 +326,10 @@ int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs);
 /* Per-stage timing of the last solve on this context, from HIP events on the
  * context's stream, in milliseconds summed over the solve; counts in calls.
  * stage: 0 dslash, 1 seed alpha scalars, 2 seed residual update, 3 (not used: the
- * shift scalars are formed inside the shift update), 4 fused shift update, 5 reliable
- * update, 6 whole iteration loop (wall clock; its count is the iterations launched).
+ * shift scalars are formed inside the shift update), 4 fused shift update (block form:
+ * the table of the iteration and the seed direction update), 5 reliable update, 6
+ * whole iteration loop (wall clock; its count is the iterations launched), 7 block
+ * sweep of the block form (composition, moment and direction kernels).
  * Timing is recorded only when enabled with sscg_set_profiling(ctx, level):
  *   level 0  off (the default);
  *   level 1  every launch of the solve loop is bracketed by events, and the loop runs
@@ -322,7 +337,8 @@ int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs);
  *   level k > 1  graph replay stays on, and every stage of the iterations i of each
  *            poll interval with i % k == k / 2 is bracketed by event-record nodes in the
  *            graph, as is every reliable update (stage 5, on the last iteration of an
- *            FP32 chunk). Stage averages are then over that sample, at a small cost
+ *            FP32 chunk); in the block form (length B) the sampled iterations are the
+ *            last of every q-th block, q = max(1, k / B) (so the sweep is timed too). Stage averages are then over that sample, at a small cost
  *            to the loop; sscg_stage_launches gives the launches to scale them by.
  * A level below 0 is SSCG_EINVAL. When timing is on, sscg_apply_A also adds its dslash
  * time to stage 0 (and blocks until it ends). */
@@ -332,6 +348,15 @@ int sscg_stage_times(const sscg_ctx *ctx, double ms[8], int64_t calls[8]);
  * counted whether or not they were timed; stage 6 holds the iterations launched.
  * A stage's time in the solve is ms[k] / calls[k] * launched[k]. */
 int sscg_stage_launches(const sscg_ctx *ctx, int64_t launched[8]);
+/* Algorithmic HBM bytes moved by the block sweeps (stage 7: the moment and direction
+ * kernels of the block form of the in-loop moment update) in the last solve on this
+ * context: per (source, block) the moment kernel reads the directions of the shifts
+ * updated in the block, the block's B residuals and the M moment sums and writes the
+ * sums; the direction kernel (run if a shift is still active) reads the same
+ * directions and the residuals and writes the active directions; 16 bytes per FP64
+ * entry, 8 per FP32 direction entry. 0 for the per-iteration form and stored
+ * solutions. Stage 7 of sscg_stage_times / sscg_stage_launches times the sweeps. */
+int sscg_sweep_bytes(const sscg_ctx *ctx, int64_t *bytes);
 
 #ifdef __cplusplus
 }

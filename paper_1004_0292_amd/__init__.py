@@ -62,7 +62,7 @@ EXPORTS = ["sscg_create", "sscg_destroy", "sscg_last_error", "sscg_global_error"
            "sscg_apply_A", "sscg_apply_A_noalloc", "sscg_default_opts", "sscg_shifted_cg_solve", "sscg_ss_moments",
            "sscg_default_ss_params", "sscg_ss_eigs", "sscg_quad_lines", "sscg_quad_circle",
            "sscg_batch_solve", "sscg_herm_eig", "sscg_set_profiling", "sscg_stage_times",
-           "sscg_stage_launches"]
+           "sscg_stage_launches", "sscg_sweep_bytes"]
 
 _lib = None
 
@@ -103,6 +103,7 @@ def lib() -> C.CDLL:
     L.sscg_set_profiling.argtypes = [vp, i32]
     L.sscg_stage_times.argtypes = [vp, pd, C.POINTER(C.c_int64)]
     L.sscg_stage_launches.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.sscg_sweep_bytes.argtypes = [vp, C.POINTER(C.c_int64)]
     _lib = L
     return L
 
@@ -312,6 +313,14 @@ class Context:
         calls = np.zeros(8, dtype=np.int64)
         lib().sscg_stage_times(self._h, _pd(ms), calls.ctypes.data_as(C.POINTER(C.c_int64)))
         return ms, calls
+
+    def sweep_bytes(self):
+        """Algorithmic HBM bytes of the block sweeps of the last solve (sscg_sweep_bytes)."""
+        b = C.c_int64(0)
+        rc = lib().sscg_sweep_bytes(self._h, C.byref(b))
+        if rc:
+            self._raise(rc)
+        return int(b.value)
 
     def stage_launches(self):
         """Launches of each stage in the last solve (timed or not); index 6 = iterations."""

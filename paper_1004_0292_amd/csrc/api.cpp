@@ -76,6 +76,7 @@ struct sscg_ctx {
   // profiling
   int profiling = 0;  // 0 off, 1 every launch, k > 1 every k-th iteration in graphs
   double stage_ms[ST_N] = {};
+  int64_t sweep_bytes = 0;  // algorithmic HBM bytes of the block sweeps of the last solve
   int64_t stage_calls[ST_N] = {};
   int64_t stage_launched[ST_N] = {};  // launches of each stage in the last solve
   std::vector<hipEvent_t> events;
@@ -276,6 +277,11 @@ int sscg_stage_times(const sscg_ctx *c, double ms[8], int64_t calls[8]) {
     ms[i] = c->stage_ms[i];
     calls[i] = c->stage_calls[i];
   }
+  return SSCG_OK;
+}
+int sscg_sweep_bytes(const sscg_ctx *c, int64_t *bytes) {
+  if (!c || !bytes) return SSCG_EINVAL;
+  *bytes = c->sweep_bytes;
   return SSCG_OK;
 }
 int sscg_stage_launches(const sscg_ctx *c, int64_t launched[8]) {
@@ -788,7 +794,7 @@ static void launch_iteration_tail(const IterPlan &pl, int prec, bool seed32, boo
     launch_seed_p_update(pl.sp, slot, st);
     if (slot == pl.blk - 1) {
       rec.mark(ST_PASS);
-      launch_blk_compose(pl.bc, pl.blk, st);
+      launch_blk_compose(pl.bc, pl.blk, prec, st);
       launch_blk_pass(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, pl.blk, st);
     }
   } else if (pl.nmom_max > 0) {  // FP64 seed in both phases (checked by run_solve)
@@ -1097,9 +1103,10 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   if (o.ru_interval < 1) o.ru_interval = 50;
   sscg_ctx *c0 = P[0].c;
   hipStream_t st = c0->work;
-  // block form of the in-loop moment update: block length 4, 8 or 16 (0: per iteration)
-  const int blk = env_int("SSCG_BLOCK", 0);
-  if (blk != 0 && blk != 4 && blk != 8 && blk != 16) return fail(c0, SSCG_EINVAL, "SSCG_BLOCK must be 0, 4, 8 or 16");
+  // block form of the in-loop moment update: block length 4, 8, 16 or 32 (0: per iteration)
+  const int blk = env_int("SSCG_BLOCK", 16);
+  if (blk != 0 && blk != 4 && blk != 8 && blk != 16 && blk != 32)
+    return fail(c0, SSCG_EINVAL, "SSCG_BLOCK must be 0, 4, 8, 16 or 32");
   for (Prob &p : P) p.blk = p.nmom > 0 ? blk : 0;
   for (Prob &p : P) {
     if (!p.c->have_gauge) return fail(p.c, SSCG_ESTATE, "no gauge field set");
@@ -1279,7 +1286,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   if (pl.blk > 0) {
     // block form: a block cut short by the iteration limit is swept now (after a
     // complete block the history is the identity and the sweep returns at once)
-    launch_blk_compose(pl.bc, pl.blk, st);
+    launch_blk_compose(pl.bc, pl.blk, prec, st);
     launch_blk_pass(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, pl.blk, st);
     if (k % pl.blk != 0) c0->stage_launched[ST_PASS] += 1;
   }
@@ -1299,6 +1306,23 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   for (Prob &p : P) {
     sscg_ctx *c = p.c;
     const int L = p.L, N = p.N;
+    c->sweep_bytes = 0;
+    if (p.blk > 0) {
+      // bytes the sweep kernels moved, from the counts the compose kernel kept: per
+      // (source, block) run of the moment kernel the residuals and the moment sums
+      // read and written, per run of the direction kernel the residuals; per direction
+      // read or written its entries (16 B FP64, 8 B FP32)
+      const BlkLayout lay = blk_layout(L, N, p.blk);
+      unsigned long long cnt[2 * kBlkCnt];
+      HIPCHK(c, hipMemcpy(cnt, (char *)c->momtab.p + lay.cnt, sizeof(cnt), hipMemcpyDeviceToHost));
+      for (int ph = 0; ph < 2; ++ph) {
+        const unsigned long long *k = cnt + ph * kBlkCnt;
+        const int64_t d = ph == 0 ? 16 : 8;
+        const int64_t per_entry = (int64_t)k[0] * (16 * p.blk + 32 * p.nmom) + (int64_t)k[1] * d +
+                                  (int64_t)k[2] * 16 * p.blk + (int64_t)(k[3] + k[4]) * d;
+        c->sweep_bytes += per_entry * c->n;
+      }
+    }
     std::vector<SeedState> seeds(L);
     std::vector<ShiftState> sh((size_t)L * N);
     HIPCHK(c, hipMemcpy(seeds.data(), c->seed.p, L * sizeof(SeedState), hipMemcpyDeviceToHost));

@@ -361,7 +361,7 @@ void launch_shift_moments_tab(const VecBatch &b, int prec, int nmom_max, int ub,
 inline size_t shift_table_bytes(int nsrc, int nshift) {
   return (size_t)nsrc * nshift * (sizeof(ShiftTab) + (size_t)kMomRows * sizeof(double2));
 }
-// Block form (VecJob::ring = B > 0, B in {4, 8, 16}): the table kernel writes the
+// Block form (VecJob::ring = B > 0, B in {4, 8, 16, 32}): the table kernel writes the
 // iteration's record of every (source, shift) into slot s of a history of B records
 // (not-updated records: alpha 0, beta 1, 1/pi 0); after the B-th iteration (and once
 // after the loop) the compose kernel folds the history into one linear map per shift
@@ -374,8 +374,14 @@ inline size_t shift_table_bytes(int nsrc, int nshift) {
 //   d     double2 [nsrc][nshift][B]        D_j(B, m), m = 1..B
 //   h     double2 [nsrc][kMomRows][B]      H_km, m = 1..B (the last is zero)
 //   e     double2 [nsrc][nshift][B]        per-shift terms of H (work area)
-//   any   int32 [nsrc]                     0: no shift of the source moved in the block
-constexpr int kMaxBlk = 16;
+//   any   int32 [nsrc]                     bit 0: a shift of the source moved in the block,
+//                                          bit 1: a shift is still active at its end
+//   cnt   uint64 [2][5]                    sweep counts per direction precision (0 FP64,
+//                                          1 FP32), summed over the solve: moment-kernel
+//                                          (source, block) runs and directions read,
+//                                          direction-kernel runs, directions read and
+//                                          directions written
+constexpr int kMaxBlk = 32;
 struct BlkShift {
   double2 c;       // C_j(B)
   int32_t any;     // updated in at least one iteration of the block (p_j(0) is read)
@@ -383,8 +389,9 @@ struct BlkShift {
   int32_t pad[2];
 };
 struct BlkLayout {
-  size_t hist, g, comp, d, h, e, any, total;
+  size_t hist, g, comp, d, h, e, any, cnt, total;
 };
+constexpr int kBlkCnt = 5;  // counts per precision in the cnt region
 __host__ __device__ inline BlkLayout blk_layout(int nsrc, int nshift, int B) {
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t sn = (size_t)nsrc * nshift;
@@ -396,16 +403,18 @@ __host__ __device__ inline BlkLayout blk_layout(int nsrc, int nshift, int B) {
   o.h = up(o.d + sn * B * sizeof(double2));
   o.e = up(o.h + (size_t)nsrc * kMomRows * B * sizeof(double2));
   o.any = up(o.e + sn * B * sizeof(double2));
-  o.total = up(o.any + (size_t)nsrc * sizeof(int32_t));
+  o.cnt = up(o.any + (size_t)nsrc * sizeof(int32_t));
+  o.total = up(o.cnt + 2 * kBlkCnt * sizeof(unsigned long long));
   return o;
 }
-// history records set to the identity (start of a solve)
+// history records set to the identity and the sweep counts to zero (start of a solve)
 void launch_blk_init(void *tab, int nsrc, int nshift, int B, hipStream_t st);
 // p <- r_{s+1} + beta_k p (the seed direction, every iteration of the block form);
 // job a = residual ring, d = seed p; one source per nblk_vec blocks like the seed passes
 void launch_seed_p_update(const VecBatch &b, int slot, hipStream_t st);
-// compose: one block per source (total_blocks = sources of all jobs); job e = table
-void launch_blk_compose(const VecBatch &b, int B, hipStream_t st);
+// compose: one block per source (total_blocks = sources of all jobs); job e = table;
+// prec: precision of the shift directions (selects the counts it adds to)
+void launch_blk_compose(const VecBatch &b, int B, int prec, hipStream_t st);
 // pass: the in-loop moment kernel's grid; job a = moments, b = shift directions
 // (chunk-blocked), c = residual ring, e = table
 void launch_blk_pass(const VecBatch &b, int prec, int nmom_max, int B, hipStream_t st);

@@ -695,9 +695,10 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_tab_kernel(VecBatch B
 // leaves C, D and the sums unchanged; a source that finished inside the block has
 // identity records for the iterations it did not run.
 
-// History records set to the identity. nrec = nsrc * nshift * B.
-__global__ void blk_init_kernel(ShiftTab *hist, int64_t nrec) {
+// History records set to the identity, sweep counts to zero. nrec = nsrc * nshift * B.
+__global__ void blk_init_kernel(ShiftTab *hist, int64_t nrec, unsigned long long *cnt) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 2 * kBlkCnt) cnt[t] = 0;
   if (t >= nrec) return;
   ShiftTab r;
   r.a = r.ipi = make_double2(0.0, 0.0);
@@ -740,10 +741,11 @@ __global__ __launch_bounds__(kBlock) void seed_p_update_kernel(VecBatch B, int s
 // Composition of a block's records, one block of threads per source: a thread per
 // shift runs the recurrences of C_j, D_j, A_j and E_j over the B records (and resets
 // them), writes C_j, the flags, D_j and G_kj, and leaves E_j in the work area; after a
-// barrier the threads form H_km = sum_j c_kj E_j(m). job: e = table.
+// barrier the threads form H_km = sum_j c_kj E_j(m). A record with upd = 0 is skipped
+// (it is the identity). job: e = table.
 template <int BB>
-__global__ __launch_bounds__(kBlock) void blk_compose_kernel(VecBatch B) {
-  __shared__ int any_sh;
+__global__ __launch_bounds__(kBlock) void blk_compose_kernel(VecBatch B, int prec) {
+  __shared__ int n_any, n_st;
   const int b = blockIdx.x;
   const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
   const int l = b - J.block_begin;
@@ -757,26 +759,30 @@ __global__ __launch_bounds__(kBlock) void blk_compose_kernel(VecBatch B) {
   double2 *H = reinterpret_cast<double2 *>(tb + lay.h) + (size_t)l * kMomRows * BB;
   double2 *E = reinterpret_cast<double2 *>(tb + lay.e) + (size_t)l * N * BB;
   int32_t *anyf = reinterpret_cast<int32_t *>(tb + lay.any);
-  if (threadIdx.x == 0) any_sh = 0;
+  if (threadIdx.x == 0) n_any = n_st = 0;
   __syncthreads();
   const double2 zero = make_double2(0.0, 0.0);
-  int any_t = 0;
+  int any_t = 0, st_t = 0;
   for (int j = threadIdx.x; j < N; j += kBlock) {
-    double2 C = make_double2(1.0, 0.0), A = zero, d[BB], e[BB];  // d[m-1] = D_j(s, m), e[m-1] = E_j(m)
-#pragma unroll
+    // C_j and A_j in registers; the rows D_j(s, .) and E_j(.) are updated in place in
+    // the table (row m - 1 for m = 1..BB: a few L2-resident kilobytes per shift)
+    double2 C = make_double2(1.0, 0.0), A = zero;
+    double2 *d = D + (size_t)j * BB, *e = E + (size_t)j * BB;
     for (int m = 0; m < BB; ++m) d[m] = e[m] = zero;
     int any = 0, frz = 0;
     ShiftTab *h = hist + (size_t)j * BB;
-#pragma unroll
     for (int s = 0; s < BB; ++s) {
       const ShiftTab t = h[s];
-      cfma(A, t.a, C);
-#pragma unroll
-      for (int m = 0; m < s; ++m) cfma(e[m], t.a, d[m]);
-      C = cmul(t.b, C);
-#pragma unroll
-      for (int m = 0; m < s; ++m) d[m] = cmul(t.b, d[m]);
-      d[s] = t.ipi;
+      if (t.upd) {  // a record not updated is the identity
+        cfma(A, t.a, C);
+        for (int m = 0; m < s; ++m) {
+          const double2 dm = d[m];
+          cfma(e[m], t.a, dm);
+          d[m] = cmul(t.b, dm);
+        }
+        C = cmul(t.b, C);
+        d[s] = t.ipi;
+      }
       any |= t.upd;
       frz |= t.pad;
     }
@@ -784,7 +790,6 @@ __global__ __launch_bounds__(kBlock) void blk_compose_kernel(VecBatch B) {
     idr.a = idr.ipi = zero;
     idr.b = make_double2(1.0, 0.0);
     idr.upd = idr.pad = 0;
-#pragma unroll
     for (int s = 0; s < BB; ++s) h[s] = idr;
     BlkShift o;
     o.c = C;
@@ -792,16 +797,13 @@ __global__ __launch_bounds__(kBlock) void blk_compose_kernel(VecBatch B) {
     o.st = any && !frz;
     o.pad[0] = o.pad[1] = 0;
     cs[j] = o;
-#pragma unroll
-    for (int m = 0; m < BB; ++m) {
-      D[(size_t)j * BB + m] = d[m];
-      E[(size_t)j * BB + m] = e[m];
-    }
     for (int k = 0; k < kMomRows; ++k)
       g[(size_t)j * kMomRows + k] = (any && k < J.nmom) ? cmul(J.mcoef[(size_t)k * N + j], A) : zero;
-    any_t |= any;
+    any_t += any;
+    st_t += o.st;
   }
-  if (any_t) any_sh = 1;
+  if (any_t) atomicAdd(&n_any, any_t);
+  if (st_t) atomicAdd(&n_st, st_t);
   __syncthreads();  // (also orders this block's E writes before the reads below)
   for (int t = threadIdx.x; t < kMomRows * BB; t += kBlock) {
     const int k = t / BB, m = t - k * BB;
@@ -810,105 +812,193 @@ __global__ __launch_bounds__(kBlock) void blk_compose_kernel(VecBatch B) {
       for (int j = 0; j < N; ++j) cfma(acc, J.mcoef[(size_t)k * N + j], E[(size_t)j * BB + m]);
     H[t] = acc;
   }
-  if (threadIdx.x == 0) anyf[l] = any_sh;
+  if (threadIdx.x == 0) {
+    anyf[l] = (n_any > 0 ? 1 : 0) | (n_st > 0 ? 2 : 0);
+    // what the two sweep kernels will move for this source (moment kernel: runs if a
+    // shift moved, reads those directions; direction kernel: runs if a shift is still
+    // active, reads the moved directions, writes the active ones)
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(tb + lay.cnt) + prec * kBlkCnt;
+    if (n_any > 0) {
+      atomicAdd(cnt + 0, 1ull);
+      atomicAdd(cnt + 1, (unsigned long long)n_any);
+    }
+    if (n_st > 0) {
+      atomicAdd(cnt + 2, 1ull);
+      atomicAdd(cnt + 3, (unsigned long long)n_any);
+      atomicAdd(cnt + 4, (unsigned long long)n_st);
+    }
+  }
 }
 
-// The block's sweep, one thread per entry of one source (the in-loop kernel's grid
-// and chunk-blocked direction layout): loads the BB residuals r(m) of the block and
-// the MM moment sums, then for every shift reads p_j(0), adds G_kj p_j(0) to the sums
-// and writes p_j(B) = C_j p_j(0) + sum_m D_j(B, m) r(m) (only for shifts still active);
-// finally adds sum_m H_km r(m). The coefficients are read at wavefront-uniform
-// addresses through the constant address space (scalar loads), and the memory
-// operations follow the in-loop kernel's order: moments and residuals first, the next
-// shift's load before this shift's store, the moments written last.
+// The block's sweep, in two kernels over the in-loop kernel's grid (one thread per
+// entry of one source, chunk-blocked directions) that never hold the moment sums and
+// the block's residuals at the same time, so both run with few registers and many
+// wavefronts per SIMD: the moment kernel reads every p_j(0) and the residuals and
+// adds sum_j G_kj p_j(0) + sum_m H_km r(m) to the MM moment sums; the direction kernel
+// then reads every p_j(0) again and writes p_j(B) = C_j p_j(0) + sum_m D_j(B, m) r(m)
+// for the shifts still active. The coefficients are read at wavefront-uniform
+// addresses through the constant address space (scalar loads). Each kernel keeps PD
+// directions in flight per thread: shift j's direction is loaded PD shifts ahead into
+// buffer slot j mod PD, in groups of PD shifts (a static slot per unrolled step, so no
+// register is copied while its load is in flight), the first group peeled so the loop
+// is entered with the memory operations in flight that every later group starts with.
 // job: a = moments, b = shift directions, c = residual ring, e = table.
-template <typename T, int MM, int BB>
-__global__ __launch_bounds__(kMomBlock) void blk_pass_kernel(VecBatch B) {
-  const int b = blockIdx.x;
-  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
-  const int lb = b - J.block_begin;
-  const int l = lb / J.nblk_mom, vb = lb - l * J.nblk_mom;
-  const int N = J.nshift;
-  const BlkLayout lay = blk_layout(J.nsrc, N, BB);
+struct BlkView {
   typedef __attribute__((address_space(4))) const double CDbl;
   typedef __attribute__((address_space(4))) const int32_t CInt;
-  const uintptr_t tb = reinterpret_cast<uintptr_t>(J.e);
-  CInt *anyf = reinterpret_cast<CInt *>(tb + lay.any);
-  if (anyf[l] == 0) return;  // uniform over the block
-  constexpr int kCsD = sizeof(BlkShift) / sizeof(double), kCsI = sizeof(BlkShift) / sizeof(int32_t);
-  constexpr int kAnyI = offsetof(BlkShift, any) / sizeof(int32_t), kStI = offsetof(BlkShift, st) / sizeof(int32_t);
-  CDbl *csd = reinterpret_cast<CDbl *>(tb + lay.comp) + (size_t)l * N * kCsD;
-  CInt *csi = reinterpret_cast<CInt *>(tb + lay.comp) + (size_t)l * N * kCsI;
-  CDbl *Dt = reinterpret_cast<CDbl *>(tb + lay.d) + (size_t)l * N * BB * 2;
-  CDbl *gtab = reinterpret_cast<CDbl *>(tb + lay.g) + (size_t)l * N * kMomRows * 2;
-  CDbl *Ht = reinterpret_cast<CDbl *>(tb + lay.h) + (size_t)l * kMomRows * BB * 2;
-  const int64_t n = J.n;
-  const int64_t nch = (n + 63) / 64;
-  const int64_t i = (int64_t)vb * kMomBlock + threadIdx.x;
-  const bool valid = i < n;
-  const int64_t ii = valid ? i : 0;  // invalid lanes read entry 0 and store nothing
-  const int64_t c = i >> 6;
-  const int q = (int)(i & 63);
+  static constexpr int kCsD = sizeof(BlkShift) / sizeof(double), kCsI = sizeof(BlkShift) / sizeof(int32_t);
+  static constexpr int kAnyI = offsetof(BlkShift, any) / sizeof(int32_t);
+  static constexpr int kStI = offsetof(BlkShift, st) / sizeof(int32_t);
+  CInt *anyf, *csi;
+  CDbl *csd, *Dt, *gtab, *Ht;
+  __device__ BlkView(const VecJob &J, int l, int BB) {
+    const BlkLayout lay = blk_layout(J.nsrc, J.nshift, BB);
+    const uintptr_t tb = reinterpret_cast<uintptr_t>(J.e);
+    const int N = J.nshift;
+    anyf = reinterpret_cast<CInt *>(tb + lay.any);
+    csd = reinterpret_cast<CDbl *>(tb + lay.comp) + (size_t)l * N * kCsD;
+    csi = reinterpret_cast<CInt *>(tb + lay.comp) + (size_t)l * N * kCsI;
+    Dt = reinterpret_cast<CDbl *>(tb + lay.d) + (size_t)l * N * BB * 2;
+    gtab = reinterpret_cast<CDbl *>(tb + lay.g) + (size_t)l * N * kMomRows * 2;
+    Ht = reinterpret_cast<CDbl *>(tb + lay.h) + (size_t)l * kMomRows * BB * 2;
+  }
+  __device__ bool any(int j) const { return csi[(size_t)j * kCsI + kAnyI] != 0; }
+  __device__ bool st(int j) const { return csi[(size_t)j * kCsI + kStI] != 0; }
+};
+
+// Thread geometry of the sweep kernels.
+struct BlkLane {
+  int l;          // source
+  int64_t i;      // entry
+  bool valid;     // i < n
+  int64_t ii;     // entry read by the thread (0 for invalid lanes, which store nothing)
+  int64_t c;      // chunk of the wavefront
+  int q;          // place in the chunk
+  __device__ BlkLane(const VecJob &J, int lb) {
+    l = lb / J.nblk_mom;
+    const int vb = lb - l * J.nblk_mom;
+    i = (int64_t)vb * kMomBlock + threadIdx.x;
+    valid = i < J.n;
+    ii = valid ? i : 0;
+    c = (int64_t)vb * (kMomBlock / 64) + uni(threadIdx.x >> 6);  // i >> 6, in a scalar register
+    q = (int)(i & 63);
+  }
+};
+
+template <typename T, int MM, int BB, int PD>
+__global__ __launch_bounds__(kMomBlock) void blk_moments_kernel(VecBatch B) {
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const BlkLane t(J, b - J.block_begin);
+  const int l = t.l, N = J.nshift;
+  const BlkView v(J, l, BB);
+  if ((v.anyf[l] & 1) == 0) return;  // no shift of the source moved in the block
+  const int64_t n = J.n, nch = (n + 63) / 64;
   const double2 *Sm = reinterpret_cast<const double2 *>(J.a);
   const int M = J.nmom;
-  const int voff16 = valid ? (int)(i * 16) : 0x7fffffff;
+  const int voff16 = t.valid ? (int)(t.i * 16) : 0x7fffffff;
   auto mom_rsrc = [&](int k) { return make_rsrc(Sm + ((size_t)k * J.nsrc + l) * n, k < M ? (int)(n * 16) : 0); };
   double2 acc[MM];
 #pragma unroll
   for (int k = 0; k < MM; ++k) acc[k] = BufIO<double, 2>::ld(mom_rsrc(k), voff16, 0);
-  const double2 *ring = reinterpret_cast<const double2 *>(J.c);
-  double2 rv[BB];
-#pragma unroll
-  for (int m = 0; m < BB; ++m) rv[m] = ring[((size_t)m * J.nsrc + l) * n + ii];
   constexpr int kW = sizeof(V2<T>);
-  const int voff = valid ? q * kW : 0x7fffffff;
+  const int voff = t.valid ? t.q * kW : 0x7fffffff;
   const double2 *W = reinterpret_cast<const double2 *>(J.b);
-  auto run_rsrc = [&](int j, bool on) { return make_rsrc(W + blk_chunk(l, c, j, nch, N), on ? 64 * kW : 0); };
-  auto fetch = [&](int j, double2 &v, bool &f) {
-    f = j < N && csi[(size_t)j * kCsI + kAnyI] != 0;
-    const V2<T> x = BufIO<T, 2>::ld(run_rsrc(j, f), voff, 0);
-    v = make_double2(x.x, x.y);
+  auto fetch = [&](int j, double2 &x, bool &f) {
+    f = j < N && v.any(j);
+    const V2<T> y = BufIO<T, 2>::ld(make_rsrc(W + blk_chunk(l, t.c, j, nch, N), f ? 64 * kW : 0), voff, 0);
+    x = make_double2(y.x, y.y);
   };
-  double2 nv;
-  bool nup;
-  fetch(0, nv, nup);
-  for (int j = 0; j < N; ++j) {
-    const double2 pv = nv;
-    const bool up = nup;
-    if (j + 1 < N) fetch(j + 1, nv, nup);
-    if (up) {  // uniform
-      CDbl *gj = gtab + (size_t)j * kMomRows * 2;
+  double2 buf[PD];
+  bool bup[PD];
 #pragma unroll
-      for (int k0 = 0; k0 < MM; k0 += 8) {
-        double gx[8], gy[8];
+  for (int u = 0; u < PD; ++u) fetch(u, buf[u], bup[u]);
+  auto group = [&](int j0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          gx[e] = gj[2 * (k0 + e)];
-          gy[e] = gj[2 * (k0 + e) + 1];
+    for (int u = 0; u < PD; ++u) {
+      const int j = j0 + u;
+      const double2 pv = buf[u];
+      if (bup[u]) {  // uniform
+        BlkView::CDbl *gj = v.gtab + (size_t)j * kMomRows * 2;
+#pragma unroll
+        for (int k0 = 0; k0 < MM; k0 += 8) {
+          double gx[8], gy[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            gx[e] = gj[2 * (k0 + e)];
+            gy[e] = gj[2 * (k0 + e) + 1];
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e) cfma(acc[k0 + e], make_double2(gx[e], gy[e]), pv);
         }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) cfma(acc[k0 + e], make_double2(gx[e], gy[e]), pv);
       }
+      fetch(j + PD, buf[u], bup[u]);
+      // keeps the refill here (the scheduler would otherwise gather the group's loads
+      // at its end, leaving none in flight while the next group starts)
+      __builtin_amdgcn_sched_barrier(0);
     }
-    const bool stj = up && csi[(size_t)j * kCsI + kStI] != 0;
-    CDbl *cj = csd + (size_t)j * kCsD;
-    CDbl *dj = Dt + (size_t)j * BB * 2;
-    double2 pn = cmul(make_double2(cj[0], cj[1]), pv);
+  };
+  group(0);
+  for (int j0 = PD; j0 < N; j0 += PD) group(j0);
+  // residual terms, one residual at a time
+  const double2 *ring = reinterpret_cast<const double2 *>(J.c);
+  for (int m = 0; m < BB; ++m) {
+    const double2 r = ring[((size_t)m * J.nsrc + l) * n + t.ii];
+    BlkView::CDbl *hm = v.Ht + 2 * m;
 #pragma unroll
-    for (int m = 0; m < BB; ++m) cfma(pn, make_double2(dj[2 * m], dj[2 * m + 1]), rv[m]);
-    V2<T> x;
-    x.x = pn.x;
-    x.y = pn.y;
-    BufIO<T, 2>::st(x, run_rsrc(j, stj), voff, 0);
-  }
-#pragma unroll
-  for (int k = 0; k < MM; ++k) {
-    CDbl *hk = Ht + (size_t)k * BB * 2;
-#pragma unroll
-    for (int m = 0; m < BB; ++m) cfma(acc[k], make_double2(hk[2 * m], hk[2 * m + 1]), rv[m]);
+    for (int k = 0; k < MM; ++k) cfma(acc[k], make_double2(hm[2 * BB * k], hm[2 * BB * k + 1]), r);
   }
 #pragma unroll
   for (int k = 0; k < MM; ++k) BufIO<double, 2>::st(acc[k], mom_rsrc(k), voff16, 0);
+}
+
+template <typename T, int BB, int PD>
+__global__ __launch_bounds__(kMomBlock) void blk_dirs_kernel(VecBatch B) {
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const BlkLane t(J, b - J.block_begin);
+  const int l = t.l, N = J.nshift;
+  const BlkView v(J, l, BB);
+  if ((v.anyf[l] & 2) == 0) return;  // every shift of the source froze (or none moved)
+  const int64_t n = J.n, nch = (n + 63) / 64;
+  const double2 *ring = reinterpret_cast<const double2 *>(J.c);
+  double2 rv[BB];
+#pragma unroll
+  for (int m = 0; m < BB; ++m) rv[m] = ring[((size_t)m * J.nsrc + l) * n + t.ii];
+  constexpr int kW = sizeof(V2<T>);
+  const int voff = t.valid ? t.q * kW : 0x7fffffff;
+  const double2 *W = reinterpret_cast<const double2 *>(J.b);
+  auto run_rsrc = [&](int j, bool on) { return make_rsrc(W + blk_chunk(l, t.c, j, nch, N), on ? 64 * kW : 0); };
+  auto fetch = [&](int j, double2 &x, bool &f) {
+    f = j < N && v.any(j);
+    const V2<T> y = BufIO<T, 2>::ld(run_rsrc(j, f), voff, 0);
+    x = make_double2(y.x, y.y);
+  };
+  double2 buf[PD];
+  bool bup[PD];
+#pragma unroll
+  for (int u = 0; u < PD; ++u) fetch(u, buf[u], bup[u]);
+  auto group = [&](int j0) {
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      const int j = j0 + u;
+      const int jj = min(j, N - 1);  // coefficients of a shift past the last are not used
+      const double2 pv = buf[u];
+      const bool stj = bup[u] && v.st(jj);
+      BlkView::CDbl *cj = v.csd + (size_t)jj * BlkView::kCsD;
+      BlkView::CDbl *dj = v.Dt + (size_t)jj * BB * 2;
+      double2 pn = cmul(make_double2(cj[0], cj[1]), pv);
+#pragma unroll
+      for (int m = 0; m < BB; ++m) cfma(pn, make_double2(dj[2 * m], dj[2 * m + 1]), rv[m]);
+      V2<T> x;
+      x.x = pn.x;
+      x.y = pn.y;
+      BufIO<T, 2>::st(x, run_rsrc(jj, stj), voff, 0);
+      fetch(j + PD, buf[u], bup[u]);
+    }
+  };
+  group(0);
+  for (int j0 = PD; j0 < N; j0 += PD) group(j0);
 }
 
 // Start of an in-loop solve: p_j = v_l in the chunk-blocked layout (padding zero).
@@ -1213,34 +1303,49 @@ void launch_to_fp32(const void *src64, void *dst32, void *zero32, int64_t n, hip
 void launch_blk_init(void *tab, int nsrc, int nshift, int B, hipStream_t st) {
   const int64_t nrec = (int64_t)nsrc * nshift * B;
   if (nrec <= 0) return;
-  hipLaunchKernelGGL(blk_init_kernel, dim3(nblocks1d(nrec)), dim3(kBlock), 0, st,
-                     reinterpret_cast<ShiftTab *>(reinterpret_cast<char *>(tab) + blk_layout(nsrc, nshift, B).hist),
-                     nrec);
+  const BlkLayout lay = blk_layout(nsrc, nshift, B);
+  char *tb = reinterpret_cast<char *>(tab);
+  hipLaunchKernelGGL(blk_init_kernel, dim3(nblocks1d(std::max<int64_t>(nrec, 2 * kBlkCnt))), dim3(kBlock), 0, st,
+                     reinterpret_cast<ShiftTab *>(tb + lay.hist), nrec,
+                     reinterpret_cast<unsigned long long *>(tb + lay.cnt));
 }
 void launch_seed_p_update(const VecBatch &b, int slot, hipStream_t st) {
   if (b.total_blocks <= 0) return;
   hipLaunchKernelGGL(seed_p_update_kernel, dim3(b.total_blocks), dim3(kBlock), 0, st, b, slot);
 }
-void launch_blk_compose(const VecBatch &b, int B, hipStream_t st) {
+void launch_blk_compose(const VecBatch &b, int B, int prec, hipStream_t st) {
   if (b.total_blocks <= 0) return;
   const dim3 g(b.total_blocks), t(kBlock);
-  if (B == 4) hipLaunchKernelGGL(blk_compose_kernel<4>, g, t, 0, st, b);
-  else if (B == 8) hipLaunchKernelGGL(blk_compose_kernel<8>, g, t, 0, st, b);
-  else hipLaunchKernelGGL(blk_compose_kernel<16>, g, t, 0, st, b);
+  const int ph = prec == 0 ? 0 : 1;
+  if (B == 4) hipLaunchKernelGGL(blk_compose_kernel<4>, g, t, 0, st, b, ph);
+  else if (B == 8) hipLaunchKernelGGL(blk_compose_kernel<8>, g, t, 0, st, b, ph);
+  else if (B == 16) hipLaunchKernelGGL(blk_compose_kernel<16>, g, t, 0, st, b, ph);
+  else hipLaunchKernelGGL(blk_compose_kernel<32>, g, t, 0, st, b, ph);
 }
+constexpr int kBlkPD = 4;  // shift directions in flight per thread of the sweep kernels
 template <typename T, int MM>
-static void launch_bp_b(const VecBatch &b, int B, hipStream_t st) {
+static void launch_bm(const VecBatch &b, int B, hipStream_t st) {
   const dim3 g(b.total_blocks), t(kMomBlock);
-  if (B == 4) hipLaunchKernelGGL((blk_pass_kernel<T, MM, 4>), g, t, 0, st, b);
-  else if (B == 8) hipLaunchKernelGGL((blk_pass_kernel<T, MM, 8>), g, t, 0, st, b);
-  else hipLaunchKernelGGL((blk_pass_kernel<T, MM, 16>), g, t, 0, st, b);
+  if (B == 4) hipLaunchKernelGGL((blk_moments_kernel<T, MM, 4, kBlkPD>), g, t, 0, st, b);
+  else if (B == 8) hipLaunchKernelGGL((blk_moments_kernel<T, MM, 8, kBlkPD>), g, t, 0, st, b);
+  else if (B == 16) hipLaunchKernelGGL((blk_moments_kernel<T, MM, 16, kBlkPD>), g, t, 0, st, b);
+  else hipLaunchKernelGGL((blk_moments_kernel<T, MM, 32, kBlkPD>), g, t, 0, st, b);
+}
+template <typename T>
+static void launch_bd(const VecBatch &b, int B, hipStream_t st) {
+  const dim3 g(b.total_blocks), t(kMomBlock);
+  if (B == 4) hipLaunchKernelGGL((blk_dirs_kernel<T, 4, kBlkPD>), g, t, 0, st, b);
+  else if (B == 8) hipLaunchKernelGGL((blk_dirs_kernel<T, 8, kBlkPD>), g, t, 0, st, b);
+  else if (B == 16) hipLaunchKernelGGL((blk_dirs_kernel<T, 16, kBlkPD>), g, t, 0, st, b);
+  else hipLaunchKernelGGL((blk_dirs_kernel<T, 32, kBlkPD>), g, t, 0, st, b);
 }
 template <typename T>
 static void launch_bp(const VecBatch &b, int mm, int B, hipStream_t st) {
-  if (mm <= 8) launch_bp_b<T, 8>(b, B, st);
-  else if (mm <= 16) launch_bp_b<T, 16>(b, B, st);
-  else if (mm <= 24) launch_bp_b<T, 24>(b, B, st);
-  else launch_bp_b<T, 32>(b, B, st);
+  if (mm <= 8) launch_bm<T, 8>(b, B, st);
+  else if (mm <= 16) launch_bm<T, 16>(b, B, st);
+  else if (mm <= 24) launch_bm<T, 24>(b, B, st);
+  else launch_bm<T, 32>(b, B, st);
+  launch_bd<T>(b, B, st);
 }
 void launch_blk_pass(const VecBatch &b, int prec, int nmom_max, int B, hipStream_t st) {
   if (b.total_blocks <= 0) return;

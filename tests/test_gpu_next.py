@@ -118,13 +118,15 @@ def test_moments_in_loop(sscg, f4, monkeypatch, prec, P, pf, ub):
     update kernel runs with ub shifts per load group, with (pf = 1) or without the next
     group's loads issued ahead of the current group's stores."""
     case(f"in-loop moments {prec} P={P} pf={pf} ub={ub}")
+    monkeypatch.setenv("SSCG_BLOCK", "0")  # the per-iteration form (pf and ub apply to it)
     monkeypatch.setenv("SSCG_MOMPF", str(pf))
     monkeypatch.setenv("SSCG_MOMUB", str(ub))
     _in_loop_vs_stored(sscg, f4, prec, P)
 
 
-@pytest.mark.parametrize("prec,P,blk", [("fp64", 1, 4), ("fp64", 1, 8), ("fp64", 1, 16), ("mixed_shifts", 1, 8),
-                                        ("fp64", 3, 8), ("mixed_shifts", 3, 16)])
+@pytest.mark.parametrize("prec,P,blk", [("fp64", 1, 4), ("fp64", 1, 8), ("fp64", 1, 16), ("fp64", 1, 32),
+                                        ("mixed_shifts", 1, 8), ("mixed_shifts", 1, 32), ("fp64", 3, 8),
+                                        ("mixed_shifts", 3, 16)])
 def test_moments_in_loop_block(sscg, f4, monkeypatch, prec, P, blk):
     """Block form of the in-loop update (the recurrences of blk iterations composed
     into one linear map per shift and applied in one sweep over the directions, the
@@ -135,7 +137,7 @@ def test_moments_in_loop_block(sscg, f4, monkeypatch, prec, P, blk):
     _in_loop_vs_stored(sscg, f4, prec, P)
 
 
-@pytest.mark.parametrize("blk", [8, 16])
+@pytest.mark.parametrize("blk", [8, 16, 32])
 def test_moments_in_loop_block_cut_short(sscg, f4, monkeypatch, blk):
     """A solve stopped by the iteration limit (37, inside a block) in the block form:
     the sweep after the loop applies the partial block, so the moments, and the
