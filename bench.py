@@ -211,7 +211,8 @@ WINDOWS = {"wilson8_fp64": dict(lo=0.3700, hi=0.3735, beta=0.5, N=32, M=8, L=4),
            # one eigenvalue (0.3454946 in the oracle's reference spectrum); SSCG_MIXED
            # is left out at this size (its FP32 seed does not converge here)
            "wilson24x48": dict(lo=0.3450, hi=0.3457, beta=0.5, N=32, M=8, L=2,
-                               modes=("fp64", "mixed_shifts", "fp64_hankel"))}
+                               modes=("fp64", "mixed_shifts", "fp64_inloop", "mixed_shifts_inloop",
+                                      "fp64_hankel"))}
 
 
 def reference_spectrum(name):
@@ -247,10 +248,12 @@ def tts_window(S, ctx, w, vd_all, steps):
     lams = {}
     ext = {}
     for name in win.get("modes", ("fp64", "mixed_shifts", "mixed", "fp64_hankel")):
-        opts = S.default_opts(tol=w.tol, prec=PRECS[name.replace("_hankel", "")], ru_interval=w.ru_interval,
-                              switch_tol=w.switch_tol)
+        # "_inloop": moments summed inside the solve (block form); otherwise stored solutions
+        base = name.replace("_hankel", "").replace("_inloop", "")
+        opts = S.default_opts(tol=w.tol, prec=PRECS[base], ru_interval=w.ru_interval, switch_tol=w.switch_tol)
         p = S.default_ss_params(gamma=gamma, rho=rho, beta=win["beta"], N=win["N"], M=win["M"], rank_tol=1e-7,
-                                spur_tol=1e-6, solve=opts, method=S.HANKEL if name.endswith("hankel") else S.RR)
+                                spur_tol=1e-6, solve=opts, method=S.HANKEL if name.endswith("hankel") else S.RR,
+                                moments_in_loop=int(name.endswith("_inloop")))
         dt, r = solve_steps(S, ctx, p, vd, 32, steps)
         s = mode_summary(r, dt * 1e3, win["L"])
         if truth is not None and len(r.lam) == len(truth) and len(truth):
@@ -265,8 +268,8 @@ def tts_window(S, ctx, w, vd_all, steps):
             continue
         out[name] = s
     a = lams["fp64"]
-    for name in ("mixed_shifts", "mixed"):
-        if name not in lams:
+    for name in lams:
+        if name in ("fp64", "fp64_hankel"):
             continue
         b = lams[name]
         out[name]["max_rel_eig_diff_vs_fp64"] = (float(np.max(np.abs(a - b) / np.abs(a)))

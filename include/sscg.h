@@ -344,9 +344,13 @@ int sscg_herm_eig(int32_t n, const double *A, double *evals, double *evecs);
  * time to stage 0 (and blocks until it ends). */
 int sscg_set_profiling(sscg_ctx *ctx, int32_t level);
 int sscg_stage_times(const sscg_ctx *ctx, double ms[8], int64_t calls[8]);
-/* Launches of each stage (indices as above) in the last solve on this context,
- * counted whether or not they were timed; stage 6 holds the iterations launched.
- * A stage's time in the solve is ms[k] / calls[k] * launched[k]. */
+/* Launches of each stage (indices as above) in the last solve on this context that did
+ * work, counted whether or not they were timed: those of the iterations in which a
+ * source still iterated (stage 7: the sweeps of blocks holding such iterations); the
+ * launches after the last source finished (up to the next poll) exit at once, and
+ * timing samples taken there are not counted in sscg_stage_times either. Stage 6 holds
+ * the iterations launched. A stage's time in the solve is ms[k] / calls[k] *
+ * launched[k]. */
 int sscg_stage_launches(const sscg_ctx *ctx, int64_t launched[8]);
 /* Algorithmic HBM bytes moved by the block sweeps (stage 7: the moment and direction
  * kernels of the block form of the in-loop moment update) in the last solve on this

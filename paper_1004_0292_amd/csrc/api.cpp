@@ -89,6 +89,7 @@ struct sscg_ctx {
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> ev;  // timing marks recorded by the graph (profiling)
     std::vector<int> stages;
+    std::vector<int> its;        // iteration (in the chunk) of each timing mark
     bool timed = false;
   } graphs[2];
 };
@@ -640,7 +641,8 @@ static void build_plan(std::vector<Prob> &P, IterPlan &pl, const sscg_solve_opts
       const int nbm = (int)((c->n + kMomBlock - 1) / kMomBlock);
       for (VecBatch *mb : {&pl.m64, &pl.m32}) {
         VecJob &j = mb->job[i];
-        mk_v(j, P[i].mom, c->W.p, pl.blk > 0 ? c->ring.p : c->r64.p, c->p64.p, bm, L * nbm);
+        mk_v(j, P[i].mom, c->W.p, pl.blk > 0 ? c->ring.p : c->r64.p, pl.blk > 0 ? c->v64.p : c->p64.p, bm,
+             L * nbm);
         j.e = c->momtab.p;
         j.ring = pl.blk;
         j.mcoef = (const double2 *)P[i].mom_coef;
@@ -701,6 +703,8 @@ struct Recorder {
   std::vector<int> stages;
   std::vector<hipEvent_t> *evs;  // event pool (nullptr: the context's)
   bool in_graph = false;
+  std::vector<int> its;  // iteration (in the chunk) of each mark
+  int cur_it = 0;        // iteration the next marks belong to
   std::vector<hipEvent_t> &pool() { return evs ? *evs : c->events; }
   // event-record node appended to the capture by hand (after the nodes captured so
   // far; the next captured launch depends on it)
@@ -739,13 +743,18 @@ struct Recorder {
       return;
     }
     stages.push_back(stage);
+    its.push_back(cur_it);
   }
   // intervals between consecutive recorded events (all complete) -> stage totals;
-  // an interval that starts at a stop mark (-1) is not counted
-  void account() {
+  // an interval that starts at a stop mark (-1) is not counted, nor one of an
+  // iteration k0 + it at or after kend (no source iterated any more: its launches
+  // exit at once), nor a block sweep whose whole block lies there (blk: block length)
+  void account(int64_t k0 = 0, int64_t kend = INT64_MAX, int blk = 0) {
     std::vector<hipEvent_t> &ev = pool();
     for (size_t k = 0; k + 1 < stages.size(); ++k) {
       if (stages[k] < 0) continue;
+      const int64_t g = k0 + (k < its.size() ? its[k] : 0);
+      if (stages[k] == ST_PASS ? g - blk + 1 >= kend : g >= kend) continue;
       float ms = 0.f;
       const hipError_t r = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
       if (r != hipSuccess) {
@@ -758,12 +767,13 @@ struct Recorder {
       c->stage_calls[stages[k]] += 1;
     }
   }
-  void flush() {
+  void flush(int64_t k0 = 0, int64_t kend = INT64_MAX, int blk = 0) {
     if (!on || stages.empty()) return;
     mark(-1);
     hipEventSynchronize(pool()[stages.size() - 1]);
-    account();
+    account(k0, kend, blk);
     stages.clear();
+    its.clear();
   }
 };
 
@@ -828,12 +838,14 @@ static void launch_iteration(const IterPlan &pl, int prec, bool seed32, bool ru,
     const bool smp = pl.blk > 0 ? (slot == pl.blk - 1 && (it / pl.blk) % q == q / 2) : it % every == every / 2;
     Recorder off{rec.c, st, false, {}, nullptr};
     Recorder &r = smp ? rec : off;
+    rec.cur_it = it;
     r.mark(ST_DSLASH);
     launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, pl.ct, st);
     launch_iteration_tail(pl, prec, seed32, ru, lr, t, st, r, smp ? nullptr : &rec, slot);
     r.mark(-1);
     return;
   }
+  rec.cur_it = it;
   rec.mark(ST_DSLASH);
   launch_dslash(sp == 0 ? pl.d64 : pl.d32, sp, t.nr, sp == 0 ? 18 : lr, t.bs, t.xcd, pl.ct, st);
   launch_iteration_tail(pl, prec, seed32, ru, lr, t, st, rec, nullptr, slot);
@@ -889,7 +901,7 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
                              hipMemcpyDeviceToDevice, st));
     launch_blk_init(c->momtab.p, (int)L, (int)N, p.blk, st);
   }
-  if (p.nmom > 0)
+  if (p.nmom > 0 && p.blk == 0)  // (the block form's first sweep reads v itself)
     launch_init_shifts_blocked(c->W.p, c->v64.p, (int64_t)n, (int)L, (int)N, st);
   else
     launch_init_shifts(p.y, c->W.p, c->v64.p, (int64_t)n, (int)L, (int)N, st);
@@ -1176,6 +1188,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       grec[prec].on = cg.timed;
       grec[prec].in_graph = true;
       grec[prec].stages = cg.stages;
+      grec[prec].its = cg.its;
       return SSCG_OK;
     }
     if (cg.exec) hipGraphExecDestroy(cg.exec);
@@ -1186,6 +1199,7 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     cap.on = c0->profiling > 0;
     cap.in_graph = true;
     cap.stages.clear();
+    cap.its.clear();
     // events exist before capture; they only time, so they skip the system-scope
     // release (cache write-back) an event normally carries, which shortens the node
     while (cap.on && cg.ev.size() < (size_t)len * (ST_N + 1) + 1) {
@@ -1210,10 +1224,12 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     }
     cg.key = key;
     cg.stages = cap.stages;
+    cg.its = cap.its;
     cg.timed = cap.on;
     return SSCG_OK;
   };
   bool ready[2] = {false, false};  // graph of this phase checked against this solve
+  int64_t kwork = 0;                // iterations in which a source still iterated
   auto t0 = std::chrono::steady_clock::now();
   int prec = 0;
   int k = 0;
@@ -1261,8 +1277,12 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
       rc = fail(c0, SSCG_EDEVICE, std::string("solve loop: ") + hipGetErrorString(e));
       break;
     }
-    rec.flush();
-    if (use_graph && full && grec[prec].on) grec[prec].account();
+    // iterations up to which a source still iterated: timing samples beyond are not
+    // counted (their launches exit at once)
+    for (Prob &p : P)
+      for (int l = 0; l < p.L; ++l) kwork = std::max<int64_t>(kwork, p.c->seed_host[l].iters);
+    rec.flush(k - chunk, kwork, pl.blk);
+    if (use_graph && full && grec[prec].on) grec[prec].account(k - chunk, kwork, pl.blk);
     for (Prob &p : P)
       for (int l = 0; l < p.L; ++l) {
         const SeedState &s = p.c->seed_host[l];
@@ -1283,12 +1303,18 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
     }
   }
   if (rc != SSCG_OK) return rc;
+  // launches that did work: the per-iteration stages of the iterations in which a source
+  // still iterated, the sweeps of blocks holding such iterations
+  {
+    int64_t *n = c0->stage_launched;
+    for (int s : {(int)ST_DSLASH, (int)ST_ALPHA, (int)ST_RUPD, (int)ST_SHIFT}) n[s] = std::min<int64_t>(n[s], kwork);
+    if (pl.blk > 0) n[ST_PASS] = (kwork + pl.blk - 1) / pl.blk;
+  }
   if (pl.blk > 0) {
     // block form: a block cut short by the iteration limit is swept now (after a
     // complete block the history is the identity and the sweep returns at once)
     launch_blk_compose(pl.bc, pl.blk, prec, st);
     launch_blk_pass(prec == 0 ? pl.m64 : pl.m32, prec, pl.nmom_max, pl.blk, st);
-    if (k % pl.blk != 0) c0->stage_launched[ST_PASS] += 1;
   }
   launch_commit(pl.d64, st);  // (every chunk ends with a commit; kept for a loop left early)
   if (prec == 1) {

@@ -375,7 +375,10 @@ inline size_t shift_table_bytes(int nsrc, int nshift) {
 //   h     double2 [nsrc][kMomRows][B]      H_km, m = 1..B (the last is zero)
 //   e     double2 [nsrc][nshift][B]        per-shift terms of H (work area)
 //   any   int32 [nsrc]                     bit 0: a shift of the source moved in the block,
-//                                          bit 1: a shift is still active at its end
+//                                          bit 1: a shift is still active at its end,
+//                                          bit 2: the block is the source's first (every
+//                                          p_j(0) is v, read from v itself)
+//   fresh int32 [nsrc]                     1 until the first block's composition
 //   cnt   uint64 [2][5]                    sweep counts per direction precision (0 FP64,
 //                                          1 FP32), summed over the solve: moment-kernel
 //                                          (source, block) runs and directions read,
@@ -389,7 +392,7 @@ struct BlkShift {
   int32_t pad[2];
 };
 struct BlkLayout {
-  size_t hist, g, comp, d, h, e, any, cnt, total;
+  size_t hist, g, comp, d, h, e, any, fresh, cnt, total;
 };
 constexpr int kBlkCnt = 5;  // counts per precision in the cnt region
 __host__ __device__ inline BlkLayout blk_layout(int nsrc, int nshift, int B) {
@@ -403,11 +406,14 @@ __host__ __device__ inline BlkLayout blk_layout(int nsrc, int nshift, int B) {
   o.h = up(o.d + sn * B * sizeof(double2));
   o.e = up(o.h + (size_t)nsrc * kMomRows * B * sizeof(double2));
   o.any = up(o.e + sn * B * sizeof(double2));
-  o.cnt = up(o.any + (size_t)nsrc * sizeof(int32_t));
+  o.fresh = up(o.any + (size_t)nsrc * sizeof(int32_t));
+  o.cnt = up(o.fresh + (size_t)nsrc * sizeof(int32_t));
   o.total = up(o.cnt + 2 * kBlkCnt * sizeof(unsigned long long));
   return o;
 }
-// history records set to the identity and the sweep counts to zero (start of a solve)
+// history records set to the identity, every source marked fresh, the sweep counts
+// zero (start of a solve; the shift directions are not written: a source's first
+// sweep reads v instead)
 void launch_blk_init(void *tab, int nsrc, int nshift, int B, hipStream_t st);
 // p <- r_{s+1} + beta_k p (the seed direction, every iteration of the block form);
 // job a = residual ring, d = seed p; one source per nblk_vec blocks like the seed passes
@@ -416,7 +422,7 @@ void launch_seed_p_update(const VecBatch &b, int slot, hipStream_t st);
 // prec: precision of the shift directions (selects the counts it adds to)
 void launch_blk_compose(const VecBatch &b, int B, int prec, hipStream_t st);
 // pass: the in-loop moment kernel's grid; job a = moments, b = shift directions
-// (chunk-blocked), c = residual ring, e = table
+// (chunk-blocked), c = residual ring, d = the sources v (planar FP64), e = table
 void launch_blk_pass(const VecBatch &b, int prec, int nmom_max, int B, hipStream_t st);
 void launch_fold_seed(const VecBatch &b, hipStream_t st);
 void launch_fold_shifts(void *y, void *W, int64_t n, int nslots, hipStream_t st);

@@ -695,10 +695,12 @@ __global__ __launch_bounds__(kMomBlock) void shift_moments_tab_kernel(VecBatch B
 // leaves C, D and the sums unchanged; a source that finished inside the block has
 // identity records for the iterations it did not run.
 
-// History records set to the identity, sweep counts to zero. nrec = nsrc * nshift * B.
-__global__ void blk_init_kernel(ShiftTab *hist, int64_t nrec, unsigned long long *cnt) {
+// History records set to the identity, every source fresh, sweep counts to zero.
+// nrec = nsrc * nshift * B.
+__global__ void blk_init_kernel(ShiftTab *hist, int64_t nrec, unsigned long long *cnt, int32_t *fresh, int nsrc) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < 2 * kBlkCnt) cnt[t] = 0;
+  if (t < nsrc) fresh[t] = 1;
   if (t >= nrec) return;
   ShiftTab r;
   r.a = r.ipi = make_double2(0.0, 0.0);
@@ -813,18 +815,26 @@ __global__ __launch_bounds__(kBlock) void blk_compose_kernel(VecBatch B, int pre
     H[t] = acc;
   }
   if (threadIdx.x == 0) {
-    anyf[l] = (n_any > 0 ? 1 : 0) | (n_st > 0 ? 2 : 0);
+    // the source's first block: its directions were never written (every p_j(0) = v)
+    int32_t *fresh = reinterpret_cast<int32_t *>(tb + lay.fresh) + l;
+    const int first = *fresh != 0 && n_any > 0;
+    if (first) *fresh = 0;
+    anyf[l] = (n_any > 0 ? 1 : 0) | (n_st > 0 ? 2 : 0) | (first ? 4 : 0);
     // what the two sweep kernels will move for this source (moment kernel: runs if a
     // shift moved, reads those directions; direction kernel: runs if a shift is still
     // active, reads the moved directions, writes the active ones)
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(tb + lay.cnt) + prec * kBlkCnt;
+    // (a first block reads v once instead of its directions: counted as one FP64
+    // direction read, in the FP64 counts it always falls in)
+    const unsigned long long nrd = first ? 1 : (unsigned long long)n_any;
+    unsigned long long *crd = first ? reinterpret_cast<unsigned long long *>(tb + lay.cnt) : cnt;
     if (n_any > 0) {
       atomicAdd(cnt + 0, 1ull);
-      atomicAdd(cnt + 1, (unsigned long long)n_any);
+      atomicAdd(crd + 1, nrd);
     }
     if (n_st > 0) {
       atomicAdd(cnt + 2, 1ull);
-      atomicAdd(cnt + 3, (unsigned long long)n_any);
+      atomicAdd(crd + 3, nrd);
       atomicAdd(cnt + 4, (unsigned long long)n_st);
     }
   }
@@ -842,7 +852,9 @@ __global__ __launch_bounds__(kBlock) void blk_compose_kernel(VecBatch B, int pre
 // buffer slot j mod PD, in groups of PD shifts (a static slot per unrolled step, so no
 // register is copied while its load is in flight), the first group peeled so the loop
 // is entered with the memory operations in flight that every later group starts with.
-// job: a = moments, b = shift directions, c = residual ring, e = table.
+// A source's first block reads v (job d) in place of every p_j(0): the directions are
+// not initialised at the start of a solve.
+// job: a = moments, b = shift directions, c = residual ring, d = sources v, e = table.
 struct BlkView {
   typedef __attribute__((address_space(4))) const double CDbl;
   typedef __attribute__((address_space(4))) const int32_t CInt;
@@ -901,13 +913,17 @@ __global__ __launch_bounds__(kMomBlock) void blk_moments_kernel(VecBatch B) {
   double2 acc[MM];
 #pragma unroll
   for (int k = 0; k < MM; ++k) acc[k] = BufIO<double, 2>::ld(mom_rsrc(k), voff16, 0);
+  // a source's first block: every p_j(0) is v (the directions were never written)
+  const bool fresh = (v.anyf[l] & 4) != 0;
+  const double2 v0 = reinterpret_cast<const double2 *>(J.d)[(size_t)l * n + t.ii];
   constexpr int kW = sizeof(V2<T>);
   const int voff = t.valid ? t.q * kW : 0x7fffffff;
   const double2 *W = reinterpret_cast<const double2 *>(J.b);
   auto fetch = [&](int j, double2 &x, bool &f) {
     f = j < N && v.any(j);
-    const V2<T> y = BufIO<T, 2>::ld(make_rsrc(W + blk_chunk(l, t.c, j, nch, N), f ? 64 * kW : 0), voff, 0);
-    x = make_double2(y.x, y.y);
+    const V2<T> y =
+        BufIO<T, 2>::ld(make_rsrc(W + blk_chunk(l, t.c, j, nch, N), f && !fresh ? 64 * kW : 0), voff, 0);
+    x = fresh ? v0 : make_double2(y.x, y.y);
   };
   double2 buf[PD];
   bool bup[PD];
@@ -969,10 +985,12 @@ __global__ __launch_bounds__(kMomBlock) void blk_dirs_kernel(VecBatch B) {
   const int voff = t.valid ? t.q * kW : 0x7fffffff;
   const double2 *W = reinterpret_cast<const double2 *>(J.b);
   auto run_rsrc = [&](int j, bool on) { return make_rsrc(W + blk_chunk(l, t.c, j, nch, N), on ? 64 * kW : 0); };
+  const bool fresh = (v.anyf[l] & 4) != 0;  // a source's first block: every p_j(0) is v
+  const double2 v0 = reinterpret_cast<const double2 *>(J.d)[(size_t)l * n + t.ii];
   auto fetch = [&](int j, double2 &x, bool &f) {
     f = j < N && v.any(j);
-    const V2<T> y = BufIO<T, 2>::ld(run_rsrc(j, f), voff, 0);
-    x = make_double2(y.x, y.y);
+    const V2<T> y = BufIO<T, 2>::ld(run_rsrc(j, f && !fresh), voff, 0);
+    x = fresh ? v0 : make_double2(y.x, y.y);
   };
   double2 buf[PD];
   bool bup[PD];
@@ -1305,9 +1323,10 @@ void launch_blk_init(void *tab, int nsrc, int nshift, int B, hipStream_t st) {
   if (nrec <= 0) return;
   const BlkLayout lay = blk_layout(nsrc, nshift, B);
   char *tb = reinterpret_cast<char *>(tab);
-  hipLaunchKernelGGL(blk_init_kernel, dim3(nblocks1d(std::max<int64_t>(nrec, 2 * kBlkCnt))), dim3(kBlock), 0, st,
-                     reinterpret_cast<ShiftTab *>(tb + lay.hist), nrec,
-                     reinterpret_cast<unsigned long long *>(tb + lay.cnt));
+  hipLaunchKernelGGL(blk_init_kernel, dim3(nblocks1d(std::max<int64_t>({nrec, 2 * kBlkCnt, nsrc}))), dim3(kBlock),
+                     0, st, reinterpret_cast<ShiftTab *>(tb + lay.hist), nrec,
+                     reinterpret_cast<unsigned long long *>(tb + lay.cnt), reinterpret_cast<int32_t *>(tb + lay.fresh),
+                     nsrc);
 }
 void launch_seed_p_update(const VecBatch &b, int slot, hipStream_t st) {
   if (b.total_blocks <= 0) return;

@@ -19,7 +19,8 @@ def test_more_than_one_gpu_is_refused():
 
 def test_committed_counter_summaries_are_well_formed():
     """Every profiles/*_pmc.txt names its kernel, workload, source file and hash, and
-    its HBM bytes are the calibrated read + write figures."""
+    its HBM bytes are the calibrated read + write figures (per dispatch of one kernel,
+    or per launch of a stage of several kernels, whose dispatches are summed)."""
     files = sorted((ROOT / "profiles").glob("*_pmc.txt"))
     assert files
     for f in files:
@@ -28,8 +29,10 @@ def test_committed_counter_summaries_are_well_formed():
                     "calibration", "command_fetch", "command_write"):
             assert key in d, (f.name, key)
         cal = d["calibration"]
-        rd = d["fetch_kib_per_dispatch"] * 1024 * cal["fetch_scale"]
-        wr = d["write_kib_per_dispatch"] * 1024 * cal["write_scale"]
+        fk = d["fetch_kib_per_launch"] if "fetch_kib_per_launch" in d else d["fetch_kib_per_dispatch"]
+        wk = d["write_kib_per_launch"] if "write_kib_per_launch" in d else d["write_kib_per_dispatch"]
+        rd = fk * 1024 * cal["fetch_scale"]
+        wr = wk * 1024 * cal["write_scale"]
         assert abs(d["hbm_bytes_per_launch"] - (rd + wr)) <= 2
         assert (ROOT / d["source"]).exists()
         assert f.name == f"{d['kernel']}_{d['workload']}_{d['prec']}_pmc.txt"
