@@ -54,7 +54,7 @@ DEFAULT_CONFIG = "wilson24x48"
 STAGES = ["dslash", "seed_alpha", "seed_r_update", "unused", "shift_update", "reliable_update",
           "solve_loop", "block_sweep"]
 TIMED_STAGES = (0, 1, 2, 4, 5, 7)
-BLOCK_DEFAULT = 16    # block length of the in-loop moment update (SSCG_BLOCK, unless set)
+BLOCK_DEFAULT = 24    # block length of the in-loop moment update (SSCG_BLOCK, unless set)
 KERNEL_SOURCES = {"shift_update": "paper_1004_0292_amd/csrc/vec.hip",
                   "shift_moments": "paper_1004_0292_amd/csrc/vec.hip",
                   "block_sweep": "paper_1004_0292_amd/csrc/vec.hip",

@@ -42,7 +42,7 @@
  *            SSCG_XCD, SSCG_CT, SSCG_TBS, SSCG_WBATCH, SSCG_UNROLL, SSCG_NT set,
  *            fixes the shapes (read at sscg_create); with fixed shapes a solve is
  *            bitwise reproducible (the reductions do not depend on the schedule).
- *            SSCG_BLOCK (0, 4, 8, 16 or 32; default 16) sets the block length B
+ *            SSCG_BLOCK (0, 4, 8, 16, 24 or 32; default 24) sets the block length B
  *            of the in-loop moment update (see moments_in_loop; 0 selects the
  *            per-iteration form); SSCG_MOMUB (1, 2 or 4; default 1) sets how many
  *            shifts' loads the per-iteration form issues together, and SSCG_MOMPF
@@ -213,7 +213,7 @@ typedef struct {
                                or SSCG_MIXED_SHIFTS and 12 V < 2^27 (vectors under
                                2 GiB), else SSCG_EINVAL. The shift directions are
                                stored in 64-entry chunks per (source, shift).
-                               Block form (the default, block length B = 16): the
+                               Block form (the default, block length B = 24): the
                                recurrences of B iterations are composed into one
                                linear map per shift, p_j(B) = C_j p_j(0) +
                                sum_m D_jm r(m) with the seed residuals r(m) of the

@@ -901,10 +901,10 @@ static int prepare_problem(Prob &p, const sscg_solve_opts &o) {
                              hipMemcpyDeviceToDevice, st));
     launch_blk_init(c->momtab.p, (int)L, (int)N, p.blk, st);
   }
-  if (p.nmom > 0 && p.blk == 0)  // (the block form's first sweep reads v itself)
-    launch_init_shifts_blocked(c->W.p, c->v64.p, (int64_t)n, (int)L, (int)N, st);
-  else
+  if (p.nmom == 0)
     launch_init_shifts(p.y, c->W.p, c->v64.p, (int64_t)n, (int)L, (int)N, st);
+  else if (p.blk == 0)  // (the block form's first sweep reads v itself)
+    launch_init_shifts_blocked(c->W.p, c->v64.p, (int64_t)n, (int)L, (int)N, st);
   // ||v||
   const int nb = 64;
   launch_norm2_partial(c->v64.p, c->n, (int)L, (double *)c->rr_part.p, nb, st);
@@ -1115,10 +1115,10 @@ static int run_solve(std::vector<Prob> &P, const sscg_solve_opts &o_in) {
   if (o.ru_interval < 1) o.ru_interval = 50;
   sscg_ctx *c0 = P[0].c;
   hipStream_t st = c0->work;
-  // block form of the in-loop moment update: block length 4, 8, 16 or 32 (0: per iteration)
-  const int blk = env_int("SSCG_BLOCK", 16);
-  if (blk != 0 && blk != 4 && blk != 8 && blk != 16 && blk != 32)
-    return fail(c0, SSCG_EINVAL, "SSCG_BLOCK must be 0, 4, 8, 16 or 32");
+  // block form of the in-loop moment update: block length 4, 8, 16, 24 or 32 (0: per iteration)
+  const int blk = env_int("SSCG_BLOCK", 24);
+  if (blk != 0 && blk != 4 && blk != 8 && blk != 16 && blk != 24 && blk != 32)
+    return fail(c0, SSCG_EINVAL, "SSCG_BLOCK must be 0, 4, 8, 16, 24 or 32");
   for (Prob &p : P) p.blk = p.nmom > 0 ? blk : 0;
   for (Prob &p : P) {
     if (!p.c->have_gauge) return fail(p.c, SSCG_ESTATE, "no gauge field set");

@@ -17,14 +17,29 @@ constexpr int kGK = 16;  // summed-index step staged in LDS
 // herm = 1 (a Hermitian product, na = nb): only the tiles on and above the diagonal
 // (the caller mirrors the rest); the blocks enumerate them row by row.
 // Held to 168 registers (three wavefronts per SIMD; the two registers it gives up are
-// spilled outside the summation loop).
+// spilled outside the summation loop). One-dimensional grid of tiles x nchunk blocks,
+// numbered so that the tiles of one row chunk run on one XCD (workgroups are dealt
+// round-robin over the 8 XCDs, each with its own L2): the chunk's rows are then fetched
+// from HBM once and re-read from that L2 by its other tiles.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void gemm_cn_kernel(const double2 *__restrict__ A, int64_t lda, int na,
                                                       const double2 *__restrict__ B, int64_t ldb, int nb,
                                                       int64_t n, double2 *partial, int nchunk, int herm) {
   __shared__ double2 As[kGK][kGT + 1];
   __shared__ double2 Bs[kGK][kGT + 1];
   const int tiles_b = (nb + kGT - 1) / kGT;
-  const int tile = blockIdx.x, chunk = blockIdx.y;
+  const int ntile = herm ? tiles_b * (tiles_b + 1) / 2 : ((na + kGT - 1) / kGT) * tiles_b;
+  const int groups = nchunk / 8;  // chunks in groups of 8, one per XCD
+  const int lin = blockIdx.x;
+  int tile, chunk;
+  if (lin < ntile * groups * 8) {
+    const int xcd = lin & 7, s = lin >> 3;
+    chunk = (s / ntile) * 8 + xcd;
+    tile = s % ntile;
+  } else {  // the chunks past the last group of 8, in plain order
+    const int r = lin - ntile * groups * 8;
+    chunk = groups * 8 + r / ntile;
+    tile = r % ntile;
+  }
   int ta = tile / tiles_b, tb = tile % tiles_b;
   if (herm) {
     ta = 0;
@@ -216,7 +231,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *part
 void launch_gemm_cn(const void *A, int64_t lda, int na, const void *B, int64_t ldb, int nb, int64_t n,
                     double *partial, int nchunk, int herm, hipStream_t st) {
   const int tiles = gemm_cn_tiles(na, nb, herm);
-  hipLaunchKernelGGL(gemm_cn_kernel, dim3(tiles, nchunk), dim3(256), 0, st, (const double2 *)A, lda, na,
+  hipLaunchKernelGGL(gemm_cn_kernel, dim3(tiles * nchunk), dim3(256), 0, st, (const double2 *)A, lda, na,
                      (const double2 *)B, ldb, nb, n, (double2 *)partial, nchunk, herm);
 }
 void launch_gemm_nn(const void *A, int64_t lda, int na, const double *T, int nb, void *C, int64_t ldc,

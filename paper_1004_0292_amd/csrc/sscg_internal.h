@@ -361,7 +361,7 @@ void launch_shift_moments_tab(const VecBatch &b, int prec, int nmom_max, int ub,
 inline size_t shift_table_bytes(int nsrc, int nshift) {
   return (size_t)nsrc * nshift * (sizeof(ShiftTab) + (size_t)kMomRows * sizeof(double2));
 }
-// Block form (VecJob::ring = B > 0, B in {4, 8, 16, 32}): the table kernel writes the
+// Block form (VecJob::ring = B > 0, B in {4, 8, 16, 24, 32}): the table kernel writes the
 // iteration's record of every (source, shift) into slot s of a history of B records
 // (not-updated records: alpha 0, beta 1, 1/pi 0); after the B-th iteration (and once
 // after the loop) the compose kernel folds the history into one linear map per shift

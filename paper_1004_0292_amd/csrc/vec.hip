@@ -1339,6 +1339,7 @@ void launch_blk_compose(const VecBatch &b, int B, int prec, hipStream_t st) {
   if (B == 4) hipLaunchKernelGGL(blk_compose_kernel<4>, g, t, 0, st, b, ph);
   else if (B == 8) hipLaunchKernelGGL(blk_compose_kernel<8>, g, t, 0, st, b, ph);
   else if (B == 16) hipLaunchKernelGGL(blk_compose_kernel<16>, g, t, 0, st, b, ph);
+  else if (B == 24) hipLaunchKernelGGL(blk_compose_kernel<24>, g, t, 0, st, b, ph);
   else hipLaunchKernelGGL(blk_compose_kernel<32>, g, t, 0, st, b, ph);
 }
 constexpr int kBlkPD = 4;  // shift directions in flight per thread of the sweep kernels
@@ -1348,6 +1349,7 @@ static void launch_bm(const VecBatch &b, int B, hipStream_t st) {
   if (B == 4) hipLaunchKernelGGL((blk_moments_kernel<T, MM, 4, kBlkPD>), g, t, 0, st, b);
   else if (B == 8) hipLaunchKernelGGL((blk_moments_kernel<T, MM, 8, kBlkPD>), g, t, 0, st, b);
   else if (B == 16) hipLaunchKernelGGL((blk_moments_kernel<T, MM, 16, kBlkPD>), g, t, 0, st, b);
+  else if (B == 24) hipLaunchKernelGGL((blk_moments_kernel<T, MM, 24, kBlkPD>), g, t, 0, st, b);
   else hipLaunchKernelGGL((blk_moments_kernel<T, MM, 32, kBlkPD>), g, t, 0, st, b);
 }
 template <typename T>
@@ -1356,6 +1358,7 @@ static void launch_bd(const VecBatch &b, int B, hipStream_t st) {
   if (B == 4) hipLaunchKernelGGL((blk_dirs_kernel<T, 4, kBlkPD>), g, t, 0, st, b);
   else if (B == 8) hipLaunchKernelGGL((blk_dirs_kernel<T, 8, kBlkPD>), g, t, 0, st, b);
   else if (B == 16) hipLaunchKernelGGL((blk_dirs_kernel<T, 16, kBlkPD>), g, t, 0, st, b);
+  else if (B == 24) hipLaunchKernelGGL((blk_dirs_kernel<T, 24, kBlkPD>), g, t, 0, st, b);
   else hipLaunchKernelGGL((blk_dirs_kernel<T, 32, kBlkPD>), g, t, 0, st, b);
 }
 template <typename T>

@@ -126,7 +126,7 @@ def test_moments_in_loop(sscg, f4, monkeypatch, prec, P, pf, ub):
 
 @pytest.mark.parametrize("prec,P,blk", [("fp64", 1, 4), ("fp64", 1, 8), ("fp64", 1, 16), ("fp64", 1, 32),
                                         ("mixed_shifts", 1, 8), ("mixed_shifts", 1, 32), ("fp64", 3, 8),
-                                        ("mixed_shifts", 3, 16)])
+                                        ("mixed_shifts", 3, 16), ("fp64", 3, 24)])
 def test_moments_in_loop_block(sscg, f4, monkeypatch, prec, P, blk):
     """Block form of the in-loop update (the recurrences of blk iterations composed
     into one linear map per shift and applied in one sweep over the directions, the
@@ -137,7 +137,7 @@ def test_moments_in_loop_block(sscg, f4, monkeypatch, prec, P, blk):
     _in_loop_vs_stored(sscg, f4, prec, P)
 
 
-@pytest.mark.parametrize("blk", [8, 16, 32])
+@pytest.mark.parametrize("blk", [8, 16, 24, 32])
 def test_moments_in_loop_block_cut_short(sscg, f4, monkeypatch, blk):
     """A solve stopped by the iteration limit (37, inside a block) in the block form:
     the sweep after the loop applies the partial block, so the moments, and the
