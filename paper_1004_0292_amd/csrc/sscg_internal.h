@@ -384,7 +384,6 @@ inline size_t shift_table_bytes(int nsrc, int nshift) {
 //                                          (source, block) runs and directions read,
 //                                          direction-kernel runs, directions read and
 //                                          directions written
-constexpr int kMaxBlk = 32;
 struct BlkShift {
   double2 c;       // C_j(B)
   int32_t any;     // updated in at least one iteration of the block (p_j(0) is read)

@@ -162,6 +162,48 @@ def test_moments_in_loop_block_cut_short(sscg, f4, monkeypatch, blk):
     assert np.all(np.abs(b.res - a.res) <= 1e-6 * a.res)
 
 
+@pytest.mark.parametrize("blk", [8, 24])
+def test_sweep_bytes_follow_the_shift_convergence(sscg, f4, monkeypatch, blk):
+    """sscg_sweep_bytes (the benchmark's algorithmic bytes of the block sweep) equals the
+    bytes the block form has to move, computed here from each shift's convergence
+    iteration c_j, taken from a stored-solution solve of the same shifts: shift j is
+    updated in iterations 0 .. c_j - 1 and freezes in the last. Per (source, block of
+    iterations lo .. hi - 1): the moment kernel runs if a shift is updated in the block
+    (c_j > lo) and reads those directions (v once in the first block), the blk residuals
+    and the M moment sums and writes the sums; the direction kernel runs if a shift is
+    still active at the block's end (c_j > hi), reads the same directions and the
+    residuals and writes the active directions; 16 bytes per FP64 entry. The
+    per-iteration form and stored solutions report 0."""
+    import torch
+    case(f"sweep bytes block {blk}")
+    U, A, lam, c = f4
+    V = synth.sources(CFG1.V, 2, 8).reshape(2, -1)
+    kw = dict(gamma=0.225, rho=0.03, beta=0.25, N=16, M=8, rank_tol=1e-7)
+    monkeypatch.setenv("SSCG_BLOCK", str(blk))
+    out = c.ss_eigs(sscg.default_ss_params(moments_in_loop=1, **kw), to_dev(V), max_eigs=32)
+    got = c.sweep_bytes()
+    z, _, _ = sscg.quad_lines(kw["N"], kw["gamma"], kw["rho"], kw["beta"])
+    y = torch.zeros((V.shape[0], kw["N"], V.shape[1]), dtype=torch.complex128, device="cuda:0")
+    r = c.shifted_cg_solve(to_dev(V), z, kw["gamma"], y, sscg.default_ss_params().solve)
+    assert r.status == sscg.OK and int(r.conv_iter.sum()) == out.info.shift_updates
+    n, B, M, d = V.shape[1], blk, kw["M"], 16
+    want = 0
+    for l in range(V.shape[0]):
+        cj = r.conv_iter[l].astype(np.int64)
+        for b in range(-(-int(r.iters[l]) // B)):
+            lo, hi = b * B, (b + 1) * B
+            n_any, n_st = int((cj > lo).sum()), int((cj > hi).sum())
+            rd = 1 if b == 0 else n_any
+            if n_any:
+                want += (16 * B + 32 * M + d * rd) * n
+            if n_st:
+                want += (16 * B + d * rd + d * n_st) * n
+    assert got == want
+    monkeypatch.setenv("SSCG_BLOCK", "0")
+    c.ss_eigs(sscg.default_ss_params(moments_in_loop=1, **kw), to_dev(V), max_eigs=32)
+    assert c.sweep_bytes() == 0
+
+
 def _in_loop_vs_stored(sscg, f4, prec, P):
     U, A, lam, c = f4
     V = synth.sources(CFG1.V, 2, 8).reshape(2, -1)
