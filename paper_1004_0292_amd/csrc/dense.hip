@@ -116,8 +116,25 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const double2 *__restrict_
                                                       int upper) {
   __shared__ double2 As[kGK][kGT + 1];  // [a][row]
   __shared__ double2 Ts[kGK][kGT + 1];  // [a][column]
-  const int64_t i0 = (int64_t)blockIdx.x * kGT;
-  const int b0 = blockIdx.y * kGT;
+  // one-dimensional grid, numbered so that the column tiles of one row tile run on one
+  // XCD one after another (workgroups are dealt round-robin over the 8 XCDs): the row
+  // tile's columns of A are fetched from HBM once and re-read from that XCD's L2
+  const int64_t rtiles = (n + kGT - 1) / kGT;
+  const int ctiles = (nb + kGT - 1) / kGT;
+  const int64_t groups = rtiles / 8, lin = blockIdx.x;
+  int64_t rt;
+  int ctl;
+  if (lin < groups * 8 * ctiles) {
+    const int64_t s = lin >> 3;
+    rt = (s / ctiles) * 8 + (lin & 7);
+    ctl = (int)(s % ctiles);
+  } else {  // the row tiles past the last group of 8, in plain order
+    const int64_t r = lin - groups * 8 * ctiles;
+    rt = groups * 8 + r / ctiles;
+    ctl = (int)(r % ctiles);
+  }
+  const int64_t i0 = rt * kGT;
+  const int b0 = ctl * kGT;
   const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
   double2 acc[4][4];
 #pragma unroll
@@ -237,7 +254,7 @@ void launch_gemm_cn(const void *A, int64_t lda, int na, const void *B, int64_t l
 void launch_gemm_nn(const void *A, int64_t lda, int na, const double *T, int nb, void *C, int64_t ldc,
                     int64_t n, int upper, hipStream_t st) {
   if (n <= 0 || na <= 0 || nb <= 0) return;
-  const dim3 grid((unsigned)((n + kGT - 1) / kGT), (nb + kGT - 1) / kGT);
+  const dim3 grid((unsigned)(((n + kGT - 1) / kGT) * ((nb + kGT - 1) / kGT)));
   hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(256), 0, st, (const double2 *)A, lda, na, (const double2 *)T, nb,
                      (double2 *)C, ldc, n, upper);
 }

@@ -99,101 +99,6 @@ __global__ __launch_bounds__(kBlock) void commit_kernel(DslashBatch B) {
 }
 
 // ---------------------------------------------------------------------------
-// r <- r - alpha q (and x_part += alpha p in the FP32 phase); partial <r, r>.
-// job: a = r, b = q, c = x_part (or null), d = p. With a residual ring (block form of
-// the in-loop update) the new r goes to ring slot `slot` and the old one is read from
-// the slot before it (cyclically), instead of updating r in place.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B, int slot) {
-  using C = V2<T>;
-  __shared__ double red[kBlock / 64];
-  const int b = blockIdx.x;
-  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
-  const int lb = b - J.block_begin;
-  const int l = lb / J.nblk_vec, vb = lb - l * J.nblk_vec;
-  SeedState &S = J.seed[l];
-  if (S.done) return;
-  C *r = reinterpret_cast<C *>(J.a) + (size_t)l * J.n;
-  const C *rin = r;
-  if (J.ring > 0) {
-    const int sin = slot == 0 ? J.ring - 1 : slot - 1;
-    rin = reinterpret_cast<const C *>(J.a) + ((size_t)sin * J.nsrc + l) * J.n;
-    r = reinterpret_cast<C *>(J.a) + ((size_t)slot * J.nsrc + l) * J.n;
-  }
-  const C *q = reinterpret_cast<const C *>(J.b) + (size_t)l * J.n;
-  C *xp = J.c ? reinterpret_cast<C *>(J.c) + (size_t)l * J.n : nullptr;
-  const C *p = J.d ? reinterpret_cast<const C *>(J.d) + (size_t)l * J.n : nullptr;
-  // chunks of kBlock kEpt entries, strided by the source's block count (at most
-  // kMaxRR blocks per source, so the consumers of the partials sum few of them); the
-  // first chunk is loaded before the step length is formed, so the two latencies overlap
-  const int64_t base0 = (int64_t)vb * kBlock * kEpt + threadIdx.x;
-  C r0[kEpt], q0[kEpt], x0[kEpt], p0[kEpt];
-#pragma unroll
-  for (int e = 0; e < kEpt; ++e) {
-    const int64_t i = base0 + (int64_t)e * kBlock;
-    if (i < J.n) {
-      r0[e] = rin[i];
-      q0[e] = q[i];
-      if (xp) {
-        x0[e] = xp[i];
-        p0[e] = p[i];
-      }
-    }
-  }
-  double alpha64;
-  if (J.npq > 0) {
-    // the step length of the alpha kernel, formed by every block from the same
-    // partials in the same order (so every block gets the same value); the first
-    // block of the source also writes the seed state
-    double v = 0.0;
-    const double *pp = J.pq_partial + (size_t)l * J.npq;
-    for (int t = threadIdx.x; t < J.npq; t += kBlock) v += pp[t];
-    const double pq = block_sum_all<kBlock / 64>(v, red);
-    const bool broke = pq == 0.0 || !isfinite(pq);
-    alpha64 = broke ? 0.0 : S.rho / pq;
-    if (vb == 0 && threadIdx.x == 0) {
-      if (broke) {
-        S.status = -5;  // SSCG_EBREAKDOWN
-        S.done = 1;
-      } else {
-        S.alpha = alpha64;
-        S.pending = 1;
-      }
-    }
-    if (broke) return;
-  } else {
-    alpha64 = S.alpha;
-  }
-  const T alpha = (T)alpha64;
-  double acc = 0.0;
-  auto update = [&](int64_t i, C rv, C qv, C xv, C pv) {
-    rv.x -= alpha * qv.x;
-    rv.y -= alpha * qv.y;
-    r[i] = rv;
-    acc += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
-    if (xp) {
-      xv.x += alpha * pv.x;
-      xv.y += alpha * pv.y;
-      xp[i] = xv;
-    }
-  };
-#pragma unroll
-  for (int e = 0; e < kEpt; ++e) {
-    const int64_t i = base0 + (int64_t)e * kBlock;
-    if (i < J.n) update(i, r0[e], q0[e], x0[e], p0[e]);
-  }
-  const int64_t stride = (int64_t)J.nblk_vec * kBlock * kEpt;
-  for (int64_t base = base0 + stride; base - threadIdx.x < J.n; base += stride) {
-#pragma unroll
-    for (int e = 0; e < kEpt; ++e) {
-      const int64_t i = base + (int64_t)e * kBlock;
-      if (i < J.n) update(i, rin[i], q[i], xp ? xp[i] : C{}, xp ? p[i] : C{});
-    }
-  }
-  const double tot = block_sum_all<kBlock / 64>(acc, red);
-  if (threadIdx.x == 0) J.partial[(size_t)l * J.nblk_vec + vb] = tot;
-}
-
 // Non-temporal (streaming) loads and stores of one complex number.
 typedef double nd2 __attribute__((ext_vector_type(2)));
 typedef float nf2 __attribute__((ext_vector_type(2)));
@@ -237,6 +142,103 @@ __device__ __forceinline__ void stc(float2 *p, float2 v) {
     *p = v;
   }
 }
+
+// r <- r - alpha q (and x_part += alpha p in the FP32 phase); partial <r, r>.
+// job: a = r, b = q, c = x_part (or null), d = p. With a residual ring (block form of
+// the in-loop update) the new r goes to ring slot `slot` and the old one is read from
+// the slot before it (cyclically), instead of updating r in place.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void seed_r_update_kernel(VecBatch B, int slot) {
+  using C = V2<T>;
+  __shared__ double red[kBlock / 64];
+  const int b = blockIdx.x;
+  const VecJob &J = B.job[job_of(B.job, B.njobs, b)];
+  const int lb = b - J.block_begin;
+  const int l = lb / J.nblk_vec, vb = lb - l * J.nblk_vec;
+  SeedState &S = J.seed[l];
+  if (S.done) return;
+  C *r = reinterpret_cast<C *>(J.a) + (size_t)l * J.n;
+  const C *rin = r;
+  if (J.ring > 0) {
+    const int sin = slot == 0 ? J.ring - 1 : slot - 1;
+    rin = reinterpret_cast<const C *>(J.a) + ((size_t)sin * J.nsrc + l) * J.n;
+    r = reinterpret_cast<C *>(J.a) + ((size_t)slot * J.nsrc + l) * J.n;
+  }
+  const C *q = reinterpret_cast<const C *>(J.b) + (size_t)l * J.n;
+  C *xp = J.c ? reinterpret_cast<C *>(J.c) + (size_t)l * J.n : nullptr;
+  const C *p = J.d ? reinterpret_cast<const C *>(J.d) + (size_t)l * J.n : nullptr;
+  // chunks of kBlock kEpt entries, strided by the source's block count (at most
+  // kMaxRR blocks per source, so the consumers of the partials sum few of them); the
+  // first chunk is loaded before the step length is formed, so the two latencies overlap
+  const int64_t base0 = (int64_t)vb * kBlock * kEpt + threadIdx.x;
+  C r0[kEpt], q0[kEpt], x0[kEpt], p0[kEpt];
+#pragma unroll
+  for (int e = 0; e < kEpt; ++e) {
+    const int64_t i = base0 + (int64_t)e * kBlock;
+    if (i < J.n) {  // streaming accesses (no vector is re-read before it leaves the caches)
+      r0[e] = ldc<true>(rin + i);
+      q0[e] = ldc<true>(q + i);
+      if (xp) {
+        x0[e] = ldc<true>(xp + i);
+        p0[e] = ldc<true>(p + i);
+      }
+    }
+  }
+  double alpha64;
+  if (J.npq > 0) {
+    // the step length of the alpha kernel, formed by every block from the same
+    // partials in the same order (so every block gets the same value); the first
+    // block of the source also writes the seed state
+    double v = 0.0;
+    const double *pp = J.pq_partial + (size_t)l * J.npq;
+    for (int t = threadIdx.x; t < J.npq; t += kBlock) v += pp[t];
+    const double pq = block_sum_all<kBlock / 64>(v, red);
+    const bool broke = pq == 0.0 || !isfinite(pq);
+    alpha64 = broke ? 0.0 : S.rho / pq;
+    if (vb == 0 && threadIdx.x == 0) {
+      if (broke) {
+        S.status = -5;  // SSCG_EBREAKDOWN
+        S.done = 1;
+      } else {
+        S.alpha = alpha64;
+        S.pending = 1;
+      }
+    }
+    if (broke) return;
+  } else {
+    alpha64 = S.alpha;
+  }
+  const T alpha = (T)alpha64;
+  double acc = 0.0;
+  auto update = [&](int64_t i, C rv, C qv, C xv, C pv) {
+    rv.x -= alpha * qv.x;
+    rv.y -= alpha * qv.y;
+    stc<true>(r + i, rv);
+    acc += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
+    if (xp) {
+      xv.x += alpha * pv.x;
+      xv.y += alpha * pv.y;
+      stc<true>(xp + i, xv);
+    }
+  };
+#pragma unroll
+  for (int e = 0; e < kEpt; ++e) {
+    const int64_t i = base0 + (int64_t)e * kBlock;
+    if (i < J.n) update(i, r0[e], q0[e], x0[e], p0[e]);
+  }
+  const int64_t stride = (int64_t)J.nblk_vec * kBlock * kEpt;
+  for (int64_t base = base0 + stride; base - threadIdx.x < J.n; base += stride) {
+#pragma unroll
+    for (int e = 0; e < kEpt; ++e) {
+      const int64_t i = base + (int64_t)e * kBlock;
+      if (i < J.n)
+        update(i, ldc<true>(rin + i), ldc<true>(q + i), xp ? ldc<true>(xp + i) : C{}, xp ? ldc<true>(p + i) : C{});
+    }
+  }
+  const double tot = block_sum_all<kBlock / 64>(acc, red);
+  if (threadIdx.x == 0) J.partial[(size_t)l * J.nblk_vec + vb] = tot;
+}
+
 
 // Fused multi-shift update. job: a = x (FP64 solution storage [nsrc][nshift][n]),
 // b = shift workspace [nsrc][nshift] slots of n double2: FP64 phase p_j;
@@ -727,15 +729,15 @@ __global__ __launch_bounds__(kBlock) void seed_p_update_kernel(VecBatch B, int s
 #pragma unroll
     for (int e = 0; e < kEpt; ++e) {
       const int64_t i = base + (int64_t)e * kBlock;
-      if (i < J.n) {
-        rv[e] = r[i];
-        pv[e] = p[i];
+      if (i < J.n) {  // streaming: neither vector is re-read before it leaves the caches
+        rv[e] = ldc<true>(r + i);
+        pv[e] = ldc<true>(p + i);
       }
     }
 #pragma unroll
     for (int e = 0; e < kEpt; ++e) {
       const int64_t i = base + (int64_t)e * kBlock;
-      if (i < J.n) p[i] = make_double2(rv[e].x + beta * pv[e].x, rv[e].y + beta * pv[e].y);
+      if (i < J.n) stc<true>(p + i, make_double2(rv[e].x + beta * pv[e].x, rv[e].y + beta * pv[e].y));
     }
   }
 }
@@ -959,7 +961,7 @@ __global__ __launch_bounds__(kMomBlock) void blk_moments_kernel(VecBatch B) {
   // residual terms, one residual at a time
   const double2 *ring = reinterpret_cast<const double2 *>(J.c);
   for (int m = 0; m < BB; ++m) {
-    const double2 r = ring[((size_t)m * J.nsrc + l) * n + t.ii];
+    const double2 r = ldc<true>(ring + ((size_t)m * J.nsrc + l) * n + t.ii);
     BlkView::CDbl *hm = v.Ht + 2 * m;
 #pragma unroll
     for (int k = 0; k < MM; ++k) cfma(acc[k], make_double2(hm[2 * BB * k], hm[2 * BB * k + 1]), r);
@@ -980,7 +982,7 @@ __global__ __launch_bounds__(kMomBlock) void blk_dirs_kernel(VecBatch B) {
   const double2 *ring = reinterpret_cast<const double2 *>(J.c);
   double2 rv[BB];
 #pragma unroll
-  for (int m = 0; m < BB; ++m) rv[m] = ring[((size_t)m * J.nsrc + l) * n + t.ii];
+  for (int m = 0; m < BB; ++m) rv[m] = ldc<true>(ring + ((size_t)m * J.nsrc + l) * n + t.ii);
   constexpr int kW = sizeof(V2<T>);
   const int voff = t.valid ? t.q * kW : 0x7fffffff;
   const double2 *W = reinterpret_cast<const double2 *>(J.b);
