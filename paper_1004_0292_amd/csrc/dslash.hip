@@ -28,6 +28,18 @@
 
 namespace sscg {
 
+// Non-temporal (streaming) store of one complex number: the output spinor is not
+// re-read by this launch, so it need not take L2 space from the neighbours' spinors.
+template <typename C>
+__device__ __forceinline__ void st_stream(C *p, C v) {
+  typedef decltype(v.x) E;
+  typedef E ev2 __attribute__((ext_vector_type(2)));
+  ev2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<ev2 *>(p));
+}
+
 // A solve-loop launch carries one extra block (the last) that commits the staged
 // state of the previous iteration of every job; the other blocks read only the done
 // flags, so at worst they compute a finished source once more, whose result is not
@@ -252,7 +264,7 @@ __global__ __launch_bounds__(BS) void dslash_kernel(DslashBatch B, int xcd_remap
             if (c < 6) { o.x = p.x - kap * a.x; o.y = p.y - kap * a.y; }
             else       { o.x = kap * a.x - p.x; o.y = kap * a.y - p.y; }
           }
-          dst[(size_t)c * V] = o;
+          st_stream(dst + (size_t)c * V, o);
           d += (double)p.x * (double)o.x + (double)p.y * (double)o.y;
         }
         dot[r] = d;
@@ -367,7 +379,7 @@ __global__ __launch_bounds__(256) void dslash_split_kernel(DslashBatch B, int xc
           if (c < 6) { o.x = p.x - kap * a.x; o.y = p.y - kap * a.y; }
           else       { o.x = kap * a.x - p.x; o.y = kap * a.y - p.y; }
         }
-        dst[(size_t)c * V] = o;
+        st_stream(dst + (size_t)c * V, o);
         dot[r] += (double)p.x * (double)o.x + (double)p.y * (double)o.y;
       }
     }
@@ -624,7 +636,7 @@ __global__ __launch_bounds__(MAXBS, (tile_min_blocks<T, NR, MAXBS>())) void dsla
             if (c < 6) { o.x = p.x - kap * a.x; o.y = p.y - kap * a.y; }
             else       { o.x = kap * a.x - p.x; o.y = kap * a.y - p.y; }
           }
-          dst[(size_t)c * V] = o;
+          st_stream(dst + (size_t)c * V, o);
           d += (double)p.x * (double)o.x + (double)p.y * (double)o.y;
         }
         dot[r] = d;
